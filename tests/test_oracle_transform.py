@@ -1,0 +1,237 @@
+"""Pins of the oracle's transforms against facts fixed independently of it:
+the defining integral of Eq. 1 evaluated by brute-force spherical quadrature
+with scipy's harmonics and explicit rotation matrices, the rotation convention
+of Sec. 2.1, the N = 1 special case (a filtered inverse spherical-harmonic
+transform), shift equivariance, the closed-form Wigner coefficients of Eq. 21,
+exact reconstruction (Sec. 3.4), and exactness of the quadratures."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import sph_harm_y, eval_legendre
+
+import oracle
+from oracle import tables
+from paper_1308_5706_amd.inputs import random_flm, random_flm_uniform
+
+
+def rot(alpha, beta, gamma):
+    """Matrix of the zyz rotation R = Rz(alpha) Ry(beta) Rz(gamma) (active, Sec. 2.1)."""
+    def rz(a):
+        return np.array([[math.cos(a), -math.sin(a), 0.0], [math.sin(a), math.cos(a), 0.0], [0.0, 0.0, 1.0]])
+
+    def ry(b):
+        return np.array([[math.cos(b), 0.0, math.sin(b)], [0.0, 1.0, 0.0], [-math.sin(b), 0.0, math.cos(b)]])
+    return rz(alpha) @ ry(beta) @ rz(gamma)
+
+
+def to_xyz(th, ph):
+    return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=-1)
+
+
+def to_angles(v):
+    th = np.arccos(np.clip(v[..., 2], -1.0, 1.0))
+    ph = np.arctan2(v[..., 1], v[..., 0])
+    return th, ph
+
+
+def expand(coeffs_by_l, L, th, ph):
+    """sum_{l<L} sum_m c[l][m] Y_lm(th, ph) with c given as {l: {m: value}}."""
+    out = np.zeros(np.shape(th), dtype=complex)
+    for el in range(L):
+        for m, v in coeffs_by_l[el].items():
+            if v != 0:
+                out += v * sph_harm_y(el, m, th, ph)
+    return out
+
+
+def test_rotation_convention():
+    # (R_rho Y_ln)(omega) = Y_ln(R^-1 omega) = sum_m D^l_mn(rho) Y_lm(omega), D = e^{-im a} d e^{-in g}
+    rng = np.random.default_rng(1)
+    a, b, g = 0.7, 1.9, 2.4
+    R = rot(a, b, g)
+    th = rng.uniform(0, math.pi, 12)
+    ph = rng.uniform(0, 2 * math.pi, 12)
+    th2, ph2 = to_angles(to_xyz(th, ph) @ R)  # rows: R^T v = R^-1 v
+    for el in [1, 2, 5]:
+        for n in range(-el, el + 1):
+            lhs = sph_harm_y(el, n, th2, ph2)
+            rhs = np.zeros(12, dtype=complex)
+            for m in range(-el, el + 1):
+                d = oracle.wigner_d(el + 1, m, n, b)[el]
+                rhs += np.exp(-1j * m * a) * d * np.exp(-1j * n * g) * sph_harm_y(el, m, th, ph)
+            assert np.max(np.abs(lhs - rhs)) < 1e-13
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_analysis_against_brute_force_eq1(N):
+    # W^j(rho) = int f(omega) conj((R_rho Psi^j)(omega)) d omega  (Eq. 1), by exact quadrature
+    L, lam, J_min = 6, 2.0, 0
+    f = random_flm(L, 7)
+    psi = tables.wavelets(L, N, lam, J_min)
+    fc = {el: {m: f[el * el + el + m] for m in range(-el, el + 1)} for el in range(L)}
+    nth, nph = 2 * L, 4 * L
+    x, w = np.polynomial.legendre.leggauss(nth)
+    TH = np.repeat(np.arccos(x), nph).reshape(nth, nph)
+    PH = np.tile(2 * math.pi * np.arange(nph) / nph, nth).reshape(nth, nph)
+    W8 = np.repeat(w, nph).reshape(nth, nph) * (2 * math.pi / nph)
+    fvals = expand(fc, L, TH, PH)
+    beta = 1.13
+    Wor = oracle.analysis_complex(f, L, N, lam, J_min, betas=[beta], psi=psi)
+    for a in [0, 3, 7]:
+        for gi in [0, 1, 2 * N - 2]:
+            alpha = 2 * math.pi * a / (2 * L - 1)
+            gamma = 2 * math.pi * gi / (2 * N - 1)
+            R = rot(alpha, beta, gamma)
+            th2, ph2 = to_angles(to_xyz(TH, PH) @ R)
+            for j in range(psi.shape[0]):
+                pc = {el: {n: psi[j, el, n + N - 1] for n in range(-(N - 1), N) if abs(n) <= el}
+                      for el in range(L)}
+                rpsi = expand(pc, L, th2, ph2)
+                ref = np.sum(W8 * fvals * np.conj(rpsi))
+                assert abs(Wor[j, gi, 0, a] - ref) < 1e-13
+
+
+def test_real_signal_gives_real_coefficients():
+    L, N = 16, 4
+    W = oracle.analysis_complex(random_flm(L, 3), L, N, 2.0, 0)
+    assert np.max(np.abs(W.imag)) < 1e-15 * max(1.0, np.max(np.abs(W.real))) * 10
+
+
+def test_axisymmetric_case_is_filtered_inverse_sht():
+    # N = 1: Psi^j_l0 = kappa^j(l), so W^j(alpha, beta) = sum f_lm kappa^j(l) sqrt(4 pi/(2l+1)) Y_lm(beta, alpha)
+    L, lam, J_min = 12, 2.0, 0
+    f = random_flm(L, 11)
+    W = oracle.analysis(f, L, 1, lam, J_min)
+    kap = tables.kappa_table(L, lam, J_min)
+    betas = oracle.mw_betas(L)
+    alphas = 2 * math.pi * np.arange(2 * L - 1) / (2 * L - 1)
+    B, A = np.meshgrid(betas, alphas, indexing="ij")
+    for j in range(kap.shape[0]):
+        c = {el: {m: f[el * el + el + m] * kap[j, el] * math.sqrt(4 * math.pi / (2 * el + 1))
+                  for m in range(-el, el + 1)} for el in range(L)}
+        ref = expand(c, L, B, A)
+        assert np.max(np.abs(W[j, 0] - ref.real)) < 1e-13
+
+
+def test_single_harmonic_closed_form():
+    # f = delta_{l0 m0}: W^j = sum_n conj(Psi^j_{l0 n}) e^{i m0 alpha} d^{l0}_{m0 n}(beta) e^{i n gamma}
+    L, N, lam = 9, 3, 2.0
+    l0, m0 = 6, -2
+    f = np.zeros(L * L, dtype=complex)
+    f[l0 * l0 + l0 + m0] = 1.0
+    psi = tables.wavelets(L, N, lam, 0)
+    W = oracle.analysis_complex(f, L, N, lam, 0, psi=psi)
+    betas = oracle.mw_betas(L)
+    from test_oracle_wigner import explicit_d
+    for j in range(psi.shape[0]):
+        for b in [0, 4, L - 1]:
+            for a in [0, 5]:
+                for g in range(2 * N - 1):
+                    al, ga = 2 * math.pi * a / (2 * L - 1), 2 * math.pi * g / (2 * N - 1)
+                    ref = sum(np.conj(psi[j, l0, n + N - 1]) * np.exp(1j * m0 * al)
+                              * float(explicit_d(l0, m0, n, betas[b])) * np.exp(1j * n * ga)
+                              for n in range(-(N - 1), N))
+                    assert abs(W[j, g, b, a] - ref) < 1e-14
+
+
+def test_shift_equivariance():
+    L, N, lam = 10, 4, 2.0
+    f = random_flm(L, 5)
+    psi = tables.wavelets(L, N, lam, 0)
+    W = oracle.analysis_complex(f, L, N, lam, 0, psi=psi)
+    ms = np.concatenate([np.arange(-el, el + 1) for el in range(L)])
+    a1 = 2 * math.pi / (2 * L - 1)
+    Wa = oracle.analysis_complex(f * np.exp(-1j * ms * a1), L, N, lam, 0, psi=psi)
+    assert np.max(np.abs(Wa - np.roll(W, 1, axis=-1))) < 1e-14
+    g1 = 2 * math.pi / (2 * N - 1)
+    ns = np.arange(-(N - 1), N)
+    Wg = oracle.analysis_complex(f, L, N, lam, 0, psi=psi * np.exp(-1j * ns * g1)[None, None, :])
+    assert np.max(np.abs(Wg - np.roll(W, -1, axis=1))) < 1e-14
+
+
+@pytest.mark.parametrize("L,N,J_min", [(8, 3, 0), (12, 4, 1), (16, 1, 0)])
+def test_wigner_coefficients_closed_form_eq21(L, N, J_min):
+    # (W^j)^l_mn = 8 pi^2/(2l+1) f_lm conj(Psi^j_ln)
+    lam = 2.0
+    f = random_flm(L, 2)
+    psi = tables.wavelets(L, N, lam, J_min)
+    W = oracle.analysis(f, L, N, lam, J_min, psi=psi)
+    wig = oracle.forward_wigner_mw(W, L, N)
+    nl = tables.n_list(N)
+    worst = 0.0
+    for el in range(L):
+        for m in range(-el, el + 1):
+            for ni, n in enumerate(nl):
+                ref = 8 * math.pi ** 2 / (2 * el + 1) * f[el * el + el + m] * np.conj(psi[:, el, n + N - 1])
+                worst = max(worst, np.max(np.abs(wig[:, el, m + L - 1, ni] - ref)))
+    assert worst < 1e-12
+
+
+@pytest.mark.parametrize("L,N,J_min,seed", [(32, 4, 0, 0), (64, 8, 1, 1), (20, 5, 0, 2), (24, 2, 2, 3)])
+def test_exact_reconstruction(L, N, J_min, seed):
+    # Sec. 3.4: analysis then synthesis recovers f_lm to machine precision
+    lam = 2.0
+    f = random_flm(L, seed)
+    W = oracle.analysis(f, L, N, lam, J_min)
+    Wphi = oracle.scaling(f, L, lam, J_min)
+    fr = oracle.synthesis(W, Wphi, L, N, lam, J_min)
+    assert np.max(np.abs(fr - f)) / np.max(np.abs(f)) < 1e-13
+
+
+def test_exact_reconstruction_paper_signal_non_dyadic_lambda():
+    L, N, lam, J_min = 27, 3, 3.0, 0
+    f = random_flm_uniform(L, 4)
+    W = oracle.analysis(f, L, N, lam, J_min)
+    fr = oracle.synthesis(W, oracle.scaling(f, L, lam, J_min), L, N, lam, J_min)
+    assert np.max(np.abs(fr - f)) < 1e-13
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_random_wigner_coefficients_roundtrip(N):
+    # any band-limited expansion (Eq. 22) is recovered by the forward transform (Eq. 23)
+    L = 8
+    nl = tables.n_list(N)
+    rng = np.random.default_rng(9)
+    c = np.zeros((2, L, 2 * L - 1, len(nl)), dtype=complex)
+    for el in range(L):
+        for m in range(-el, el + 1):
+            for ni, n in enumerate(nl):
+                if abs(n) <= el:
+                    c[:, el, m + L - 1, ni] = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+    g = oracle.inverse_wigner(c, L, nl, oracle.mw_betas(L), 2 * L - 1, 2 * N - 1, 2 * N - 1)
+    wig = oracle.forward_wigner_mw(g, L, N)
+    els = np.arange(L)[None, :, None, None]
+    assert np.max(np.abs(wig - 8 * math.pi ** 2 / (2 * els + 1) * c)) < 1e-12
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_driscoll_healy_grid_reconstruction(N):
+    # the paper's own discretisation (Sec. 3.1): DH colatitudes with q weights, gamma on [0, pi), z_n = 1/N
+    L, lam, J_min = 10, 2.0, 0
+    f = random_flm(L, 6)
+    W = oracle.analysis_dh(f, L, N, lam, J_min)
+    assert np.max(np.abs(W.imag)) < 1e-14
+    fr = oracle.synthesis_dh(W.real, oracle.scaling(f, L, lam, J_min), L, N, lam, J_min)
+    assert np.max(np.abs(fr - f)) < 1e-13
+
+
+def test_dh_quadrature_exactness():
+    # Eq. 17: exact for band-limit 2L: sum_t q_t P_k(cos theta_t) = int_0^pi sin(theta) P_k = 2 delta_k0
+    for L in [4, 8, 32]:
+        th = oracle.dh_betas(L)
+        q = oracle.dh_weights(L)
+        assert abs(q.sum() - 2.0) < 1e-14
+        for k in range(1, 2 * L):
+            assert abs(np.dot(q, eval_legendre(k, np.cos(th)))) < 1e-14
+        assert abs(np.dot(q, eval_legendre(2 * L, np.cos(th)))) > 1e-6
+
+
+def test_sphere_transforms():
+    L = 14
+    f = random_flm(L, 8)
+    fmap = oracle.sht_inverse_mw(f, L)
+    B, A = np.meshgrid(oracle.mw_betas(L), 2 * math.pi * np.arange(2 * L - 1) / (2 * L - 1), indexing="ij")
+    ref = expand({el: {m: f[el * el + el + m] for m in range(-el, el + 1)} for el in range(L)}, L, B, A)
+    assert np.max(np.abs(fmap - ref)) < 1e-13
+    assert np.max(np.abs(oracle.sht_forward_mw(fmap.real, L) - f)) < 1e-13
