@@ -6,7 +6,7 @@ library is checked against.  It shares no code with the GPU library.
 Everything here follows the printed definitions one to one:
   s(t), s_lambda(t)            Eq. 12
   k_lambda(t)                  Eq. 13, both integrals by adaptive Gauss-Kronrod
-  kappa_lambda(t)              Eq. 14
+  kappa_lambda(t)              Eq. 14 (the difference of Eq. 13 taken as one integral)
   kappa^j(l)                   Eq. 15
   J_L(lambda)                  the smallest integer J with lambda^{-J} L <= 1
   Phi_{l0}                     Eq. 16
@@ -64,8 +64,18 @@ def k_lambda(t: float, lam: float) -> float:
 
 
 def kappa_lambda(t: float, lam: float) -> float:
-    """kappa_lambda(t) = sqrt(k_lambda(t/lambda) - k_lambda(t)) (Eq. 14)."""
-    v = k_lambda(t / lam, lam) - k_lambda(t, lam)
+    """kappa_lambda(t) = sqrt(k_lambda(t/lambda) - k_lambda(t)) (Eq. 14).
+
+    Both terms of the difference are the same integral of Eq. 13 with the same upper
+    limit, so the difference is that integral over [t/lambda, t], clipped to the
+    support [1/lambda, 1] of s_lambda.  It is evaluated as one integral: subtracting
+    two values close to 1 would leave kappa with an absolute error of ~1e-8 (the square
+    root of the rounding error) near the ends of its support."""
+    a = max(t / lam, 1.0 / lam)
+    b = min(t, 1.0)
+    if not b > a:
+        return 0.0
+    v = _quad(a, b, lam) / _k_denominator(lam)
     return math.sqrt(v) if v > 0.0 else 0.0
 
 
