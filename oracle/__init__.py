@@ -14,6 +14,12 @@ Layout conventions (the same ones the library's C ABI documents):
     highest-frequency wavelet.
   * Scaling coefficients: complex harmonic W^Phi_lm, [L*L] (Eq. 31).
 
+Synthesis of samples that are not band-limited: the beta integral is taken of the
+unique trigonometric polynomial of degree < L through the samples extended to the
+full circle with the parity (-1)^{m+n}; that polynomial times d^l_mn is a polynomial
+in cos(beta) only when the extension is consistent at beta = pi, so the integral is
+evaluated with a converged Gauss-Legendre rule in beta itself (``beta_rule``).
+
 Functions whose result has a plain definition evaluate it as written
 (analysis: Eq. 20 with Eq. 24; scaling: Eq. 31; synthesis: Eq. 32, 33 and
 41 with exact quadratures).  See ``orc.c`` for the numerical details.
@@ -80,6 +86,15 @@ def mw_betas(L: int) -> np.ndarray:
 def dh_betas(L: int) -> np.ndarray:
     """theta_t = pi (2t+1)/(4L), t < 2L (Sec. 3.1)."""
     return np.pi * (2.0 * np.arange(2 * L) + 1.0) / (4.0 * L)
+
+
+def beta_rule(L: int) -> tuple[np.ndarray, np.ndarray]:
+    """Nodes in [0, pi] and weights (times sin(beta)) of the Gauss-Legendre rule in beta used
+    to integrate sin(beta) G(beta) d^l_mn(beta), G a trigonometric polynomial of degree < L:
+    4L+16 nodes put the quadrature error of this entire integrand below e^(-5L)."""
+    x, w = np.polynomial.legendre.leggauss(4 * L + 16)
+    b = 0.5 * np.pi * (x + 1.0)
+    return np.ascontiguousarray(b), np.ascontiguousarray(0.5 * np.pi * w * np.sin(b))
 
 
 def dh_weights(L: int) -> np.ndarray:
@@ -184,14 +199,12 @@ def forward_wigner_mw(W, L: int, N: int, m_range=None) -> np.ndarray:
     S = W.shape[0]
     nl = tables.n_list(N)
     nla = np.ascontiguousarray(np.array(nl, dtype=np.int32))
-    xg, wg = np.polynomial.legendre.leggauss(L)
-    xg = np.ascontiguousarray(xg)
-    wg = np.ascontiguousarray(wg)
+    xg, wg = beta_rule(L)
     lo, hi = (-(L - 1), L - 1) if m_range is None else m_range
     out = np.zeros((S, L, 2 * L - 1, len(nl)), dtype=np.complex128)
     rc = _load().orc_forward_wigner_mw(ctypes.c_int(L), ctypes.c_int(len(nl)), _ip(nla), ctypes.c_int(S),
                                        _dp(W.view(np.float64)), ctypes.c_int(2 * L - 1), ctypes.c_int(2 * N - 1),
-                                       ctypes.c_int(2 * N - 1), ctypes.c_int(L), _dp(xg), _dp(wg),
+                                       ctypes.c_int(2 * N - 1), ctypes.c_int(len(xg)), _dp(xg), _dp(wg),
                                        ctypes.c_int(lo), ctypes.c_int(hi), _dp(out.view(np.float64)),
                                        ctypes.c_int(_nthreads()))
     if rc != 0:

@@ -22,12 +22,14 @@
  *     summed over l first, then n, then m, each as a plain direct sum.
  *   - The forward Wigner transform (Eq. 23 / Eq. 33) of samples on the
  *     equiangular grid alpha_a = 2 pi a/(2L-1), beta_b = pi(2b+1)/(2L-1)
- *     (b < L), gamma_g = 2 pi g/(2N-1), by exact quadrature: the uniform
- *     rules in alpha (Eq. 19) and gamma, and in beta the unique
- *     trigonometric polynomial of degree <= L-1 through the samples extended
- *     to the full circle with the parity (-1)^{m+n}, integrated against
- *     sin(beta) d^l_{mn}(beta) by Gauss-Legendre quadrature in cos(beta)
- *     (exact: the integrand is a polynomial of degree <= 2L-2 in cos(beta)).
+ *     (b < L), gamma_g = 2 pi g/(2N-1), by quadrature: the uniform rules in
+ *     alpha (Eq. 19) and gamma, and in beta the unique trigonometric
+ *     polynomial of degree <= L-1 through the samples extended to the full
+ *     circle with the parity (-1)^{m+n}, integrated against
+ *     sin(beta) d^l_{mn}(beta) over [0, pi] by a Gauss-Legendre rule in beta
+ *     with enough nodes (4L+16) that the integral of this entire integrand is
+ *     converged to rounding (the nodes and weights, sin(beta) included, come
+ *     from the caller).
  *   - The same forward transform on the paper's Driscoll-Healy grid
  *     (Sec. 3.1, Eq. 17-18; gamma on [0, pi) with weight 2 pi z_n, Eq. 39).
  *
@@ -336,7 +338,8 @@ static int alpha_gamma_rules(int L, int nn, const int *nlist, int S, const doubl
  * Forward Wigner transform of samples on the equiangular grid with L samples in
  * beta (beta_b = pi(2b+1)/(2L-1)), na = 2L-1 in alpha and ng = mg = 2N-1 in gamma:
  *   out[s][l][m+L-1][ni] = int W^s(rho) D^l_{mn}(rho) d rho     (Eq. 23)
- * W complex [S][ng][L][na]; xgl, wgl: Gauss-Legendre nodes/weights (ngl >= L).
+ * W complex [S][ng][L][na]; xgl, wgl: quadrature colatitudes in [0, pi] and weights
+ * (including the sin(beta) of the measure).
  * Only the columns m in [m_lo, m_hi] are produced (the rest of out is left as is).
  */
 int orc_forward_wigner_mw(int L, int nn, const int *nlist, int S, const double *W,
@@ -354,7 +357,7 @@ int orc_forward_wigner_mw(int L, int nn, const int *nlist, int S, const double *
     /* e^{i pi k/(2L-1)} for the extended beta grid beta_t = pi(2t+1)/(2L-1) */
     int P2 = 2 * T;
     double *eb = (double *)malloc(sizeof(double) * 2 * (size_t)P2);
-    /* e^{i p theta_k} at the Gauss-Legendre colatitudes, p in [-(L-1), L-1] */
+    /* e^{i p theta_k} at the quadrature colatitudes, p in [-(L-1), L-1] */
     double *ek = (double *)malloc(sizeof(double) * 2 * (size_t)ngl * M);
     if (!eb || !ek) { free(gw); free(Gt); free(eb); free(ek); return -1; }
     for (int k = 0; k < P2; ++k) {
@@ -362,7 +365,7 @@ int orc_forward_wigner_mw(int L, int nn, const int *nlist, int S, const double *
         eb[2 * k] = (double)cosl(t); eb[2 * k + 1] = (double)sinl(t);
     }
     for (int k = 0; k < ngl; ++k) {
-        ld th = acosl((ld)xgl[k]);
+        ld th = (ld)xgl[k];
         for (int p = -(L - 1); p <= L - 1; ++p) {
             size_t o = (size_t)k * M + (size_t)(p + L - 1);
             ek[2 * o] = (double)cosl((ld)p * th);
@@ -410,7 +413,7 @@ int orc_forward_wigner_mw(int L, int nn, const int *nlist, int S, const double *
                     gh[2 * (p + L - 1)] = sr / (double)T;
                     gh[2 * (p + L - 1) + 1] = si / (double)T;
                 }
-                /* the interpolant at the Gauss-Legendre colatitudes */
+                /* the interpolant at the quadrature colatitudes */
                 for (int k = 0; k < ngl; ++k) {
                     const double *e = ek + 2 * (size_t)k * M;
                     double sr = 0.0, si = 0.0;
@@ -437,7 +440,7 @@ int orc_forward_wigner_mw(int L, int nn, const int *nlist, int S, const double *
                 continue;
             }
             for (int k = 0; k < ngl; ++k) {
-                ld th = acosl((ld)xgl[k]);
+                ld th = (ld)xgl[k];
                 wigner_run(L, m, n, cosl(th), cosl(th / 2.0L), sinl(th / 2.0L), d);
                 for (int s = 0; s < S; ++s) {
                     ld gr = gk[2 * ((size_t)s * ngl + k)] * (ld)wgl[k];

@@ -235,3 +235,33 @@ def test_sphere_transforms():
     ref = expand({el: {m: f[el * el + el + m] for m in range(-el, el + 1)} for el in range(L)}, L, B, A)
     assert np.max(np.abs(fmap - ref)) < 1e-13
     assert np.max(np.abs(oracle.sht_forward_mw(fmap.real, L) - f)) < 1e-13
+
+
+def test_beta_integral_of_interpolant_for_arbitrary_samples():
+    # For samples that are not band-limited, the synthesis integrates the trigonometric
+    # interpolant of the (-1)^{m+n}-extended samples exactly.  Check the oracle's forward
+    # transform (N = 1, i.e. the sphere transform) against mpmath adaptive quadrature of
+    # sin(beta) G(beta) d^l_{m0}(beta) with Wigner's explicit sum, including odd m where the
+    # extension is not odd at beta = pi.
+    import mpmath
+    from test_oracle_wigner import explicit_d
+    L = 5
+    rng = np.random.default_rng(21)
+    fmap = rng.standard_normal((L, 2 * L - 1))
+    got = oracle.sht_forward_mw(fmap, L)
+    T = 2 * L - 1
+    alphas = 2 * math.pi * np.arange(T) / T
+    bt = math.pi * (2 * np.arange(T) + 1) / T
+    for m in range(-(L - 1), L):
+        Gm = (2 * math.pi / T) * (fmap * np.exp(-1j * m * alphas)[None, :]).sum(axis=1)
+        ext = np.array([Gm[t] if t < L else (-1) ** m * Gm[2 * L - 2 - t] for t in range(T)])
+        ps = np.arange(-(L - 1), L)
+        gh = np.array([(ext * np.exp(-1j * p * bt)).sum() / T for p in ps])
+
+        def G(b):
+            return sum(complex(gh[i]) * mpmath.exp(1j * int(ps[i]) * b) for i in range(len(ps)))
+        for el in range(abs(m), L):
+            mpmath.mp.dps = 30
+            val = mpmath.quad(lambda b: mpmath.sin(b) * G(b) * explicit_d(el, m, 0, b, dps=30), [0, mpmath.pi])
+            ref = math.sqrt((2 * el + 1) / (4 * math.pi)) * complex(val)
+            assert abs(got[el * el + el + m] - ref) < 1e-13, (el, m)
