@@ -1,0 +1,178 @@
+"""Benchmark: SO(3) wavelet coefficients per second, analysis + synthesis, on one MI355X.
+
+A step is one round trip of one map through the whole hot path: wavelet analysis
+(Wigner stage + beta/gamma/alpha stages) with the scaling coefficients, then the exact
+synthesis back to f_lm.  Workload (the metric's configuration): L = 1024, N = 8,
+lambda = 2, J_min = 1 (10 scales, full-resolution grid 15 x 1024 x 2047 per scale),
+f_lm synthetic (seeded complex Gaussian, C_l = 1/(l+1)^2, real-signal symmetry),
+resident in HBM before the timed region.
+
+Prints one JSON line.  The roofline entry covers the kernel that takes the most time,
+timed live with HIP events on the stream the library launches on; cpu_baseline times
+the CPU reference on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+
+
+def n_list(N):
+    return [n for n in range(-(N - 1), N) if (N + n) % 2 == 1]
+
+
+def wigner_terms(kappa, N):
+    """Terms of the l-sum (or the m'-contraction) over the m >= 0, m' >= 0 quarter:
+    sum_j sum_{l: kappa^j(l) > 0} (l+1)^2 #{n carried with |n| <= l}."""
+    nl = n_list(N)
+    T = 0
+    S, L = kappa.shape
+    for j in range(S):
+        for el in range(L):
+            if kappa[j, el] > 0.0:
+                T += (el + 1) ** 2 * sum(1 for n in nl if abs(n) <= el)
+    return T
+
+
+def cpu_baseline(L, N, lam, J_min, budget_rows=None, budget_cols=None):
+    """The CPU reference timed on a bounded sample of the workload, scaled to coefficients/s.
+    Sample: analysis of `budget_rows` of the L beta rows (all scales, alpha, gamma);
+    synthesis alpha/gamma rules on `budget_rows` rows and the beta/Wigner step on
+    `budget_cols` of the 2L-1 m columns.  Each part's cost is linear in its rows/columns."""
+    import numpy as np
+    import oracle
+    from oracle import tables
+    from paper_1308_5706_amd.inputs import random_flm, random_wavelet_samples
+    threads = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    budget_rows = budget_rows or threads
+    budget_cols = budget_cols or max(2, threads // 4)
+    f = random_flm(L, 0)
+    psi = tables.wavelets(L, N, lam, J_min)
+    S = psi.shape[0]
+    betas = oracle.mw_betas(L)
+    t0 = time.perf_counter()
+    oracle.analysis(f, L, N, lam, J_min, betas=betas[:budget_rows], psi=psi)
+    t_an = (time.perf_counter() - t0) * L / budget_rows
+    Ws = random_wavelet_samples(S, 2 * N - 1, budget_rows, 2 * L - 1, 1)
+    t0 = time.perf_counter()
+    oracle.alpha_gamma_rules_mw(Ws, L, N)
+    t_rules = (time.perf_counter() - t0) * L / budget_rows
+    Gt = np.zeros((S, len(n_list(N)), L, 2 * L - 1), dtype=np.complex128)
+    t0 = time.perf_counter()
+    oracle.beta_wigner_mw(Gt, L, N, (0, budget_cols - 1))
+    t_beta = (time.perf_counter() - t0) * (2 * L - 1) / budget_cols
+    coeffs = S * (2 * N - 1) * L * (2 * L - 1)
+    total = t_an + t_rules + t_beta
+    return {"value": coeffs / total, "unit": "SO(3) coeffs/s", "cores": threads,
+            "kind": "oracle",
+            "sample": (f"analysis of {budget_rows}/{L} beta rows; synthesis alpha/gamma rules on {budget_rows}/{L} "
+                       f"rows and beta/Wigner step on {budget_cols}/{2 * L - 1} m columns; each scaled linearly "
+                       f"to the full map (estimated round trip {total:.1f} s)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=1024)
+    ap.add_argument("--N", type=int, default=8)
+    ap.add_argument("--lam", type=float, default=2.0)
+    ap.add_argument("--jmin", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the transform is single-GPU; a multi-GPU split is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1308_5706_amd import s2dw
+    from paper_1308_5706_amd.inputs import random_flm
+
+    L, N, lam, J_min = args.L, args.N, args.lam, args.jmin
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S = s2dw.num_scales(L, lam, J_min)
+    f_host = random_flm(L, 0)
+    f = torch.as_tensor(f_host).to(dev)
+    W = torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=torch.float64, device=dev)
+    fr = torch.empty(L * L, dtype=torch.complex128, device=dev)
+    print(f"# workload L={L} N={N} lambda={lam} J_min={J_min} scales={S}", file=sys.stderr, flush=True)
+
+    def step():
+        _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=W)
+        s2dw.synthesis(W, Wp, L, N, lam, J_min, out=fr)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"# warmup step {i} done", file=sys.stderr, flush=True)
+    rt_err = float((fr - f).abs().max().item() / f.abs().max().item())
+
+    s2dw.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = s2dw.profile_read()
+    s2dw.profile(False)
+    print(f"# timed {args.steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    coeffs = S * (2 * N - 1) * L * (2 * L - 1)
+    value = coeffs / (ms_step * 1e-3)
+
+    # roofline of the kernel with the largest total device time
+    kappa, _, _ = s2dw.wavelet_tables(L, N, lam, J_min)
+    T = wigner_terms(kappa, N)
+    w_bytes = 8.0 * coeffs
+    per_stage = {k: {"ms_per_launch": v[0] / v[1], "launches_per_step": v[1] / args.steps,
+                     "ms_per_step": v[0] / args.steps} for k, v in stages.items()}
+    dom = max(per_stage, key=lambda k: per_stage[k]["ms_per_step"])
+    if dom in ("wigner_fwd", "wigner_adj"):
+        # 5 FLOP per term (1 mul + 2 FMA on the complex coefficient), per direction
+        achieved = 5.0 * T / (per_stage[dom]["ms_per_step"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
+    else:
+        # W is written (alpha_fwd) or read (alpha_adj) once per direction; other stages: W-sized
+        achieved = w_bytes / (per_stage[dom]["ms_per_step"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    roof["kernel"] = dom
+    roof["ms_per_step"] = per_stage[dom]["ms_per_step"]
+
+    out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8",
+           "value": value, "unit": "SO(3) coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"SD wavelet round trip, one map, L={L}, N={N}, lambda={lam}, J_min={J_min}, "
+                                  f"{S} scales, grid {2 * N - 1}x{L}x{2 * L - 1}",
+                      "L": L, "N": N, "lambda": lam, "J_min": J_min, "scales": S, "coeffs_per_map": coeffs,
+                      "round_trip_rel_err": rt_err},
+           "roofline": roof,
+           "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in per_stage.items()},
+           "wigner_terms_per_direction": T}
+    if not args.no_cpu_baseline:
+        print("# cpu baseline sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(L, N, lam, J_min)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

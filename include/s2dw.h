@@ -1,0 +1,162 @@
+/*
+ * s2dw.h -- C ABI of the MI355X directional scale-discretized wavelet
+ * transform on the sphere (McEwen, Vandergheynst & Wiaux, "On the
+ * computation of directional scale-discretized wavelet transforms on the
+ * sphere", SPIE 2013).
+ *
+ * The problem statement the arguments follow (Sec. 2): a signal f on the
+ * sphere, band-limited at L (f_lm = 0 for l >= L), is given by its
+ * spherical-harmonic coefficients f_lm.  Wavelets Psi^j (Eq. 7) with
+ * azimuthal band-limit N (Eq. 8), dilation parameter lambda > 1 (Eq. 12)
+ * and scales j = 0..J, J = J_L(lambda) - J_min with J_L(lambda) =
+ * ceil(log_lambda L), give wavelet coefficients W^j(alpha, beta, gamma)
+ * on the rotation group (Eq. 1, computed through Eq. 20) and scaling
+ * coefficients W^Phi (Eq. 3, 31).  Synthesis (Eq. 4, computed through
+ * Eq. 32-41) recovers f_lm exactly.
+ *
+ * Conventions
+ *  - Complex arrays are interleaved (re, im) doubles.
+ *  - f_lm and the harmonic scaling coefficients W^Phi_lm: L*L complex,
+ *    index l*l + l + m, -l <= m <= l.
+ *  - Wavelet coefficients W: real, [S][2N-1][L][2L-1] = [j][gamma_g][beta_b]
+ *    [alpha_a] with alpha fastest, on the equiangular grid
+ *        alpha_a = 2 pi a/(2L-1),  beta_b = pi (2b+1)/(2L-1) (b < L),
+ *        gamma_g = 2 pi g/(2N-1).
+ *    Scale index j = 0 is the highest-frequency wavelet (the paper's
+ *    footnote to Eq. 15); S = J + 1.  Elements are doubles for
+ *    S2DW_FP64 and floats for S2DW_MIXED.
+ *  - Sphere maps: real [L][2L-1] = [theta_b][phi_a] on the same beta/alpha
+ *    samples.
+ *  - Only real signals are supported (reality = 1): f_{l,-m} =
+ *    (-1)^m conj(f_lm), which makes W real.  The library reads f_lm for
+ *    m >= 0 only and writes all m on output.
+ *
+ * Memory and execution
+ *  - Every data pointer is a DEVICE pointer owned by the caller (usually a
+ *    torch tensor's data_ptr); the library never frees or keeps it past the
+ *    call.  Pointers must be 8-byte aligned.
+ *  - stream is a hipStream_t (NULL = the legacy default stream).  Every
+ *    call is asynchronous on it; results are ready when the stream is.
+ *  - The library owns per-parameter plans (tables + workspace) in a cache
+ *    that s2dw_release_caches() frees.  The first call with new parameters
+ *    builds the plan on the host and uploads it (it synchronises the
+ *    stream once).  Calls that share a plan must not overlap on different
+ *    streams: they share its workspace.
+ *
+ * Errors: every function returns S2DW_OK (0) or a negative code.  Argument
+ * errors are found before any device work and leave outputs untouched.
+ * HIP launch failures return S2DW_E_DEVICE; asynchronous device faults show
+ * up at the caller's next synchronisation.  No C++ exception crosses the ABI.
+ */
+#ifndef S2DW_H
+#define S2DW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    S2DW_OK = 0,
+    S2DW_E_ARG = -1,         /* invalid argument (value, null or misaligned pointer) */
+    S2DW_E_NOMEM = -2,       /* device or host allocation failed */
+    S2DW_E_DEVICE = -3,      /* a HIP call failed */
+    S2DW_E_UNSUPPORTED = -4, /* valid but not implemented (e.g. complex signals) */
+    S2DW_E_INTERNAL = -5
+};
+
+enum { S2DW_GRID_MW = 0 /* alpha 2L-1, beta L (incl. pi), gamma 2N-1 */ };
+enum { S2DW_FP64 = 0, S2DW_MIXED = 1 };
+
+typedef struct s2dw_params {
+    int32_t L;         /* harmonic band-limit, 2 <= L <= 4096 */
+    int32_t N;         /* azimuthal band-limit of the wavelets, 1 <= N <= min(L, 16) (Eq. 8) */
+    double lambda;     /* dilation parameter, finite and > 1 (Eq. 12) */
+    int32_t J_min;     /* 0 <= J_min <= J_L(lambda); scales j = 0..J_L(lambda) - J_min */
+    int32_t grid;      /* S2DW_GRID_MW */
+    int32_t precision; /* S2DW_FP64 or S2DW_MIXED (W stored and transformed in FP32) */
+    int32_t reality;   /* must be 1 (real signal) */
+} s2dw_params;
+
+/* Number of wavelet scales S = J_L(lambda) - J_min + 1 (Sec. 2.2). */
+int s2dw_num_scales(const s2dw_params *p, int32_t *S);
+
+/* Grid shape {n_gamma, n_beta, n_alpha} = {2N-1, L, 2L-1}. */
+int s2dw_grid_shape(const s2dw_params *p, int32_t shape[3]);
+
+/* Bytes of the wavelet-coefficient array W for all S scales. */
+int s2dw_wavelet_bytes(const s2dw_params *p, uint64_t *bytes);
+
+/*
+ * Wavelet analysis (Eq. 20 by the factoring of rotations, Eq. 25-30).
+ *   flm      in : L*L complex, real-signal symmetric.
+ *   W        out: [S][2N-1][L][2L-1] real (double or float, see precision).
+ *   Wphi_lm  out: L*L complex harmonic scaling coefficients (Eq. 31), or NULL.
+ */
+int s2dw_analysis(const s2dw_params *p, const double *flm, void *W, double *Wphi_lm, void *stream);
+
+/*
+ * Wavelet synthesis (Eq. 4 through Eq. 32-41, with exact quadrature on the
+ * equiangular grid).
+ *   W        in : [S][2N-1][L][2L-1] real.
+ *   Wphi_lm  in : L*L complex scaling coefficients, or NULL for the wavelet part only.
+ *   flm_out  out: L*L complex.
+ */
+int s2dw_synthesis(const s2dw_params *p, const void *W, const double *Wphi_lm, double *flm_out, void *stream);
+
+/*
+ * Scaling coefficients (Eq. 3, 31): W^Phi_lm = sqrt(4 pi/(2l+1)) f_lm Phi_l0.
+ *   Wphi_lm  out: L*L complex, or NULL.
+ *   Wphi_map out: real [L][2L-1] sphere map of the scaling coefficients
+ *                 (the inverse spherical-harmonic transform of W^Phi), or NULL.
+ */
+int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, double *Wphi_map, void *stream);
+
+/*
+ * Forward spherical-harmonic transform of a real band-limited map sampled on
+ * the equiangular grid [L][2L-1] (exact; the precondition of Sec. 3.1 that
+ * f_lm be computed by a sampling theorem).  Only p->L is used.
+ */
+int s2dw_sht_forward(const s2dw_params *p, const double *f_map, double *flm, void *stream);
+
+/* Inverse spherical-harmonic transform onto the equiangular grid [L][2L-1]. */
+int s2dw_sht_inverse(const s2dw_params *p, const double *flm, double *f_map, void *stream);
+
+/*
+ * The harmonic wavelet tables of p (Sec. 2.2), written to HOST memory:
+ *   kappa  [S][L]  kernel kappa^j(l) (Eq. 14-15), or NULL
+ *   phi    [L]     scaling function Phi_l0 (Eq. 16), or NULL
+ *   s_ln   [L][2N-1] complex directionality s_ln (Eq. 11), index n + N - 1, or NULL
+ * Psi^j_ln = kappa^j(l) s_ln (Eq. 7).  Needs no GPU.
+ */
+int s2dw_wavelet_tables(const s2dw_params *p, double *kappa, double *phi, double *s_ln);
+
+/*
+ * Stage timing.  While enabled, each launch sequence records a HIP event on the
+ * caller's stream before and after every kernel, so the time between the two is
+ * that kernel's device time.  s2dw_profile(1) enables and clears the totals,
+ * s2dw_profile(0) disables.  s2dw_profile_read waits for the recorded events and
+ * fills up to max entries (host memory) with per-stage totals since the last clear;
+ * *n receives the number of stages.  Names: wigner_fwd, beta_fwd, alpha_fwd,
+ * alpha_adj, beta_hat, beta_conv, wigner_adj, syn_final, pad, scaling.
+ */
+typedef struct s2dw_stage_time {
+    char name[24];
+    double ms;      /* summed device time */
+    int64_t count;  /* launches */
+} s2dw_stage_time;
+int s2dw_profile(int enable);
+int s2dw_profile_read(s2dw_stage_time *out, int32_t max, int32_t *n);
+
+/* Human-readable text of a status code. */
+const char *s2dw_strerror(int code);
+
+/* Free every cached plan (tables and workspaces). Synchronises the device. */
+void s2dw_release_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S2DW_H */

@@ -212,6 +212,41 @@ def forward_wigner_mw(W, L: int, N: int, m_range=None) -> np.ndarray:
     return out
 
 
+def alpha_gamma_rules_mw(W, L: int, N: int) -> np.ndarray:
+    """First step of forward_wigner_mw for the given rows: W [S][2N-1][nb][2L-1] ->
+    complex [S][len(n_list)][nb][2L-1] (Eq. 19 and its gamma analogue)."""
+    W = _cplx(W)
+    S, _, nb, _ = W.shape
+    nl = tables.n_list(N)
+    nla = np.ascontiguousarray(np.array(nl, dtype=np.int32))
+    out = np.zeros((S, len(nl), nb, 2 * L - 1), dtype=np.complex128)
+    rc = _load().orc_alpha_gamma_rules_mw(ctypes.c_int(L), ctypes.c_int(len(nl)), _ip(nla), ctypes.c_int(S),
+                                          _dp(W.view(np.float64)), ctypes.c_int(nb), ctypes.c_int(2 * L - 1),
+                                          ctypes.c_int(2 * N - 1), ctypes.c_int(2 * N - 1),
+                                          _dp(out.view(np.float64)), ctypes.c_int(_nthreads()))
+    if rc != 0:
+        raise MemoryError("oracle alpha/gamma rules failed")
+    return out
+
+
+def beta_wigner_mw(Gt, L: int, N: int, m_range) -> np.ndarray:
+    """Second step of forward_wigner_mw: Gt [S][len(n_list)][L][2L-1] -> Wigner coefficients of
+    the columns m in m_range (complex [S][L][2L-1][len(n_list)], others zero)."""
+    Gt = _cplx(Gt)
+    S = Gt.shape[0]
+    nl = tables.n_list(N)
+    nla = np.ascontiguousarray(np.array(nl, dtype=np.int32))
+    xg, wg = beta_rule(L)
+    out = np.zeros((S, L, 2 * L - 1, len(nl)), dtype=np.complex128)
+    rc = _load().orc_beta_wigner_mw(ctypes.c_int(L), ctypes.c_int(len(nl)), _ip(nla), ctypes.c_int(S),
+                                    _dp(Gt.view(np.float64)), ctypes.c_int(len(xg)), _dp(xg), _dp(wg),
+                                    ctypes.c_int(m_range[0]), ctypes.c_int(m_range[1]), _dp(out.view(np.float64)),
+                                    ctypes.c_int(_nthreads()))
+    if rc != 0:
+        raise MemoryError("oracle beta/Wigner step failed")
+    return out
+
+
 def forward_wigner_dh(W, L: int, N: int) -> np.ndarray:
     """As forward_wigner_mw on the Driscoll-Healy discretisation of Sec. 3.1:
     W [S][N][2L][2L-1] with gamma_g = pi g/N; q weights (Eq. 18), z_n = 1/N (Eq. 39)."""

@@ -342,24 +342,34 @@ static int alpha_gamma_rules(int L, int nn, const int *nlist, int S, const doubl
  * (including the sin(beta) of the measure).
  * Only the columns m in [m_lo, m_hi] are produced (the rest of out is left as is).
  */
-int orc_forward_wigner_mw(int L, int nn, const int *nlist, int S, const double *W,
-                          int na, int ng, int mg, int ngl, const double *xgl, const double *wgl,
-                          int m_lo, int m_hi, double *out, int nthreads)
+/* First step of the forward transform on the equiangular grid: the alpha and gamma
+ * rules for nb rows of samples, Gt complex [S][nn][nb][2L-1] (see alpha_gamma_rules). */
+int orc_alpha_gamma_rules_mw(int L, int nn, const int *nlist, int S, const double *W, int nb,
+                             int na, int ng, int mg, double *Gt, int nthreads)
+{
+    double *gw = (double *)malloc(sizeof(double) * (size_t)nn);
+    if (!gw) return -1;
+    for (int ni = 0; ni < nn; ++ni) gw[ni] = (double)(2.0L * PI_L / (ld)ng);
+    int err = alpha_gamma_rules(L, nn, nlist, S, W, nb, na, ng, mg, gw, Gt, nthreads);
+    free(gw);
+    return err;
+}
+
+/* Second step: the beta integral of the interpolant of Gt (all L rows) against
+ * sin(beta) d^l_mn(beta), for the columns m in [m_lo, m_hi]. */
+int orc_beta_wigner_mw(int L, int nn, const int *nlist, int S, const double *Gt,
+                       int ngl, const double *xgl, const double *wgl,
+                       int m_lo, int m_hi, double *out, int nthreads)
 {
     int M = 2 * L - 1;
     int T = 2 * L - 1; /* samples on the full circle after the extension */
-    double *gw = (double *)malloc(sizeof(double) * (size_t)nn);
-    double *Gt = (double *)malloc(sizeof(double) * 2 * (size_t)S * nn * L * M);
-    if (!gw || !Gt) { free(gw); free(Gt); return -1; }
-    for (int ni = 0; ni < nn; ++ni) gw[ni] = (double)(2.0L * PI_L / (ld)ng);
-    int err = alpha_gamma_rules(L, nn, nlist, S, W, L, na, ng, mg, gw, Gt, nthreads);
-    if (err) { free(gw); free(Gt); return err; }
+    int err = 0;
     /* e^{i pi k/(2L-1)} for the extended beta grid beta_t = pi(2t+1)/(2L-1) */
     int P2 = 2 * T;
     double *eb = (double *)malloc(sizeof(double) * 2 * (size_t)P2);
     /* e^{i p theta_k} at the quadrature colatitudes, p in [-(L-1), L-1] */
     double *ek = (double *)malloc(sizeof(double) * 2 * (size_t)ngl * M);
-    if (!eb || !ek) { free(gw); free(Gt); free(eb); free(ek); return -1; }
+    if (!eb || !ek) { free(eb); free(ek); return -1; }
     for (int k = 0; k < P2; ++k) {
         ld t = PI_L * (ld)k / (ld)T;
         eb[2 * k] = (double)cosl(t); eb[2 * k + 1] = (double)sinl(t);
@@ -460,7 +470,20 @@ int orc_forward_wigner_mw(int L, int nn, const int *nlist, int S, const double *
             free(acc); free(ext); free(gh); free(gk); free(d);
         }
     }
-    free(gw); free(Gt); free(eb); free(ek);
+    free(eb); free(ek);
+    return err;
+}
+
+int orc_forward_wigner_mw(int L, int nn, const int *nlist, int S, const double *W,
+                          int na, int ng, int mg, int ngl, const double *xgl, const double *wgl,
+                          int m_lo, int m_hi, double *out, int nthreads)
+{
+    int M = 2 * L - 1;
+    double *Gt = (double *)malloc(sizeof(double) * 2 * (size_t)S * nn * L * M);
+    if (!Gt) return -1;
+    int err = orc_alpha_gamma_rules_mw(L, nn, nlist, S, W, L, na, ng, mg, Gt, nthreads);
+    if (!err) err = orc_beta_wigner_mw(L, nn, nlist, S, Gt, ngl, xgl, wgl, m_lo, m_hi, out, nthreads);
+    free(Gt);
     return err;
 }
 

@@ -1,0 +1,628 @@
+// C ABI of the directional scale-discretized wavelet library: argument checks,
+// per-parameter plans (tables, tile lists, workspaces) and the launch sequences.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+
+#include "../../include/s2dw.h"
+#include "kernels.h"
+
+namespace s2dw {
+namespace {
+
+enum PlanKind { kWavelet = 0, kShtInverse = 1, kShtForward = 2 };
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Plan {
+    int kind = 0, L = 0, N = 0, J_min = 0, S = 0, K = 0, Lp = 0, R = 0, group = 0, Lmax = 0;
+    double lam = 2.0;
+    HostTables ht;
+    SegTab seg{};
+    ScaleTab sc{};
+    int eoff = 0;
+    // device tables
+    double2 *pq = nullptr, *uv = nullptr, *twa = nullptr, *twb = nullptr, *twg = nullptr;
+    double *kb2 = nullptr, *seed = nullptr, *seedm = nullptr, *phi = nullptr, *fac = nullptr, *wt = nullptr;
+    int *seede = nullptr;
+    int2 *tiles_fwd = nullptr, *tiles_adj = nullptr;
+    int nfwd_plain = 0, nfwd_x = 0, nadj_plain = 0, nadj_x = 0;
+    // workspaces
+    double2 *fpad = nullptr, *U = nullptr, *Ub = nullptr, *Gh = nullptr, *Fpart = nullptr;
+    int nblk = 0;
+    std::vector<void *> allocs;
+    size_t dev_bytes = 0;
+    ~Plan() {
+        for (void *p : allocs) hipFree(p);
+    }
+};
+
+// ----------------------------------------------------------------------- stage timing
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec {
+        const char *name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::map<std::string, std::pair<double, int64_t>> totals;
+};
+Prof g_prof;
+
+hipEvent_t prof_event() {
+    if (g_prof.used == g_prof.pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_prof.pool.push_back(e);
+    }
+    return g_prof.pool[g_prof.used++];
+}
+
+// Records events around one launch when timing is on.
+struct Stage {
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    const char *name;
+    Stage(const char *n, hipStream_t s) : st(s), name(n) {
+        if (!g_prof.on) return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        a = prof_event();
+        if (a) hipEventRecord(a, st);
+    }
+    ~Stage() {
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        hipEvent_t b = prof_event();
+        if (!b) return;
+        hipEventRecord(b, st);
+        g_prof.recs.push_back({name, a, b});
+    }
+};
+
+void prof_collect() {
+    for (auto &r : g_prof.recs) {
+        float ms = 0.f;
+        hipEventSynchronize(r.b);
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto &t = g_prof.totals[r.name];
+            t.first += ms;
+            t.second += 1;
+        }
+    }
+    g_prof.recs.clear();
+    g_prof.used = 0;
+}
+
+typedef std::tuple<int, int, int, double, int> PlanKey;
+std::mutex g_mu;
+std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
+
+template <typename T>
+bool dalloc(Plan &pl, T *&p, size_t count) {
+    p = nullptr;
+    if (count == 0) count = 1;
+    void *q = nullptr;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return false;
+    pl.allocs.push_back(q);
+    pl.dev_bytes += count * sizeof(T);
+    p = (T *)q;
+    return true;
+}
+
+template <typename T>
+bool upload(Plan &pl, T *&p, const std::vector<T> &h) {
+    if (!dalloc(pl, p, h.size())) return false;
+    return hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+// Segments of [0, L) on which the active scales are fixed.
+bool build_segments(const HostTables &t, SegTab &seg) {
+    std::vector<int> b = {0, t.L};
+    for (int j = 0; j < t.S; ++j)
+        if (t.hi[j] >= t.lo[j]) {
+            b.push_back(t.lo[j]);
+            b.push_back(t.hi[j] + 1);
+        }
+    std::sort(b.begin(), b.end());
+    b.erase(std::unique(b.begin(), b.end()), b.end());
+    seg.n = 0;
+    for (size_t i = 0; i + 1 < b.size(); ++i) {
+        if (b[i] >= t.L) break;
+        if (seg.n >= kMaxSegs) return false;
+        int s0 = b[i], s1 = std::min(b[i + 1], t.L);
+        int je = -1, jo = -1;
+        for (int j = 0; j < t.S; ++j) {
+            if (t.hi[j] < t.lo[j]) continue;
+            if (t.lo[j] <= s0 && t.hi[j] >= s1 - 1) {
+                int &slot = (j % 2 == 0) ? je : jo;
+                if (slot >= 0) return false;  // two scales of one parity overlap
+                slot = j;
+            }
+        }
+        seg.s0[seg.n] = s0;
+        seg.s1[seg.n] = s1;
+        seg.je[seg.n] = (int8_t)je;
+        seg.jo[seg.n] = (int8_t)jo;
+        ++seg.n;
+    }
+    return true;
+}
+
+// Tile lists for the Wigner kernels: (m0, m'0) pairs, heaviest first; tiles holding a
+// start value below 2^-1000 go to the extended-exponent list.
+void build_tiles(const Plan &pl, const DeltaTables &dt, int mgroup, std::vector<int2> &plain,
+                 std::vector<int2> &xn) {
+    std::vector<std::pair<long, int2>> a, b;
+    const int L = pl.L, Lmax = pl.Lmax;
+    for (int m0 = 0; m0 < Lmax; m0 += 64)
+        for (int p0 = 0; p0 < Lmax; p0 += mgroup) {
+            long work = Lmax - std::max(m0, p0);
+            bool x = false;
+            for (int mp = p0; mp < std::min(p0 + mgroup, L) && !x; ++mp)
+                for (int m = m0; m < std::min(m0 + 64, L); ++m)
+                    if (dt.seede[(size_t)mp * dt.Lp + m] < -1000) {
+                        x = true;
+                        break;
+                    }
+            (x ? b : a).push_back({work, make_int2(m0, p0)});
+        }
+    auto cmp = [](const std::pair<long, int2> &u, const std::pair<long, int2> &v) { return u.first > v.first; };
+    std::stable_sort(a.begin(), a.end(), cmp);
+    std::stable_sort(b.begin(), b.end(), cmp);
+    plain.clear();
+    xn.clear();
+    for (auto &e : a) plain.push_back(e.second);
+    for (auto &e : b) xn.push_back(e.second);
+}
+
+int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
+    std::unique_ptr<Plan> pl(new (std::nothrow) Plan());
+    if (!pl) return S2DW_E_NOMEM;
+    pl->kind = kind;
+    pl->L = L;
+    pl->N = N;
+    pl->lam = lam;
+    pl->J_min = J_min;
+    HostTables &t = pl->ht;
+    if (kind == kWavelet) {
+        if (!build_wavelet_tables(L, N, lam, J_min, t)) return S2DW_E_ARG;
+    } else {
+        // a single pseudo-scale with n = 0 only: the spherical-harmonic transforms
+        t.L = L;
+        t.N = 1;
+        t.S = 1;
+        t.K = 1;
+        t.eta_imag = false;
+        t.nk = {0};
+        t.kappa.assign(L, 1.0);
+        if (kind == kShtInverse)
+            for (int l = 0; l < L; ++l) t.kappa[l] = std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI));
+        t.phi.assign(L, 0.0);
+        t.sig.assign(L, 1.0);
+        t.lo = {0};
+        t.hi = {L - 1};
+    }
+    pl->S = t.S;
+    pl->K = t.K;
+    pl->eoff = t.eta_imag ? 3 : 0;
+    if (!build_segments(t, pl->seg)) return S2DW_E_INTERNAL;
+    pl->sc.S = t.S;
+    int64_t off = 0, boff = 0;
+    pl->Lmax = 0;
+    for (int j = 0; j < t.S; ++j) {
+        int Lj = t.hi[j] >= t.lo[j] ? t.hi[j] + 1 : 0;
+        pl->sc.Lj[j] = Lj;
+        pl->sc.off[j] = off;
+        pl->sc.boff[j] = boff;
+        off += (int64_t)std::max(t.N, 2 * t.K) * Lj * Lj;
+        boff += (int64_t)t.N * L * Lj;
+        pl->Lmax = std::max(pl->Lmax, Lj);
+    }
+    // Delta tables
+    DeltaTables dt;
+    build_delta_tables(L, dt);
+    pl->Lp = dt.Lp;
+    std::vector<double> ncol;
+    build_delta_ncols(dt, t.nk, ncol);
+    const int K = t.K, Lp = dt.Lp;
+    std::vector<double> kb2((size_t)Lp * L * 2 * K, 0.0);
+    for (int mp = 0; mp < L; ++mp)
+        for (int l = 0; l < L; ++l) {
+            int si = 0;
+            while (pl->seg.s1[si] <= l) ++si;
+            const int js[2] = {pl->seg.je[si], pl->seg.jo[si]};
+            for (int s = 0; s < 2; ++s) {
+                if (js[s] < 0) continue;
+                const double kap = t.kappa[(size_t)js[s] * L + l];
+                for (int k = 0; k < K; ++k)
+                    kb2[(((size_t)mp * L + l) * 2 + s) * K + k] =
+                        kap * t.sig[(size_t)l * K + k] * ncol[((size_t)mp * L + l) * K + k];
+            }
+        }
+    Plan &P = *pl;
+    const int M = 2 * L - 1;
+    std::vector<double2> twa(M), twb(4 * L - 2), twg(2 * t.N - 1);
+    for (int k = 0; k < M; ++k) {
+        long double a = 2.0L * 3.141592653589793238462643383279502884L * k / M;
+        twa[k] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    for (int k = 0; k < 4 * L - 2; ++k) {
+        long double a = 3.141592653589793238462643383279502884L * k / M;
+        twb[k] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    for (int k = 0; k < 2 * t.N - 1; ++k) {
+        long double a = 2.0L * 3.141592653589793238462643383279502884L * k / (2 * t.N - 1);
+        twg[k] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    std::vector<double> wt(6 * L + 1, 0.0);
+    for (int q = -3 * L; q <= 3 * L; ++q)
+        if ((q & 1) == 0) wt[q + 3 * L] = 2.0 / (1.0 - (double)q * (double)q);
+    std::vector<double> fac(L);
+    for (int l = 0; l < L; ++l)
+        fac[l] = kind == kShtForward ? std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) / (2.0 * M_PI)
+                                     : (2.0 * l + 1.0) / (8.0 * M_PI * M_PI);
+    std::vector<double2> pqv((size_t)L * Lp), uvv((size_t)Lp * L);
+    memcpy(pqv.data(), dt.pq.data(), pqv.size() * sizeof(double2));
+    memcpy(uvv.data(), dt.uv.data(), uvv.size() * sizeof(double2));
+    bool ok = upload(P, P.pq, pqv) && upload(P, P.uv, uvv) && upload(P, P.kb2, kb2) && upload(P, P.seed, dt.seed) &&
+              upload(P, P.seedm, dt.seedm) && upload(P, P.seede, dt.seede) && upload(P, P.twa, twa) &&
+              upload(P, P.twb, twb) && upload(P, P.twg, twg) && upload(P, P.wt, wt) && upload(P, P.fac, fac) &&
+              upload(P, P.phi, t.phi);
+    if (!ok) return S2DW_E_NOMEM;
+    // tiles
+    P.R = wig_slots(K);
+    std::vector<int2> pl_a, x_a, pl_s, x_s;
+    build_tiles(P, dt, 4 * P.R, pl_a, x_a);
+    P.group = kAdjWaves * P.R;
+    build_tiles(P, dt, P.group, pl_s, x_s);
+    P.nfwd_plain = (int)pl_a.size();
+    P.nfwd_x = (int)x_a.size();
+    P.nadj_plain = (int)pl_s.size();
+    P.nadj_x = (int)x_s.size();
+    std::vector<int2> ta(pl_a), ts(pl_s);
+    ta.insert(ta.end(), x_a.begin(), x_a.end());
+    ts.insert(ts.end(), x_s.begin(), x_s.end());
+    if (!upload(P, P.tiles_fwd, ta) || !upload(P, P.tiles_adj, ts)) return S2DW_E_NOMEM;
+    // workspaces
+    int maxLj = 0;
+    for (int j = 0; j < t.S; ++j) maxLj = std::max(maxLj, P.sc.Lj[j]);
+    P.nblk = (L + P.group - 1) / P.group;
+    if (!dalloc(P, P.fpad, (size_t)L * Lp) || !dalloc(P, P.U, (size_t)std::max<int64_t>(off, 1)) ||
+        !dalloc(P, P.Ub, (size_t)std::max<int64_t>(boff, 1)) || !dalloc(P, P.Gh, (size_t)t.N * M * std::max(maxLj, 1)) ||
+        !dalloc(P, P.Fpart, (size_t)P.nblk * L * Lp))
+        return S2DW_E_NOMEM;
+    out = pl.release();
+    return S2DW_OK;
+}
+
+int get_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    PlanKey key(kind, L, kind == kWavelet ? N : 1, kind == kWavelet ? lam : 0.0, kind == kWavelet ? J_min : 0);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        out = it->second.get();
+        return S2DW_OK;
+    }
+    Plan *p = nullptr;
+    int rc = build_plan(kind, L, N, lam, J_min, p);
+    if (rc != S2DW_OK) return rc;
+    g_plans[key].reset(p);
+    out = p;
+    return S2DW_OK;
+}
+
+int check_params(const s2dw_params *p) {
+    if (!p) return S2DW_E_ARG;
+    if (p->L < 2 || p->L > 4096) return S2DW_E_ARG;
+    if (p->N < 1 || p->N > p->L || p->N > 2 * kMaxK) return S2DW_E_ARG;
+    if (!(p->lambda > 1.0) || !std::isfinite(p->lambda)) return S2DW_E_ARG;
+    int JL = jmax_of(p->L, p->lambda);
+    if (p->J_min < 0 || p->J_min > JL || JL - p->J_min + 1 > kMaxScales) return S2DW_E_ARG;
+    if (p->grid != S2DW_GRID_MW) return S2DW_E_ARG;
+    if (p->precision != S2DW_FP64 && p->precision != S2DW_MIXED) return S2DW_E_ARG;
+    if (p->precision == S2DW_MIXED) return S2DW_E_UNSUPPORTED;
+    if (p->reality != 1) return p->reality == 0 ? S2DW_E_UNSUPPORTED : S2DW_E_ARG;
+    return S2DW_OK;
+}
+
+bool aligned(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+#define S2DW_CHECK_HIP(x)                               \
+    do {                                                \
+        if ((x) != hipSuccess) return S2DW_E_DEVICE;    \
+    } while (0)
+
+// Wigner-stage analysis + beta/gamma/alpha sums: coefficients c_lm (m >= 0) -> W.
+int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
+    const int L = P.L;
+    {
+        Stage sg("pad", st);
+        S2DW_CHECK_HIP(launch_pad_flm(flm, P.fpad, L, P.Lp, st));
+    }
+    WigFwdArgs a{};
+    a.fpad = P.fpad;
+    a.pq = P.pq;
+    a.uv = P.uv;
+    a.kb2 = P.kb2;
+    a.seed = P.seed;
+    a.seedm = P.seedm;
+    a.seede = P.seede;
+    a.U = P.U;
+    a.L = L;
+    a.Lp = P.Lp;
+    a.N = P.ht.N;
+    a.eoff = P.eoff;
+    for (int k = 0; k < P.K; ++k) a.nk[k] = P.ht.nk[k];
+    a.seg = P.seg;
+    a.sc = P.sc;
+    {
+        Stage sg("wigner_fwd", st);
+        a.tiles = P.tiles_fwd;
+        S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.nfwd_plain, false, st));
+        a.tiles = P.tiles_fwd + P.nfwd_plain;
+        S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.nfwd_x, true, st));
+    }
+    const size_t per_scale = (size_t)(2 * P.ht.N - 1) * L * (2 * L - 1);
+    for (int j = 0; j < P.S; ++j) {
+        const int Lj = P.sc.Lj[j];
+        void *Wj = f32 ? (void *)((float *)W + per_scale * j) : (void *)((double *)W + per_scale * j);
+        if (Lj == 0) {
+            S2DW_CHECK_HIP(hipMemsetAsync(Wj, 0, per_scale * (f32 ? 4 : 8), st));
+            continue;
+        }
+        BetaFwdArgs b{P.U + P.sc.off[j], P.Ub + P.sc.boff[j], P.twb, L, Lj, P.ht.N};
+        {
+            Stage sg("beta_fwd", st);
+            S2DW_CHECK_HIP(launch_beta_fwd(b, st));
+        }
+        AlphaFwdArgs c{P.Ub + P.sc.boff[j], Wj, P.twa, P.twg, L, Lj, P.ht.N, f32};
+        {
+            Stage sg("alpha_fwd", st);
+            S2DW_CHECK_HIP(launch_alpha_fwd(c, st));
+        }
+    }
+    return S2DW_OK;
+}
+
+// alpha/gamma/beta quadratures + Wigner-stage contraction: W -> f_lm.
+int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f32, hipStream_t st) {
+    const int L = P.L, M = 2 * L - 1, N = P.ht.N;
+    const size_t per_scale = (size_t)(2 * N - 1) * L * M;
+    for (int j = 0; j < P.S; ++j) {
+        const int Lj = P.sc.Lj[j];
+        if (Lj == 0) continue;
+        const void *Wj = f32 ? (const void *)((const float *)W + per_scale * j)
+                             : (const void *)((const double *)W + per_scale * j);
+        double2 *G = P.Ub + P.sc.boff[j];
+        AlphaAdjArgs c{Wj, G, P.twa, P.twg, L, Lj, N, f32,
+                       (2.0 * M_PI / M) * (2.0 * M_PI / (2 * N - 1))};
+        {
+            Stage sg("alpha_adj", st);
+            S2DW_CHECK_HIP(launch_alpha_adj(c, st));
+        }
+        BetaHatArgs h{G, P.Gh, P.twb, L, Lj, N};
+        {
+            Stage sg("beta_hat", st);
+            S2DW_CHECK_HIP(launch_beta_hat(h, st));
+        }
+        BetaConvArgs v{};
+        v.Gh = P.Gh;
+        v.V = P.U + P.sc.off[j];
+        v.wt = P.wt;
+        v.L = L;
+        v.Lj = Lj;
+        v.N = N;
+        v.K = P.K;
+        for (int k = 0; k < P.K; ++k) v.nk[k] = P.ht.nk[k];
+        v.eta_imag = P.ht.eta_imag ? 1 : 0;
+        {
+            Stage sg("beta_conv", st);
+            S2DW_CHECK_HIP(launch_beta_conv(v, st));
+        }
+    }
+    WigAdjArgs a{};
+    a.pq = P.pq;
+    a.uv = P.uv;
+    a.kb2 = P.kb2;
+    a.seed = P.seed;
+    a.seedm = P.seedm;
+    a.seede = P.seede;
+    a.V = P.U;
+    a.Fpart = P.Fpart;
+    a.L = L;
+    a.Lp = P.Lp;
+    a.group = P.group;
+    a.seg = P.seg;
+    a.sc = P.sc;
+    {
+        Stage sg("wigner_adj", st);
+        a.tiles = P.tiles_adj;
+        S2DW_CHECK_HIP(launch_wig_adj(a, P.K, P.nadj_plain, false, st));
+        a.tiles = P.tiles_adj + P.nadj_plain;
+        S2DW_CHECK_HIP(launch_wig_adj(a, P.K, P.nadj_x, true, st));
+    }
+    {
+        Stage sg("syn_final", st);
+        S2DW_CHECK_HIP(launch_syn_final(P.Fpart, P.nblk, P.group, P.Lmax, P.fac, wphi, P.phi, flm, L, P.Lp, st));
+    }
+    return S2DW_OK;
+}
+
+}  // namespace
+}  // namespace s2dw
+
+using namespace s2dw;
+
+extern "C" {
+
+int s2dw_num_scales(const s2dw_params *p, int32_t *S) {
+    if (!p || !S || p->L < 2 || !(p->lambda > 1.0) || !std::isfinite(p->lambda)) return S2DW_E_ARG;
+    int JL = jmax_of(p->L, p->lambda);
+    if (p->J_min < 0 || p->J_min > JL) return S2DW_E_ARG;
+    *S = JL - p->J_min + 1;
+    return S2DW_OK;
+}
+
+int s2dw_grid_shape(const s2dw_params *p, int32_t shape[3]) {
+    if (!p || !shape || p->L < 2 || p->N < 1) return S2DW_E_ARG;
+    shape[0] = 2 * p->N - 1;
+    shape[1] = p->L;
+    shape[2] = 2 * p->L - 1;
+    return S2DW_OK;
+}
+
+int s2dw_wavelet_bytes(const s2dw_params *p, uint64_t *bytes) {
+    int32_t S = 0;
+    int rc = s2dw_num_scales(p, &S);
+    if (rc != S2DW_OK) return rc;
+    if (!bytes || p->N < 1) return S2DW_E_ARG;
+    uint64_t el = p->precision == S2DW_MIXED ? 4 : 8;
+    *bytes = (uint64_t)S * (2 * p->N - 1) * p->L * (2 * (uint64_t)p->L - 1) * el;
+    return S2DW_OK;
+}
+
+int s2dw_analysis(const s2dw_params *p, const double *flm, void *W, double *Wphi_lm, void *stream) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    if (!flm || !W || !aligned(flm) || !aligned(W) || (Wphi_lm && !aligned(Wphi_lm))) return S2DW_E_ARG;
+    Plan *P = nullptr;
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P);
+    if (rc != S2DW_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = run_inverse(*P, (const double2 *)flm, W, 0, st);
+    if (rc != S2DW_OK) return rc;
+    if (Wphi_lm) {
+        Stage sg("scaling", st);
+        S2DW_CHECK_HIP(launch_scaling((const double2 *)flm, P->phi, (double2 *)Wphi_lm, p->L, st));
+    }
+    return S2DW_OK;
+}
+
+int s2dw_synthesis(const s2dw_params *p, const void *W, const double *Wphi_lm, double *flm_out, void *stream) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    if (!W || !flm_out || !aligned(W) || !aligned(flm_out) || (Wphi_lm && !aligned(Wphi_lm))) return S2DW_E_ARG;
+    Plan *P = nullptr;
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P);
+    if (rc != S2DW_OK) return rc;
+    return run_forward(*P, W, (const double2 *)Wphi_lm, (double2 *)flm_out, 0, (hipStream_t)stream);
+}
+
+int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, double *Wphi_map, void *stream) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    if (!flm || !aligned(flm) || (Wphi_lm && !aligned(Wphi_lm)) || (Wphi_map && !aligned(Wphi_map))) return S2DW_E_ARG;
+    if (!Wphi_lm && !Wphi_map) return S2DW_OK;
+    Plan *P = nullptr;
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P);
+    if (rc != S2DW_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double2 *wphi = (double2 *)Wphi_lm;
+    if (!wphi) wphi = P->fpad;  // scratch: L*Lp >= L*L complex
+    S2DW_CHECK_HIP(launch_scaling((const double2 *)flm, P->phi, wphi, p->L, st));
+    if (Wphi_map) {
+        Plan *Q = nullptr;
+        rc = get_plan(kShtInverse, p->L, 1, 0.0, 0, Q);
+        if (rc != S2DW_OK) return rc;
+        rc = run_inverse(*Q, wphi, Wphi_map, 0, st);
+    }
+    return rc;
+}
+
+int s2dw_sht_forward(const s2dw_params *p, const double *f_map, double *flm, void *stream) {
+    if (!p || p->L < 2 || p->L > 4096 || !f_map || !flm || !aligned(f_map) || !aligned(flm)) return S2DW_E_ARG;
+    Plan *Q = nullptr;
+    int rc = get_plan(kShtForward, p->L, 1, 0.0, 0, Q);
+    if (rc != S2DW_OK) return rc;
+    return run_forward(*Q, f_map, nullptr, (double2 *)flm, 0, (hipStream_t)stream);
+}
+
+int s2dw_sht_inverse(const s2dw_params *p, const double *flm, double *f_map, void *stream) {
+    if (!p || p->L < 2 || p->L > 4096 || !f_map || !flm || !aligned(f_map) || !aligned(flm)) return S2DW_E_ARG;
+    Plan *Q = nullptr;
+    int rc = get_plan(kShtInverse, p->L, 1, 0.0, 0, Q);
+    if (rc != S2DW_OK) return rc;
+    return run_inverse(*Q, (const double2 *)flm, f_map, 0, (hipStream_t)stream);
+}
+
+int s2dw_wavelet_tables(const s2dw_params *p, double *kappa, double *phi, double *s_ln) {
+    if (!p || p->L < 2 || p->L > 4096 || p->N < 1 || p->N > p->L || p->N > 2 * kMaxK) return S2DW_E_ARG;
+    HostTables t;
+    if (!build_wavelet_tables(p->L, p->N, p->lambda, p->J_min, t)) return S2DW_E_ARG;
+    const int L = p->L, N = p->N;
+    if (kappa) memcpy(kappa, t.kappa.data(), sizeof(double) * t.kappa.size());
+    if (phi) memcpy(phi, t.phi.data(), sizeof(double) * L);
+    if (s_ln) {
+        memset(s_ln, 0, sizeof(double) * 2 * (size_t)L * (2 * N - 1));
+        for (int l = 0; l < L; ++l)
+            for (int k = 0; k < t.K; ++k) {
+                const double v = t.sig[(size_t)l * t.K + k];
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    const int n = sg * t.nk[k];
+                    double *o = s_ln + 2 * ((size_t)l * (2 * N - 1) + n + N - 1);
+                    o[t.eta_imag ? 1 : 0] = v;  // eta_N = i for even N (Eq. 11)
+                    if (n == 0) break;
+                }
+            }
+    }
+    return S2DW_OK;
+}
+
+int s2dw_profile(int enable) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    prof_collect();
+    g_prof.totals.clear();
+    g_prof.on = enable != 0;
+    return S2DW_OK;
+}
+
+int s2dw_profile_read(s2dw_stage_time *out, int32_t max, int32_t *n) {
+    if (!n || (max > 0 && !out)) return S2DW_E_ARG;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    prof_collect();
+    int i = 0;
+    for (auto &kv : g_prof.totals) {
+        if (i < max) {
+            memset(out[i].name, 0, sizeof(out[i].name));
+            strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+            out[i].ms = kv.second.first;
+            out[i].count = kv.second.second;
+        }
+        ++i;
+    }
+    *n = i;
+    return S2DW_OK;
+}
+
+const char *s2dw_strerror(int code) {
+    switch (code) {
+        case S2DW_OK: return "ok";
+        case S2DW_E_ARG: return "invalid argument";
+        case S2DW_E_NOMEM: return "out of memory";
+        case S2DW_E_DEVICE: return "HIP call failed";
+        case S2DW_E_UNSUPPORTED: return "not supported";
+        case S2DW_E_INTERNAL: return "internal error";
+        default: return "unknown status";
+    }
+}
+
+void s2dw_release_caches(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_plans.empty()) hipDeviceSynchronize();
+    g_plans.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Kernel argument blocks and launchers of the wavelet library (device side).
+#pragma once
+
+#include "s2dw_internal.h"
+
+namespace s2dw {
+
+constexpr int kAdjWaves = 8;                 // waves per synthesis Wigner workgroup
+constexpr int kAdjThreads = kAdjWaves * 64;
+constexpr int kAdjWin = 8;                   // l-window reduced in LDS across the workgroup (fixed order)
+
+struct WigFwdArgs {
+    const double2 *fpad;   // [L][Lp]   f_lm for m <= l (0 elsewhere)
+    const double2 *pq;     // [L][Lp]   (p_l(m), q_l(m))
+    const double2 *uv;     // [Lp][L]   (u_l(m'), v_l(m'))
+    const double *kb2;     // [Lp][L][2][K]  kappa^{j(slot,l)}(l) sigma_{l,n_k} Delta^l_{m' n_k}
+    const double *seed;    // [Lp][Lp]  Delta^{max(m',m)}_{m'm}
+    const double *seedm;   // [Lp][Lp]  its mantissa (extended-exponent variant)
+    const int *seede;      // [Lp][Lp]  its exponent
+    const int2 *tiles;     // (m0, m'0) per workgroup
+    double2 *U;            // workspace; scale j at sc.off[j]: [N][Lj][Lj] = [n][m'][m]
+    int L, Lp, N, eoff;    // eoff = 3 when eta_N = i (conj(eta) = i^3), else 0
+    int nk[kMaxK];
+    SegTab seg;
+    ScaleTab sc;
+};
+
+struct WigAdjArgs {
+    const double2 *pq;
+    const double2 *uv;
+    const double *kb2;
+    const double *seed;
+    const double *seedm;
+    const int *seede;
+    const int2 *tiles;
+    const double2 *V;      // scale j at sc.off[j]: [K][2][Lj][Lj] = [k][P|Q][m'][m]
+    double2 *Fpart;        // [L / group][L][Lp] partial sums over each m' group
+    int L, Lp, group;
+    SegTab seg;
+    ScaleTab sc;
+};
+
+int wig_slots(int K);
+hipError_t launch_wig_fwd(const WigFwdArgs &a, int K, int ntiles, bool xn, hipStream_t st);
+hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int ntiles, bool xn, hipStream_t st);
+
+// ---------------------------------------------------------------- beta / alpha / gamma stages
+
+struct BetaFwdArgs {
+    const double2 *U;   // [N][Lj][Lj]
+    double2 *Ub;        // [N][L][Lj]
+    const double2 *twb; // e^{i pi k/(2L-1)}, k < 4L-2
+    int L, Lj, N;
+};
+hipError_t launch_beta_fwd(const BetaFwdArgs &a, hipStream_t st);
+
+struct AlphaFwdArgs {
+    const double2 *Ub;  // [N][L][Lj]
+    void *W;            // [2N-1][L][2L-1] of this scale (double or float)
+    const double2 *twa; // e^{2 pi i k/(2L-1)}
+    const double2 *twg; // e^{2 pi i k/(2N-1)}
+    int L, Lj, N, f32;
+};
+hipError_t launch_alpha_fwd(const AlphaFwdArgs &a, hipStream_t st);
+
+struct AlphaAdjArgs {
+    const void *W;      // [2N-1][L][2L-1] of this scale
+    double2 *G;         // [N][L][Lj]
+    const double2 *twa;
+    const double2 *twg;
+    int L, Lj, N, f32;
+    double scale;       // (2 pi/(2L-1)) (2 pi/(2N-1))
+};
+hipError_t launch_alpha_adj(const AlphaAdjArgs &a, hipStream_t st);
+
+struct BetaHatArgs {
+    const double2 *G;   // [N][L][Lj]   samples G_mn(beta_b)
+    double2 *Gh;        // [N][2L-1][Lj] Fourier coefficients of the extended samples
+    const double2 *twb; // e^{i pi k/(2L-1)}, k < 4L-2
+    int L, Lj, N;
+};
+hipError_t launch_beta_hat(const BetaHatArgs &a, hipStream_t st);
+
+struct BetaConvArgs {
+    const double2 *Gh;  // [N][2L-1][Lj]
+    double2 *V;         // [K][2][Lj][Lj]
+    const double *wt;   // w(q) = int_0^pi sin(b) cos(q b) db for q in [-(3L), 3L], index q + 3L
+    int L, Lj, N, K;
+    int nk[kMaxK];
+    int eta_imag;
+};
+hipError_t launch_beta_conv(const BetaConvArgs &a, hipStream_t st);
+
+// --------------------------------------------------------------------------------- misc
+
+hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, hipStream_t st);
+hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, hipStream_t st);
+hipError_t launch_syn_final(const double2 *Fpart, int nblk, int group, int Lmax, const double *fac,
+                            const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, hipStream_t st);
+hipError_t launch_zero(double2 *p, size_t n, hipStream_t st);
+
+}  // namespace s2dw

@@ -1,0 +1,203 @@
+"""Python binding of the C ABI in ``include/s2dw.h`` (argument marshalling only).
+
+Every transform runs in the HIP kernels of ``libs2dw.so``; this module only
+checks tensor shapes, allocates outputs with torch and passes device pointers
+and the current HIP stream.  It raises if the library is not built: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libs2dw.so")
+
+FP64, MIXED = 0, 1
+GRID_MW = 0
+
+_lib = None
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("N", ctypes.c_int32), ("lam", ctypes.c_double),
+                ("J_min", ctypes.c_int32), ("grid", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reality", ctypes.c_int32)]
+
+
+class StageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_double), ("count", ctypes.c_int64)]
+
+
+class S2DWError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {lib().s2dw_strerror(code).decode()} ({code})")
+        self.code = code
+
+
+def lib():
+    """The loaded libs2dw.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, cp = ctypes.c_void_p, ctypes.POINTER(Params)
+        for name, args in [("s2dw_num_scales", [cp, ctypes.POINTER(ctypes.c_int32)]),
+                           ("s2dw_grid_shape", [cp, ctypes.POINTER(ctypes.c_int32)]),
+                           ("s2dw_wavelet_bytes", [cp, ctypes.POINTER(ctypes.c_uint64)]),
+                           ("s2dw_analysis", [cp, vp, vp, vp, vp]),
+                           ("s2dw_synthesis", [cp, vp, vp, vp, vp]),
+                           ("s2dw_scaling", [cp, vp, vp, vp, vp]),
+                           ("s2dw_sht_forward", [cp, vp, vp, vp]),
+                           ("s2dw_sht_inverse", [cp, vp, vp, vp])]:
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.s2dw_strerror.argtypes = [ctypes.c_int]
+        L.s2dw_strerror.restype = ctypes.c_char_p
+        L.s2dw_release_caches.argtypes = []
+        L.s2dw_release_caches.restype = None
+        L.s2dw_wavelet_tables.argtypes = [cp, vp, vp, vp]
+        L.s2dw_wavelet_tables.restype = ctypes.c_int
+        L.s2dw_profile.argtypes = [ctypes.c_int]
+        L.s2dw_profile.restype = ctypes.c_int
+        L.s2dw_profile_read.argtypes = [ctypes.POINTER(StageTime), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.s2dw_profile_read.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_analysis", "s2dw_synthesis",
+            "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
+            "s2dw_profile_read",
+            "s2dw_strerror", "s2dw_release_caches"]
+
+
+def params(L: int, N: int, lam: float = 2.0, J_min: int = 0, precision: str = "fp64") -> Params:
+    return Params(L, N, float(lam), J_min, GRID_MW, FP64 if precision == "fp64" else MIXED, 1)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise S2DWError(rc, what)
+
+
+def num_scales(L: int, lam: float = 2.0, J_min: int = 0) -> int:
+    s = ctypes.c_int32()
+    _check(lib().s2dw_num_scales(ctypes.byref(params(L, 1, lam, J_min)), ctypes.byref(s)), "num_scales")
+    return s.value
+
+
+def wavelet_tables(L: int, N: int, lam: float = 2.0, J_min: int = 0):
+    """Host numpy arrays (kappa [S][L], phi [L], s_ln complex [L][2N-1]) built by the library."""
+    import numpy as np
+    S = num_scales(L, lam, J_min)
+    kap = np.zeros((S, L))
+    phi = np.zeros(L)
+    s = np.zeros((L, 2 * N - 1), dtype=np.complex128)
+    _check(lib().s2dw_wavelet_tables(ctypes.byref(params(L, N, lam, J_min)), ctypes.c_void_p(kap.ctypes.data),
+                                     ctypes.c_void_p(phi.ctypes.data), ctypes.c_void_p(s.ctypes.data)),
+           "s2dw_wavelet_tables")
+    return kap, phi, s
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _as_complex(x: torch.Tensor, n: int, what: str) -> torch.Tensor:
+    if not x.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if x.dtype == torch.complex128:
+        x = torch.view_as_real(x)
+    if x.dtype != torch.float64 or x.numel() != 2 * n:
+        raise ValueError(f"{what}: expected {n} complex128 values")
+    return x.contiguous()
+
+
+def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0, *, scaling: bool = True,
+             out: torch.Tensor | None = None, stream=None):
+    """Wavelet coefficients W [S][2N-1][L][2L-1] (float64) and, if scaling, the harmonic
+    scaling coefficients W^Phi_lm (complex128 [L*L])."""
+    p = params(L, N, lam, J_min)
+    f = _as_complex(flm, L * L, "flm")
+    S = num_scales(L, lam, J_min)
+    W = out if out is not None else torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=torch.float64, device=f.device)
+    if W.dtype != torch.float64 or W.numel() != S * (2 * N - 1) * L * (2 * L - 1) or not W.is_contiguous():
+        raise ValueError("W: wrong shape, dtype or layout")
+    Wp = torch.empty(L * L, dtype=torch.complex128, device=f.device) if scaling else None
+    _check(lib().s2dw_analysis(ctypes.byref(p), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(W.data_ptr()),
+                               ctypes.c_void_p(Wp.data_ptr() if Wp is not None else None), _stream(stream)),
+           "s2dw_analysis")
+    return W, Wp
+
+
+def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,
+              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """f_lm (complex128 [L*L]) from W and the scaling coefficients (or the wavelet part only)."""
+    p = params(L, N, lam, J_min)
+    S = num_scales(L, lam, J_min)
+    if W.dtype != torch.float64 or W.numel() != S * (2 * N - 1) * L * (2 * L - 1) or not W.is_cuda:
+        raise ValueError("W: wrong shape or dtype")
+    W = W.contiguous()
+    wp = _as_complex(Wphi, L * L, "Wphi") if Wphi is not None else None
+    f = out if out is not None else torch.empty(L * L, dtype=torch.complex128, device=W.device)
+    _check(lib().s2dw_synthesis(ctypes.byref(p), ctypes.c_void_p(W.data_ptr()),
+                                ctypes.c_void_p(wp.data_ptr() if wp is not None else None),
+                                ctypes.c_void_p(f.data_ptr()), _stream(stream)), "s2dw_synthesis")
+    return f
+
+
+def scaling(flm: torch.Tensor, L: int, N: int = 1, lam: float = 2.0, J_min: int = 0, *, sphere_map: bool = False,
+            stream=None):
+    """Harmonic scaling coefficients (complex128 [L*L]) and optionally their sphere map [L][2L-1]."""
+    p = params(L, N, lam, J_min)
+    f = _as_complex(flm, L * L, "flm")
+    Wp = torch.empty(L * L, dtype=torch.complex128, device=f.device)
+    mp = torch.empty((L, 2 * L - 1), dtype=torch.float64, device=f.device) if sphere_map else None
+    _check(lib().s2dw_scaling(ctypes.byref(p), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(Wp.data_ptr()),
+                              ctypes.c_void_p(mp.data_ptr() if mp is not None else None), _stream(stream)),
+           "s2dw_scaling")
+    return Wp, mp
+
+
+def sht_forward(fmap: torch.Tensor, L: int, stream=None) -> torch.Tensor:
+    """f_lm of a real map on the equiangular grid [L][2L-1]."""
+    if fmap.dtype != torch.float64 or tuple(fmap.shape) != (L, 2 * L - 1) or not fmap.is_cuda:
+        raise ValueError("fmap: expected float64 [L][2L-1] on the device")
+    fmap = fmap.contiguous()
+    f = torch.empty(L * L, dtype=torch.complex128, device=fmap.device)
+    _check(lib().s2dw_sht_forward(ctypes.byref(params(L, 1)), ctypes.c_void_p(fmap.data_ptr()),
+                                  ctypes.c_void_p(f.data_ptr()), _stream(stream)), "s2dw_sht_forward")
+    return f
+
+
+def sht_inverse(flm: torch.Tensor, L: int, stream=None) -> torch.Tensor:
+    """The real map [L][2L-1] of f_lm on the equiangular grid."""
+    f = _as_complex(flm, L * L, "flm")
+    m = torch.empty((L, 2 * L - 1), dtype=torch.float64, device=f.device)
+    _check(lib().s2dw_sht_inverse(ctypes.byref(params(L, 1)), ctypes.c_void_p(f.data_ptr()),
+                                  ctypes.c_void_p(m.data_ptr()), _stream(stream)), "s2dw_sht_inverse")
+    return m
+
+
+def profile(enable: bool) -> None:
+    """Turn per-kernel stage timing on (clearing totals) or off."""
+    _check(lib().s2dw_profile(1 if enable else 0), "s2dw_profile")
+
+
+def profile_read() -> dict:
+    """{stage: (total_ms, launches)} since the last clear (waits for the recorded events)."""
+    buf = (StageTime * 64)()
+    n = ctypes.c_int32()
+    _check(lib().s2dw_profile_read(buf, 64, ctypes.byref(n)), "s2dw_profile_read")
+    return {buf[i].name.decode(): (buf[i].ms, buf[i].count) for i in range(min(n.value, 64))}
+
+
+def release_caches():
+    lib().s2dw_release_caches()
