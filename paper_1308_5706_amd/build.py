@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libs2dw.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "tables.cpp", "wigner.hip", "transforms.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "wigner.hip", "stages.hip", "misc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("S2DW_ARCH", "gfx950")

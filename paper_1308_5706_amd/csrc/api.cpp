@@ -33,12 +33,18 @@ struct Plan {
     int eoff = 0;
     // device tables
     double2 *pq = nullptr, *uv = nullptr, *twa = nullptr, *twb = nullptr, *twg = nullptr;
-    double *kb2 = nullptr, *seed = nullptr, *seedm = nullptr, *phi = nullptr, *fac = nullptr, *wt = nullptr;
+    double *kb2 = nullptr, *seed = nullptr, *seedm = nullptr, *phi = nullptr, *fac = nullptr;
     int *seede = nullptr;
     int2 *tiles_fwd = nullptr, *tiles_adj = nullptr;
     int nfwd_plain = 0, nfwd_x = 0, nadj_plain = 0, nadj_x = 0;
+    // Bluestein stages: transform sizes and chirp spectra per scale, twiddles per size
+    std::vector<int> PA, PB;                    // beta (analysis), alpha (both directions)
+    int PD = 0;                                 // beta (synthesis)
+    std::vector<double2 *> hA, hB, hC, hD2;     // per scale
+    double2 *hD1 = nullptr;
+    std::map<int, double2 *> twP;               // e^{-2 pi i k/P}
     // workspaces
-    double2 *fpad = nullptr, *U = nullptr, *Ub = nullptr, *Gh = nullptr, *Fpart = nullptr;
+    double2 *fpad = nullptr, *U = nullptr, *Ub = nullptr, *Hg = nullptr, *Fpart = nullptr;
     int nblk = 0;
     std::vector<void *> allocs;
     size_t dev_bytes = 0;
@@ -188,6 +194,64 @@ void build_tiles(const Plan &pl, const DeltaTables &dt, int mgroup, std::vector<
     for (auto &e : b) xn.push_back(e.second);
 }
 
+typedef long double ld;
+const ld kPiL = 3.141592653589793238462643383279502884L;
+
+// In-place radix-2 FFT in long double (host), X_k = sum_n x_n e^{-2 pi i n k/P}.
+void host_fft(std::vector<ld> &re, std::vector<ld> &im) {
+    const int P = (int)re.size();
+    for (int i = 1, j = 0; i < P; ++i) {
+        int bit = P >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            std::swap(re[i], re[j]);
+            std::swap(im[i], im[j]);
+        }
+    }
+    for (int len = 2; len <= P; len <<= 1) {
+        for (int i = 0; i < P; i += len)
+            for (int k = 0; k < len / 2; ++k) {
+                const ld a = -2.0L * kPiL * k / len;
+                const ld c = cosl(a), sn = sinl(a);
+                const int u = i + k, v = i + k + len / 2;
+                const ld xr = re[v] * c - im[v] * sn, xi = re[v] * sn + im[v] * c;
+                re[v] = re[u] - xr;
+                im[v] = im[u] - xi;
+                re[u] += xr;
+                im[u] += xi;
+            }
+    }
+}
+
+int pow2_at_least(int n) {
+    int p = 32;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// FFT of h'(i), i < len (zero beyond), divided by P and by `div`; h'(i) given by f(i).
+template <typename F>
+std::vector<double2> spectrum(int P, int len, ld div, F f) {
+    std::vector<ld> re(P, 0.0L), im(P, 0.0L);
+    for (int i = 0; i < len && i < P; ++i) {
+        const std::pair<ld, ld> v = f(i);
+        re[i] = v.first;
+        im[i] = v.second;
+    }
+    host_fft(re, im);
+    std::vector<double2> out(P);
+    for (int i = 0; i < P; ++i) out[i] = make_double2((double)(re[i] / (P * div)), (double)(im[i] / (P * div)));
+    return out;
+}
+
+// e^{sign i pi d^2 / T} with d^2 reduced exactly modulo 2T.
+std::pair<ld, ld> chirp_val(long long d, int T, int sign) {
+    const long long r = (d * d) % (2LL * T);
+    const ld a = sign * kPiL * (ld)r / (ld)T;
+    return {cosl(a), sinl(a)};
+}
+
 int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     std::unique_ptr<Plan> pl(new (std::nothrow) Plan());
     if (!pl) return S2DW_E_NOMEM;
@@ -267,9 +331,6 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
         long double a = 2.0L * 3.141592653589793238462643383279502884L * k / (2 * t.N - 1);
         twg[k] = make_double2((double)cosl(a), (double)sinl(a));
     }
-    std::vector<double> wt(6 * L + 1, 0.0);
-    for (int q = -3 * L; q <= 3 * L; ++q)
-        if ((q & 1) == 0) wt[q + 3 * L] = 2.0 / (1.0 - (double)q * (double)q);
     std::vector<double> fac(L);
     for (int l = 0; l < L; ++l)
         fac[l] = kind == kShtForward ? std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) / (2.0 * M_PI)
@@ -279,7 +340,7 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     memcpy(uvv.data(), dt.uv.data(), uvv.size() * sizeof(double2));
     bool ok = upload(P, P.pq, pqv) && upload(P, P.uv, uvv) && upload(P, P.kb2, kb2) && upload(P, P.seed, dt.seed) &&
               upload(P, P.seedm, dt.seedm) && upload(P, P.seede, dt.seede) && upload(P, P.twa, twa) &&
-              upload(P, P.twb, twb) && upload(P, P.twg, twg) && upload(P, P.wt, wt) && upload(P, P.fac, fac) &&
+              upload(P, P.twb, twb) && upload(P, P.twg, twg) && upload(P, P.fac, fac) &&
               upload(P, P.phi, t.phi);
     if (!ok) return S2DW_E_NOMEM;
     // tiles
@@ -296,12 +357,63 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     ta.insert(ta.end(), x_a.begin(), x_a.end());
     ts.insert(ts.end(), x_s.begin(), x_s.end());
     if (!upload(P, P.tiles_fwd, ta) || !upload(P, P.tiles_adj, ts)) return S2DW_E_NOMEM;
+    // Bluestein chirp spectra (see stages.hip for the convolution layout)
+    const int T = M;
+    P.PD = pow2_at_least(2 * T - 1);
+    if (P.PD > 8192) return S2DW_E_UNSUPPORTED;
+    {
+        auto hd1 = spectrum(P.PD, 2 * T - 1, (ld)T, [&](int i) { return chirp_val((long long)i - L - T + 2, T, +1); });
+        if (!upload(P, P.hD1, hd1)) return S2DW_E_NOMEM;
+    }
+    P.PA.assign(t.S, 0);
+    P.PB.assign(t.S, 0);
+    P.hA.assign(t.S, nullptr);
+    P.hB.assign(t.S, nullptr);
+    P.hC.assign(t.S, nullptr);
+    P.hD2.assign(t.S, nullptr);
+    std::vector<int> sizes = {P.PD};
+    for (int j = 0; j < t.S; ++j) {
+        const int Lj = P.sc.Lj[j];
+        if (Lj == 0) continue;
+        P.PA[j] = pow2_at_least(2 * Lj + L - 2);
+        P.PB[j] = pow2_at_least(2 * Lj + T - 2);
+        sizes.push_back(P.PA[j]);
+        sizes.push_back(P.PB[j]);
+        auto ha = spectrum(P.PA[j], 2 * Lj + L - 2, 1.0L,
+                           [&](int i) { return chirp_val((long long)i - Lj + 1, T, -1); });
+        auto hb = spectrum(P.PB[j], 2 * Lj + T - 2, 1.0L,
+                           [&](int i) { return chirp_val((long long)i - Lj + 1, T, -1); });
+        auto hc = spectrum(P.PB[j], 2 * Lj + T - 2, 1.0L,
+                           [&](int i) { return chirp_val((long long)i - Lj - T + 2, T, +1); });
+        // w(q) = int_0^pi sin(b) e^{i q b} db at q = Lj + L - 2 - i
+        auto hd2 = spectrum(P.PD, T + 2 * Lj - 2, 1.0L, [&](int i) {
+            const long long q = (long long)Lj + L - 2 - i;
+            if (q == 1) return std::pair<ld, ld>(0.0L, kPiL / 2);
+            if (q == -1) return std::pair<ld, ld>(0.0L, -kPiL / 2);
+            if (q % 2 == 0) return std::pair<ld, ld>(2.0L / (1.0L - (ld)q * (ld)q), 0.0L);
+            return std::pair<ld, ld>(0.0L, 0.0L);
+        });
+        if (!upload(P, P.hA[j], ha) || !upload(P, P.hB[j], hb) || !upload(P, P.hC[j], hc) || !upload(P, P.hD2[j], hd2))
+            return S2DW_E_NOMEM;
+    }
+    for (int Psz : sizes) {
+        if (P.twP.count(Psz)) continue;
+        std::vector<double2> tw(Psz);
+        for (int k = 0; k < Psz; ++k) {
+            const ld a = -2.0L * kPiL * k / Psz;
+            tw[k] = make_double2((double)cosl(a), (double)sinl(a));
+        }
+        double2 *d = nullptr;
+        if (!upload(P, d, tw)) return S2DW_E_NOMEM;
+        P.twP[Psz] = d;
+    }
     // workspaces
     int maxLj = 0;
     for (int j = 0; j < t.S; ++j) maxLj = std::max(maxLj, P.sc.Lj[j]);
     P.nblk = (L + P.group - 1) / P.group;
+    const size_t G = 2 * t.N - 1;
     if (!dalloc(P, P.fpad, (size_t)L * Lp) || !dalloc(P, P.U, (size_t)std::max<int64_t>(off, 1)) ||
-        !dalloc(P, P.Ub, (size_t)std::max<int64_t>(boff, 1)) || !dalloc(P, P.Gh, (size_t)t.N * M * std::max(maxLj, 1)) ||
+        !dalloc(P, P.Ub, (size_t)t.N * L * std::max(maxLj, 1)) || !dalloc(P, P.Hg, G * L * std::max(maxLj, 1)) ||
         !dalloc(P, P.Fpart, (size_t)P.nblk * L * Lp))
         return S2DW_E_NOMEM;
     out = pl.release();
@@ -327,6 +439,7 @@ int get_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
 int check_params(const s2dw_params *p) {
     if (!p) return S2DW_E_ARG;
     if (p->L < 2 || p->L > 4096) return S2DW_E_ARG;
+    if (p->L > 2048) return S2DW_E_UNSUPPORTED;
     if (p->N < 1 || p->N > p->L || p->N > 2 * kMaxK) return S2DW_E_ARG;
     if (!(p->lambda > 1.0) || !std::isfinite(p->lambda)) return S2DW_E_ARG;
     int JL = jmax_of(p->L, p->lambda);
@@ -375,7 +488,8 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
         a.tiles = P.tiles_fwd + P.nfwd_plain;
         S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.nfwd_x, true, st));
     }
-    const size_t per_scale = (size_t)(2 * P.ht.N - 1) * L * (2 * L - 1);
+    const int N = P.ht.N, G = 2 * N - 1;
+    const size_t per_scale = (size_t)G * L * (2 * L - 1);
     for (int j = 0; j < P.S; ++j) {
         const int Lj = P.sc.Lj[j];
         void *Wj = f32 ? (void *)((float *)W + per_scale * j) : (void *)((double *)W + per_scale * j);
@@ -383,15 +497,35 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
             S2DW_CHECK_HIP(hipMemsetAsync(Wj, 0, per_scale * (f32 ? 4 : 8), st));
             continue;
         }
-        BetaFwdArgs b{P.U + P.sc.off[j], P.Ub + P.sc.boff[j], P.twb, L, Lj, P.ht.N};
+        StageArgs b{};
+        b.in = P.U + P.sc.off[j];
+        b.out = P.Ub;
+        b.hh = P.hA[j];
+        b.tw = P.twP[P.PA[j]];
+        b.twb = P.twb;
+        b.L = L;
+        b.Lj = Lj;
+        b.N = N;
+        b.G = G;
         {
             Stage sg("beta_fwd", st);
-            S2DW_CHECK_HIP(launch_beta_fwd(b, st));
+            S2DW_CHECK_HIP(launch_beta_fwd_fft(b, P.PA[j], st));
         }
-        AlphaFwdArgs c{P.Ub + P.sc.boff[j], Wj, P.twa, P.twg, L, Lj, P.ht.N, f32};
+        GammaArgs g{P.Ub, P.Hg, P.twg, L, Lj, N, 0, 1.0};
+        {
+            Stage sg("gamma_fwd", st);
+            S2DW_CHECK_HIP(launch_gamma_fwd(g, st));
+        }
+        StageArgs c = b;
+        c.in = P.Hg;
+        c.out = nullptr;
+        c.wout = Wj;
+        c.f32 = f32;
+        c.hh = P.hB[j];
+        c.tw = P.twP[P.PB[j]];
         {
             Stage sg("alpha_fwd", st);
-            S2DW_CHECK_HIP(launch_alpha_fwd(c, st));
+            S2DW_CHECK_HIP(launch_alpha_fwd_fft(c, P.PB[j], st));
         }
     }
     return S2DW_OK;
@@ -399,38 +533,47 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
 
 // alpha/gamma/beta quadratures + Wigner-stage contraction: W -> f_lm.
 int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f32, hipStream_t st) {
-    const int L = P.L, M = 2 * L - 1, N = P.ht.N;
-    const size_t per_scale = (size_t)(2 * N - 1) * L * M;
+    const int L = P.L, M = 2 * L - 1, N = P.ht.N, G = 2 * N - 1;
+    const size_t per_scale = (size_t)G * L * M;
     for (int j = 0; j < P.S; ++j) {
         const int Lj = P.sc.Lj[j];
         if (Lj == 0) continue;
         const void *Wj = f32 ? (const void *)((const float *)W + per_scale * j)
                              : (const void *)((const double *)W + per_scale * j);
-        double2 *G = P.Ub + P.sc.boff[j];
-        AlphaAdjArgs c{Wj, G, P.twa, P.twg, L, Lj, N, f32,
-                       (2.0 * M_PI / M) * (2.0 * M_PI / (2 * N - 1))};
+        StageArgs c{};
+        c.win = Wj;
+        c.out = P.Hg;
+        c.hh = P.hC[j];
+        c.tw = P.twP[P.PB[j]];
+        c.twb = P.twb;
+        c.L = L;
+        c.Lj = Lj;
+        c.N = N;
+        c.G = G;
+        c.K = P.K;
+        c.f32 = f32;
+        c.scale = 2.0 * M_PI / M;
         {
             Stage sg("alpha_adj", st);
-            S2DW_CHECK_HIP(launch_alpha_adj(c, st));
+            S2DW_CHECK_HIP(launch_alpha_adj_fft(c, P.PB[j], st));
         }
-        BetaHatArgs h{G, P.Gh, P.twb, L, Lj, N};
+        GammaArgs g{P.Hg, P.Ub, P.twg, L, Lj, N, 0, 2.0 * M_PI / G};
         {
-            Stage sg("beta_hat", st);
-            S2DW_CHECK_HIP(launch_beta_hat(h, st));
+            Stage sg("gamma_adj", st);
+            S2DW_CHECK_HIP(launch_gamma_adj(g, st));
         }
-        BetaConvArgs v{};
-        v.Gh = P.Gh;
-        v.V = P.U + P.sc.off[j];
-        v.wt = P.wt;
-        v.L = L;
-        v.Lj = Lj;
-        v.N = N;
-        v.K = P.K;
+        StageArgs v = c;
+        v.in = P.Ub;
+        v.out = P.U + P.sc.off[j];
+        v.win = nullptr;
+        v.hh = P.hD1;
+        v.hh2 = P.hD2[j];
+        v.tw = P.twP[P.PD];
         for (int k = 0; k < P.K; ++k) v.nk[k] = P.ht.nk[k];
         v.eta_imag = P.ht.eta_imag ? 1 : 0;
         {
-            Stage sg("beta_conv", st);
-            S2DW_CHECK_HIP(launch_beta_conv(v, st));
+            Stage sg("beta_adj", st);
+            S2DW_CHECK_HIP(launch_beta_adj_fft(v, P.PD, st));
         }
     }
     WigAdjArgs a{};
@@ -544,6 +687,7 @@ int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, doubl
 
 int s2dw_sht_forward(const s2dw_params *p, const double *f_map, double *flm, void *stream) {
     if (!p || p->L < 2 || p->L > 4096 || !f_map || !flm || !aligned(f_map) || !aligned(flm)) return S2DW_E_ARG;
+    if (p->L > 2048) return S2DW_E_UNSUPPORTED;
     Plan *Q = nullptr;
     int rc = get_plan(kShtForward, p->L, 1, 0.0, 0, Q);
     if (rc != S2DW_OK) return rc;
@@ -552,6 +696,7 @@ int s2dw_sht_forward(const s2dw_params *p, const double *f_map, double *flm, voi
 
 int s2dw_sht_inverse(const s2dw_params *p, const double *flm, double *f_map, void *stream) {
     if (!p || p->L < 2 || p->L > 4096 || !f_map || !flm || !aligned(f_map) || !aligned(flm)) return S2DW_E_ARG;
+    if (p->L > 2048) return S2DW_E_UNSUPPORTED;
     Plan *Q = nullptr;
     int rc = get_plan(kShtInverse, p->L, 1, 0.0, 0, Q);
     if (rc != S2DW_OK) return rc;

@@ -1,0 +1,165 @@
+// Power-of-two FFTs held in LDS for gfx950 (FP64 complex), used as the engine of the
+// odd-length (2L-1) transforms through Bluestein's chirp convolution.
+//
+// Stockham autosort formulation: a length-P transform runs as passes of radix R in
+// {16, 8, 4, 2}; pass s reads the P values with stride P/R, multiplies by the twiddles
+// of the current span Ns, does an R-point DFT in registers and writes the outputs at
+// their sorted positions.  The pass is in place: every thread reads its inputs, the
+// workgroup synchronises, then every thread writes.  A column uses P/16 threads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace s2dw {
+namespace fft {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+    return make_double2(fma(a.x, b.x, a.y * b.y), fma(a.y, b.x, -a.x * b.y));
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// a * (SIGN i)
+template <int SIGN>
+__device__ __forceinline__ double2 mul_si(double2 a) {
+    return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// In-register DFTs: v'[k] = sum_r v[r] e^{SIGN 2 pi i r k / R}, natural order in and out.
+template <int SIGN>
+__device__ __forceinline__ void dft2(double2 *v) {
+    const double2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft4s(double2 &v0, double2 &v1, double2 &v2, double2 &v3) {
+    const double2 a = cadd(v0, v2), b = csub(v0, v2), c = cadd(v1, v3), d = mul_si<SIGN>(csub(v1, v3));
+    v0 = cadd(a, c);
+    v2 = csub(a, c);
+    v1 = cadd(b, d);
+    v3 = csub(b, d);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft4(double2 *v) {
+    dft4s<SIGN>(v[0], v[1], v[2], v[3]);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft8(double2 *v) {
+    // n = 2 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle w8^{n2 k1}, DFT2 over n2
+    constexpr double c = 0.70710678118654752440;
+    dft4s<SIGN>(v[0], v[2], v[4], v[6]);
+    dft4s<SIGN>(v[1], v[3], v[5], v[7]);
+    v[3] = cmul(v[3], make_double2(c, SIGN * c));
+    v[5] = mul_si<SIGN>(v[5]);
+    v[7] = cmul(v[7], make_double2(-c, SIGN * c));
+    double2 o[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        o[k1] = cadd(v[2 * k1], v[2 * k1 + 1]);
+        o[k1 + 4] = csub(v[2 * k1], v[2 * k1 + 1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = o[i];
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft16(double2 *v) {
+    // n = 4 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle w16^{n2 k1}, DFT4 over n2
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4s<SIGN>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    // Y[n2][k1] sits at v[n2 + 4 k1]
+    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, c2 = 0.70710678118654752440;
+    v[1 + 4 * 1] = cmul(v[1 + 4 * 1], make_double2(c1, SIGN * s1));   // w^1
+    v[1 + 4 * 2] = cmul(v[1 + 4 * 2], make_double2(c2, SIGN * c2));   // w^2
+    v[1 + 4 * 3] = cmul(v[1 + 4 * 3], make_double2(s1, SIGN * c1));   // w^3
+    v[2 + 4 * 1] = cmul(v[2 + 4 * 1], make_double2(c2, SIGN * c2));   // w^2
+    v[2 + 4 * 2] = mul_si<SIGN>(v[2 + 4 * 2]);                         // w^4
+    v[2 + 4 * 3] = cmul(v[2 + 4 * 3], make_double2(-c2, SIGN * c2));  // w^6
+    v[3 + 4 * 1] = cmul(v[3 + 4 * 1], make_double2(s1, SIGN * c1));   // w^3
+    v[3 + 4 * 2] = cmul(v[3 + 4 * 2], make_double2(-c2, SIGN * c2));  // w^6
+    v[3 + 4 * 3] = cmul(v[3 + 4 * 3], make_double2(-c1, -SIGN * s1)); // w^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4s<SIGN>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // X[k1 + 4 k2] sits at v[k2 + 4 k1]: transpose
+    double2 o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[k2 + 4 * k1];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = o[i];
+}
+
+template <int R, int SIGN>
+__device__ __forceinline__ void dft_reg(double2 *v) {
+    if constexpr (R == 2) dft2<SIGN>(v);
+    else if constexpr (R == 4) dft4<SIGN>(v);
+    else if constexpr (R == 8) dft8<SIGN>(v);
+    else dft16<SIGN>(v);
+}
+
+// One Stockham pass of radix R over a column of P values in LDS.  tw[t] = e^{-2 pi i t/P};
+// the inverse transform (SIGN = +1) uses its conjugate.
+template <int P, int R, int SIGN>
+__device__ __forceinline__ void pass(double2 *buf, int Ns, int tid, const double2 *__restrict__ tw) {
+    constexpr int NB = P / R;       // butterflies
+    constexpr int NT = P / 16;      // threads of the column
+    constexpr int PER = NB / NT;    // butterflies per thread
+    double2 v[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * NT;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * NB];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * NT;
+        const int k = j & (Ns - 1);
+        if (Ns > 1) {
+            const int st = k * (P / (Ns * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const double2 w = tw[st * r];
+                v[q][r] = SIGN < 0 ? cmul(v[q][r], w) : cmulc(v[q][r], w);
+            }
+        }
+        dft_reg<R, SIGN>(v[q]);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q][r];
+    }
+    __syncthreads();
+}
+
+// Unnormalised DFT of a column: X_k = sum_n x_n e^{SIGN 2 pi i n k / P}, P = 16^a * r.
+template <int P, int SIGN>
+__device__ __forceinline__ void transform(double2 *buf, int tid, const double2 *__restrict__ tw) {
+    static_assert(P >= 32 && (P & (P - 1)) == 0, "power of two >= 32");
+    int Ns = 1;
+    constexpr int REM = (P == 32 || P == 512 || P == 8192) ? 2 : (P == 64 || P == 1024 || P == 16384) ? 4
+                      : (P == 128 || P == 2048) ? 8 : 1;
+    constexpr int N16 = (REM == 1) ? ((P == 256) ? 2 : (P == 4096) ? 3 : 4) : ((P <= 128) ? 1 : (P <= 2048) ? 2 : 3);
+    if constexpr (REM > 1) {
+        pass<P, REM, SIGN>(buf, Ns, tid, tw);
+        Ns *= REM;
+    }
+#pragma unroll
+    for (int s = 0; s < N16; ++s) {
+        pass<P, 16, SIGN>(buf, Ns, tid, tw);
+        Ns *= 16;
+    }
+}
+
+}  // namespace fft
+}  // namespace s2dw

@@ -18,7 +18,7 @@ struct WigFwdArgs {
     const double *seedm;   // [Lp][Lp]  its mantissa (extended-exponent variant)
     const int *seede;      // [Lp][Lp]  its exponent
     const int2 *tiles;     // (m0, m'0) per workgroup
-    double2 *U;            // workspace; scale j at sc.off[j]: [N][Lj][Lj] = [n][m'][m]
+    double2 *U;            // workspace; scale j at sc.off[j]: [N][Lj][Lj] = [n][m][m']
     int L, Lp, N, eoff;    // eoff = 3 when eta_N = i (conj(eta) = i^3), else 0
     int nk[kMaxK];
     SegTab seg;
@@ -33,7 +33,7 @@ struct WigAdjArgs {
     const double *seedm;
     const int *seede;
     const int2 *tiles;
-    const double2 *V;      // scale j at sc.off[j]: [K][2][Lj][Lj] = [k][P|Q][m'][m]
+    const double2 *V;      // scale j at sc.off[j]: [K][2][Lj][Lj] = [k][P|Q][m][m']
     double2 *Fpart;        // [L / group][L][Lp] partial sums over each m' group
     int L, Lp, group;
     SegTab seg;
@@ -45,51 +45,37 @@ hipError_t launch_wig_fwd(const WigFwdArgs &a, int K, int ntiles, bool xn, hipSt
 hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int ntiles, bool xn, hipStream_t st);
 
 // ---------------------------------------------------------------- beta / alpha / gamma stages
-
-struct BetaFwdArgs {
-    const double2 *U;   // [N][Lj][Lj]
-    double2 *Ub;        // [N][L][Lj]
-    const double2 *twb; // e^{i pi k/(2L-1)}, k < 4L-2
-    int L, Lj, N;
-};
-hipError_t launch_beta_fwd(const BetaFwdArgs &a, hipStream_t st);
-
-struct AlphaFwdArgs {
-    const double2 *Ub;  // [N][L][Lj]
-    void *W;            // [2N-1][L][2L-1] of this scale (double or float)
-    const double2 *twa; // e^{2 pi i k/(2L-1)}
-    const double2 *twg; // e^{2 pi i k/(2N-1)}
-    int L, Lj, N, f32;
-};
-hipError_t launch_alpha_fwd(const AlphaFwdArgs &a, hipStream_t st);
-
-struct AlphaAdjArgs {
-    const void *W;      // [2N-1][L][2L-1] of this scale
-    double2 *G;         // [N][L][Lj]
-    const double2 *twa;
-    const double2 *twg;
-    int L, Lj, N, f32;
-    double scale;       // (2 pi/(2L-1)) (2 pi/(2N-1))
-};
-hipError_t launch_alpha_adj(const AlphaAdjArgs &a, hipStream_t st);
-
-struct BetaHatArgs {
-    const double2 *G;   // [N][L][Lj]   samples G_mn(beta_b)
-    double2 *Gh;        // [N][2L-1][Lj] Fourier coefficients of the extended samples
-    const double2 *twb; // e^{i pi k/(2L-1)}, k < 4L-2
-    int L, Lj, N;
-};
-hipError_t launch_beta_hat(const BetaHatArgs &a, hipStream_t st);
-
-struct BetaConvArgs {
-    const double2 *Gh;  // [N][2L-1][Lj]
-    double2 *V;         // [K][2][Lj][Lj]
-    const double *wt;   // w(q) = int_0^pi sin(b) cos(q b) db for q in [-(3L), 3L], index q + 3L
-    int L, Lj, N, K;
+// Bluestein stages (stages.hip).  Layouts per scale j (Lj = band-limit of the scale):
+//   analysis:  U [N][Lj][Lj] = [n][m][m'] -> Ub [N][Lj][L] = [n][m][b]
+//              -> Hg [2N-1][L][Lj] = [g][b][m] -> W [2N-1][L][2L-1]
+//   synthesis: W -> Wh [2N-1][L][Lj] -> G [N][Lj][L] = [n][m][b] -> V [K][2][Lj][Lj] = [k][P|Q][m][m']
+struct StageArgs {
+    const double2 *in;
+    double2 *out;
+    const void *win;       // wavelet coefficients read (synthesis alpha stage)
+    void *wout;            // wavelet coefficients written (analysis alpha stage)
+    const double2 *hh;     // FFT of the stage's chirp (or kernel) sequence, divided by P
+    const double2 *hh2;    // FFT of the w(q) sequence (synthesis beta stage), divided by P
+    const double2 *tw;     // e^{-2 pi i k/P}, k < P
+    const double2 *twb;    // e^{i pi k/T}, k < 2T, T = 2L - 1
+    int L, Lj, N, G, K, f32, eta_imag;
     int nk[kMaxK];
-    int eta_imag;
+    double scale;
 };
-hipError_t launch_beta_conv(const BetaConvArgs &a, hipStream_t st);
+hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, hipStream_t st);
+hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, hipStream_t st);
+hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, hipStream_t st);
+hipError_t launch_beta_adj_fft(const StageArgs &a, int P, hipStream_t st);
+
+struct GammaArgs {
+    const double2 *in;
+    double2 *out;
+    const double2 *twg;    // e^{2 pi i k/(2N-1)}
+    int L, Lj, N, gbase;
+    double scale;
+};
+hipError_t launch_gamma_fwd(const GammaArgs &a, hipStream_t st);
+hipError_t launch_gamma_adj(const GammaArgs &a, hipStream_t st);
 
 // --------------------------------------------------------------------------------- misc
 

@@ -1,0 +1,87 @@
+// Small kernels of the wavelet library: input padding, scaling coefficients, and the
+// final reduction of the synthesis.
+#include "kernels.h"
+
+namespace s2dw {
+
+// ---------------------------------------------------------------------------------- misc
+
+__global__ void pad_flm_kernel(const double2 *flm, double2 *fpad, int L, int Lp) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (m >= Lp) return;
+    fpad[(size_t)l * Lp + m] = (m <= l) ? flm[(size_t)l * l + l + m] : make_double2(0.0, 0.0);
+}
+
+hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, hipStream_t st) {
+    hipLaunchKernelGGL(pad_flm_kernel, dim3((Lp + 255) / 256, L), dim3(256), 0, st, flm, fpad, L, Lp);
+    return hipGetLastError();
+}
+
+// W^Phi_lm = sqrt(4 pi/(2l+1)) f_lm Phi_l0 (Eq. 31); Phi is real.
+__global__ void scaling_kernel(const double2 *flm, const double *phi, double2 *wphi, int L) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (m > 2 * l) return;
+    const size_t i = (size_t)l * l + m;
+    const double c = sqrt(4.0 * 3.14159265358979323846 / (2.0 * l + 1.0)) * phi[l];
+    const double2 f = flm[i];
+    wphi[i] = make_double2(c * f.x, c * f.y);
+}
+
+hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, hipStream_t st) {
+    hipLaunchKernelGGL(scaling_kernel, dim3((2 * L - 1 + 255) / 256, L), dim3(256), 0, st, flm, phi, wphi, L);
+    return hipGetLastError();
+}
+
+// f_lm = fac_l sum_g Fpart[g][l][m] + sqrt((2l+1)/(4 pi)) W^Phi_lm Phi_l0   (Eq. 32, 41), m >= 0;
+// f_{l,-m} = (-1)^m conj(f_lm).
+__global__ void syn_final_kernel(const double2 *Fpart, int nblk, int group, int Lmax, const double *fac,
+                                 const double2 *wphi, const double *phi, double2 *flm, int L, int Lp) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (m > l) return;
+    double fr = 0.0, fi = 0.0;
+    // no wavelet coefficient reaches l >= Lmax; blocks starting above l hold no term of row l
+    const int gmax = (l < Lmax && m < Lmax) ? min(nblk - 1, l / group) : -1;
+    for (int g = 0; g <= gmax; ++g) {
+        const double2 v = Fpart[((size_t)g * L + l) * Lp + m];
+        fr += v.x;
+        fi += v.y;
+    }
+    fr *= fac[l];
+    fi *= fac[l];
+    if (wphi) {
+        const double c = sqrt((2.0 * l + 1.0) / (4.0 * 3.14159265358979323846)) * phi[l];
+        const double2 w = wphi[(size_t)l * l + l + m];
+        fr += c * w.x;
+        fi += c * w.y;
+    }
+    flm[(size_t)l * l + l + m] = make_double2(fr, fi);
+    if (m > 0) {
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        flm[(size_t)l * l + l - m] = make_double2(sg * fr, -sg * fi);
+    }
+}
+
+hipError_t launch_syn_final(const double2 *Fpart, int nblk, int group, int Lmax, const double *fac,
+                            const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, hipStream_t st) {
+    hipLaunchKernelGGL(syn_final_kernel, dim3((L + 255) / 256, L), dim3(256), 0, st, Fpart, nblk, group, Lmax, fac,
+                       wphi, phi, flm, L, Lp);
+    return hipGetLastError();
+}
+
+__global__ void zero_kernel(double2 *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_zero(double2 *p, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace s2dw
