@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--lam", type=float, default=2.0)
     ap.add_argument("--jmin", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device-to-device copy of this many GiB (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -101,6 +103,17 @@ def main():
     import torch
     from paper_1308_5706_amd import s2dw
     from paper_1308_5706_amd.inputs import random_flm
+
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "copies": 3}), flush=True)
+        return
 
     L, N, lam, J_min = args.L, args.N, args.lam, args.jmin
     dev = torch.device("cuda:0")
