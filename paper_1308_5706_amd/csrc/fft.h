@@ -1,6 +1,10 @@
 // Power-of-two FFTs held in LDS for gfx950 (FP64 complex), used as the engine of the
 // odd-length (2L-1) transforms through Bluestein's chirp convolution.
 //
+// LDS layout: element i of a column lives at pad(i) = i + i/16, so that the stride-16
+// stores of the first radix-16 pass spread over all banks.  A column needs padded(P)
+// double2 slots.
+//
 // Stockham autosort formulation: a length-P transform runs as passes of radix R in
 // {16, 8, 4, 2}; pass s reads the P values with stride P/R, multiplies by the twiddles
 // of the current span Ns, does an R-point DFT in registers and writes the outputs at
@@ -25,6 +29,9 @@ __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
 // a * (SIGN i)
+__host__ __device__ constexpr int padded(int P) { return P + P / 16; }
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
 template <int SIGN>
 __device__ __forceinline__ double2 mul_si(double2 a) {
     return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
@@ -89,14 +96,13 @@ __device__ __forceinline__ void dft16(double2 *v) {
     v[3 + 4 * 3] = cmul(v[3 + 4 * 3], make_double2(-c1, -SIGN * s1)); // w^9
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1) dft4s<SIGN>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
-    // X[k1 + 4 k2] sits at v[k2 + 4 k1]: transpose
-    double2 o[16];
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1)
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[k2 + 4 * k1];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = o[i];
+    // X[k1 + 4 k2] now sits at v[k2 + 4 k1] (out_pos gives the position of X[k])
+}
+
+// Register holding output k of dft_reg<R>: natural order except for R = 16.
+template <int R>
+__device__ __forceinline__ constexpr int out_pos(int k) {
+    return R == 16 ? ((k >> 2) + 4 * (k & 3)) : k;
 }
 
 template <int R, int SIGN>
@@ -119,7 +125,7 @@ __device__ __forceinline__ void pass(double2 *buf, int Ns, int tid, const double
     for (int q = 0; q < PER; ++q) {
         const int j = tid + q * NT;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * NB];
+        for (int r = 0; r < R; ++r) v[q][r] = buf[pad(j + r * NB)];
     }
     __syncthreads();
 #pragma unroll
@@ -137,7 +143,7 @@ __device__ __forceinline__ void pass(double2 *buf, int Ns, int tid, const double
         dft_reg<R, SIGN>(v[q]);
         const int base = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q][r];
+        for (int r = 0; r < R; ++r) buf[pad(base + r * Ns)] = v[q][out_pos<R>(r)];
     }
     __syncthreads();
 }

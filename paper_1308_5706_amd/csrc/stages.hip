@@ -11,7 +11,7 @@
 // A convolution z(k) = sum_n a(n) h(k - n), n in [n0, n0+Na), k in [k0, k0+Nk), is
 // computed as c = IFFT(FFT(a') * FFT(h')) with a'(i) = a(n0+i) and
 // h'(i) = h(k0 - n0 - Na + 1 + i) (i < Na + Nk - 1, zero elsewhere), P >= Na + Nk - 1;
-// then z(k0 + q) = c[q + Na - 1].
+// then z(k0 + q) = c[q + Na - 1].  Column element i is held at LDS slot fft::pad(i).
 #include "fft.h"
 #include "kernels.h"
 
@@ -23,6 +23,7 @@ using fft::cmul;
 using fft::cmulc;
 using fft::cscale;
 using fft::csub;
+using fft::pad;
 
 namespace {
 
@@ -44,7 +45,7 @@ __device__ __forceinline__ void convolve(double2 *buf, const double2 *__restrict
                                          int tid) {
     constexpr int NT = P / 16;
     fft::transform<P, -1>(buf, tid, tw);
-    for (int i = tid; i < P; i += NT) buf[i] = cmul(buf[i], hh[i]);
+    for (int i = tid; i < P; i += NT) buf[pad(i)] = cmul(buf[pad(i)], hh[i]);
     __syncthreads();
     fft::transform<P, +1>(buf, tid, tw);
 }
@@ -57,7 +58,7 @@ __device__ __forceinline__ void convolve(double2 *buf, const double2 *__restrict
 // 2 pi m' b/T + pi m'/T, the chirp input is U e^{i pi m'(m'+1)/T}.
 template <int P>
 __global__ void __launch_bounds__(P / 16) beta_fwd_fft_kernel(const StageArgs a) {
-    __shared__ double2 buf[P];
+    __shared__ double2 buf[fft::padded(P)];
     constexpr int NT = P / 16;
     const int tid = threadIdx.x;
     const int Lj = a.Lj, L = a.L, T2 = 2 * (2 * L - 1);
@@ -75,12 +76,12 @@ __global__ void __launch_bounds__(P / 16) beta_fwd_fft_kernel(const StageArgs a)
             if (mp < 0 && odd) v = make_double2(-v.x, -v.y);
             v = cmul(v, chirp(a.twb, (long long)mp * (mp + 1), T2));
         }
-        buf[i] = v;
+        buf[pad(i)] = v;
     }
     __syncthreads();
     convolve<P>(buf, a.hh, a.tw, tid);
     double2 *__restrict__ out = a.out + (size_t)col * L;
-    for (int b = tid; b < L; b += NT) out[b] = cmul(buf[b + Na - 1], chirp(a.twb, (long long)b * b, T2));
+    for (int b = tid; b < L; b += NT) out[b] = cmul(buf[pad(b + Na - 1)], chirp(a.twb, (long long)b * b, T2));
 }
 
 // ------------------------------------------------------ analysis: alpha (Eq. 30), two gamma rows
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(P / 16) beta_fwd_fft_kernel(const StageArgs a)
 // are packed as H1 + i H2, whose transform is W1 + i W2.
 template <int P>
 __global__ void __launch_bounds__(P / 16) alpha_fwd_fft_kernel(const StageArgs a) {
-    __shared__ double2 buf[P];
+    __shared__ double2 buf[fft::padded(P)];
     constexpr int NT = P / 16;
     const int tid = threadIdx.x;
     const int Lj = a.Lj, L = a.L, T = 2 * L - 1, T2 = 2 * T, G = a.G;
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(P / 16) alpha_fwd_fft_kernel(const StageArgs a
             }
             v = cmul(make_double2(h1.x - h2.y, h1.y + h2.x), chirp(a.twb, (long long)m * m, T2));
         }
-        buf[i] = v;
+        buf[pad(i)] = v;
     }
     __syncthreads();
     convolve<P>(buf, a.hh, a.tw, tid);
@@ -122,7 +123,7 @@ __global__ void __launch_bounds__(P / 16) alpha_fwd_fft_kernel(const StageArgs a
     float *Wf = (float *)a.wout;
     const size_t o1 = ((size_t)g1 * L + b) * T, o2 = ((size_t)g2 * L + b) * T;
     for (int x = tid; x < T; x += NT) {
-        const double2 c = cmul(buf[x + Na - 1], chirp(a.twb, (long long)x * x, T2));
+        const double2 c = cmul(buf[pad(x + Na - 1)], chirp(a.twb, (long long)x * x, T2));
         if (a.f32) {
             Wf[o1 + x] = (float)c.x;
             if (two) Wf[o2 + x] = (float)c.y;
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(P / 16) alpha_fwd_fft_kernel(const StageArgs a
 // W1h(m) = (Zh(m) + conj Zh(-m))/2, W2h(m) = (Zh(m) - conj Zh(-m))/(2i), times 2 pi/T.
 template <int P>
 __global__ void __launch_bounds__(P / 16) alpha_adj_fft_kernel(const StageArgs a) {
-    __shared__ double2 buf[P];
+    __shared__ double2 buf[fft::padded(P)];
     constexpr int NT = P / 16;
     constexpr int MAXH = 8;  // 2L - 1 <= P/2: a thread holds at most P/(2 NT) = 8 of the outputs
     const int tid = threadIdx.x;
@@ -157,11 +158,11 @@ __global__ void __launch_bounds__(P / 16) alpha_adj_fft_kernel(const StageArgs a
             const double w2 = two ? (a.f32 ? (double)Wf[o2 + i] : W[o2 + i]) : 0.0;
             v = cmulc(make_double2(w1, w2), chirp(a.twb, (long long)i * i, T2));
         }
-        buf[i] = v;
+        buf[pad(i)] = v;
     }
     __syncthreads();
     convolve<P>(buf, a.hh, a.tw, tid);
-    // Zh(m) for m = q - (Lj-1), q < 2Lj-1, sits at buf[q + T - 1]; compact it to buf[q]
+    // Zh(m) for m = q - (Lj-1), q < 2Lj-1, sits at buf[pad(q + T - 1)]; compact it to buf[pad(q)]
     const int Nk = 2 * Lj - 1;
     double2 z[MAXH];
 #pragma unroll
@@ -169,21 +170,21 @@ __global__ void __launch_bounds__(P / 16) alpha_adj_fft_kernel(const StageArgs a
         const int q = tid + s * NT;
         if (q < Nk) {
             const int m = q - (Lj - 1);
-            z[s] = cmulc(buf[q + T - 1], chirp(a.twb, (long long)m * m, T2));
+            z[s] = cmulc(buf[pad(q + T - 1)], chirp(a.twb, (long long)m * m, T2));
         }
     }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < MAXH; ++s) {
         const int q = tid + s * NT;
-        if (q < Nk) buf[q] = z[s];
+        if (q < Nk) buf[pad(q)] = z[s];
     }
     __syncthreads();
     const double wa = a.scale;
     double2 *__restrict__ out1 = a.out + ((size_t)g1 * L + b) * Lj;
     double2 *__restrict__ out2 = a.out + ((size_t)g2 * L + b) * Lj;
     for (int m = tid; m < Lj; m += NT) {
-        const double2 zp = buf[m + Lj - 1], zm = buf[-m + Lj - 1];
+        const double2 zp = buf[pad(m + Lj - 1)], zm = buf[pad(-m + Lj - 1)];
         out1[m] = make_double2(0.5 * wa * (zp.x + zm.x), 0.5 * wa * (zp.y - zm.y));
         if (two) out2[m] = make_double2(0.5 * wa * (zp.y + zm.y), -0.5 * wa * (zp.x - zm.x));
     }
@@ -269,7 +270,7 @@ __global__ void __launch_bounds__(1024) gamma_adj_kernel(const GammaArgs a) {
 // combinations P, Q of the two n columns (see the synthesis Wigner kernel).
 template <int P>
 __global__ void __launch_bounds__(P / 16) beta_adj_fft_kernel(const StageArgs a) {
-    __shared__ double2 buf[P];
+    __shared__ double2 buf[fft::padded(P)];
     constexpr int NT = P / 16;
     constexpr int MAXH = 8;  // 2L - 1 <= P/2: a thread holds at most P/(2 NT) = 8 of the values
     const int tid = threadIdx.x;
@@ -290,34 +291,34 @@ __global__ void __launch_bounds__(P / 16) beta_adj_fft_kernel(const StageArgs a)
                 if (i >= L && odd) v = make_double2(-v.x, -v.y);
                 v = cmulc(v, chirp(a.twb, (long long)i * i, T2));
             }
-            buf[i] = v;
+            buf[pad(i)] = v;
         }
         __syncthreads();
         convolve<P>(buf, a.hh, a.tw, tid);
-        // Gh(p) at buf[q + T - 1], q = p + L - 1 < T (1/T folded into the chirp spectrum)
+        // Gh(p) at buf[pad(q + T - 1)], q = p + L - 1 < T (1/T folded into the chirp spectrum)
         double2 gh[MAXH];
 #pragma unroll
         for (int s = 0; s < MAXH; ++s) {
             const int q = tid + s * NT;
             if (q < T) {
                 const int p = q - (L - 1);
-                gh[s] = cmulc(buf[q + T - 1], chirp(a.twb, (long long)p * (p + 1), T2));
+                gh[s] = cmulc(buf[pad(q + T - 1)], chirp(a.twb, (long long)p * (p + 1), T2));
             }
         }
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < MAXH; ++s) {
             const int q = tid + s * NT;
-            if (q < T) buf[q] = gh[s];
+            if (q < T) buf[pad(q)] = gh[s];
         }
-        for (int q = T + tid; q < P; q += NT) buf[q] = make_double2(0.0, 0.0);
+        for (int q = T + tid; q < P; q += NT) buf[pad(q)] = make_double2(0.0, 0.0);
         __syncthreads();
         convolve<P>(buf, a.hh2, a.tw, tid);
-        // V(m') at buf[q + T - 1], q = m' + Lj - 1 < 2Lj - 1
+        // V(m') at buf[pad(q + T - 1)], q = m' + Lj - 1 < 2Lj - 1
 #pragma unroll
         for (int s = 0; s < MAXH; ++s) {
             const int q = tid + s * NT;
-            if (q < Nk) keep[c][s] = buf[q + T - 1];
+            if (q < Nk) keep[c][s] = buf[pad(q + T - 1)];
         }
         __syncthreads();
     }
@@ -326,16 +327,16 @@ __global__ void __launch_bounds__(P / 16) beta_adj_fft_kernel(const StageArgs a)
 #pragma unroll
         for (int s = 0; s < MAXH; ++s) {
             const int q = tid + s * NT;
-            if (c < ncol && q < Nk) buf[c * Nk + q] = keep[c][s];
+            if (c < ncol && q < Nk) buf[pad(c * Nk + q)] = keep[c][s];
         }
     __syncthreads();
     const int eta = a.eta_imag ? 1 : 0;
     double2 *__restrict__ Po = a.out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
     double2 *__restrict__ Qo = a.out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
     for (int mp = tid; mp < Lj; mp += NT) {
-        double2 tp = buf[mp + Lj - 1], tm = ncol > 1 ? buf[Nk + mp + Lj - 1] : make_double2(0.0, 0.0);
+        double2 tp = buf[pad(mp + Lj - 1)], tm = ncol > 1 ? buf[pad(Nk + mp + Lj - 1)] : make_double2(0.0, 0.0);
         if (mp > 0) {
-            double2 up = buf[-mp + Lj - 1], um = ncol > 1 ? buf[Nk - mp + Lj - 1] : make_double2(0.0, 0.0);
+            double2 up = buf[pad(-mp + Lj - 1)], um = ncol > 1 ? buf[pad(Nk - mp + Lj - 1)] : make_double2(0.0, 0.0);
             if (odd) {
                 up = make_double2(-up.x, -up.y);
                 um = make_double2(-um.x, -um.y);
