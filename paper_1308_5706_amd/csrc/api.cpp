@@ -32,7 +32,7 @@ struct Plan {
     ScaleTab sc{};
     int eoff = 0;
     // device tables
-    double2 *pq = nullptr, *uv = nullptr, *twa = nullptr, *twb = nullptr, *twg = nullptr;
+    double2 *pq = nullptr, *uv = nullptr, *twa = nullptr, *csq = nullptr, *cpp = nullptr, *twg = nullptr;
     double *kb2 = nullptr, *seed = nullptr, *seedm = nullptr, *phi = nullptr, *fac = nullptr;
     int *seede = nullptr;
     int2 *tiles_fwd = nullptr, *tiles_adj = nullptr;
@@ -318,14 +318,18 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
         }
     Plan &P = *pl;
     const int M = 2 * L - 1;
-    std::vector<double2> twa(M), twb(4 * L - 2), twg(2 * t.N - 1);
+    std::vector<double2> twa(M), csq(M), cpp(M), twg(2 * t.N - 1);
     for (int k = 0; k < M; ++k) {
         long double a = 2.0L * 3.141592653589793238462643383279502884L * k / M;
         twa[k] = make_double2((double)cosl(a), (double)sinl(a));
     }
-    for (int k = 0; k < 4 * L - 2; ++k) {
-        long double a = 3.141592653589793238462643383279502884L * k / M;
-        twb[k] = make_double2((double)cosl(a), (double)sinl(a));
+    // chirps with the phase reduced exactly modulo 2T
+    for (int i = 0; i < M; ++i) {
+        const long long p = i - (L - 1);
+        const long long r2 = ((long long)i * i) % (2LL * M), rp = ((p * (p + 1)) % (2LL * M) + 2LL * M) % (2LL * M);
+        const ld a2 = kPiL * (ld)r2 / (ld)M, ap = kPiL * (ld)rp / (ld)M;
+        csq[i] = make_double2((double)cosl(a2), (double)sinl(a2));
+        cpp[i] = make_double2((double)cosl(ap), (double)sinl(ap));
     }
     for (int k = 0; k < 2 * t.N - 1; ++k) {
         long double a = 2.0L * 3.141592653589793238462643383279502884L * k / (2 * t.N - 1);
@@ -340,7 +344,7 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     memcpy(uvv.data(), dt.uv.data(), uvv.size() * sizeof(double2));
     bool ok = upload(P, P.pq, pqv) && upload(P, P.uv, uvv) && upload(P, P.kb2, kb2) && upload(P, P.seed, dt.seed) &&
               upload(P, P.seedm, dt.seedm) && upload(P, P.seede, dt.seede) && upload(P, P.twa, twa) &&
-              upload(P, P.twb, twb) && upload(P, P.twg, twg) && upload(P, P.fac, fac) &&
+              upload(P, P.csq, csq) && upload(P, P.cpp, cpp) && upload(P, P.twg, twg) && upload(P, P.fac, fac) &&
               upload(P, P.phi, t.phi);
     if (!ok) return S2DW_E_NOMEM;
     // tiles
@@ -502,7 +506,8 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
         b.out = P.Ub;
         b.hh = P.hA[j];
         b.tw = P.twP[P.PA[j]];
-        b.twb = P.twb;
+        b.csq = P.csq;
+        b.cpp = P.cpp;
         b.L = L;
         b.Lj = Lj;
         b.N = N;
@@ -545,7 +550,8 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
         c.out = P.Hg;
         c.hh = P.hC[j];
         c.tw = P.twP[P.PB[j]];
-        c.twb = P.twb;
+        c.csq = P.csq;
+        c.cpp = P.cpp;
         c.L = L;
         c.Lj = Lj;
         c.N = N;

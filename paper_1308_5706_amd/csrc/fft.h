@@ -9,7 +9,8 @@
 // {16, 8, 4, 2}; pass s reads the P values with stride P/R, multiplies by the twiddles
 // of the current span Ns, does an R-point DFT in registers and writes the outputs at
 // their sorted positions.  The pass is in place: every thread reads its inputs, the
-// workgroup synchronises, then every thread writes.  A column uses P/16 threads.
+// workgroup synchronises, then every thread writes.  A column uses P/RM threads for a
+// main radix RM.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,10 +29,10 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
-// a * (SIGN i)
 __host__ __device__ constexpr int padded(int P) { return P + P / 16; }
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
+// a * (SIGN i)
 template <int SIGN>
 __device__ __forceinline__ double2 mul_si(double2 a) {
     return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
@@ -113,19 +114,60 @@ __device__ __forceinline__ void dft_reg(double2 *v) {
     else dft16<SIGN>(v);
 }
 
-// One Stockham pass of radix R over a column of P values in LDS.  tw[t] = e^{-2 pi i t/P};
-// the inverse transform (SIGN = +1) uses its conjugate.
-template <int P, int R, int SIGN>
-__device__ __forceinline__ void pass(double2 *buf, int Ns, int tid, const double2 *__restrict__ tw) {
+// Reads and writes of a column held in LDS.
+struct LdsIn {
+    const double2 *buf;
+    __device__ __forceinline__ double2 operator()(int i) const { return buf[pad(i)]; }
+};
+struct LdsOut {
+    double2 *buf;
+    __device__ __forceinline__ void operator()(int i, double2 v) const { buf[pad(i)] = v; }
+};
+
+// log2 of a power of two, at compile time
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
+// Pass structure of a length-P transform with main radix RM on NT = P/RM threads: one
+// leading pass of radix REM (what is left of P after the radix-RM passes), then NMAIN
+// passes of radix RM.  Every thread handles RM values in every pass.
+template <int P, int RM>
+struct Plan {
+    static constexpr int NT = P / RM;
+    static constexpr int NMAIN = ilog2(P) / ilog2(RM);
+    static constexpr int REM = 1 << (ilog2(P) % ilog2(RM));
+    static constexpr int NPASS = NMAIN + (REM > 1 ? 1 : 0);
+};
+
+// One Stockham pass of radix R over a column of P values held by NT threads: inputs come
+// from `in` (LDS or a loader), outputs go to `out` (LDS or a storer).  tw[t] = e^{-2 pi i
+// t/P} (the inverse transform, SIGN = +1, uses its conjugate).  If pm is not null each
+// output X[i] is multiplied by pm[i] before it is stored.  The pass is in place: all
+// reads, a barrier, all writes, a barrier.  The twiddles are requested before the reads
+// so that their latency overlaps the reads and the barrier.
+template <int P, int NT, int R, int SIGN, class In, class Out>
+__device__ __forceinline__ void pass(int Ns, int tid0, const double2 *__restrict__ tw, const double2 *__restrict__ pm,
+                                     In in, Out out) {
     constexpr int NB = P / R;       // butterflies
-    constexpr int NT = P / 16;      // threads of the column
     constexpr int PER = NB / NT;    // butterflies per thread
-    double2 v[PER][R];
+    // The thread index is made opaque per pass so that the index arithmetic and bounds
+    // masks of one pass are not hoisted and kept live across the others.
+    int tid = tid0;
+    __asm__ volatile("" : "+v"(tid));
+    double2 v[PER][R], w[PER][R];
+    if (Ns > 1) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int j = tid + q * NT;
+            const int st = (j & (Ns - 1)) * (P / (Ns * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[q][r] = tw[st * r];
+        }
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int j = tid + q * NT;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = buf[pad(j + r * NB)];
+        for (int r = 0; r < R; ++r) v[q][r] = in(j + r * NB);
     }
     __syncthreads();
 #pragma unroll
@@ -133,38 +175,59 @@ __device__ __forceinline__ void pass(double2 *buf, int Ns, int tid, const double
         const int j = tid + q * NT;
         const int k = j & (Ns - 1);
         if (Ns > 1) {
-            const int st = k * (P / (Ns * R));
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                const double2 w = tw[st * r];
-                v[q][r] = SIGN < 0 ? cmul(v[q][r], w) : cmulc(v[q][r], w);
-            }
+            for (int r = 1; r < R; ++r) v[q][r] = SIGN < 0 ? cmul(v[q][r], w[q][r]) : cmulc(v[q][r], w[q][r]);
         }
         dft_reg<R, SIGN>(v[q]);
         const int base = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[pad(base + r * Ns)] = v[q][out_pos<R>(r)];
+        for (int r = 0; r < R; ++r) {
+            double2 x = v[q][out_pos<R>(r)];
+            if (pm) x = cmul(x, pm[base + r * Ns]);
+            out(base + r * Ns, x);
+        }
     }
     __syncthreads();
 }
 
-// Unnormalised DFT of a column: X_k = sum_n x_n e^{SIGN 2 pi i n k / P}, P = 16^a * r.
-template <int P, int SIGN>
-__device__ __forceinline__ void transform(double2 *buf, int tid, const double2 *__restrict__ tw) {
+// Unnormalised DFT of a column, X_k = sum_n x_n e^{SIGN 2 pi i n k / P}, on P/RM threads:
+// the first pass reads x through `in`, the last pass writes X (times pm, if given)
+// through `out`; the passes in between work in LDS (buf).
+template <int P, int RM, int SIGN, class In, class Out>
+__device__ __forceinline__ void transform_io(double2 *buf, int tid, const double2 *__restrict__ tw,
+                                             const double2 *__restrict__ pm, In in, Out out) {
     static_assert(P >= 32 && (P & (P - 1)) == 0, "power of two >= 32");
+    using PL = Plan<P, RM>;
+    constexpr int NT = PL::NT;
+    LdsIn li{buf};
+    LdsOut lo{buf};
     int Ns = 1;
-    constexpr int REM = (P == 32 || P == 512 || P == 8192) ? 2 : (P == 64 || P == 1024 || P == 16384) ? 4
-                      : (P == 128 || P == 2048) ? 8 : 1;
-    constexpr int N16 = (REM == 1) ? ((P == 256) ? 2 : (P == 4096) ? 3 : 4) : ((P <= 128) ? 1 : (P <= 2048) ? 2 : 3);
-    if constexpr (REM > 1) {
-        pass<P, REM, SIGN>(buf, Ns, tid, tw);
-        Ns *= REM;
+    int p = 0;
+    if constexpr (PL::REM > 1) {
+        if constexpr (PL::NPASS == 1) pass<P, NT, PL::REM, SIGN>(Ns, tid, tw, pm, in, out);
+        else pass<P, NT, PL::REM, SIGN>(Ns, tid, tw, nullptr, in, lo);
+        Ns *= PL::REM;
+        ++p;
     }
 #pragma unroll
-    for (int s = 0; s < N16; ++s) {
-        pass<P, 16, SIGN>(buf, Ns, tid, tw);
-        Ns *= 16;
+    for (int s = 0; s < PL::NMAIN; ++s) {
+        const bool first = (p == 0), last = (p == PL::NPASS - 1);
+        if (first && last) pass<P, NT, RM, SIGN>(Ns, tid, tw, pm, in, out);
+        else if (first) pass<P, NT, RM, SIGN>(Ns, tid, tw, nullptr, in, lo);
+        else if (last) pass<P, NT, RM, SIGN>(Ns, tid, tw, pm, li, out);
+        else pass<P, NT, RM, SIGN>(Ns, tid, tw, nullptr, li, lo);
+        Ns *= RM;
+        ++p;
     }
+}
+
+// Linear convolution through the FFT: the column is read by `in`, transformed, multiplied
+// by the spectrum hh, transformed back and written by `out` (unnormalised: hh carries 1/P).
+template <int P, int RM, class In, class Out>
+__device__ __forceinline__ void convolve_io(double2 *buf, int tid, const double2 *__restrict__ tw,
+                                            const double2 *__restrict__ hh, In in, Out out) {
+    transform_io<P, RM, -1>(buf, tid, tw, hh, in, LdsOut{buf});
+    transform_io<P, RM, +1>(buf, tid, tw, nullptr, LdsIn{buf}, out);
 }
 
 }  // namespace fft

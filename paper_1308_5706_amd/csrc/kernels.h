@@ -57,7 +57,8 @@ struct StageArgs {
     const double2 *hh;     // FFT of the stage's chirp (or kernel) sequence, divided by P
     const double2 *hh2;    // FFT of the w(q) sequence (synthesis beta stage), divided by P
     const double2 *tw;     // e^{-2 pi i k/P}, k < P
-    const double2 *twb;    // e^{i pi k/T}, k < 2T, T = 2L - 1
+    const double2 *csq;    // e^{i pi i^2/T}, i < T, T = 2L - 1
+    const double2 *cpp;    // e^{i pi p(p+1)/T} at p + L - 1, |p| < L
     int L, Lj, N, G, K, f32, eta_imag;
     int nk[kMaxK];
     double scale;

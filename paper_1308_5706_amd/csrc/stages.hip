@@ -5,8 +5,9 @@
 // 2 x y = x^2 + y^2 - (y - x)^2,
 //   sum_x a_x e^{2 pi i x y/T} = e^{i pi y^2/T} sum_x (a_x e^{i pi x^2/T}) e^{-i pi (y-x)^2/T},
 // a linear convolution evaluated by a power-of-two FFT of size P held in LDS (fft.h);
-// the spectrum of each chirp (divided by P) is precomputed per plan.  Phases are
-// reduced exactly: e^{i pi r/T} is read from a table at r = (integer) mod 2T.
+// the spectrum of each chirp (divided by P) and the chirps themselves,
+// csq[i] = e^{i pi i^2/T} (i < T) and cpp[p + L - 1] = e^{i pi p(p+1)/T} (|p| < L), are
+// precomputed per plan with the phases reduced exactly modulo 2T.
 //
 // A convolution z(k) = sum_n a(n) h(k - n), n in [n0, n0+Na), k in [k0, k0+Nk), is
 // computed as c = IFFT(FFT(a') * FFT(h')) with a'(i) = a(n0+i) and
@@ -14,6 +15,10 @@
 // then z(k0 + q) = c[q + Na - 1].  Column element i is held at LDS slot fft::pad(i).
 #include "fft.h"
 #include "kernels.h"
+
+#ifndef S2DW_FFT_RADIX
+#define S2DW_FFT_RADIX 16
+#endif
 
 namespace s2dw {
 
@@ -27,9 +32,10 @@ using fft::pad;
 
 namespace {
 
-__device__ __forceinline__ double2 chirp(const double2 *__restrict__ twb, long long r, int T2) {
-    return twb[(int)(r % T2)];
-}
+// Main FFT radix: a column of P values is handled by P / kRM threads.
+constexpr int kRM = S2DW_FFT_RADIX;
+// Waves per SIMD the FFT kernels must fit (two P = 4096 columns share a CU's LDS).
+constexpr int kMinWaves = kRM >= 16 ? 2 : 4;
 
 __device__ __forceinline__ double2 rot_i(double2 z, int e) {
     e &= 3;
@@ -39,16 +45,7 @@ __device__ __forceinline__ double2 rot_i(double2 z, int e) {
     return make_double2(z.y, -z.x);
 }
 
-// FFT, pointwise product with the chirp spectrum, inverse FFT (all in LDS).
-template <int P>
-__device__ __forceinline__ void convolve(double2 *buf, const double2 *__restrict__ hh, const double2 *__restrict__ tw,
-                                         int tid) {
-    constexpr int NT = P / 16;
-    fft::transform<P, -1>(buf, tid, tw);
-    for (int i = tid; i < P; i += NT) buf[pad(i)] = cmul(buf[pad(i)], hh[i]);
-    __syncthreads();
-    fft::transform<P, +1>(buf, tid, tw);
-}
+__device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
 
 }  // namespace
 
@@ -57,137 +54,136 @@ __device__ __forceinline__ void convolve(double2 *buf, const double2 *__restrict
 // U_{m,-m',n} = (-1)^{m+n} U_{m m' n} (only m' >= 0 is stored).  Since m' beta_b =
 // 2 pi m' b/T + pi m'/T, the chirp input is U e^{i pi m'(m'+1)/T}.
 template <int P>
-__global__ void __launch_bounds__(P / 16) beta_fwd_fft_kernel(const StageArgs a) {
+__global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const StageArgs a) {
     __shared__ double2 buf[fft::padded(P)];
-    constexpr int NT = P / 16;
     const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L, T2 = 2 * (2 * L - 1);
+    const int Lj = a.Lj, L = a.L;
     const int col = blockIdx.x;  // ni * Lj + m
     const int ni = col / Lj, m = col - ni * Lj;
     const int n = 2 * ni - (a.N - 1);
     const bool odd = ((m + n) & 1) != 0;
     const double2 *__restrict__ Uc = a.in + (size_t)col * Lj;
+    const double2 *__restrict__ cpp = a.cpp + (L - 1);
+    const double2 *__restrict__ csq = a.csq;
     const int Na = 2 * Lj - 1;
-    for (int i = tid; i < P; i += NT) {
-        double2 v = make_double2(0.0, 0.0);
-        if (i < Na) {
-            const int mp = i - (Lj - 1);
-            v = Uc[mp < 0 ? -mp : mp];
-            if (mp < 0 && odd) v = make_double2(-v.x, -v.y);
-            v = cmul(v, chirp(a.twb, (long long)mp * (mp + 1), T2));
-        }
-        buf[pad(i)] = v;
-    }
-    __syncthreads();
-    convolve<P>(buf, a.hh, a.tw, tid);
     double2 *__restrict__ out = a.out + (size_t)col * L;
-    for (int b = tid; b < L; b += NT) out[b] = cmul(buf[pad(b + Na - 1)], chirp(a.twb, (long long)b * b, T2));
+    auto in = [&](int i) {
+        if (i >= Na) return zero2();
+        const int mp = i - (Lj - 1);
+        double2 v = Uc[mp < 0 ? -mp : mp];
+        if (mp < 0 && odd) v = make_double2(-v.x, -v.y);
+        return cmul(v, cpp[mp]);
+    };
+    auto st = [&](int i, double2 v) {
+        const int b = i - (Na - 1);
+        if (b >= 0 && b < L) out[b] = cmul(v, csq[b]);
+    };
+    fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
 }
 
 // ------------------------------------------------------ analysis: alpha (Eq. 30), two gamma rows
 // W(a) = sum_{|m|<Lj} H_m e^{2 pi i m a/T} with H_{-m} = conj(H_m) (real W); the rows g1 and g2
 // are packed as H1 + i H2, whose transform is W1 + i W2.
 template <int P>
-__global__ void __launch_bounds__(P / 16) alpha_fwd_fft_kernel(const StageArgs a) {
+__global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const StageArgs a) {
     __shared__ double2 buf[fft::padded(P)];
-    constexpr int NT = P / 16;
     const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, T2 = 2 * T, G = a.G;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, G = a.G;
     const int ngp = (G + 1) / 2;
     const int b = blockIdx.x / ngp, gp = blockIdx.x - (blockIdx.x / ngp) * ngp;
     const int g1 = 2 * gp, g2 = 2 * gp + 1;
     const bool two = g2 < G;
     const double2 *__restrict__ H1 = a.in + ((size_t)g1 * L + b) * Lj;
     const double2 *__restrict__ H2 = a.in + ((size_t)(two ? g2 : g1) * L + b) * Lj;
+    const double2 *__restrict__ csq = a.csq;
     const int Na = 2 * Lj - 1;
-    for (int i = tid; i < P; i += NT) {
-        double2 v = make_double2(0.0, 0.0);
-        if (i < Na) {
-            const int m = i - (Lj - 1);
-            const int am = m < 0 ? -m : m;
-            double2 h1 = H1[am], h2 = two ? H2[am] : make_double2(0.0, 0.0);
-            if (m == 0) {
-                h1.y = 0.0;
-                h2.y = 0.0;
-            } else if (m < 0) {
-                h1.y = -h1.y;
-                h2.y = -h2.y;
-            }
-            v = cmul(make_double2(h1.x - h2.y, h1.y + h2.x), chirp(a.twb, (long long)m * m, T2));
+    auto in = [&](int i) {
+        if (i >= Na) return zero2();
+        const int m = i - (Lj - 1);
+        const int am = m < 0 ? -m : m;
+        double2 h1 = H1[am], h2 = two ? H2[am] : zero2();
+        if (m == 0) {
+            h1.y = 0.0;
+            h2.y = 0.0;
+        } else if (m < 0) {
+            h1.y = -h1.y;
+            h2.y = -h2.y;
         }
-        buf[pad(i)] = v;
-    }
-    __syncthreads();
-    convolve<P>(buf, a.hh, a.tw, tid);
-    double *W = (double *)a.wout;
-    float *Wf = (float *)a.wout;
+        return cmul(make_double2(h1.x - h2.y, h1.y + h2.x), csq[am]);
+    };
     const size_t o1 = ((size_t)g1 * L + b) * T, o2 = ((size_t)g2 * L + b) * T;
-    for (int x = tid; x < T; x += NT) {
-        const double2 c = cmul(buf[pad(x + Na - 1)], chirp(a.twb, (long long)x * x, T2));
-        if (a.f32) {
-            Wf[o1 + x] = (float)c.x;
-            if (two) Wf[o2 + x] = (float)c.y;
-        } else {
-            W[o1 + x] = c.x;
-            if (two) W[o2 + x] = c.y;
-        }
+    if (a.f32) {
+        float *Wf = (float *)a.wout;
+        auto st = [&](int i, double2 v) {
+            const int x = i - (Na - 1);
+            if (x >= 0 && x < T) {
+                const double2 c = cmul(v, csq[x]);
+                Wf[o1 + x] = (float)c.x;
+                if (two) Wf[o2 + x] = (float)c.y;
+            }
+        };
+        fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
+    } else {
+        double *W = (double *)a.wout;
+        auto st = [&](int i, double2 v) {
+            const int x = i - (Na - 1);
+            if (x >= 0 && x < T) {
+                const double2 c = cmul(v, csq[x]);
+                W[o1 + x] = c.x;
+                if (two) W[o2 + x] = c.y;
+            }
+        };
+        fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
     }
 }
 
 // ----------------------------------------------------- synthesis: alpha (Eq. 37), two gamma rows
 // Zh(m) = sum_a (W1 + i W2)(a) e^{-2 pi i m a/T} for |m| < Lj; then
 // W1h(m) = (Zh(m) + conj Zh(-m))/2, W2h(m) = (Zh(m) - conj Zh(-m))/(2i), times 2 pi/T.
-template <int P>
-__global__ void __launch_bounds__(P / 16) alpha_adj_fft_kernel(const StageArgs a) {
-    __shared__ double2 buf[fft::padded(P)];
-    constexpr int NT = P / 16;
-    constexpr int MAXH = 8;  // 2L - 1 <= P/2: a thread holds at most P/(2 NT) = 8 of the outputs
+template <int P, bool F32>
+__device__ __forceinline__ void alpha_adj_body(const StageArgs &a, double2 *buf) {
     const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, T2 = 2 * T, G = a.G;
+    constexpr int NT = P / kRM;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, G = a.G;
     const int ngp = (G + 1) / 2;
     const int b = blockIdx.x / ngp, gp = blockIdx.x - (blockIdx.x / ngp) * ngp;
     const int g1 = 2 * gp, g2 = 2 * gp + 1;
     const bool two = g2 < G;
-    const double *W = (const double *)a.win;
-    const float *Wf = (const float *)a.win;
-    const size_t o1 = ((size_t)g1 * L + b) * T, o2 = ((size_t)g2 * L + b) * T;
-    for (int i = tid; i < P; i += NT) {
-        double2 v = make_double2(0.0, 0.0);
-        if (i < T) {
-            const double w1 = a.f32 ? (double)Wf[o1 + i] : W[o1 + i];
-            const double w2 = two ? (a.f32 ? (double)Wf[o2 + i] : W[o2 + i]) : 0.0;
-            v = cmulc(make_double2(w1, w2), chirp(a.twb, (long long)i * i, T2));
-        }
-        buf[pad(i)] = v;
-    }
-    __syncthreads();
-    convolve<P>(buf, a.hh, a.tw, tid);
-    // Zh(m) for m = q - (Lj-1), q < 2Lj-1, sits at buf[pad(q + T - 1)]; compact it to buf[pad(q)]
+    using WT = typename std::conditional<F32, float, double>::type;
+    const WT *__restrict__ W1 = (const WT *)a.win + ((size_t)g1 * L + b) * T;
+    const WT *__restrict__ W2 = (const WT *)a.win + ((size_t)(two ? g2 : g1) * L + b) * T;
+    const double2 *__restrict__ csq = a.csq;
+    auto in = [&](int i) {
+        if (i >= T) return zero2();
+        const double w1 = (double)W1[i];
+        const double w2 = two ? (double)W2[i] : 0.0;
+        return cmulc(make_double2(w1, w2), csq[i]);
+    };
+    // Zh(m) for m = q - (Lj-1), q < 2Lj-1, comes out at q + T - 1; it is stored at slot q
     const int Nk = 2 * Lj - 1;
-    double2 z[MAXH];
-#pragma unroll
-    for (int s = 0; s < MAXH; ++s) {
-        const int q = tid + s * NT;
-        if (q < Nk) {
+    auto st = [&](int i, double2 v) {
+        const int q = i - (T - 1);
+        if (q >= 0 && q < Nk) {
             const int m = q - (Lj - 1);
-            z[s] = cmulc(buf[pad(q + T - 1)], chirp(a.twb, (long long)m * m, T2));
+            buf[pad(q)] = cmulc(v, csq[m < 0 ? -m : m]);
         }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < MAXH; ++s) {
-        const int q = tid + s * NT;
-        if (q < Nk) buf[pad(q)] = z[s];
-    }
-    __syncthreads();
-    const double wa = a.scale;
+    };
+    fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
+    const double wa = 0.5 * a.scale;
     double2 *__restrict__ out1 = a.out + ((size_t)g1 * L + b) * Lj;
     double2 *__restrict__ out2 = a.out + ((size_t)g2 * L + b) * Lj;
     for (int m = tid; m < Lj; m += NT) {
         const double2 zp = buf[pad(m + Lj - 1)], zm = buf[pad(-m + Lj - 1)];
-        out1[m] = make_double2(0.5 * wa * (zp.x + zm.x), 0.5 * wa * (zp.y - zm.y));
-        if (two) out2[m] = make_double2(0.5 * wa * (zp.y + zm.y), -0.5 * wa * (zp.x - zm.x));
+        out1[m] = make_double2(wa * (zp.x + zm.x), wa * (zp.y - zm.y));
+        if (two) out2[m] = make_double2(wa * (zp.y + zm.y), -wa * (zp.x - zm.x));
     }
+}
+
+template <int P>
+__global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const StageArgs a) {
+    __shared__ double2 buf[fft::padded(P)];
+    if (a.f32) alpha_adj_body<P, true>(a, buf);
+    else alpha_adj_body<P, false>(a, buf);
 }
 
 // -------------------------------------------- gamma sums fused with the (m, b) <-> (b, m) transposes
@@ -269,74 +265,69 @@ __global__ void __launch_bounds__(1024) gamma_adj_kernel(const GammaArgs a) {
 // interpolant against e^{-i m' beta}; (3) the fold over +-m' and the even/odd-l
 // combinations P, Q of the two n columns (see the synthesis Wigner kernel).
 template <int P>
-__global__ void __launch_bounds__(P / 16) beta_adj_fft_kernel(const StageArgs a) {
+__global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const StageArgs a) {
     __shared__ double2 buf[fft::padded(P)];
-    constexpr int NT = P / 16;
-    constexpr int MAXH = 8;  // 2L - 1 <= P/2: a thread holds at most P/(2 NT) = 8 of the values
+    constexpr int NT = P / kRM;
     const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, T2 = 2 * T, N = a.N;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N;
     const int k = blockIdx.x / Lj, m = blockIdx.x - (blockIdx.x / Lj) * Lj;
-    const int n = a.nk[k];
+    int n = 0;  // a.nk[k] without a dynamically indexed copy of the argument block
+#pragma unroll
+    for (int kk = 0; kk < kMaxK; ++kk)
+        if (kk == k) n = a.nk[kk];
     const int ncol = n == 0 ? 1 : 2;
     const bool odd = ((m + n) & 1) != 0;
     const int Nk = 2 * Lj - 1;
-    double2 keep[2][MAXH];
+    const double2 *__restrict__ csq = a.csq;
+    const double2 *__restrict__ cpp = a.cpp;
+    double2 *__restrict__ Po = a.out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
+    double2 *__restrict__ Qo = a.out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
         const double2 *__restrict__ Gc = a.in + ((size_t)ni * Lj + m) * L;
-        for (int i = tid; i < P; i += NT) {
-            double2 v = make_double2(0.0, 0.0);
-            if (i < T) {
-                v = i < L ? Gc[i] : Gc[2 * L - 2 - i];
-                if (i >= L && odd) v = make_double2(-v.x, -v.y);
-                v = cmulc(v, chirp(a.twb, (long long)i * i, T2));
-            }
-            buf[pad(i)] = v;
+        auto in1 = [&](int i) {
+            if (i >= T) return zero2();
+            double2 v = i < L ? Gc[i] : Gc[2 * L - 2 - i];
+            if (i >= L && odd) v = make_double2(-v.x, -v.y);
+            return cmulc(v, csq[i]);
+        };
+        // Gh(p), q = p + L - 1 < T, comes out at q + T - 1 (1/T is folded into the spectrum)
+        auto st1 = [&](int i, double2 v) {
+            const int q = i - (T - 1);
+            if (q >= 0 && q < T) buf[pad(q)] = cmulc(v, cpp[q]);
+        };
+        fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in1, st1);
+        auto in2 = [&](int i) { return i < T ? buf[pad(i)] : zero2(); };
+        // V(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + T - 1.  With two columns the
+        // first one waits in this block's own output rows (2 Lj slots) while the second one
+        // uses the whole buffer; the second one goes to slots Nk + q.
+        if (c == 0 && ncol > 1) {
+            auto st2 = [&](int i, double2 v) {
+                const int q = i - (T - 1);
+                if (q >= 0 && q < Nk) {
+                    if (q < Lj) Po[q] = v;
+                    else Qo[q - Lj] = v;
+                }
+            };
+            fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh2, in2, st2);
+        } else {
+            const int sh = c * Nk;
+            auto st2 = [&](int i, double2 v) {
+                const int q = i - (T - 1);
+                if (q >= 0 && q < Nk) buf[pad(sh + q)] = v;
+            };
+            fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh2, in2, st2);
         }
-        __syncthreads();
-        convolve<P>(buf, a.hh, a.tw, tid);
-        // Gh(p) at buf[pad(q + T - 1)], q = p + L - 1 < T (1/T folded into the chirp spectrum)
-        double2 gh[MAXH];
-#pragma unroll
-        for (int s = 0; s < MAXH; ++s) {
-            const int q = tid + s * NT;
-            if (q < T) {
-                const int p = q - (L - 1);
-                gh[s] = cmulc(buf[pad(q + T - 1)], chirp(a.twb, (long long)p * (p + 1), T2));
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < MAXH; ++s) {
-            const int q = tid + s * NT;
-            if (q < T) buf[pad(q)] = gh[s];
-        }
-        for (int q = T + tid; q < P; q += NT) buf[pad(q)] = make_double2(0.0, 0.0);
-        __syncthreads();
-        convolve<P>(buf, a.hh2, a.tw, tid);
-        // V(m') at buf[pad(q + T - 1)], q = m' + Lj - 1 < 2Lj - 1
-#pragma unroll
-        for (int s = 0; s < MAXH; ++s) {
-            const int q = tid + s * NT;
-            if (q < Nk) keep[c][s] = buf[pad(q + T - 1)];
-        }
+    }
+    if (ncol > 1) {
+        for (int q = tid; q < Nk; q += NT) buf[pad(q)] = q < Lj ? Po[q] : Qo[q - Lj];
         __syncthreads();
     }
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int s = 0; s < MAXH; ++s) {
-            const int q = tid + s * NT;
-            if (c < ncol && q < Nk) buf[pad(c * Nk + q)] = keep[c][s];
-        }
-    __syncthreads();
     const int eta = a.eta_imag ? 1 : 0;
-    double2 *__restrict__ Po = a.out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
-    double2 *__restrict__ Qo = a.out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
     for (int mp = tid; mp < Lj; mp += NT) {
-        double2 tp = buf[pad(mp + Lj - 1)], tm = ncol > 1 ? buf[pad(Nk + mp + Lj - 1)] : make_double2(0.0, 0.0);
+        double2 tp = buf[pad(mp + Lj - 1)], tm = ncol > 1 ? buf[pad(Nk + mp + Lj - 1)] : zero2();
         if (mp > 0) {
-            double2 up = buf[pad(-mp + Lj - 1)], um = ncol > 1 ? buf[pad(Nk - mp + Lj - 1)] : make_double2(0.0, 0.0);
+            double2 up = buf[pad(-mp + Lj - 1)], um = ncol > 1 ? buf[pad(Nk - mp + Lj - 1)] : zero2();
             if (odd) {
                 up = make_double2(-up.x, -up.y);
                 um = make_double2(-um.x, -um.y);
@@ -363,15 +354,15 @@ __global__ void __launch_bounds__(P / 16) beta_adj_fft_kernel(const StageArgs a)
 
 #define S2DW_P_SWITCH(P, KER, GRID, ARGS)                                                        \
     switch (P) {                                                                                 \
-        case 32: hipLaunchKernelGGL(KER<32>, GRID, dim3(2), 0, st, ARGS); break;                 \
-        case 64: hipLaunchKernelGGL(KER<64>, GRID, dim3(4), 0, st, ARGS); break;                 \
-        case 128: hipLaunchKernelGGL(KER<128>, GRID, dim3(8), 0, st, ARGS); break;               \
-        case 256: hipLaunchKernelGGL(KER<256>, GRID, dim3(16), 0, st, ARGS); break;              \
-        case 512: hipLaunchKernelGGL(KER<512>, GRID, dim3(32), 0, st, ARGS); break;              \
-        case 1024: hipLaunchKernelGGL(KER<1024>, GRID, dim3(64), 0, st, ARGS); break;            \
-        case 2048: hipLaunchKernelGGL(KER<2048>, GRID, dim3(128), 0, st, ARGS); break;           \
-        case 4096: hipLaunchKernelGGL(KER<4096>, GRID, dim3(256), 0, st, ARGS); break;           \
-        case 8192: hipLaunchKernelGGL(KER<8192>, GRID, dim3(512), 0, st, ARGS); break;           \
+        case 32: hipLaunchKernelGGL(KER<32>, GRID, dim3(32 / kRM), 0, st, ARGS); break;          \
+        case 64: hipLaunchKernelGGL(KER<64>, GRID, dim3(64 / kRM), 0, st, ARGS); break;          \
+        case 128: hipLaunchKernelGGL(KER<128>, GRID, dim3(128 / kRM), 0, st, ARGS); break;       \
+        case 256: hipLaunchKernelGGL(KER<256>, GRID, dim3(256 / kRM), 0, st, ARGS); break;       \
+        case 512: hipLaunchKernelGGL(KER<512>, GRID, dim3(512 / kRM), 0, st, ARGS); break;       \
+        case 1024: hipLaunchKernelGGL(KER<1024>, GRID, dim3(1024 / kRM), 0, st, ARGS); break;    \
+        case 2048: hipLaunchKernelGGL(KER<2048>, GRID, dim3(2048 / kRM), 0, st, ARGS); break;    \
+        case 4096: hipLaunchKernelGGL(KER<4096>, GRID, dim3(4096 / kRM), 0, st, ARGS); break;    \
+        case 8192: hipLaunchKernelGGL(KER<8192>, GRID, dim3(8192 / kRM), 0, st, ARGS); break;    \
         default: return hipErrorInvalidValue;                                                    \
     }
 
