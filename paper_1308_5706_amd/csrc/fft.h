@@ -159,8 +159,9 @@ __device__ __forceinline__ void pass(int Ns, int tid0, const double2 *__restrict
         for (int q = 0; q < PER; ++q) {
             const int j = tid + q * NT;
             const int st = (j & (Ns - 1)) * (P / (Ns * R));
-#pragma unroll
-            for (int r = 1; r < R; ++r) w[q][r] = tw[st * r];
+            // w^r for r < R from one table entry: w^2 = w w, w^4 = w^2 w^2, ... and the
+            // other powers as products of those (at most six products deep: a few ulp)
+            w[q][1] = tw[st];
         }
     }
 #pragma unroll
@@ -175,6 +176,11 @@ __device__ __forceinline__ void pass(int Ns, int tid0, const double2 *__restrict
         const int j = tid + q * NT;
         const int k = j & (Ns - 1);
         if (Ns > 1) {
+#pragma unroll
+            for (int r = 2; r < R; ++r) {
+                if ((r & (r - 1)) == 0) w[q][r] = cmul(w[q][r / 2], w[q][r / 2]);
+                else w[q][r] = cmul(w[q][r & (r - 1)], w[q][r & -r]);
+            }
 #pragma unroll
             for (int r = 1; r < R; ++r) v[q][r] = SIGN < 0 ? cmul(v[q][r], w[q][r]) : cmulc(v[q][r], w[q][r]);
         }

@@ -17,7 +17,7 @@
 #include "kernels.h"
 
 #ifndef S2DW_FFT_RADIX
-#define S2DW_FFT_RADIX 16
+#define S2DW_FFT_RADIX 8
 #endif
 
 namespace s2dw {
