@@ -32,7 +32,8 @@ struct Plan {
     ScaleTab sc{};
     int eoff = 0;
     // device tables
-    double2 *pq = nullptr, *uv = nullptr, *twa = nullptr, *csq = nullptr, *cpp = nullptr, *twg = nullptr;
+    double2 *pq = nullptr, *uv = nullptr, *twa = nullptr, *csq = nullptr, *cpp = nullptr;
+    double2 *tgf = nullptr, *tga = nullptr;     // gamma pass factors [2N-1][Nh]
     double *kb2 = nullptr, *seed = nullptr, *seedm = nullptr, *phi = nullptr, *fac = nullptr;
     int *seede = nullptr;
     int2 *tiles_fwd = nullptr, *tiles_adj = nullptr;
@@ -44,7 +45,8 @@ struct Plan {
     double2 *hD1 = nullptr;
     std::map<int, double2 *> twP;               // e^{-2 pi i k/P}
     // workspaces
-    double2 *fpad = nullptr, *U = nullptr, *Ub = nullptr, *Hg = nullptr, *Fpart = nullptr;
+    double2 *fpad = nullptr, *U = nullptr, *Ub = nullptr, *Y = nullptr, *Fpart = nullptr;
+    int Nh = 0;                                 // orders n >= 0 carried: ceil(N/2)
     int nblk = 0;
     std::vector<void *> allocs;
     size_t dev_bytes = 0;
@@ -318,7 +320,7 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
         }
     Plan &P = *pl;
     const int M = 2 * L - 1;
-    std::vector<double2> twa(M), csq(M), cpp(M), twg(2 * t.N - 1);
+    std::vector<double2> twa(M), csq(M), cpp(M);
     for (int k = 0; k < M; ++k) {
         long double a = 2.0L * 3.141592653589793238462643383279502884L * k / M;
         twa[k] = make_double2((double)cosl(a), (double)sinl(a));
@@ -331,10 +333,19 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
         csq[i] = make_double2((double)cosl(a2), (double)sinl(a2));
         cpp[i] = make_double2((double)cosl(ap), (double)sinl(ap));
     }
-    for (int k = 0; k < 2 * t.N - 1; ++k) {
-        long double a = 2.0L * 3.141592653589793238462643383279502884L * k / (2 * t.N - 1);
-        twg[k] = make_double2((double)cosl(a), (double)sinl(a));
-    }
+    // gamma pass factors for the orders n >= 0, n = 2 ni - (N - 1), ni = N/2 + k
+    const int Gn = 2 * t.N - 1;
+    P.Nh = t.N - t.N / 2;
+    std::vector<double2> tgf((size_t)Gn * P.Nh), tga((size_t)Gn * P.Nh);
+    for (int g = 0; g < Gn; ++g)
+        for (int k = 0; k < P.Nh; ++k) {
+            const long long n = 2LL * (t.N / 2 + k) - (t.N - 1);
+            const long long r = (n * g) % Gn;
+            const ld a = 2.0L * kPiL * (ld)r / (ld)Gn;
+            const ld f = n == 0 ? 1.0L : 2.0L;
+            tgf[(size_t)g * P.Nh + k] = make_double2((double)(f * cosl(a)), (double)(f * sinl(a)));
+            tga[(size_t)g * P.Nh + k] = make_double2((double)cosl(a), (double)-sinl(a));
+        }
     std::vector<double> fac(L);
     for (int l = 0; l < L; ++l)
         fac[l] = kind == kShtForward ? std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) / (2.0 * M_PI)
@@ -344,7 +355,7 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     memcpy(uvv.data(), dt.uv.data(), uvv.size() * sizeof(double2));
     bool ok = upload(P, P.pq, pqv) && upload(P, P.uv, uvv) && upload(P, P.kb2, kb2) && upload(P, P.seed, dt.seed) &&
               upload(P, P.seedm, dt.seedm) && upload(P, P.seede, dt.seede) && upload(P, P.twa, twa) &&
-              upload(P, P.csq, csq) && upload(P, P.cpp, cpp) && upload(P, P.twg, twg) && upload(P, P.fac, fac) &&
+              upload(P, P.csq, csq) && upload(P, P.cpp, cpp) && upload(P, P.tgf, tgf) && upload(P, P.tga, tga) && upload(P, P.fac, fac) &&
               upload(P, P.phi, t.phi);
     if (!ok) return S2DW_E_NOMEM;
     // tiles
@@ -417,7 +428,7 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     P.nblk = (L + P.group - 1) / P.group;
     const size_t G = 2 * t.N - 1;
     if (!dalloc(P, P.fpad, (size_t)L * Lp) || !dalloc(P, P.U, (size_t)std::max<int64_t>(off, 1)) ||
-        !dalloc(P, P.Ub, (size_t)t.N * L * std::max(maxLj, 1)) || !dalloc(P, P.Hg, G * L * std::max(maxLj, 1)) ||
+        !dalloc(P, P.Ub, (size_t)t.N * L * std::max(maxLj, 1)) || !dalloc(P, P.Y, (size_t)P.Nh * L * M) ||
         !dalloc(P, P.Fpart, (size_t)P.nblk * L * Lp))
         return S2DW_E_NOMEM;
     out = pl.release();
@@ -511,26 +522,32 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
         b.L = L;
         b.Lj = Lj;
         b.N = N;
-        b.G = G;
+        b.Nh = P.Nh;
         {
             Stage sg("beta_fwd", st);
             S2DW_CHECK_HIP(launch_beta_fwd_fft(b, P.PA[j], st));
         }
-        GammaArgs g{P.Ub, P.Hg, P.twg, L, Lj, N, 0, 1.0};
-        {
-            Stage sg("gamma_fwd", st);
-            S2DW_CHECK_HIP(launch_gamma_fwd(g, st));
-        }
         StageArgs c = b;
-        c.in = P.Hg;
-        c.out = nullptr;
-        c.wout = Wj;
-        c.f32 = f32;
+        c.in = P.Ub;
+        c.out = P.Y;
         c.hh = P.hB[j];
         c.tw = P.twP[P.PB[j]];
         {
             Stage sg("alpha_fwd", st);
             S2DW_CHECK_HIP(launch_alpha_fwd_fft(c, P.PB[j], st));
+        }
+        GammaArgs g{};
+        g.wout = Wj;
+        g.in = P.Y;
+        g.tg = P.tgf;
+        g.L = L;
+        g.T = 2 * L - 1;
+        g.G = G;
+        g.Nh = P.Nh;
+        g.f32 = f32;
+        {
+            Stage sg("gamma_fwd", st);
+            S2DW_CHECK_HIP(launch_gamma_fwd(g, st));
         }
     }
     return S2DW_OK;
@@ -545,9 +562,22 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
         if (Lj == 0) continue;
         const void *Wj = f32 ? (const void *)((const float *)W + per_scale * j)
                              : (const void *)((const double *)W + per_scale * j);
+        GammaArgs g{};
+        g.win = Wj;
+        g.out = P.Y;
+        g.tg = P.tga;
+        g.L = L;
+        g.T = M;
+        g.G = G;
+        g.Nh = P.Nh;
+        g.f32 = f32;
+        {
+            Stage sg("gamma_adj", st);
+            S2DW_CHECK_HIP(launch_gamma_adj(g, st));
+        }
         StageArgs c{};
-        c.win = Wj;
-        c.out = P.Hg;
+        c.in = P.Y;
+        c.out = P.Ub;
         c.hh = P.hC[j];
         c.tw = P.twP[P.PB[j]];
         c.csq = P.csq;
@@ -555,23 +585,16 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
         c.L = L;
         c.Lj = Lj;
         c.N = N;
-        c.G = G;
+        c.Nh = P.Nh;
         c.K = P.K;
-        c.f32 = f32;
-        c.scale = 2.0 * M_PI / M;
+        c.scale = (2.0 * M_PI / M) * (2.0 * M_PI / G);
         {
             Stage sg("alpha_adj", st);
             S2DW_CHECK_HIP(launch_alpha_adj_fft(c, P.PB[j], st));
         }
-        GammaArgs g{P.Hg, P.Ub, P.twg, L, Lj, N, 0, 2.0 * M_PI / G};
-        {
-            Stage sg("gamma_adj", st);
-            S2DW_CHECK_HIP(launch_gamma_adj(g, st));
-        }
         StageArgs v = c;
         v.in = P.Ub;
         v.out = P.U + P.sc.off[j];
-        v.win = nullptr;
         v.hh = P.hD1;
         v.hh2 = P.hD2[j];
         v.tw = P.twP[P.PD];

@@ -45,21 +45,21 @@ hipError_t launch_wig_fwd(const WigFwdArgs &a, int K, int ntiles, bool xn, hipSt
 hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int ntiles, bool xn, hipStream_t st);
 
 // ---------------------------------------------------------------- beta / alpha / gamma stages
-// Bluestein stages (stages.hip).  Layouts per scale j (Lj = band-limit of the scale):
+// Bluestein stages (stages.hip).  Layouts per scale j (Lj = band-limit of the scale,
+// T = 2L - 1, Nh = ceil(N/2) orders n >= 0):
 //   analysis:  U [N][Lj][Lj] = [n][m][m'] -> Ub [N][Lj][L] = [n][m][b]
-//              -> Hg [2N-1][L][Lj] = [g][b][m] -> W [2N-1][L][2L-1]
-//   synthesis: W -> Wh [2N-1][L][Lj] -> G [N][Lj][L] = [n][m][b] -> V [K][2][Lj][Lj] = [k][P|Q][m][m']
+//              -> Y [Nh][L][T] (alpha sums, n >= 0) -> W [2N-1][L][T] (gamma pass)
+//   synthesis: W -> X [Nh][L][T] (gamma pass) -> G [N][Lj][L] = [n][m][b] (alpha sums)
+//              -> V [K][2][Lj][Lj] = [k][P|Q][m][m']
 struct StageArgs {
     const double2 *in;
     double2 *out;
-    const void *win;       // wavelet coefficients read (synthesis alpha stage)
-    void *wout;            // wavelet coefficients written (analysis alpha stage)
     const double2 *hh;     // FFT of the stage's chirp (or kernel) sequence, divided by P
     const double2 *hh2;    // FFT of the w(q) sequence (synthesis beta stage), divided by P
     const double2 *tw;     // e^{-2 pi i k/P}, k < P
     const double2 *csq;    // e^{i pi i^2/T}, i < T, T = 2L - 1
     const double2 *cpp;    // e^{i pi p(p+1)/T} at p + L - 1, |p| < L
-    int L, Lj, N, G, K, f32, eta_imag;
+    int L, Lj, N, Nh, K, eta_imag;
     int nk[kMaxK];
     double scale;
 };
@@ -69,11 +69,12 @@ hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, hipStream_t st);
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, hipStream_t st);
 
 struct GammaArgs {
-    const double2 *in;
-    double2 *out;
-    const double2 *twg;    // e^{2 pi i k/(2N-1)}
-    int L, Lj, N, gbase;
-    double scale;
+    const void *win;       // W read (synthesis), float64 or float32
+    void *wout;            // W written (analysis)
+    const double2 *in;     // Y (analysis)
+    double2 *out;          // X (synthesis)
+    const double2 *tg;     // [2N-1][Nh]: (1 or 2) e^{i n gamma_g} (analysis), e^{-i n gamma_g} (synthesis)
+    int L, T, G, Nh, f32;
 };
 hipError_t launch_gamma_fwd(const GammaArgs &a, hipStream_t st);
 hipError_t launch_gamma_adj(const GammaArgs &a, hipStream_t st);

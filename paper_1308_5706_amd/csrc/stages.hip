@@ -81,179 +81,138 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const 
     fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
 }
 
-// ------------------------------------------------------ analysis: alpha (Eq. 30), two gamma rows
-// W(a) = sum_{|m|<Lj} H_m e^{2 pi i m a/T} with H_{-m} = conj(H_m) (real W); the rows g1 and g2
-// are packed as H1 + i H2, whose transform is W1 + i W2.
+// ------------------------------------------------------------------ alpha and gamma stages
+// Only the orders n with N + n odd are present, and W is real, so the coefficients obey
+// C_{-n}(-m) = conj(C_n(m)).  The alpha sums therefore run over the rows n >= 0 only
+// (Nh = ceil(N/2) complex rows per beta ring instead of 2N - 1 real ones), and the gamma
+// sums are separate streaming passes over the sample grid:
+//   analysis:  Y_n(b, a) = sum_{|m|<Lj} C_n(b, m) e^{i m alpha_a}   (Eq. 30, n >= 0)
+//              W(g, b, a) = Re Y_0 + 2 Re sum_{n>0} Y_n e^{i n gamma_g}   (Eq. 28)
+//   synthesis: X_n(b, a) = sum_g W(g, b, a) e^{-i n gamma_g}   (Eq. 39, n >= 0)
+//              Gs_n(b, m) = wa wg sum_a X_n(b, a) e^{-i m alpha_a},  Gs_{-n}(b, m) = conj Gs_n(b, -m)
+// with C_n(b, m) = Ub[n][m][b] for m >= 0 and conj(Ub[-n][-m][b]) for m < 0.
+//
+// Column order: blockIdx.x -> t = (b, n') is remapped so that the workgroups that run on
+// one XCD (dispatched round-robin over the 8 XCDs) take consecutive t; the [n][m][b]
+// arrays, read and written with stride L along m, then share L2 lines across neighbouring
+// rings b.
+__device__ __forceinline__ int xcd_column(int x, int ncols) {
+    const int per = (ncols + 7) >> 3;
+    return (x & 7) * per + (x >> 3);
+}
+
 template <int P>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const StageArgs a) {
     __shared__ double2 buf[fft::padded(P)];
     const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, G = a.G;
-    const int ngp = (G + 1) / 2;
-    const int b = blockIdx.x / ngp, gp = blockIdx.x - (blockIdx.x / ngp) * ngp;
-    const int g1 = 2 * gp, g2 = 2 * gp + 1;
-    const bool two = g2 < G;
-    const double2 *__restrict__ H1 = a.in + ((size_t)g1 * L + b) * Lj;
-    const double2 *__restrict__ H2 = a.in + ((size_t)(two ? g2 : g1) * L + b) * Lj;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh;
+    const int t = xcd_column(blockIdx.x, Nh * L);
+    if (t >= Nh * L) return;
+    const int b = t / Nh, np = t - (t / Nh) * Nh;
+    const int ni = (N / 2) + np, nj = N - 1 - ni;  // rows of n >= 0 and of -n
+    const bool zero_n = ni == nj;
+    const double2 *__restrict__ Up = a.in + (size_t)ni * Lj * L + b;
+    const double2 *__restrict__ Um = a.in + (size_t)nj * Lj * L + b;
     const double2 *__restrict__ csq = a.csq;
     const int Na = 2 * Lj - 1;
     auto in = [&](int i) {
         if (i >= Na) return zero2();
         const int m = i - (Lj - 1);
-        const int am = m < 0 ? -m : m;
-        double2 h1 = H1[am], h2 = two ? H2[am] : zero2();
-        if (m == 0) {
-            h1.y = 0.0;
-            h2.y = 0.0;
-        } else if (m < 0) {
-            h1.y = -h1.y;
-            h2.y = -h2.y;
+        double2 c;
+        if (m >= 0) {
+            c = Up[(size_t)m * L];
+            if (m == 0 && zero_n) c.y = 0.0;
+        } else {
+            c = cconj(Um[(size_t)(-m) * L]);
         }
-        return cmul(make_double2(h1.x - h2.y, h1.y + h2.x), csq[am]);
+        return cmul(c, csq[m < 0 ? -m : m]);
     };
-    const size_t o1 = ((size_t)g1 * L + b) * T, o2 = ((size_t)g2 * L + b) * T;
-    if (a.f32) {
-        float *Wf = (float *)a.wout;
-        auto st = [&](int i, double2 v) {
-            const int x = i - (Na - 1);
-            if (x >= 0 && x < T) {
-                const double2 c = cmul(v, csq[x]);
-                Wf[o1 + x] = (float)c.x;
-                if (two) Wf[o2 + x] = (float)c.y;
-            }
-        };
-        fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
-    } else {
-        double *W = (double *)a.wout;
-        auto st = [&](int i, double2 v) {
-            const int x = i - (Na - 1);
-            if (x >= 0 && x < T) {
-                const double2 c = cmul(v, csq[x]);
-                W[o1 + x] = c.x;
-                if (two) W[o2 + x] = c.y;
-            }
-        };
-        fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
-    }
-}
-
-// ----------------------------------------------------- synthesis: alpha (Eq. 37), two gamma rows
-// Zh(m) = sum_a (W1 + i W2)(a) e^{-2 pi i m a/T} for |m| < Lj; then
-// W1h(m) = (Zh(m) + conj Zh(-m))/2, W2h(m) = (Zh(m) - conj Zh(-m))/(2i), times 2 pi/T.
-template <int P, bool F32>
-__device__ __forceinline__ void alpha_adj_body(const StageArgs &a, double2 *buf) {
-    const int tid = threadIdx.x;
-    constexpr int NT = P / kRM;
-    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, G = a.G;
-    const int ngp = (G + 1) / 2;
-    const int b = blockIdx.x / ngp, gp = blockIdx.x - (blockIdx.x / ngp) * ngp;
-    const int g1 = 2 * gp, g2 = 2 * gp + 1;
-    const bool two = g2 < G;
-    using WT = typename std::conditional<F32, float, double>::type;
-    const WT *__restrict__ W1 = (const WT *)a.win + ((size_t)g1 * L + b) * T;
-    const WT *__restrict__ W2 = (const WT *)a.win + ((size_t)(two ? g2 : g1) * L + b) * T;
-    const double2 *__restrict__ csq = a.csq;
-    auto in = [&](int i) {
-        if (i >= T) return zero2();
-        const double w1 = (double)W1[i];
-        const double w2 = two ? (double)W2[i] : 0.0;
-        return cmulc(make_double2(w1, w2), csq[i]);
-    };
-    // Zh(m) for m = q - (Lj-1), q < 2Lj-1, comes out at q + T - 1; it is stored at slot q
-    const int Nk = 2 * Lj - 1;
+    double2 *__restrict__ Y = a.out + ((size_t)np * L + b) * T;
     auto st = [&](int i, double2 v) {
-        const int q = i - (T - 1);
-        if (q >= 0 && q < Nk) {
-            const int m = q - (Lj - 1);
-            buf[pad(q)] = cmulc(v, csq[m < 0 ? -m : m]);
-        }
+        const int x = i - (Na - 1);
+        if (x >= 0 && x < T) Y[x] = cmul(v, csq[x]);
     };
     fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
-    const double wa = 0.5 * a.scale;
-    double2 *__restrict__ out1 = a.out + ((size_t)g1 * L + b) * Lj;
-    double2 *__restrict__ out2 = a.out + ((size_t)g2 * L + b) * Lj;
-    for (int m = tid; m < Lj; m += NT) {
-        const double2 zp = buf[pad(m + Lj - 1)], zm = buf[pad(-m + Lj - 1)];
-        out1[m] = make_double2(wa * (zp.x + zm.x), wa * (zp.y - zm.y));
-        if (two) out2[m] = make_double2(wa * (zp.y + zm.y), -wa * (zp.x - zm.x));
-    }
 }
 
 template <int P>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const StageArgs a) {
     __shared__ double2 buf[fft::padded(P)];
-    if (a.f32) alpha_adj_body<P, true>(a, buf);
-    else alpha_adj_body<P, false>(a, buf);
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh;
+    const int t = xcd_column(blockIdx.x, Nh * L);
+    if (t >= Nh * L) return;
+    const int b = t / Nh, np = t - (t / Nh) * Nh;
+    const int ni = (N / 2) + np, nj = N - 1 - ni;
+    const bool zero_n = ni == nj;
+    const double2 *__restrict__ X = a.in + ((size_t)np * L + b) * T;
+    const double2 *__restrict__ csq = a.csq;
+    auto in = [&](int i) { return i < T ? cmulc(X[i], csq[i]) : zero2(); };
+    // Zh(m), q = m + Lj - 1 < 2Lj - 1, comes out at q + T - 1
+    const int Nk = 2 * Lj - 1;
+    const double s = a.scale;
+    double2 *__restrict__ Gp = a.out + (size_t)ni * Lj * L + b;
+    double2 *__restrict__ Gm = a.out + (size_t)nj * Lj * L + b;
+    auto st = [&](int i, double2 v) {
+        const int q = i - (T - 1);
+        if (q >= 0 && q < Nk) {
+            const int m = q - (Lj - 1);
+            const double2 z = cscale(cmulc(v, csq[m < 0 ? -m : m]), s);
+            if (m >= 0) Gp[(size_t)m * L] = z;
+            if (m <= 0 && !zero_n) Gm[(size_t)(-m) * L] = cconj(z);
+        }
+    };
+    fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
 }
 
-// -------------------------------------------- gamma sums fused with the (m, b) <-> (b, m) transposes
-// Analysis (Eq. 28): Hg[g][b][m] = sum_n Ub[n][m][b] e^{i n gamma_g}, g in [gbase, gbase + 16).
-__global__ void __launch_bounds__(1024) gamma_fwd_kernel(const GammaArgs a) {
-    __shared__ double2 tile[32][33];
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int b0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
-    const int L = a.L, Lj = a.Lj, N = a.N, G = 2 * N - 1;
-    double2 acc[16];
+// Analysis gamma pass: W[g][b][a] = sum_{n'} Re(Y[n'][b][a] tg[g][n']), tg = (1 or 2) e^{i n gamma_g}.
+template <typename WT>
+__global__ void __launch_bounds__(256) gamma_fwd_kernel(const GammaArgs a) {
+    const size_t plane = (size_t)a.L * a.T;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= plane) return;
+    double2 y[kMaxK];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = make_double2(0.0, 0.0);
-    for (int ni = 0; ni < N; ++ni) {
-        const int mm = m0 + ty, bb = b0 + tx;
-        tile[ty][tx] = (mm < Lj && bb < L) ? a.in[((size_t)ni * Lj + mm) * L + bb] : make_double2(0.0, 0.0);
-        __syncthreads();
-        const double2 w = tile[tx][ty];  // element (m0 + tx, b0 + ty)
-        const int n = 2 * ni - (N - 1);
+    for (int k = 0; k < kMaxK; ++k)
+        if (k < a.Nh) y[k] = a.in[k * plane + e];
+    WT *__restrict__ W = (WT *)a.wout;
+    for (int g = 0; g < a.G; ++g) {
+        double acc = 0.0;
 #pragma unroll
-        for (int gg = 0; gg < 16; ++gg) {
-            const int g = a.gbase + gg;
-            if (g < G) {
-                int k = (n * g) % G;
-                if (k < 0) k += G;
-                acc[gg] = cadd(acc[gg], cmul(w, a.twg[k]));
+        for (int k = 0; k < kMaxK; ++k) {
+            if (k < a.Nh) {
+                const double2 w = a.tg[g * a.Nh + k];
+                acc = fma(y[k].x, w.x, fma(-y[k].y, w.y, acc));
             }
         }
-        __syncthreads();
-    }
-    const int bb = b0 + ty, mm = m0 + tx;
-    if (bb < L && mm < Lj) {
-#pragma unroll
-        for (int gg = 0; gg < 16; ++gg) {
-            const int g = a.gbase + gg;
-            if (g < G) a.out[((size_t)g * L + bb) * Lj + mm] = acc[gg];
-        }
+        W[g * plane + e] = (WT)acc;
     }
 }
 
-// Synthesis (Eq. 39 with the uniform rule): Gout[n][m][b] = wg sum_g Wh[g][b][m] e^{-i n gamma_g}.
-__global__ void __launch_bounds__(1024) gamma_adj_kernel(const GammaArgs a) {
-    __shared__ double2 tile[32][33];
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int b0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
-    const int L = a.L, Lj = a.Lj, N = a.N, G = 2 * N - 1;
-    double2 acc[16];
+// Synthesis gamma pass: X[n'][b][a] = sum_g W[g][b][a] tg[g][n'], tg = e^{-i n gamma_g}.
+template <typename WT>
+__global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
+    const size_t plane = (size_t)a.L * a.T;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= plane) return;
+    const WT *__restrict__ W = (const WT *)a.win;
+    double2 x[kMaxK];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = make_double2(0.0, 0.0);
-    for (int g = 0; g < G; ++g) {
-        const int bb = b0 + ty, mm = m0 + tx;
-        tile[ty][tx] = (bb < L && mm < Lj) ? a.in[((size_t)g * L + bb) * Lj + mm] : make_double2(0.0, 0.0);
-        __syncthreads();
-        const double2 w = tile[tx][ty];  // element (b0 + tx, m0 + ty)
+    for (int k = 0; k < kMaxK; ++k) x[k] = zero2();
+    for (int g = 0; g < a.G; ++g) {
+        const double w = (double)W[g * plane + e];
 #pragma unroll
-        for (int ni = 0; ni < 16; ++ni) {
-            if (ni < N) {
-                const int n = 2 * ni - (N - 1);
-                int k = (n * g) % G;
-                if (k < 0) k += G;
-                acc[ni] = cadd(acc[ni], cmulc(w, a.twg[k]));
+        for (int k = 0; k < kMaxK; ++k) {
+            if (k < a.Nh) {
+                const double2 t = a.tg[g * a.Nh + k];
+                x[k].x = fma(w, t.x, x[k].x);
+                x[k].y = fma(w, t.y, x[k].y);
             }
         }
-        __syncthreads();
     }
-    const int mm = m0 + ty, bb = b0 + tx;
-    if (bb < L && mm < Lj) {
 #pragma unroll
-        for (int ni = 0; ni < 16; ++ni)
-            if (ni < N) a.out[((size_t)ni * Lj + mm) * L + bb] = cscale(acc[ni], a.scale);
-    }
+    for (int k = 0; k < kMaxK; ++k)
+        if (k < a.Nh) a.out[k * plane + e] = x[k];
 }
 
 // ------------------------------------------ synthesis: beta integral and m' folding (Eq. 35, 40)
@@ -372,12 +331,12 @@ hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, hipStream_t st) {
 }
 
 hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, hipStream_t st) {
-    S2DW_P_SWITCH(P, alpha_fwd_fft_kernel, dim3(a.L * ((a.G + 1) / 2)), a)
+    S2DW_P_SWITCH(P, alpha_fwd_fft_kernel, dim3(8 * ((a.Nh * a.L + 7) / 8)), a)
     return hipGetLastError();
 }
 
 hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, hipStream_t st) {
-    S2DW_P_SWITCH(P, alpha_adj_fft_kernel, dim3(a.L * ((a.G + 1) / 2)), a)
+    S2DW_P_SWITCH(P, alpha_adj_fft_kernel, dim3(8 * ((a.Nh * a.L + 7) / 8)), a)
     return hipGetLastError();
 }
 
@@ -386,20 +345,19 @@ hipError_t launch_beta_adj_fft(const StageArgs &a, int P, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_gamma_fwd(const GammaArgs &a0, hipStream_t st) {
-    dim3 grid((a0.L + 31) / 32, (a0.Lj + 31) / 32);
-    const int G = 2 * a0.N - 1;
-    for (int gb = 0; gb < G; gb += 16) {
-        GammaArgs a = a0;
-        a.gbase = gb;
-        hipLaunchKernelGGL(gamma_fwd_kernel, grid, dim3(1024), 0, st, a);
-    }
+hipError_t launch_gamma_fwd(const GammaArgs &a, hipStream_t st) {
+    const size_t plane = (size_t)a.L * a.T;
+    const dim3 grid((unsigned)((plane + 255) / 256));
+    if (a.f32) hipLaunchKernelGGL(gamma_fwd_kernel<float>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(gamma_fwd_kernel<double>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_gamma_adj(const GammaArgs &a, hipStream_t st) {
-    dim3 grid((a.L + 31) / 32, (a.Lj + 31) / 32);
-    hipLaunchKernelGGL(gamma_adj_kernel, grid, dim3(1024), 0, st, a);
+    const size_t plane = (size_t)a.L * a.T;
+    const dim3 grid((unsigned)((plane + 255) / 256));
+    if (a.f32) hipLaunchKernelGGL(gamma_adj_kernel<float>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(gamma_adj_kernel<double>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
