@@ -499,9 +499,8 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
     {
         Stage sg("wigner_fwd", st);
         a.tiles = P.tiles_fwd;
-        S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.nfwd_plain, false, st));
-        a.tiles = P.tiles_fwd + P.nfwd_plain;
-        S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.nfwd_x, true, st));
+        a.nplain = P.nfwd_plain;
+        S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.nfwd_plain + P.nfwd_x, st));
     }
     const int N = P.ht.N, G = 2 * N - 1;
     const size_t per_scale = (size_t)G * L * (2 * L - 1);
@@ -622,9 +621,8 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
     {
         Stage sg("wigner_adj", st);
         a.tiles = P.tiles_adj;
-        S2DW_CHECK_HIP(launch_wig_adj(a, P.K, P.nadj_plain, false, st));
-        a.tiles = P.tiles_adj + P.nadj_plain;
-        S2DW_CHECK_HIP(launch_wig_adj(a, P.K, P.nadj_x, true, st));
+        a.nplain = P.nadj_plain;
+        S2DW_CHECK_HIP(launch_wig_adj(a, P.K, P.nadj_plain + P.nadj_x, st));
     }
     {
         Stage sg("syn_final", st);

@@ -18,6 +18,7 @@ struct WigFwdArgs {
     const double *seedm;   // [Lp][Lp]  its mantissa (extended-exponent variant)
     const int *seede;      // [Lp][Lp]  its exponent
     const int2 *tiles;     // (m0, m'0) per workgroup
+    int nplain;            // workgroups [0, nplain) take plain tiles, the rest extended-exponent ones
     double2 *U;            // workspace; scale j at sc.off[j]: [N][Lj][Lj] = [n][m][m']
     int L, Lp, N, eoff;    // eoff = 3 when eta_N = i (conj(eta) = i^3), else 0
     int nk[kMaxK];
@@ -33,6 +34,7 @@ struct WigAdjArgs {
     const double *seedm;
     const int *seede;
     const int2 *tiles;
+    int nplain;
     const double2 *V;      // scale j at sc.off[j]: [K][2][Lj][Lj] = [k][P|Q][m][m']
     double2 *Fpart;        // [L / group][L][Lp] partial sums over each m' group
     int L, Lp, group;
@@ -41,8 +43,8 @@ struct WigAdjArgs {
 };
 
 int wig_slots(int K);
-hipError_t launch_wig_fwd(const WigFwdArgs &a, int K, int ntiles, bool xn, hipStream_t st);
-hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int ntiles, bool xn, hipStream_t st);
+hipError_t launch_wig_fwd(const WigFwdArgs &a, int K, int ntiles, hipStream_t st);
+hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int ntiles, hipStream_t st);
 
 // ---------------------------------------------------------------- beta / alpha / gamma stages
 // Bluestein stages (stages.hip).  Layouts per scale j (Lj = band-limit of the scale,
