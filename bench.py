@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 
 
@@ -79,6 +79,59 @@ def cpu_baseline(L, N, lam, J_min, budget_rows=None, budget_cols=None):
             "sample": (f"analysis of {budget_rows}/{L} beta rows; synthesis alpha/gamma rules on {budget_rows}/{L} "
                        f"rows and beta/Wigner step on {budget_cols}/{2 * L - 1} m columns; each scaled linearly "
                        f"to the full map (estimated round trip {total:.1f} s)")}
+
+
+def stage_units(kappa, L, N, T):
+    """Algorithmic work of one launch of each stage, averaged over the launches of a step.
+
+    Wigner stages (one launch per direction): 5 FLOP per term of the l-sum / m'-contraction
+    over the m >= 0, m' >= 0 quarter (1 multiply for Delta Delta, 2 FMA for the complex
+    product).  Bluestein and gamma stages (one launch per scale j): bytes of the arrays the
+    stage must read and write, T = 2L - 1, G = 2N - 1, Nh = ceil(N/2), Lj = band-limit:
+      beta_fwd  U quarter 16 N Lj^2 in,      Ub 16 N Lj L out
+      alpha_fwd Ub 16 N Lj L in,             Y 16 Nh L T out
+      gamma_fwd Y 16 Nh L T in,              W 8 G L T out
+      gamma_adj W 8 G L T in,                X 16 Nh L T out
+      alpha_adj X 16 Nh L T in,              G 16 N Lj L out
+      beta_adj  G 16 N Lj L in,              V 32 Nh Lj^2 out
+    """
+    S = kappa.shape[0]
+    Tg, G, Nh = 2 * L - 1, 2 * N - 1, N - N // 2
+    Ljs = []
+    for j in range(S):
+        nz = [l for l in range(L) if kappa[j, l] > 0.0]
+        if nz:
+            Ljs.append(max(nz) + 1)
+    per = {
+        "beta_fwd": [16 * N * Lj * Lj + 16 * N * Lj * L for Lj in Ljs],
+        "alpha_fwd": [16 * N * Lj * L + 16 * Nh * L * Tg for Lj in Ljs],
+        "gamma_fwd": [16 * Nh * L * Tg + 8 * G * L * Tg for Lj in Ljs],
+        "gamma_adj": [8 * G * L * Tg + 16 * Nh * L * Tg for Lj in Ljs],
+        "alpha_adj": [16 * Nh * L * Tg + 16 * N * Lj * L for Lj in Ljs],
+        "beta_adj": [16 * N * Lj * L + 32 * Nh * Lj * Lj for Lj in Ljs],
+    }
+    units = {k: ("hbm", sum(v) / len(v)) for k, v in per.items() if v}
+    units["wigner_fwd"] = ("alu", 5.0 * T)
+    units["wigner_adj"] = ("alu", 5.0 * T)
+    return units
+
+
+def roofline(stage, ps, units):
+    kind, per_launch = units.get(stage, ("hbm", 0.0))
+    sec = ps["ms_per_launch"] * 1e-3
+    if kind == "alu":
+        achieved = per_launch / sec / 1e12
+        r = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        achieved = per_launch / sec / 1e9
+        r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = None
+    r["kernel"] = stage
+    r["algorithmic_per_launch"] = per_launch
+    r["launch_ms"] = ps["ms_per_launch"]
+    r["launches_per_step"] = ps["launches_per_step"]
+    return r
 
 
 def main():
@@ -150,27 +203,27 @@ def main():
     coeffs = S * (2 * N - 1) * L * (2 * L - 1)
     value = coeffs / (ms_step * 1e-3)
 
-    # roofline of the kernel with the largest total device time
+    # roofline of the kernel with the largest device time per step (one stage = one kernel
+    # launch per scale, or per direction for the Wigner stages), timed with HIP events
     kappa, _, _ = s2dw.wavelet_tables(L, N, lam, J_min)
     T = wigner_terms(kappa, N)
-    w_bytes = 8.0 * coeffs
     per_stage = {k: {"ms_per_launch": v[0] / v[1], "launches_per_step": v[1] / args.steps,
                      "ms_per_step": v[0] / args.steps} for k, v in stages.items()}
+    units = stage_units(kappa, L, N, T)
     dom = max(per_stage, key=lambda k: per_stage[k]["ms_per_step"])
-    if dom in ("wigner_fwd", "wigner_adj"):
-        # 5 FLOP per term (1 mul + 2 FMA on the complex coefficient), per direction
-        achieved = 5.0 * T / (per_stage[dom]["ms_per_step"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
-    else:
-        # W is written (alpha_fwd) or read (alpha_adj) once per direction; other stages: W-sized
-        achieved = w_bytes / (per_stage[dom]["ms_per_step"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel"] = dom
-    roof["ms_per_step"] = per_stage[dom]["ms_per_step"]
+    roof = roofline(dom, per_stage[dom], units)
+    traffic = None
+    try:
+        from paper_1308_5706_amd import profiling
+        st = profiling.read_stage_traffic(f"round_trip_L{L}_N{N}")
+        if st and dom in st:
+            traffic = st[dom]["bytes_per_dispatch"]
+    except Exception as e:  # a missing or unreadable summary leaves traffic unknown
+        print(f"# traffic summary not used: {e}", file=sys.stderr)
+    roof["traffic"] = traffic
+    stage_roofs = {k: roofline(k, v, units) for k, v in per_stage.items() if k in units}
 
-    out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8",
+    out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8; p50/p99 mixed-L",
            "value": value, "unit": "SO(3) coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
@@ -180,6 +233,7 @@ def main():
                       "round_trip_rel_err": rt_err},
            "roofline": roof,
            "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in per_stage.items()},
+           "stages_frac": {k: round(v["frac"], 4) for k, v in stage_roofs.items()},
            "wigner_terms_per_direction": T}
     if not args.no_cpu_baseline:
         print("# cpu baseline sample", file=sys.stderr, flush=True)

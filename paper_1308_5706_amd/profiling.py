@@ -1,0 +1,180 @@
+"""Summaries of rocprofv3 runs of ``bench.py`` (kernel trace and HBM counters).
+
+Usage (after the rocprofv3 runs listed in the summary header have written their
+databases under one directory)::
+
+    python -m paper_1308_5706_amd.profiling DIR NAME "COMMANDS"
+
+writes ``profiles/NAME_kernels.md`` (per-kernel device time from the trace) and
+``profiles/NAME_hbm_traffic.txt`` (JSON: HBM bytes per dispatch from FETCH_SIZE and
+WRITE_SIZE, each scaled by what the same counter reads for a plain device copy of known
+size, grouped by the library's stage names, with a hash of the kernel sources so that a
+reader can tell whether the kernels changed since the counters were taken).
+
+Expected layout of DIR: ``trace/``, ``fetch/``, ``write/``, ``cfetch/``, ``cwrite/``, each
+holding one ``*_results.db`` (rocpd SQLite) from, in order: ``--kernel-trace --stats`` on
+the bench, ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` on the bench, and the two
+counters on ``bench.py --copy-calibration GIB``.
+"""
+from __future__ import annotations
+
+import glob
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+# library stage name -> substring of the kernel symbol (demangled) that implements it
+STAGE_KERNELS = {
+    "wigner_fwd": "wig_fwd_kernel",
+    "wigner_adj": "wig_adj_kernel",
+    "beta_fwd": "beta_fwd_fft_kernel",
+    "alpha_fwd": "alpha_fwd_fft_kernel",
+    "gamma_fwd": "gamma_fwd_kernel",
+    "gamma_adj": "gamma_adj_kernel",
+    "alpha_adj": "alpha_adj_fft_kernel",
+    "beta_adj": "beta_adj_fft_kernel",
+    "syn_final": "syn_final_kernel",
+    "pad": "pad_flm_kernel",
+    "scaling": "scaling_kernel",
+}
+
+
+def kernel_sources_hash() -> str:
+    """sha256 over the HIP/C++ sources of the library (sorted by name)."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if p.endswith((".hip", ".h", ".cpp")):
+            h.update(os.path.basename(p).encode())
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def stage_of(kernel_name: str):
+    for st, sub in STAGE_KERNELS.items():
+        if sub in kernel_name:
+            return st
+    return None
+
+
+def _db(d: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *_results.db under {d}")
+    return hits[-1]
+
+
+def _q(path: str, sql: str):
+    con = sqlite3.connect(path)
+    try:
+        return list(con.execute(sql))
+    finally:
+        con.close()
+
+
+def counter_per_dispatch(d: str, counter: str):
+    """{kernel name: [counter value per dispatch]} (values in the counter's unit, KiB)."""
+    rows = _q(_db(d), "select kernel_name, counter_name, value from counters_collection")
+    out = defaultdict(list)
+    for k, c, v in rows:
+        if c == counter:
+            out[k].append(float(v))
+    return out
+
+
+def calibration(d: str, counter: str, copy_bytes: int) -> float:
+    """Bytes per counter unit, from a plain device copy of copy_bytes."""
+    per = counter_per_dispatch(d, counter)
+    vals = [v for k, vs in per.items() if "copyBuffer" in k for v in vs]
+    if not vals:
+        raise RuntimeError(f"no copy kernel dispatch with {counter} in {d}")
+    return copy_bytes / (sum(vals) / len(vals))
+
+
+def summarize(d: str, copy_bytes: int):
+    trace = _q(_db(os.path.join(d, "trace")),
+               "select name, count(*), sum(end - start), avg(end - start) from kernels group by name")
+    cal = {c: calibration(os.path.join(d, sub), c, copy_bytes)
+           for c, sub in (("FETCH_SIZE", "cfetch"), ("WRITE_SIZE", "cwrite"))}
+    fetch = counter_per_dispatch(os.path.join(d, "fetch"), "FETCH_SIZE")
+    write = counter_per_dispatch(os.path.join(d, "write"), "WRITE_SIZE")
+    kernels = {}
+    for name, n, tot, avg in trace:
+        kernels[name] = {"dispatches": int(n), "total_ns": float(tot), "avg_ns": float(avg)}
+    traffic = {}
+    for name in set(fetch) | set(write):
+        f, w = fetch.get(name, []), write.get(name, [])
+        traffic[name] = {
+            "dispatches": max(len(f), len(w)),
+            "fetch_bytes_per_dispatch": (sum(f) / len(f)) * cal["FETCH_SIZE"] if f else None,
+            "write_bytes_per_dispatch": (sum(w) / len(w)) * cal["WRITE_SIZE"] if w else None,
+        }
+    stages = defaultdict(lambda: {"fetch_bytes": 0.0, "write_bytes": 0.0, "dispatches": 0})
+    for name, t in traffic.items():
+        st = stage_of(name)
+        if st is None or t["fetch_bytes_per_dispatch"] is None or t["write_bytes_per_dispatch"] is None:
+            continue
+        stages[st]["fetch_bytes"] += t["fetch_bytes_per_dispatch"] * t["dispatches"]
+        stages[st]["write_bytes"] += t["write_bytes_per_dispatch"] * t["dispatches"]
+        stages[st]["dispatches"] += t["dispatches"]
+    for st, v in stages.items():
+        v["bytes_per_dispatch"] = (v["fetch_bytes"] + v["write_bytes"]) / max(v["dispatches"], 1)
+    return kernels, traffic, dict(stages), cal
+
+
+def write_profiles(d: str, name: str, commands: str, copy_bytes: int, out_dir: str | None = None):
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    kernels, traffic, stages, cal = summarize(d, copy_bytes)
+    src = kernel_sources_hash()
+    lines = [f"# rocprofv3 kernel trace: {name}", "", "Commands (from the repository root on the GPU box):", "",
+             "```", commands.strip(), "```", "",
+             f"Kernel sources sha256: `{src}`", "",
+             "| kernel | dispatches | total ms | avg us | stage | HBM read MB/dispatch | HBM write MB/dispatch |",
+             "|---|---:|---:|---:|---|---:|---:|"]
+    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ns"]):
+        t = traffic.get(k, {})
+        fr = t.get("fetch_bytes_per_dispatch")
+        wr = t.get("write_bytes_per_dispatch")
+        lines.append(f"| `{k[:90]}` | {v['dispatches']} | {v['total_ns'] / 1e6:.3f} | {v['avg_ns'] / 1e3:.2f} | "
+                     f"{stage_of(k) or ''} | {'' if fr is None else f'{fr / 1e6:.1f}'} | "
+                     f"{'' if wr is None else f'{wr / 1e6:.1f}'} |")
+    lines += ["", f"HBM counters scaled by a {copy_bytes / 2**30:.0f} GiB device copy: FETCH_SIZE x "
+              f"{cal['FETCH_SIZE'] / 1024:.4f}, WRITE_SIZE x {cal['WRITE_SIZE'] / 1024:.4f} (KiB counted -> KiB moved).", ""]
+    with open(os.path.join(out_dir, f"{name}_kernels.md"), "w") as f:
+        f.write("\n".join(lines))
+    with open(os.path.join(out_dir, f"{name}_hbm_traffic.txt"), "w") as f:
+        json.dump({"workload": name, "commands": commands.strip(), "kernel_sources_sha256": src,
+                   "calibration_bytes_per_counter_unit": cal, "stages": stages,
+                   "kernels": {k: {**kernels.get(k, {}), **traffic.get(k, {})} for k in set(kernels) | set(traffic)}},
+                  f, indent=1, sort_keys=True)
+    return stages
+
+
+def read_stage_traffic(name: str, out_dir: str | None = None):
+    """HBM bytes per dispatch for each stage from a committed summary, or None when the
+    summary is missing or the kernel sources changed since it was taken."""
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    p = os.path.join(out_dir, f"{name}_hbm_traffic.txt")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    return d.get("stages")
+
+
+if __name__ == "__main__":
+    if len(sys.argv) < 4:
+        print(__doc__)
+        sys.exit(2)
+    gib = float(os.environ.get("COPY_GIB", "1"))
+    st = write_profiles(sys.argv[1], sys.argv[2], sys.argv[3], int(gib * (1 << 30)))
+    print(json.dumps(st, indent=1))
