@@ -227,13 +227,78 @@ __device__ __forceinline__ void transform_io(double2 *buf, int tid, const double
     }
 }
 
+// The last forward pass, the product with the spectrum and the first inverse pass, fused
+// in registers.  With the partial pass of radix R = P / (P/R) taken last in the forward
+// transform and first in the inverse one, butterfly j of the forward pass produces
+// X[j + r P/R] (r < R) and butterfly j of the inverse pass consumes exactly those values,
+// so they never go through LDS.  Outputs of the inverse pass go to out(j R + r).
+template <int P, int NT, int R, class In, class Out>
+__device__ __forceinline__ void mid_pass(int tid0, const double2 *__restrict__ tw, const double2 *__restrict__ hh,
+                                         In in, Out out) {
+    constexpr int NB = P / R;
+    constexpr int PER = NB / NT;
+    int tid = tid0;
+    __asm__ volatile("" : "+v"(tid));
+    double2 v[PER][R], w[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * NT;
+        w[q][1] = tw[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = in(j + r * NB);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * NT;
+#pragma unroll
+        for (int r = 2; r < R; ++r) {
+            if ((r & (r - 1)) == 0) w[q][r] = cmul(w[q][r / 2], w[q][r / 2]);
+            else w[q][r] = cmul(w[q][r & (r - 1)], w[q][r & -r]);
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[q][r]);
+        dft_reg<R, -1>(v[q]);
+        double2 x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = cmul(v[q][out_pos<R>(r)], hh[j + r * NB]);
+        dft_reg<R, +1>(x);
+#pragma unroll
+        for (int r = 0; r < R; ++r) out(j * R + r, x[out_pos<R>(r)]);
+    }
+    __syncthreads();
+}
+
 // Linear convolution through the FFT: the column is read by `in`, transformed, multiplied
 // by the spectrum hh, transformed back and written by `out` (unnormalised: hh carries 1/P).
+// Forward passes: radix RM (span 1, RM, ...), then the partial radix last; inverse passes:
+// the partial radix first, then radix RM.  The pass at the junction is fused (mid_pass).
 template <int P, int RM, class In, class Out>
 __device__ __forceinline__ void convolve_io(double2 *buf, int tid, const double2 *__restrict__ tw,
                                             const double2 *__restrict__ hh, In in, Out out) {
-    transform_io<P, RM, -1>(buf, tid, tw, hh, in, LdsOut{buf});
-    transform_io<P, RM, +1>(buf, tid, tw, nullptr, LdsIn{buf}, out);
+    static_assert(P >= 32 && (P & (P - 1)) == 0, "power of two >= 32");
+    using PL = Plan<P, RM>;
+    constexpr int NT = PL::NT;
+    constexpr int RJ = PL::REM > 1 ? PL::REM : RM;  // radix at the junction
+    constexpr int NSIDE = PL::NPASS - 1;             // passes on each side of the junction
+    LdsIn li{buf};
+    LdsOut lo{buf};
+    int Ns = 1;
+#pragma unroll
+    for (int s = 0; s < NSIDE; ++s) {
+        if (s == 0) pass<P, NT, RM, -1>(Ns, tid, tw, nullptr, in, lo);
+        else pass<P, NT, RM, -1>(Ns, tid, tw, nullptr, li, lo);
+        Ns *= RM;
+    }
+    if constexpr (NSIDE == 0) mid_pass<P, NT, RJ>(tid, tw, hh, in, out);
+    else mid_pass<P, NT, RJ>(tid, tw, hh, li, lo);
+    Ns = RJ;
+#pragma unroll
+    for (int s = 0; s < NSIDE; ++s) {
+        if (s == NSIDE - 1) pass<P, NT, RM, +1>(Ns, tid, tw, nullptr, li, out);
+        else pass<P, NT, RM, +1>(Ns, tid, tw, nullptr, li, lo);
+        Ns *= RM;
+    }
 }
 
 }  // namespace fft
