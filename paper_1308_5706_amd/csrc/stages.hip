@@ -165,54 +165,100 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const
     fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
 }
 
-// Analysis gamma pass: W[g][b][a] = sum_{n'} Re(Y[n'][b][a] tg[g][n']), tg = (1 or 2) e^{i n gamma_g}.
-template <typename WT>
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 nt_load2(const double2 *p) {
+    const nt_double2 v = __builtin_nontemporal_load((const nt_double2 *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void nt_store2(double2 x, double2 *p) {
+    nt_double2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_nontemporal_store(v, (nt_double2 *)p);
+}
+
+// Gamma passes: streaming kernels, each thread takes V consecutive grid points (b, a) of one
+// plane (V = 2 when the plane size L T is even, so that W moves in 16-byte accesses).  W, Y
+// and X are touched once per pass, so the accesses are marked non-temporal.
+//
+// Analysis: W[g][b][a] = sum_{n'} Re(Y[n'][b][a] tg[g][n']), tg = (1 or 2) e^{i n gamma_g}.
+template <typename WT, int V>
 __global__ void __launch_bounds__(256) gamma_fwd_kernel(const GammaArgs a) {
     const size_t plane = (size_t)a.L * a.T;
-    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= plane) return;
-    double2 y[kMaxK];
+    const size_t e0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * V;
+    if (e0 >= plane) return;
+    double2 y[kMaxK][V];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
-        if (k < a.Nh) y[k] = a.in[k * plane + e];
+        if (k < a.Nh) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) y[k][v] = nt_load2(a.in + k * plane + e0 + v);
+        }
     WT *__restrict__ W = (WT *)a.wout;
     for (int g = 0; g < a.G; ++g) {
-        double acc = 0.0;
+        double acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0.0;
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k) {
             if (k < a.Nh) {
                 const double2 w = a.tg[g * a.Nh + k];
-                acc = fma(y[k].x, w.x, fma(-y[k].y, w.y, acc));
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] = fma(y[k][v].x, w.x, fma(-y[k][v].y, w.y, acc[v]));
             }
         }
-        W[g * plane + e] = (WT)acc;
+        WT *dst = W + g * plane + e0;
+        if constexpr (V == 2 && sizeof(WT) == 8) {
+            nt_store2(make_double2(acc[0], acc[1]), (double2 *)dst);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) __builtin_nontemporal_store((WT)acc[v], dst + v);
+        }
     }
 }
 
-// Synthesis gamma pass: X[n'][b][a] = sum_g W[g][b][a] tg[g][n'], tg = e^{-i n gamma_g}.
-template <typename WT>
+// Synthesis: X[n'][b][a] = sum_g W[g][b][a] tg[g][n'], tg = e^{-i n gamma_g}.
+template <typename WT, int V>
 __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
     const size_t plane = (size_t)a.L * a.T;
-    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= plane) return;
+    const size_t e0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * V;
+    if (e0 >= plane) return;
     const WT *__restrict__ W = (const WT *)a.win;
-    double2 x[kMaxK];
+    double2 x[kMaxK][V];
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k) x[k] = zero2();
+    for (int k = 0; k < kMaxK; ++k)
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[k][v] = zero2();
     for (int g = 0; g < a.G; ++g) {
-        const double w = (double)W[g * plane + e];
+        double w[V];
+        const WT *src = W + g * plane + e0;
+        if constexpr (V == 2 && sizeof(WT) == 8) {
+            const double2 t = nt_load2((const double2 *)src);
+            w[0] = t.x;
+            w[1] = t.y;
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) w[v] = (double)__builtin_nontemporal_load(src + v);
+        }
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k) {
             if (k < a.Nh) {
                 const double2 t = a.tg[g * a.Nh + k];
-                x[k].x = fma(w, t.x, x[k].x);
-                x[k].y = fma(w, t.y, x[k].y);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    x[k][v].x = fma(w[v], t.x, x[k][v].x);
+                    x[k][v].y = fma(w[v], t.y, x[k][v].y);
+                }
             }
         }
     }
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
-        if (k < a.Nh) a.out[k * plane + e] = x[k];
+        if (k < a.Nh) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) nt_store2(x[k][v], a.out + k * plane + e0 + v);
+        }
 }
 
 // ------------------------------------------ synthesis: beta integral and m' folding (Eq. 35, 40)
@@ -345,20 +391,23 @@ hipError_t launch_beta_adj_fft(const StageArgs &a, int P, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_gamma_fwd(const GammaArgs &a, hipStream_t st) {
-    const size_t plane = (size_t)a.L * a.T;
-    const dim3 grid((unsigned)((plane + 255) / 256));
-    if (a.f32) hipLaunchKernelGGL(gamma_fwd_kernel<float>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(gamma_fwd_kernel<double>, grid, dim3(256), 0, st, a);
-    return hipGetLastError();
-}
+#define S2DW_GAMMA_LAUNCH(KER)                                                                  \
+    {                                                                                           \
+        const size_t plane = (size_t)a.L * a.T;                                                 \
+        if (plane % 2 == 0) {                                                                   \
+            const dim3 grid((unsigned)((plane / 2 + 255) / 256));                               \
+            if (a.f32) hipLaunchKernelGGL((KER<float, 2>), grid, dim3(256), 0, st, a);          \
+            else hipLaunchKernelGGL((KER<double, 2>), grid, dim3(256), 0, st, a);               \
+        } else {                                                                                \
+            const dim3 grid((unsigned)((plane + 255) / 256));                                   \
+            if (a.f32) hipLaunchKernelGGL((KER<float, 1>), grid, dim3(256), 0, st, a);          \
+            else hipLaunchKernelGGL((KER<double, 1>), grid, dim3(256), 0, st, a);               \
+        }                                                                                       \
+        return hipGetLastError();                                                               \
+    }
 
-hipError_t launch_gamma_adj(const GammaArgs &a, hipStream_t st) {
-    const size_t plane = (size_t)a.L * a.T;
-    const dim3 grid((unsigned)((plane + 255) / 256));
-    if (a.f32) hipLaunchKernelGGL(gamma_adj_kernel<float>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(gamma_adj_kernel<double>, grid, dim3(256), 0, st, a);
-    return hipGetLastError();
-}
+hipError_t launch_gamma_fwd(const GammaArgs &a, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_fwd_kernel)
+
+hipError_t launch_gamma_adj(const GammaArgs &a, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_adj_kernel)
 
 }  // namespace s2dw
