@@ -1,0 +1,50 @@
+"""Parity at the full sizes of the large configurations, on outputs the oracle can compute
+one at a time: whole beta rows of W (every scale, gamma and alpha sample), in the same
+launch configuration the benchmark times; plus the exact round trip, which holds at any
+size.  FP64 bar: relative max-error <= 1e-11 per scale, relative to the largest magnitude
+of the oracle's sampled rows of that scale."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import tables
+from paper_1308_5706_amd import s2dw
+from paper_1308_5706_amd.inputs import random_flm
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+FULL = [  # (L, N, J_min): the large configuration and the benchmark workload
+    (2048, 4, 4),
+    (1024, 8, 1),
+]
+
+
+@pytest.mark.parametrize("L,N,J_min", FULL)
+def test_full_size_rows_and_round_trip(L, N, J_min):
+    lam = 2.0
+    print(f"full size L={L} N={N} J_min={J_min}: analysis on the GPU", flush=True)
+    f = random_flm(L, 0)
+    fd = torch.as_tensor(f).to("cuda")
+    W, Wp = s2dw.analysis(fd, L, N, lam, J_min)
+    torch.cuda.synchronize()
+    rows = [0, L // 3, L - 2, L - 1]  # includes beta = pi (b = L - 1)
+    got = W[:, :, rows, :].cpu().numpy()
+    print("  oracle on the sampled beta rows", flush=True)
+    psi = tables.wavelets(L, N, lam, J_min)
+    ref = oracle.analysis(f, L, N, lam, J_min, betas=oracle.mw_betas(L)[rows], psi=psi)
+    assert got.shape == ref.shape
+    for j in range(ref.shape[0]):
+        den = np.max(np.abs(ref[j]))
+        err = float(np.max(np.abs(got[j] - ref[j])) / den)
+        assert err < TOL, (j, err)
+    print("  synthesis on the GPU (round trip)", flush=True)
+    fr = s2dw.synthesis(W, Wp, L, N, lam, J_min)
+    torch.cuda.synchronize()
+    rt = float((fr - fd).abs().max().item() / fd.abs().max().item())
+    assert rt < 1e-12, rt
+    del W, Wp, fr
+    s2dw.release_caches()
+    torch.cuda.empty_cache()
