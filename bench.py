@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--N", type=int, default=8)
     ap.add_argument("--lam", type=float, default=2.0)
     ap.add_argument("--jmin", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="mixed: W in FP32 and the FFT stages / m'-sum in FP32 (Delta recursion and l-sum FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (to scale HBM counters)")
@@ -174,13 +176,15 @@ def main():
     S = s2dw.num_scales(L, lam, J_min)
     f_host = random_flm(L, 0)
     f = torch.as_tensor(f_host).to(dev)
-    W = torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=torch.float64, device=dev)
+    prec = args.precision
+    W = torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=torch.float64 if prec == "fp64" else torch.float32,
+                    device=dev)
     fr = torch.empty(L * L, dtype=torch.complex128, device=dev)
     print(f"# workload L={L} N={N} lambda={lam} J_min={J_min} scales={S}", file=sys.stderr, flush=True)
 
     def step():
-        _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=W)
-        s2dw.synthesis(W, Wp, L, N, lam, J_min, out=fr)
+        _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=W, precision=prec)
+        s2dw.synthesis(W, Wp, L, N, lam, J_min, out=fr, precision=prec)
 
     for i in range(args.warmup):
         step()
@@ -226,11 +230,11 @@ def main():
     out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8; p50/p99 mixed-L",
            "value": value, "unit": "SO(3) coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64", "data": "synthetic",
+           "dtype": "f64" if prec == "fp64" else "f32/f64", "data": "synthetic",
            "config": {"workload": f"SD wavelet round trip, one map, L={L}, N={N}, lambda={lam}, J_min={J_min}, "
                                   f"{S} scales, grid {2 * N - 1}x{L}x{2 * L - 1}",
                       "L": L, "N": N, "lambda": lam, "J_min": J_min, "scales": S, "coeffs_per_map": coeffs,
-                      "round_trip_rel_err": rt_err},
+                      "precision": prec, "round_trip_rel_err": rt_err},
            "roofline": roof,
            "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in per_stage.items()},
            "stages_frac": {k: round(v["frac"], 4) for k, v in stage_roofs.items()},

@@ -45,6 +45,13 @@ struct Plan {
     double2 *hD1 = nullptr;
     std::map<int, double2 *> twP;               // e^{-2 pi i k/P}
     // workspaces
+    // FP32 copies of the stage tables for the mixed-precision path (built on first use)
+    bool f32_ready = false;
+    float2 *csqf = nullptr, *cppf = nullptr, *tgff = nullptr, *tgaf = nullptr, *hD1f = nullptr;
+    std::vector<float2 *> hAf, hBf, hCf, hD2f;
+    std::map<int, float2 *> twPf;
+    float *kb2f = nullptr;
+    size_t n_kb2 = 0, n_tg = 0;
     double2 *fpad = nullptr, *U = nullptr, *Ub = nullptr, *Y = nullptr, *Fpart = nullptr;
     int Nh = 0;                                 // orders n >= 0 carried: ceil(N/2)
     int nblk = 0;
@@ -353,6 +360,8 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     std::vector<double2> pqv((size_t)L * Lp), uvv((size_t)Lp * L);
     memcpy(pqv.data(), dt.pq.data(), pqv.size() * sizeof(double2));
     memcpy(uvv.data(), dt.uv.data(), uvv.size() * sizeof(double2));
+    P.n_kb2 = kb2.size();
+    P.n_tg = tgf.size();
     bool ok = upload(P, P.pq, pqv) && upload(P, P.uv, uvv) && upload(P, P.kb2, kb2) && upload(P, P.seed, dt.seed) &&
               upload(P, P.seedm, dt.seedm) && upload(P, P.seede, dt.seede) && upload(P, P.twa, twa) &&
               upload(P, P.csq, csq) && upload(P, P.cpp, cpp) && upload(P, P.tgf, tgf) && upload(P, P.tga, tga) && upload(P, P.fac, fac) &&
@@ -435,20 +444,56 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     return S2DW_OK;
 }
 
-int get_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
+// FP32 copy of a device table of n complex (or, with real = true, n real) FP64 values.
+template <typename F>
+bool f32_copy(Plan &P, F *&dst, const void *src, size_t n_values) {
+    if (!dalloc(P, dst, n_values)) return false;
+    const size_t words = n_values * sizeof(F) / sizeof(float);
+    return launch_to_f32((const double *)src, (float *)dst, words, 0) == hipSuccess;
+}
+
+// Builds the FP32 table set of a plan (once; caller holds g_mu).
+int ensure_f32(Plan &P) {
+    if (P.f32_ready) return S2DW_OK;
+    const int L = P.L, T = 2 * L - 1, S = P.S;
+    bool ok = f32_copy(P, P.csqf, P.csq, T) && f32_copy(P, P.cppf, P.cpp, T) && f32_copy(P, P.tgff, P.tgf, P.n_tg) &&
+              f32_copy(P, P.tgaf, P.tga, P.n_tg) && f32_copy(P, P.hD1f, P.hD1, P.PD) &&
+              f32_copy(P, P.kb2f, P.kb2, P.n_kb2);
+    P.hAf.assign(S, nullptr);
+    P.hBf.assign(S, nullptr);
+    P.hCf.assign(S, nullptr);
+    P.hD2f.assign(S, nullptr);
+    for (int j = 0; ok && j < S; ++j) {
+        if (P.sc.Lj[j] == 0) continue;
+        ok = f32_copy(P, P.hAf[j], P.hA[j], P.PA[j]) && f32_copy(P, P.hBf[j], P.hB[j], P.PB[j]) &&
+             f32_copy(P, P.hCf[j], P.hC[j], P.PB[j]) && f32_copy(P, P.hD2f[j], P.hD2[j], P.PD);
+    }
+    for (auto &kv : P.twP) {
+        if (!ok) break;
+        float2 *d = nullptr;
+        ok = f32_copy(P, d, kv.second, kv.first);
+        P.twPf[kv.first] = d;
+    }
+    if (!ok) return S2DW_E_NOMEM;
+    if (hipStreamSynchronize(0) != hipSuccess) return S2DW_E_DEVICE;
+    P.f32_ready = true;
+    return S2DW_OK;
+}
+
+int get_plan(int kind, int L, int N, double lam, int J_min, Plan *&out, bool f32 = false) {
     std::lock_guard<std::mutex> lk(g_mu);
     PlanKey key(kind, L, kind == kWavelet ? N : 1, kind == kWavelet ? lam : 0.0, kind == kWavelet ? J_min : 0);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         out = it->second.get();
-        return S2DW_OK;
+        return f32 ? ensure_f32(*out) : S2DW_OK;
     }
     Plan *p = nullptr;
     int rc = build_plan(kind, L, N, lam, J_min, p);
     if (rc != S2DW_OK) return rc;
     g_plans[key].reset(p);
     out = p;
-    return S2DW_OK;
+    return f32 ? ensure_f32(*out) : S2DW_OK;
 }
 
 int check_params(const s2dw_params *p) {
@@ -461,7 +506,6 @@ int check_params(const s2dw_params *p) {
     if (p->J_min < 0 || p->J_min > JL || JL - p->J_min + 1 > kMaxScales) return S2DW_E_ARG;
     if (p->grid != S2DW_GRID_MW) return S2DW_E_ARG;
     if (p->precision != S2DW_FP64 && p->precision != S2DW_MIXED) return S2DW_E_ARG;
-    if (p->precision == S2DW_MIXED) return S2DW_E_UNSUPPORTED;
     if (p->reality != 1) return p->reality == 0 ? S2DW_E_UNSUPPORTED : S2DW_E_ARG;
     return S2DW_OK;
 }
@@ -508,16 +552,17 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
         const int Lj = P.sc.Lj[j];
         void *Wj = f32 ? (void *)((float *)W + per_scale * j) : (void *)((double *)W + per_scale * j);
         if (Lj == 0) {
-            S2DW_CHECK_HIP(hipMemsetAsync(Wj, 0, per_scale * (f32 ? 4 : 8), st));
+            S2DW_CHECK_HIP(launch_zero_words(Wj, per_scale * (f32 ? 1 : 2), st));
             continue;
         }
         StageArgs b{};
+        b.f32 = f32;
         b.in = P.U + P.sc.off[j];
         b.out = P.Ub;
-        b.hh = P.hA[j];
-        b.tw = P.twP[P.PA[j]];
-        b.csq = P.csq;
-        b.cpp = P.cpp;
+        b.hh = f32 ? (const void *)P.hAf[j] : P.hA[j];
+        b.tw = f32 ? (const void *)P.twPf[P.PA[j]] : P.twP[P.PA[j]];
+        b.csq = f32 ? (const void *)P.csqf : P.csq;
+        b.cpp = f32 ? (const void *)P.cppf : P.cpp;
         b.L = L;
         b.Lj = Lj;
         b.N = N;
@@ -529,8 +574,8 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
         StageArgs c = b;
         c.in = P.Ub;
         c.out = P.Y;
-        c.hh = P.hB[j];
-        c.tw = P.twP[P.PB[j]];
+        c.hh = f32 ? (const void *)P.hBf[j] : P.hB[j];
+        c.tw = f32 ? (const void *)P.twPf[P.PB[j]] : P.twP[P.PB[j]];
         {
             Stage sg("alpha_fwd", st);
             S2DW_CHECK_HIP(launch_alpha_fwd_fft(c, P.PB[j], st));
@@ -538,7 +583,7 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
         GammaArgs g{};
         g.wout = Wj;
         g.in = P.Y;
-        g.tg = P.tgf;
+        g.tg = f32 ? (const void *)P.tgff : P.tgf;
         g.L = L;
         g.T = 2 * L - 1;
         g.G = G;
@@ -564,7 +609,7 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
         GammaArgs g{};
         g.win = Wj;
         g.out = P.Y;
-        g.tg = P.tga;
+        g.tg = f32 ? (const void *)P.tgaf : P.tga;
         g.L = L;
         g.T = M;
         g.G = G;
@@ -575,12 +620,13 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
             S2DW_CHECK_HIP(launch_gamma_adj(g, st));
         }
         StageArgs c{};
+        c.f32 = f32;
         c.in = P.Y;
         c.out = P.Ub;
-        c.hh = P.hC[j];
-        c.tw = P.twP[P.PB[j]];
-        c.csq = P.csq;
-        c.cpp = P.cpp;
+        c.hh = f32 ? (const void *)P.hCf[j] : P.hC[j];
+        c.tw = f32 ? (const void *)P.twPf[P.PB[j]] : P.twP[P.PB[j]];
+        c.csq = f32 ? (const void *)P.csqf : P.csq;
+        c.cpp = f32 ? (const void *)P.cppf : P.cpp;
         c.L = L;
         c.Lj = Lj;
         c.N = N;
@@ -593,10 +639,12 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
         }
         StageArgs v = c;
         v.in = P.Ub;
-        v.out = P.U + P.sc.off[j];
-        v.hh = P.hD1;
-        v.hh2 = P.hD2[j];
-        v.tw = P.twP[P.PD];
+        // V of scale j starts sc.off[j] complex elements into the workspace (the synthesis
+        // Wigner kernel indexes it with the same element type)
+        v.out = f32 ? (void *)((float2 *)P.U + P.sc.off[j]) : (void *)(P.U + P.sc.off[j]);
+        v.hh = f32 ? (const void *)P.hD1f : P.hD1;
+        v.hh2 = f32 ? (const void *)P.hD2f[j] : P.hD2[j];
+        v.tw = f32 ? (const void *)P.twPf[P.PD] : P.twP[P.PD];
         for (int k = 0; k < P.K; ++k) v.nk[k] = P.ht.nk[k];
         v.eta_imag = P.ht.eta_imag ? 1 : 0;
         {
@@ -607,7 +655,7 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
     WigAdjArgs a{};
     a.pq = P.pq;
     a.uv = P.uv;
-    a.kb2 = P.kb2;
+    a.kb2 = f32 ? (const void *)P.kb2f : P.kb2;
     a.seed = P.seed;
     a.seedm = P.seedm;
     a.seede = P.seede;
@@ -616,6 +664,7 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
     a.L = L;
     a.Lp = P.Lp;
     a.group = P.group;
+    a.f32 = f32;
     a.seg = P.seg;
     a.sc = P.sc;
     {
@@ -626,7 +675,7 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
     }
     {
         Stage sg("syn_final", st);
-        S2DW_CHECK_HIP(launch_syn_final(P.Fpart, P.nblk, P.group, P.Lmax, P.fac, wphi, P.phi, flm, L, P.Lp, st));
+        S2DW_CHECK_HIP(launch_syn_final(P.Fpart, f32, P.nblk, P.group, P.Lmax, P.fac, wphi, P.phi, flm, L, P.Lp, st));
     }
     return S2DW_OK;
 }
@@ -669,10 +718,11 @@ int s2dw_analysis(const s2dw_params *p, const double *flm, void *W, double *Wphi
     if (rc != S2DW_OK) return rc;
     if (!flm || !W || !aligned(flm) || !aligned(W) || (Wphi_lm && !aligned(Wphi_lm))) return S2DW_E_ARG;
     Plan *P = nullptr;
-    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P);
+    const int f32 = p->precision == S2DW_MIXED ? 1 : 0;
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0);
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    rc = run_inverse(*P, (const double2 *)flm, W, 0, st);
+    rc = run_inverse(*P, (const double2 *)flm, W, f32, st);
     if (rc != S2DW_OK) return rc;
     if (Wphi_lm) {
         Stage sg("scaling", st);
@@ -686,9 +736,10 @@ int s2dw_synthesis(const s2dw_params *p, const void *W, const double *Wphi_lm, d
     if (rc != S2DW_OK) return rc;
     if (!W || !flm_out || !aligned(W) || !aligned(flm_out) || (Wphi_lm && !aligned(Wphi_lm))) return S2DW_E_ARG;
     Plan *P = nullptr;
-    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P);
+    const int f32 = p->precision == S2DW_MIXED ? 1 : 0;
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0);
     if (rc != S2DW_OK) return rc;
-    return run_forward(*P, W, (const double2 *)Wphi_lm, (double2 *)flm_out, 0, (hipStream_t)stream);
+    return run_forward(*P, W, (const double2 *)Wphi_lm, (double2 *)flm_out, f32, (hipStream_t)stream);
 }
 
 int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, double *Wphi_map, void *stream) {

@@ -29,15 +29,15 @@ struct WigFwdArgs {
 struct WigAdjArgs {
     const double2 *pq;
     const double2 *uv;
-    const double *kb2;
+    const void *kb2;       // double, or float if f32 (same layout as in WigFwdArgs)
     const double *seed;
     const double *seedm;
     const int *seede;
     const int2 *tiles;
     int nplain;
-    const double2 *V;      // scale j at sc.off[j]: [K][2][Lj][Lj] = [k][P|Q][m][m']
-    double2 *Fpart;        // [L / group][L][Lp] partial sums over each m' group
-    int L, Lp, group;
+    const void *V;         // scale j at sc.off[j]: [K][2][Lj][Lj] = [k][P|Q][m][m'], double2 or float2
+    void *Fpart;           // [L / group][L][Lp] partial sums over each m' group, double2 or float2
+    int L, Lp, group, f32;
     SegTab seg;
     ScaleTab sc;
 };
@@ -54,14 +54,16 @@ hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int ntiles, hipStream_t st
 //   synthesis: W -> X [Nh][L][T] (gamma pass) -> G [N][Lj][L] = [n][m][b] (alpha sums)
 //              -> V [K][2][Lj][Lj] = [k][P|Q][m][m']
 struct StageArgs {
-    const double2 *in;
-    double2 *out;
-    const double2 *hh;     // FFT of the stage's chirp (or kernel) sequence, divided by P
-    const double2 *hh2;    // FFT of the w(q) sequence (synthesis beta stage), divided by P
-    const double2 *tw;     // e^{-2 pi i k/P}, k < P
-    const double2 *csq;    // e^{i pi i^2/T}, i < T, T = 2L - 1
-    const double2 *cpp;    // e^{i pi p(p+1)/T} at p + L - 1, |p| < L
-    int L, Lj, N, Nh, K, eta_imag;
+    // Arrays are double2 (FP64 path) or float2 (f32 = 1, mixed precision), except the
+    // analysis beta input U, which is double2 in both.
+    const void *in;
+    void *out;
+    const void *hh;        // FFT of the stage's chirp (or kernel) sequence, divided by P
+    const void *hh2;       // FFT of the w(q) sequence (synthesis beta stage), divided by P
+    const void *tw;        // e^{-2 pi i k/P}, k < P
+    const void *csq;       // e^{i pi i^2/T}, i < T, T = 2L - 1
+    const void *cpp;       // e^{i pi p(p+1)/T} at p + L - 1, |p| < L
+    int L, Lj, N, Nh, K, eta_imag, f32;
     int nk[kMaxK];
     double scale;
 };
@@ -71,11 +73,11 @@ hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, hipStream_t st);
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, hipStream_t st);
 
 struct GammaArgs {
-    const void *win;       // W read (synthesis), float64 or float32
+    const void *win;       // W read (synthesis): double, or float if f32
     void *wout;            // W written (analysis)
-    const double2 *in;     // Y (analysis)
-    double2 *out;          // X (synthesis)
-    const double2 *tg;     // [2N-1][Nh]: (1 or 2) e^{i n gamma_g} (analysis), e^{-i n gamma_g} (synthesis)
+    const void *in;        // Y (analysis): double2, or float2 if f32
+    void *out;             // X (synthesis)
+    const void *tg;        // [2N-1][Nh]: (1 or 2) e^{i n gamma_g} (analysis), e^{-i n gamma_g} (synthesis)
     int L, T, G, Nh, f32;
 };
 hipError_t launch_gamma_fwd(const GammaArgs &a, hipStream_t st);
@@ -85,8 +87,9 @@ hipError_t launch_gamma_adj(const GammaArgs &a, hipStream_t st);
 
 hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, hipStream_t st);
 hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, hipStream_t st);
-hipError_t launch_syn_final(const double2 *Fpart, int nblk, int group, int Lmax, const double *fac,
+hipError_t launch_syn_final(const void *Fpart, int f32, int nblk, int group, int Lmax, const double *fac,
                             const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, hipStream_t st);
-hipError_t launch_zero(double2 *p, size_t n, hipStream_t st);
+hipError_t launch_zero_words(void *p, size_t n, hipStream_t st);
+hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t st);
 
 }  // namespace s2dw

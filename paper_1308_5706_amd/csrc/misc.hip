@@ -36,7 +36,10 @@ hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, 
 
 // f_lm = fac_l sum_g Fpart[g][l][m] + sqrt((2l+1)/(4 pi)) W^Phi_lm Phi_l0   (Eq. 32, 41), m >= 0;
 // f_{l,-m} = (-1)^m conj(f_lm).
-__global__ void syn_final_kernel(const double2 *Fpart, int nblk, int group, int Lmax, const double *fac,
+// Fpart holds double2 (FP64 path) or float2 (mixed precision) partial sums; the final sum
+// over the m' groups and the harmonic synthesis factor are applied in FP64.
+template <class VC>
+__global__ void syn_final_kernel(const VC *Fpart, int nblk, int group, int Lmax, const double *fac,
                                  const double2 *wphi, const double *phi, double2 *flm, int L, int Lp) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int l = blockIdx.y;
@@ -45,9 +48,9 @@ __global__ void syn_final_kernel(const double2 *Fpart, int nblk, int group, int 
     // no wavelet coefficient reaches l >= Lmax; blocks starting above l hold no term of row l
     const int gmax = (l < Lmax && m < Lmax) ? min(nblk - 1, l / group) : -1;
     for (int g = 0; g <= gmax; ++g) {
-        const double2 v = Fpart[((size_t)g * L + l) * Lp + m];
-        fr += v.x;
-        fi += v.y;
+        const VC v = Fpart[((size_t)g * L + l) * Lp + m];
+        fr += (double)v.x;
+        fi += (double)v.y;
     }
     fr *= fac[l];
     fi *= fac[l];
@@ -64,23 +67,42 @@ __global__ void syn_final_kernel(const double2 *Fpart, int nblk, int group, int 
     }
 }
 
-hipError_t launch_syn_final(const double2 *Fpart, int nblk, int group, int Lmax, const double *fac,
+hipError_t launch_syn_final(const void *Fpart, int f32, int nblk, int group, int Lmax, const double *fac,
                             const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, hipStream_t st) {
-    hipLaunchKernelGGL(syn_final_kernel, dim3((L + 255) / 256, L), dim3(256), 0, st, Fpart, nblk, group, Lmax, fac,
-                       wphi, phi, flm, L, Lp);
+    if (f32)
+        hipLaunchKernelGGL(syn_final_kernel<float2>, dim3((L + 255) / 256, L), dim3(256), 0, st, (const float2 *)Fpart,
+                           nblk, group, Lmax, fac, wphi, phi, flm, L, Lp);
+    else
+        hipLaunchKernelGGL(syn_final_kernel<double2>, dim3((L + 255) / 256, L), dim3(256), 0, st,
+                           (const double2 *)Fpart, nblk, group, Lmax, fac, wphi, phi, flm, L, Lp);
     return hipGetLastError();
 }
 
-__global__ void zero_kernel(double2 *p, size_t n) {
+// Clears n 32-bit words (a kernel rather than a memset node, so the call can be captured).
+__global__ void zero_kernel(uint32_t *p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = make_double2(0.0, 0.0);
+        p[i] = 0u;
 }
 
-hipError_t launch_zero(double2 *p, size_t n, hipStream_t st) {
+hipError_t launch_zero_words(void *p, size_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, n);
+    return hipGetLastError();
+}
+
+// FP32 copies of plan tables for the mixed-precision path (round to nearest).
+__global__ void to_f32_kernel(const double *src, float *dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
     return hipGetLastError();
 }
 

@@ -13,6 +13,10 @@
 // computed as c = IFFT(FFT(a') * FFT(h')) with a'(i) = a(n0+i) and
 // h'(i) = h(k0 - n0 - Na + 1 + i) (i < Na + Nk - 1, zero elsewhere), P >= Na + Nk - 1;
 // then z(k0 + q) = c[q + Na - 1].  Column element i is held at LDS slot fft::pad(i).
+//
+// Every stage kernel is a template over the complex type C: double2 for the FP64 path,
+// float2 for the mixed-precision path (FP32 transforms, tables and accumulation; the
+// analysis input U is FP64 in both).
 #include "fft.h"
 #include "kernels.h"
 
@@ -37,15 +41,23 @@ constexpr int kRM = S2DW_FFT_RADIX;
 // Waves per SIMD the FFT kernels must fit (two P = 4096 columns share a CU's LDS).
 constexpr int kMinWaves = kRM >= 16 ? 2 : 4;
 
-__device__ __forceinline__ double2 rot_i(double2 z, int e) {
+using fft::mk;
+using fft::real_t;
+
+template <class C>
+__device__ __forceinline__ C rot_i(C z, int e) {
     e &= 3;
     if (e == 0) return z;
-    if (e == 1) return make_double2(-z.y, z.x);
-    if (e == 2) return make_double2(-z.x, -z.y);
-    return make_double2(z.y, -z.x);
+    if (e == 1) return mk<C>(-z.y, z.x);
+    if (e == 2) return mk<C>(-z.x, -z.y);
+    return mk<C>(z.y, -z.x);
 }
 
-__device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
+template <class C>
+__device__ __forceinline__ C zero2() { return mk<C>(0, 0); }
+
+template <class C>
+__device__ __forceinline__ C to_c(double2 v) { return mk<C>((real_t<C>)v.x, (real_t<C>)v.y); }
 
 }  // namespace
 
@@ -53,32 +65,32 @@ __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
 // Column (n, m) of scale j: Ub(b) = sum_{|m'|<Lj} U_{m m' n} e^{i m' beta_b}, b < L, with
 // U_{m,-m',n} = (-1)^{m+n} U_{m m' n} (only m' >= 0 is stored).  Since m' beta_b =
 // 2 pi m' b/T + pi m'/T, the chirp input is U e^{i pi m'(m'+1)/T}.
-template <int P>
+template <class C, int P>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const StageArgs a) {
-    __shared__ double2 buf[fft::padded(P)];
+    __shared__ C buf[fft::padded(P)];
     const int tid = threadIdx.x;
     const int Lj = a.Lj, L = a.L;
     const int col = blockIdx.x;  // ni * Lj + m
     const int ni = col / Lj, m = col - ni * Lj;
     const int n = 2 * ni - (a.N - 1);
     const bool odd = ((m + n) & 1) != 0;
-    const double2 *__restrict__ Uc = a.in + (size_t)col * Lj;
-    const double2 *__restrict__ cpp = a.cpp + (L - 1);
-    const double2 *__restrict__ csq = a.csq;
+    const double2 *__restrict__ Uc = (const double2 *)a.in + (size_t)col * Lj;
+    const C *__restrict__ cpp = (const C *)a.cpp + (L - 1);
+    const C *__restrict__ csq = (const C *)a.csq;
     const int Na = 2 * Lj - 1;
-    double2 *__restrict__ out = a.out + (size_t)col * L;
+    C *__restrict__ out = (C *)a.out + (size_t)col * L;
     auto in = [&](int i) {
-        if (i >= Na) return zero2();
+        if (i >= Na) return zero2<C>();
         const int mp = i - (Lj - 1);
-        double2 v = Uc[mp < 0 ? -mp : mp];
-        if (mp < 0 && odd) v = make_double2(-v.x, -v.y);
+        C v = to_c<C>(Uc[mp < 0 ? -mp : mp]);
+        if (mp < 0 && odd) v = mk<C>(-v.x, -v.y);
         return cmul(v, cpp[mp]);
     };
-    auto st = [&](int i, double2 v) {
+    auto st = [&](int i, C v) {
         const int b = i - (Na - 1);
         if (b >= 0 && b < L) out[b] = cmul(v, csq[b]);
     };
-    fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
+    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
 }
 
 // ------------------------------------------------------------------ alpha and gamma stages
@@ -101,9 +113,9 @@ __device__ __forceinline__ int xcd_column(int x, int ncols) {
     return (x & 7) * per + (x >> 3);
 }
 
-template <int P>
+template <class C, int P>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const StageArgs a) {
-    __shared__ double2 buf[fft::padded(P)];
+    __shared__ C buf[fft::padded(P)];
     const int tid = threadIdx.x;
     const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh;
     const int t = xcd_column(blockIdx.x, Nh * L);
@@ -111,14 +123,14 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const
     const int b = t / Nh, np = t - (t / Nh) * Nh;
     const int ni = (N / 2) + np, nj = N - 1 - ni;  // rows of n >= 0 and of -n
     const bool zero_n = ni == nj;
-    const double2 *__restrict__ Up = a.in + (size_t)ni * Lj * L + b;
-    const double2 *__restrict__ Um = a.in + (size_t)nj * Lj * L + b;
-    const double2 *__restrict__ csq = a.csq;
+    const C *__restrict__ Up = (const C *)a.in + (size_t)ni * Lj * L + b;
+    const C *__restrict__ Um = (const C *)a.in + (size_t)nj * Lj * L + b;
+    const C *__restrict__ csq = (const C *)a.csq;
     const int Na = 2 * Lj - 1;
     auto in = [&](int i) {
-        if (i >= Na) return zero2();
+        if (i >= Na) return zero2<C>();
         const int m = i - (Lj - 1);
-        double2 c;
+        C c;
         if (m >= 0) {
             c = Up[(size_t)m * L];
             if (m == 0 && zero_n) c.y = 0.0;
@@ -127,17 +139,17 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const
         }
         return cmul(c, csq[m < 0 ? -m : m]);
     };
-    double2 *__restrict__ Y = a.out + ((size_t)np * L + b) * T;
-    auto st = [&](int i, double2 v) {
+    C *__restrict__ Y = (C *)a.out + ((size_t)np * L + b) * T;
+    auto st = [&](int i, C v) {
         const int x = i - (Na - 1);
         if (x >= 0 && x < T) Y[x] = cmul(v, csq[x]);
     };
-    fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
+    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
 }
 
-template <int P>
+template <class C, int P>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const StageArgs a) {
-    __shared__ double2 buf[fft::padded(P)];
+    __shared__ C buf[fft::padded(P)];
     const int tid = threadIdx.x;
     const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh;
     const int t = xcd_column(blockIdx.x, Nh * L);
@@ -145,106 +157,123 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const
     const int b = t / Nh, np = t - (t / Nh) * Nh;
     const int ni = (N / 2) + np, nj = N - 1 - ni;
     const bool zero_n = ni == nj;
-    const double2 *__restrict__ X = a.in + ((size_t)np * L + b) * T;
-    const double2 *__restrict__ csq = a.csq;
-    auto in = [&](int i) { return i < T ? cmulc(X[i], csq[i]) : zero2(); };
+    const C *__restrict__ X = (const C *)a.in + ((size_t)np * L + b) * T;
+    const C *__restrict__ csq = (const C *)a.csq;
+    auto in = [&](int i) { return i < T ? cmulc(X[i], csq[i]) : zero2<C>(); };
     // Zh(m), q = m + Lj - 1 < 2Lj - 1, comes out at q + T - 1
     const int Nk = 2 * Lj - 1;
-    const double s = a.scale;
-    double2 *__restrict__ Gp = a.out + (size_t)ni * Lj * L + b;
-    double2 *__restrict__ Gm = a.out + (size_t)nj * Lj * L + b;
-    auto st = [&](int i, double2 v) {
+    const real_t<C> s = (real_t<C>)a.scale;
+    C *__restrict__ Gp = (C *)a.out + (size_t)ni * Lj * L + b;
+    C *__restrict__ Gm = (C *)a.out + (size_t)nj * Lj * L + b;
+    auto st = [&](int i, C v) {
         const int q = i - (T - 1);
         if (q >= 0 && q < Nk) {
             const int m = q - (Lj - 1);
-            const double2 z = cscale(cmulc(v, csq[m < 0 ? -m : m]), s);
+            const C z = cscale(cmulc(v, csq[m < 0 ? -m : m]), s);
             if (m >= 0) Gp[(size_t)m * L] = z;
             if (m <= 0 && !zero_n) Gm[(size_t)(-m) * L] = cconj(z);
         }
     };
-    fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in, st);
+    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
 }
 
 typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ double2 nt_load2(const double2 *p) {
+// non-temporal 16-byte (double2) or 8-byte (float2) accesses
+__device__ __forceinline__ double2 nt_load(const double2 *p) {
     const nt_double2 v = __builtin_nontemporal_load((const nt_double2 *)p);
     return make_double2(v.x, v.y);
 }
-__device__ __forceinline__ void nt_store2(double2 x, double2 *p) {
+__device__ __forceinline__ float2 nt_load(const float2 *p) {
+    const nt_float2 v = __builtin_nontemporal_load((const nt_float2 *)p);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void nt_store(double2 x, double2 *p) {
     nt_double2 v;
     v.x = x.x;
     v.y = x.y;
     __builtin_nontemporal_store(v, (nt_double2 *)p);
 }
+__device__ __forceinline__ void nt_store(float2 x, float2 *p) {
+    nt_float2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_nontemporal_store(v, (nt_float2 *)p);
+}
 
 // Gamma passes: streaming kernels, each thread takes V consecutive grid points (b, a) of one
-// plane (V = 2 when the plane size L T is even, so that W moves in 16-byte accesses).  W, Y
-// and X are touched once per pass, so the accesses are marked non-temporal.
+// plane (V = 2 when the plane size L T is even, so that W moves in pairs).  W, Y and X are
+// touched once per pass, so the accesses are marked non-temporal.  C = double2 with W in
+// FP64, or float2 with W in FP32 (mixed precision: FP32 arithmetic and accumulation).
 //
 // Analysis: W[g][b][a] = sum_{n'} Re(Y[n'][b][a] tg[g][n']), tg = (1 or 2) e^{i n gamma_g}.
-template <typename WT, int V>
+template <class C, int V>
 __global__ void __launch_bounds__(256) gamma_fwd_kernel(const GammaArgs a) {
+    using R = real_t<C>;
     const size_t plane = (size_t)a.L * a.T;
     const size_t e0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * V;
     if (e0 >= plane) return;
-    double2 y[kMaxK][V];
+    const C *__restrict__ Y = (const C *)a.in;
+    const C *__restrict__ tg = (const C *)a.tg;
+    C y[kMaxK][V];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
         if (k < a.Nh) {
 #pragma unroll
-            for (int v = 0; v < V; ++v) y[k][v] = nt_load2(a.in + k * plane + e0 + v);
+            for (int v = 0; v < V; ++v) y[k][v] = nt_load(Y + k * plane + e0 + v);
         }
-    WT *__restrict__ W = (WT *)a.wout;
+    R *__restrict__ W = (R *)a.wout;
     for (int g = 0; g < a.G; ++g) {
-        double acc[V];
+        R acc[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] = 0.0;
+        for (int v = 0; v < V; ++v) acc[v] = 0;
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k) {
             if (k < a.Nh) {
-                const double2 w = a.tg[g * a.Nh + k];
+                const C w = tg[g * a.Nh + k];
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc[v] = fma(y[k][v].x, w.x, fma(-y[k][v].y, w.y, acc[v]));
             }
         }
-        WT *dst = W + g * plane + e0;
-        if constexpr (V == 2 && sizeof(WT) == 8) {
-            nt_store2(make_double2(acc[0], acc[1]), (double2 *)dst);
+        R *dst = W + g * plane + e0;
+        if constexpr (V == 2) {
+            nt_store(mk<C>(acc[0], acc[1]), (C *)dst);
         } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) __builtin_nontemporal_store((WT)acc[v], dst + v);
+            __builtin_nontemporal_store(acc[0], dst);
         }
     }
 }
 
 // Synthesis: X[n'][b][a] = sum_g W[g][b][a] tg[g][n'], tg = e^{-i n gamma_g}.
-template <typename WT, int V>
+template <class C, int V>
 __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
+    using R = real_t<C>;
     const size_t plane = (size_t)a.L * a.T;
     const size_t e0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * V;
     if (e0 >= plane) return;
-    const WT *__restrict__ W = (const WT *)a.win;
-    double2 x[kMaxK][V];
+    const R *__restrict__ W = (const R *)a.win;
+    const C *__restrict__ tg = (const C *)a.tg;
+    C *__restrict__ X = (C *)a.out;
+    C x[kMaxK][V];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
 #pragma unroll
-        for (int v = 0; v < V; ++v) x[k][v] = zero2();
+        for (int v = 0; v < V; ++v) x[k][v] = zero2<C>();
     for (int g = 0; g < a.G; ++g) {
-        double w[V];
-        const WT *src = W + g * plane + e0;
-        if constexpr (V == 2 && sizeof(WT) == 8) {
-            const double2 t = nt_load2((const double2 *)src);
+        R w[V];
+        const R *src = W + g * plane + e0;
+        if constexpr (V == 2) {
+            const C t = nt_load((const C *)src);
             w[0] = t.x;
             w[1] = t.y;
         } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) w[v] = (double)__builtin_nontemporal_load(src + v);
+            w[0] = __builtin_nontemporal_load(src);
         }
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k) {
             if (k < a.Nh) {
-                const double2 t = a.tg[g * a.Nh + k];
+                const C t = tg[g * a.Nh + k];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     x[k][v].x = fma(w[v], t.x, x[k][v].x);
@@ -257,7 +286,7 @@ __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
     for (int k = 0; k < kMaxK; ++k)
         if (k < a.Nh) {
 #pragma unroll
-            for (int v = 0; v < V; ++v) nt_store2(x[k][v], a.out + k * plane + e0 + v);
+            for (int v = 0; v < V; ++v) nt_store(x[k][v], X + k * plane + e0 + v);
         }
 }
 
@@ -269,9 +298,9 @@ __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
 // (2/(1-q^2) for even q, +-i pi/2 for q = +-1, else 0): the exact beta integral of the
 // interpolant against e^{-i m' beta}; (3) the fold over +-m' and the even/odd-l
 // combinations P, Q of the two n columns (see the synthesis Wigner kernel).
-template <int P>
+template <class C, int P>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const StageArgs a) {
-    __shared__ double2 buf[fft::padded(P)];
+    __shared__ C buf[fft::padded(P)];
     constexpr int NT = P / kRM;
     const int tid = threadIdx.x;
     const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N;
@@ -283,45 +312,45 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
     const int ncol = n == 0 ? 1 : 2;
     const bool odd = ((m + n) & 1) != 0;
     const int Nk = 2 * Lj - 1;
-    const double2 *__restrict__ csq = a.csq;
-    const double2 *__restrict__ cpp = a.cpp;
-    double2 *__restrict__ Po = a.out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
-    double2 *__restrict__ Qo = a.out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
+    const C *__restrict__ csq = (const C *)a.csq;
+    const C *__restrict__ cpp = (const C *)a.cpp;
+    C *__restrict__ Po = (C *)a.out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
+    C *__restrict__ Qo = (C *)a.out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
-        const double2 *__restrict__ Gc = a.in + ((size_t)ni * Lj + m) * L;
+        const C *__restrict__ Gc = (const C *)a.in + ((size_t)ni * Lj + m) * L;
         auto in1 = [&](int i) {
-            if (i >= T) return zero2();
-            double2 v = i < L ? Gc[i] : Gc[2 * L - 2 - i];
-            if (i >= L && odd) v = make_double2(-v.x, -v.y);
+            if (i >= T) return zero2<C>();
+            C v = i < L ? Gc[i] : Gc[2 * L - 2 - i];
+            if (i >= L && odd) v = mk<C>(-v.x, -v.y);
             return cmulc(v, csq[i]);
         };
         // Gh(p), q = p + L - 1 < T, comes out at q + T - 1 (1/T is folded into the spectrum)
-        auto st1 = [&](int i, double2 v) {
+        auto st1 = [&](int i, C v) {
             const int q = i - (T - 1);
             if (q >= 0 && q < T) buf[pad(q)] = cmulc(v, cpp[q]);
         };
-        fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh, in1, st1);
-        auto in2 = [&](int i) { return i < T ? buf[pad(i)] : zero2(); };
+        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in1, st1);
+        auto in2 = [&](int i) { return i < T ? buf[pad(i)] : zero2<C>(); };
         // V(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + T - 1.  With two columns the
         // first one waits in this block's own output rows (2 Lj slots) while the second one
         // uses the whole buffer; the second one goes to slots Nk + q.
         if (c == 0 && ncol > 1) {
-            auto st2 = [&](int i, double2 v) {
+            auto st2 = [&](int i, C v) {
                 const int q = i - (T - 1);
                 if (q >= 0 && q < Nk) {
                     if (q < Lj) Po[q] = v;
                     else Qo[q - Lj] = v;
                 }
             };
-            fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh2, in2, st2);
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh2, in2, st2);
         } else {
             const int sh = c * Nk;
-            auto st2 = [&](int i, double2 v) {
+            auto st2 = [&](int i, C v) {
                 const int q = i - (T - 1);
                 if (q >= 0 && q < Nk) buf[pad(sh + q)] = v;
             };
-            fft::convolve_io<P, kRM>(buf, tid, a.tw, a.hh2, in2, st2);
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh2, in2, st2);
         }
     }
     if (ncol > 1) {
@@ -330,23 +359,23 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
     }
     const int eta = a.eta_imag ? 1 : 0;
     for (int mp = tid; mp < Lj; mp += NT) {
-        double2 tp = buf[pad(mp + Lj - 1)], tm = ncol > 1 ? buf[pad(Nk + mp + Lj - 1)] : zero2();
+        C tp = buf[pad(mp + Lj - 1)], tm = ncol > 1 ? buf[pad(Nk + mp + Lj - 1)] : zero2<C>();
         if (mp > 0) {
-            double2 up = buf[pad(-mp + Lj - 1)], um = ncol > 1 ? buf[pad(Nk - mp + Lj - 1)] : zero2();
+            C up = buf[pad(-mp + Lj - 1)], um = ncol > 1 ? buf[pad(Nk - mp + Lj - 1)] : zero2<C>();
             if (odd) {
-                up = make_double2(-up.x, -up.y);
-                um = make_double2(-um.x, -um.y);
+                up = mk<C>(-up.x, -up.y);
+                um = mk<C>(-um.x, -um.y);
             }
             tp = cadd(tp, up);
             tm = cadd(tm, um);
         }
-        double2 Pv, Qv;
+        C Pv, Qv;
         if (n == 0) {
             Pv = Qv = rot_i(tp, m + eta);
         } else {
-            const double2 A = rot_i(tp, -n);
-            double2 B = rot_i(tm, n);
-            if (mp & 1) B = make_double2(-B.x, -B.y);
+            const C A = rot_i(tp, -n);
+            C B = rot_i(tm, n);
+            if (mp & 1) B = mk<C>(-B.x, -B.y);
             Pv = rot_i(cadd(A, B), m + eta);
             Qv = rot_i(csub(A, B), m + eta);
         }
@@ -357,18 +386,28 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
 
 // ------------------------------------------------------------------------------ launchers
 
-#define S2DW_P_SWITCH(P, KER, GRID, ARGS)                                                        \
-    switch (P) {                                                                                 \
-        case 32: hipLaunchKernelGGL(KER<32>, GRID, dim3(32 / kRM), 0, st, ARGS); break;          \
-        case 64: hipLaunchKernelGGL(KER<64>, GRID, dim3(64 / kRM), 0, st, ARGS); break;          \
-        case 128: hipLaunchKernelGGL(KER<128>, GRID, dim3(128 / kRM), 0, st, ARGS); break;       \
-        case 256: hipLaunchKernelGGL(KER<256>, GRID, dim3(256 / kRM), 0, st, ARGS); break;       \
-        case 512: hipLaunchKernelGGL(KER<512>, GRID, dim3(512 / kRM), 0, st, ARGS); break;       \
-        case 1024: hipLaunchKernelGGL(KER<1024>, GRID, dim3(1024 / kRM), 0, st, ARGS); break;    \
-        case 2048: hipLaunchKernelGGL(KER<2048>, GRID, dim3(2048 / kRM), 0, st, ARGS); break;    \
-        case 4096: hipLaunchKernelGGL(KER<4096>, GRID, dim3(4096 / kRM), 0, st, ARGS); break;    \
-        case 8192: hipLaunchKernelGGL(KER<8192>, GRID, dim3(8192 / kRM), 0, st, ARGS); break;    \
-        default: return hipErrorInvalidValue;                                                    \
+#define S2DW_P_CASE(C, KER, PV, GRID, ARGS) \
+    case PV: hipLaunchKernelGGL((KER<C, PV>), GRID, dim3(PV / kRM), 0, st, ARGS); break;
+
+#define S2DW_P_SWITCH_T(C, P, KER, GRID, ARGS)           \
+    switch (P) {                                          \
+        S2DW_P_CASE(C, KER, 32, GRID, ARGS)               \
+        S2DW_P_CASE(C, KER, 64, GRID, ARGS)               \
+        S2DW_P_CASE(C, KER, 128, GRID, ARGS)              \
+        S2DW_P_CASE(C, KER, 256, GRID, ARGS)              \
+        S2DW_P_CASE(C, KER, 512, GRID, ARGS)              \
+        S2DW_P_CASE(C, KER, 1024, GRID, ARGS)             \
+        S2DW_P_CASE(C, KER, 2048, GRID, ARGS)             \
+        S2DW_P_CASE(C, KER, 4096, GRID, ARGS)             \
+        S2DW_P_CASE(C, KER, 8192, GRID, ARGS)             \
+        default: return hipErrorInvalidValue;             \
+    }
+
+#define S2DW_P_SWITCH(P, KER, GRID, ARGS)                                   \
+    if (ARGS.f32) {                                                         \
+        S2DW_P_SWITCH_T(float2, P, KER, GRID, ARGS)                          \
+    } else {                                                                \
+        S2DW_P_SWITCH_T(double2, P, KER, GRID, ARGS)                         \
     }
 
 hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, hipStream_t st) {
@@ -396,12 +435,12 @@ hipError_t launch_beta_adj_fft(const StageArgs &a, int P, hipStream_t st) {
         const size_t plane = (size_t)a.L * a.T;                                                 \
         if (plane % 2 == 0) {                                                                   \
             const dim3 grid((unsigned)((plane / 2 + 255) / 256));                               \
-            if (a.f32) hipLaunchKernelGGL((KER<float, 2>), grid, dim3(256), 0, st, a);          \
-            else hipLaunchKernelGGL((KER<double, 2>), grid, dim3(256), 0, st, a);               \
+            if (a.f32) hipLaunchKernelGGL((KER<float2, 2>), grid, dim3(256), 0, st, a);         \
+            else hipLaunchKernelGGL((KER<double2, 2>), grid, dim3(256), 0, st, a);              \
         } else {                                                                                \
             const dim3 grid((unsigned)((plane + 255) / 256));                                   \
-            if (a.f32) hipLaunchKernelGGL((KER<float, 1>), grid, dim3(256), 0, st, a);          \
-            else hipLaunchKernelGGL((KER<double, 1>), grid, dim3(256), 0, st, a);               \
+            if (a.f32) hipLaunchKernelGGL((KER<float2, 1>), grid, dim3(256), 0, st, a);         \
+            else hipLaunchKernelGGL((KER<double2, 1>), grid, dim3(256), 0, st, a);              \
         }                                                                                       \
         return hipGetLastError();                                                               \
     }

@@ -120,15 +120,22 @@ def _as_complex(x: torch.Tensor, n: int, what: str) -> torch.Tensor:
     return x.contiguous()
 
 
+def _w_dtype(precision: str):
+    if precision not in ("fp64", "mixed"):
+        raise ValueError(f"precision must be 'fp64' or 'mixed', not {precision!r}")
+    return torch.float64 if precision == "fp64" else torch.float32
+
+
 def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0, *, scaling: bool = True,
-             out: torch.Tensor | None = None, stream=None):
-    """Wavelet coefficients W [S][2N-1][L][2L-1] (float64) and, if scaling, the harmonic
-    scaling coefficients W^Phi_lm (complex128 [L*L])."""
-    p = params(L, N, lam, J_min)
+             out: torch.Tensor | None = None, stream=None, precision: str = "fp64"):
+    """Wavelet coefficients W [S][2N-1][L][2L-1] (float64, or float32 with precision="mixed")
+    and, if scaling, the harmonic scaling coefficients W^Phi_lm (complex128 [L*L])."""
+    p = params(L, N, lam, J_min, precision)
+    wdt = _w_dtype(precision)
     f = _as_complex(flm, L * L, "flm")
     S = num_scales(L, lam, J_min)
-    W = out if out is not None else torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=torch.float64, device=f.device)
-    if W.dtype != torch.float64 or W.numel() != S * (2 * N - 1) * L * (2 * L - 1) or not W.is_contiguous():
+    W = out if out is not None else torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=wdt, device=f.device)
+    if W.dtype != wdt or W.numel() != S * (2 * N - 1) * L * (2 * L - 1) or not W.is_contiguous():
         raise ValueError("W: wrong shape, dtype or layout")
     Wp = torch.empty(L * L, dtype=torch.complex128, device=f.device) if scaling else None
     _check(lib().s2dw_analysis(ctypes.byref(p), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(W.data_ptr()),
@@ -138,11 +145,12 @@ def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0
 
 
 def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,
-              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """f_lm (complex128 [L*L]) from W and the scaling coefficients (or the wavelet part only)."""
-    p = params(L, N, lam, J_min)
+              out: torch.Tensor | None = None, stream=None, precision: str = "fp64") -> torch.Tensor:
+    """f_lm (complex128 [L*L]) from W (float64, or float32 with precision="mixed") and the
+    scaling coefficients (or the wavelet part only)."""
+    p = params(L, N, lam, J_min, precision)
     S = num_scales(L, lam, J_min)
-    if W.dtype != torch.float64 or W.numel() != S * (2 * N - 1) * L * (2 * L - 1) or not W.is_cuda:
+    if W.dtype != _w_dtype(precision) or W.numel() != S * (2 * N - 1) * L * (2 * L - 1) or not W.is_cuda:
         raise ValueError("W: wrong shape or dtype")
     W = W.contiguous()
     wp = _as_complex(Wphi, L * L, "Wphi") if Wphi is not None else None

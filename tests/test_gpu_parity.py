@@ -131,3 +131,29 @@ def test_repeat_calls_are_bitwise_stable():
     r1 = s2dw.synthesis(W1, None, L, N, 2.0, 0)
     r2 = s2dw.synthesis(W1, None, L, N, 2.0, 0)
     assert torch.equal(r1, r2)
+
+
+MIXED_TOL = 1e-5  # FP32 stages: bound on the relative max-error against the FP64 oracle
+
+
+@pytest.mark.parametrize("L,N,J_min,seed", [(32, 4, 0, 0), (70, 5, 2, 4), (130, 2, 3, 5)])
+def test_mixed_precision_against_oracle(L, N, J_min, seed):
+    print(f"mixed precision L={L} N={N} J_min={J_min}", flush=True)
+    lam = 2.0
+    f = random_flm(L, seed)
+    ref = oracle.analysis(f, L, N, lam, J_min)
+    W, Wp = s2dw.analysis(dev(f), L, N, lam, J_min, precision="mixed")
+    assert W.dtype == torch.float32
+    Wh = host(W)
+    errs = [rel(Wh[j], ref[j]) for j in range(ref.shape[0])]
+    print("  analysis per-scale rel. error", ["%.1e" % e for e in errs], flush=True)
+    assert max(errs) < MIXED_TOL
+    S = tables.num_scales(L, lam, J_min)
+    Wa = random_wavelet_samples(S, 2 * N - 1, L, 2 * L - 1, seed).astype(np.float32)
+    refs = oracle.synthesis(Wa.astype(np.float64), None, L, N, lam, J_min)
+    got = host(s2dw.synthesis(dev(Wa), None, L, N, lam, J_min, precision="mixed"))
+    e_syn = rel(got, refs)
+    fr = host(s2dw.synthesis(W, Wp, L, N, lam, J_min, precision="mixed"))
+    e_rt = rel(fr, f)
+    print(f"  synthesis rel. error {e_syn:.1e}, round trip {e_rt:.1e}", flush=True)
+    assert e_syn < MIXED_TOL and e_rt < MIXED_TOL
