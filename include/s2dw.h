@@ -40,8 +40,9 @@
  *  - The library owns per-parameter plans (tables + workspace) in a cache
  *    that s2dw_release_caches() frees.  The first call with new parameters
  *    builds the plan on the host and uploads it (it synchronises the
- *    stream once).  Calls that share a plan must not overlap on different
- *    streams: they share its workspace.
+ *    stream once).  Workspaces are per stream: the first call on a stream
+ *    (or a larger batch) allocates them, and calls on different streams may
+ *    overlap.
  *
  * Errors: every function returns S2DW_OK (0) or a negative code.  Argument
  * errors are found before any device work and leave outputs untouched.
@@ -109,6 +110,29 @@ int s2dw_analysis(const s2dw_params *p, const double *flm, void *W, double *Wphi
  *   flm_out  out: L*L complex.
  */
 int s2dw_synthesis(const s2dw_params *p, const void *W, const double *Wphi_lm, double *flm_out, void *stream);
+
+/*
+ * Batched forms: `count` maps with the same parameters in contiguous arrays, map i at
+ *   flm + i L*L complex, W + i S (2N-1) L (2L-1) elements, Wphi_lm + i L*L complex.
+ * The maps run through the same kernel launches (the map index is a grid dimension), in
+ * chunks of maps whose size the plan holds (see s2dw_autotune).  Each map's result is
+ * bitwise the one of the single-map call.  The calls launch kernels only (no memset
+ * nodes), so after a first call with the same parameters and stream, which allocates the
+ * stream's workspace, they can be captured in a HIP graph.
+ */
+int s2dw_analysis_batched(const s2dw_params *p, int32_t count, const double *flm, void *W, double *Wphi_lm,
+                          void *stream);
+int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, const double *Wphi_lm,
+                           double *flm_out, void *stream);
+
+/*
+ * Autotuner: times round trips (analysis + synthesis) of zero-filled probe maps on
+ * `stream` for each compiled Wigner tile shape (m' slots per wave, 1, 2 or 4 depending on
+ * the number of carried orders) and for batch chunks 1, 2, 4, ... up to min(count, what
+ * fits 8 GiB of workspace), keeps the fastest per map in the plan of p, and reports them.
+ * Synchronises the stream; allocates probe buffers.  slots and chunk may be NULL.
+ */
+int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *slots, int32_t *chunk);
 
 /*
  * Scaling coefficients (Eq. 3, 31): W^Phi_lm = sqrt(4 pi/(2l+1)) f_lm Phi_l0.

@@ -38,6 +38,13 @@ struct Plan {
     int *seede = nullptr;
     int2 *tiles_fwd = nullptr, *tiles_adj = nullptr;
     int nfwd_plain = 0, nfwd_x = 0, nadj_plain = 0, nadj_x = 0;
+    // tile lists per number R of m' slots per wave (the Wigner tile shape), built on demand
+    struct TileSet {
+        int2 *fwd = nullptr, *adj = nullptr;
+        int nfwd_plain = 0, nfwd_x = 0, nadj_plain = 0, nadj_x = 0;
+    };
+    std::map<int, TileSet> tilesets;
+    std::vector<int> seede_h;                   // start-value exponents [Lp][Lp] (host)
     // Bluestein stages: transform sizes and chirp spectra per scale, twiddles per size
     std::vector<int> PA, PB;                    // beta (analysis), alpha (both directions)
     int PD = 0;                                 // beta (synthesis)
@@ -52,15 +59,33 @@ struct Plan {
     std::map<int, float2 *> twPf;
     float *kb2f = nullptr;
     size_t n_kb2 = 0, n_tg = 0;
-    double2 *fpad = nullptr, *U = nullptr, *Ub = nullptr, *Y = nullptr, *Fpart = nullptr;
     int Nh = 0;                                 // orders n >= 0 carried: ceil(N/2)
     int nblk = 0;
+    int chunk = 1;                              // maps per batched launch sequence (tunable)
+    // per-map workspace sizes (complex elements)
+    size_t s_fpad = 0, s_U = 0, s_Ub = 0, s_Y = 0, s_F = 0;
     std::vector<void *> allocs;
     size_t dev_bytes = 0;
-    ~Plan() {
+    // workspaces, one context per stream (calls on different streams may overlap)
+    std::map<void *, std::unique_ptr<struct Work>> work;
+    ~Plan();
+};
+
+// Workspace of one stream: room for `cap` maps of a batch, map i at i * Plan::s_*.
+struct Work {
+    int cap = 0;
+    double2 *fpad = nullptr, *U = nullptr, *Ub = nullptr, *Y = nullptr, *Fpart = nullptr;
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    ~Work() {
         for (void *p : allocs) hipFree(p);
     }
 };
+
+Plan::~Plan() {
+    work.clear();
+    for (void *p : allocs) hipFree(p);
+}
 
 // ----------------------------------------------------------------------- stage timing
 struct Prof {
@@ -178,7 +203,7 @@ bool build_segments(const HostTables &t, SegTab &seg) {
 
 // Tile lists for the Wigner kernels: (m0, m'0) pairs, heaviest first; tiles holding a
 // start value below 2^-1000 go to the extended-exponent list.
-void build_tiles(const Plan &pl, const DeltaTables &dt, int mgroup, std::vector<int2> &plain,
+void build_tiles(const Plan &pl, const std::vector<int> &seede, int Lp, int mgroup, std::vector<int2> &plain,
                  std::vector<int2> &xn) {
     std::vector<std::pair<long, int2>> a, b;
     const int L = pl.L, Lmax = pl.Lmax;
@@ -188,7 +213,7 @@ void build_tiles(const Plan &pl, const DeltaTables &dt, int mgroup, std::vector<
             bool x = false;
             for (int mp = p0; mp < std::min(p0 + mgroup, L) && !x; ++mp)
                 for (int m = m0; m < std::min(m0 + 64, L); ++m)
-                    if (dt.seede[(size_t)mp * dt.Lp + m] < -1000) {
+                    if (seede[(size_t)mp * Lp + m] < -1000) {
                         x = true;
                         break;
                     }
@@ -201,6 +226,50 @@ void build_tiles(const Plan &pl, const DeltaTables &dt, int mgroup, std::vector<
     xn.clear();
     for (auto &e : a) plain.push_back(e.second);
     for (auto &e : b) xn.push_back(e.second);
+}
+
+// Selects the Wigner tile shape: R m' slots per wave (the analysis workgroup covers 4R
+// m', the synthesis one kAdjWaves R).  Tile lists are built once per R.  The caller makes
+// sure that no call of the plan is in flight (workspaces are dropped: the partial-sum
+// buffer depends on R).
+int set_slots(Plan &P, int R) {
+    auto it = P.tilesets.find(R);
+    if (it == P.tilesets.end()) {
+        Plan::TileSet ts;
+        std::vector<int2> pl_a, x_a, pl_s, x_s;
+        build_tiles(P, P.seede_h, P.Lp, 4 * R, pl_a, x_a);
+        build_tiles(P, P.seede_h, P.Lp, kAdjWaves * R, pl_s, x_s);
+        ts.nfwd_plain = (int)pl_a.size();
+        ts.nfwd_x = (int)x_a.size();
+        ts.nadj_plain = (int)pl_s.size();
+        ts.nadj_x = (int)x_s.size();
+        pl_a.insert(pl_a.end(), x_a.begin(), x_a.end());
+        pl_s.insert(pl_s.end(), x_s.begin(), x_s.end());
+        if (!upload(P, ts.fwd, pl_a) || !upload(P, ts.adj, pl_s)) return S2DW_E_NOMEM;
+        it = P.tilesets.emplace(R, ts).first;
+    }
+    const Plan::TileSet &ts = it->second;
+    P.R = R;
+    P.tiles_fwd = ts.fwd;
+    P.tiles_adj = ts.adj;
+    P.nfwd_plain = ts.nfwd_plain;
+    P.nfwd_x = ts.nfwd_x;
+    P.nadj_plain = ts.nadj_plain;
+    P.nadj_x = ts.nadj_x;
+    P.group = kAdjWaves * R;
+    P.nblk = (P.L + P.group - 1) / P.group;
+    const size_t s_F = (size_t)P.nblk * P.L * P.Lp;
+    if (s_F != P.s_F) {
+        P.work.clear();
+        P.s_F = s_F;
+    }
+    return S2DW_OK;
+}
+
+// Default maps per batched launch sequence: as many as fit 8 GiB of workspace, at most 64.
+int default_chunk(const Plan &P) {
+    const double per_map = 16.0 * (double)(P.s_fpad + P.s_U + P.s_Ub + P.s_Y + P.s_F);
+    return (int)std::max(1.0, std::min(64.0, std::floor(8.0 * (1ull << 30) / per_map)));
 }
 
 typedef long double ld;
@@ -368,19 +437,9 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
               upload(P, P.phi, t.phi);
     if (!ok) return S2DW_E_NOMEM;
     // tiles
-    P.R = wig_slots(K);
-    std::vector<int2> pl_a, x_a, pl_s, x_s;
-    build_tiles(P, dt, 4 * P.R, pl_a, x_a);
-    P.group = kAdjWaves * P.R;
-    build_tiles(P, dt, P.group, pl_s, x_s);
-    P.nfwd_plain = (int)pl_a.size();
-    P.nfwd_x = (int)x_a.size();
-    P.nadj_plain = (int)pl_s.size();
-    P.nadj_x = (int)x_s.size();
-    std::vector<int2> ta(pl_a), ts(pl_s);
-    ta.insert(ta.end(), x_a.begin(), x_a.end());
-    ts.insert(ts.end(), x_s.begin(), x_s.end());
-    if (!upload(P, P.tiles_fwd, ta) || !upload(P, P.tiles_adj, ts)) return S2DW_E_NOMEM;
+    P.seede_h = dt.seede;
+    int rc_t = set_slots(P, wig_slots(K));
+    if (rc_t != S2DW_OK) return rc_t;
     // Bluestein chirp spectra (see stages.hip for the convolution layout)
     const int T = M;
     P.PD = pow2_at_least(2 * T - 1);
@@ -434,12 +493,11 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     // workspaces
     int maxLj = 0;
     for (int j = 0; j < t.S; ++j) maxLj = std::max(maxLj, P.sc.Lj[j]);
-    P.nblk = (L + P.group - 1) / P.group;
-    const size_t G = 2 * t.N - 1;
-    if (!dalloc(P, P.fpad, (size_t)L * Lp) || !dalloc(P, P.U, (size_t)std::max<int64_t>(off, 1)) ||
-        !dalloc(P, P.Ub, (size_t)t.N * L * std::max(maxLj, 1)) || !dalloc(P, P.Y, (size_t)P.Nh * L * M) ||
-        !dalloc(P, P.Fpart, (size_t)P.nblk * L * Lp))
-        return S2DW_E_NOMEM;
+    P.s_fpad = (size_t)L * Lp;
+    P.s_U = (size_t)std::max<int64_t>(off, 1);
+    P.s_Ub = (size_t)t.N * L * std::max(maxLj, 1);
+    P.s_Y = (size_t)P.Nh * L * M;
+    P.chunk = default_chunk(P);
     out = pl.release();
     return S2DW_OK;
 }
@@ -496,6 +554,42 @@ int get_plan(int kind, int L, int N, double lam, int J_min, Plan *&out, bool f32
     return f32 ? ensure_f32(*out) : S2DW_OK;
 }
 
+template <typename T>
+bool walloc(Work &w, T *&p, size_t count) {
+    p = nullptr;
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return false;
+    w.allocs.push_back(q);
+    w.bytes += count * sizeof(T);
+    p = (T *)q;
+    return true;
+}
+
+// The workspace of `stream` for a batch of `maps` maps (grown on demand: the first call on a
+// stream, or a larger batch, allocates; the old buffers are freed after the stream drains).
+int get_work(Plan &P, hipStream_t stream, int maps, Work *&out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto &slot = P.work[(void *)stream];
+    if (slot && slot->cap >= maps) {
+        out = slot.get();
+        return S2DW_OK;
+    }
+    if (slot) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return S2DW_E_DEVICE;
+        slot.reset();
+    }
+    std::unique_ptr<Work> w(new (std::nothrow) Work());
+    if (!w) return S2DW_E_NOMEM;
+    const size_t n = (size_t)maps;
+    if (!walloc(*w, w->fpad, n * P.s_fpad) || !walloc(*w, w->U, n * P.s_U) || !walloc(*w, w->Ub, n * P.s_Ub) ||
+        !walloc(*w, w->Y, n * P.s_Y) || !walloc(*w, w->Fpart, n * P.s_F))
+        return S2DW_E_NOMEM;
+    w->cap = maps;
+    slot = std::move(w);
+    out = slot.get();
+    return S2DW_OK;
+}
+
 int check_params(const s2dw_params *p) {
     if (!p) return S2DW_E_ARG;
     if (p->L < 2 || p->L > 4096) return S2DW_E_ARG;
@@ -517,22 +611,25 @@ bool aligned(const void *p) { return ((uintptr_t)p & 7u) == 0; }
         if ((x) != hipSuccess) return S2DW_E_DEVICE;    \
     } while (0)
 
-// Wigner-stage analysis + beta/gamma/alpha sums: coefficients c_lm (m >= 0) -> W.
-int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
+// Wigner-stage analysis + beta/alpha/gamma sums for a batch of `maps` maps: f_lm of map i at
+// flm + i L^2, its W at W + i S (2N-1) L (2L-1) (elements of the W type).
+int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32, hipStream_t st) {
     const int L = P.L;
     {
         Stage sg("pad", st);
-        S2DW_CHECK_HIP(launch_pad_flm(flm, P.fpad, L, P.Lp, st));
+        S2DW_CHECK_HIP(launch_pad_flm(flm, w.fpad, L, P.Lp, P.s_fpad, maps, st));
     }
     WigFwdArgs a{};
-    a.fpad = P.fpad;
+    a.fpad = w.fpad;
     a.pq = P.pq;
     a.uv = P.uv;
     a.kb2 = P.kb2;
     a.seed = P.seed;
     a.seedm = P.seedm;
     a.seede = P.seede;
-    a.U = P.U;
+    a.U = w.U;
+    a.s_fpad = P.s_fpad;
+    a.s_U = P.s_U;
     a.L = L;
     a.Lp = P.Lp;
     a.N = P.ht.N;
@@ -544,21 +641,27 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
         Stage sg("wigner_fwd", st);
         a.tiles = P.tiles_fwd;
         a.nplain = P.nfwd_plain;
-        S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.nfwd_plain + P.nfwd_x, st));
+        S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.R, P.nfwd_plain + P.nfwd_x, maps, st));
     }
     const int N = P.ht.N, G = 2 * N - 1;
     const size_t per_scale = (size_t)G * L * (2 * L - 1);
+    const size_t per_map = per_scale * P.S;
     for (int j = 0; j < P.S; ++j) {
         const int Lj = P.sc.Lj[j];
         void *Wj = f32 ? (void *)((float *)W + per_scale * j) : (void *)((double *)W + per_scale * j);
         if (Lj == 0) {
-            S2DW_CHECK_HIP(launch_zero_words(Wj, per_scale * (f32 ? 1 : 2), st));
+            for (int i = 0; i < maps; ++i) {
+                void *Wij = f32 ? (void *)((float *)Wj + per_map * i) : (void *)((double *)Wj + per_map * i);
+                S2DW_CHECK_HIP(launch_zero_words(Wij, per_scale * (f32 ? 1 : 2), st));
+            }
             continue;
         }
         StageArgs b{};
         b.f32 = f32;
-        b.in = P.U + P.sc.off[j];
-        b.out = P.Ub;
+        b.in = w.U + P.sc.off[j];
+        b.out = w.Ub;
+        b.s_in = P.s_U;
+        b.s_out = P.s_Ub;
         b.hh = f32 ? (const void *)P.hAf[j] : P.hA[j];
         b.tw = f32 ? (const void *)P.twPf[P.PA[j]] : P.twP[P.PA[j]];
         b.csq = f32 ? (const void *)P.csqf : P.csq;
@@ -569,20 +672,24 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
         b.Nh = P.Nh;
         {
             Stage sg("beta_fwd", st);
-            S2DW_CHECK_HIP(launch_beta_fwd_fft(b, P.PA[j], st));
+            S2DW_CHECK_HIP(launch_beta_fwd_fft(b, P.PA[j], maps, st));
         }
         StageArgs c = b;
-        c.in = P.Ub;
-        c.out = P.Y;
+        c.in = w.Ub;
+        c.out = w.Y;
+        c.s_in = P.s_Ub;
+        c.s_out = P.s_Y;
         c.hh = f32 ? (const void *)P.hBf[j] : P.hB[j];
         c.tw = f32 ? (const void *)P.twPf[P.PB[j]] : P.twP[P.PB[j]];
         {
             Stage sg("alpha_fwd", st);
-            S2DW_CHECK_HIP(launch_alpha_fwd_fft(c, P.PB[j], st));
+            S2DW_CHECK_HIP(launch_alpha_fwd_fft(c, P.PB[j], maps, st));
         }
         GammaArgs g{};
         g.wout = Wj;
-        g.in = P.Y;
+        g.in = w.Y;
+        g.s_w = per_map;
+        g.s_y = P.s_Y;
         g.tg = f32 ? (const void *)P.tgff : P.tgf;
         g.L = L;
         g.T = 2 * L - 1;
@@ -591,16 +698,19 @@ int run_inverse(Plan &P, const double2 *flm, void *W, int f32, hipStream_t st) {
         g.f32 = f32;
         {
             Stage sg("gamma_fwd", st);
-            S2DW_CHECK_HIP(launch_gamma_fwd(g, st));
+            S2DW_CHECK_HIP(launch_gamma_fwd(g, maps, st));
         }
     }
     return S2DW_OK;
 }
 
-// alpha/gamma/beta quadratures + Wigner-stage contraction: W -> f_lm.
-int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f32, hipStream_t st) {
+// gamma/alpha/beta quadratures + Wigner-stage contraction for a batch: W -> f_lm (same
+// per-map layout as run_inverse; wphi of map i at wphi + i L^2, or null).
+int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, double2 *flm, int f32,
+                hipStream_t st) {
     const int L = P.L, M = 2 * L - 1, N = P.ht.N, G = 2 * N - 1;
     const size_t per_scale = (size_t)G * L * M;
+    const size_t per_map = per_scale * P.S;
     for (int j = 0; j < P.S; ++j) {
         const int Lj = P.sc.Lj[j];
         if (Lj == 0) continue;
@@ -608,7 +718,9 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
                              : (const void *)((const double *)W + per_scale * j);
         GammaArgs g{};
         g.win = Wj;
-        g.out = P.Y;
+        g.out = w.Y;
+        g.s_w = per_map;
+        g.s_y = P.s_Y;
         g.tg = f32 ? (const void *)P.tgaf : P.tga;
         g.L = L;
         g.T = M;
@@ -617,12 +729,14 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
         g.f32 = f32;
         {
             Stage sg("gamma_adj", st);
-            S2DW_CHECK_HIP(launch_gamma_adj(g, st));
+            S2DW_CHECK_HIP(launch_gamma_adj(g, maps, st));
         }
         StageArgs c{};
         c.f32 = f32;
-        c.in = P.Y;
-        c.out = P.Ub;
+        c.in = w.Y;
+        c.out = w.Ub;
+        c.s_in = P.s_Y;
+        c.s_out = P.s_Ub;
         c.hh = f32 ? (const void *)P.hCf[j] : P.hC[j];
         c.tw = f32 ? (const void *)P.twPf[P.PB[j]] : P.twP[P.PB[j]];
         c.csq = f32 ? (const void *)P.csqf : P.csq;
@@ -635,13 +749,15 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
         c.scale = (2.0 * M_PI / M) * (2.0 * M_PI / G);
         {
             Stage sg("alpha_adj", st);
-            S2DW_CHECK_HIP(launch_alpha_adj_fft(c, P.PB[j], st));
+            S2DW_CHECK_HIP(launch_alpha_adj_fft(c, P.PB[j], maps, st));
         }
         StageArgs v = c;
-        v.in = P.Ub;
+        v.in = w.Ub;
+        v.s_in = P.s_Ub;
         // V of scale j starts sc.off[j] complex elements into the workspace (the synthesis
-        // Wigner kernel indexes it with the same element type)
-        v.out = f32 ? (void *)((float2 *)P.U + P.sc.off[j]) : (void *)(P.U + P.sc.off[j]);
+        // Wigner kernel indexes it with the same element type); per-map stride s_U elements
+        v.out = f32 ? (void *)((float2 *)w.U + P.sc.off[j]) : (void *)(w.U + P.sc.off[j]);
+        v.s_out = P.s_U;
         v.hh = f32 ? (const void *)P.hD1f : P.hD1;
         v.hh2 = f32 ? (const void *)P.hD2f[j] : P.hD2[j];
         v.tw = f32 ? (const void *)P.twPf[P.PD] : P.twP[P.PD];
@@ -649,7 +765,7 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
         v.eta_imag = P.ht.eta_imag ? 1 : 0;
         {
             Stage sg("beta_adj", st);
-            S2DW_CHECK_HIP(launch_beta_adj_fft(v, P.PD, st));
+            S2DW_CHECK_HIP(launch_beta_adj_fft(v, P.PD, maps, st));
         }
     }
     WigAdjArgs a{};
@@ -659,8 +775,10 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
     a.seed = P.seed;
     a.seedm = P.seedm;
     a.seede = P.seede;
-    a.V = P.U;
-    a.Fpart = P.Fpart;
+    a.V = w.U;
+    a.Fpart = w.Fpart;
+    a.s_V = P.s_U;
+    a.s_F = P.s_F;
     a.L = L;
     a.Lp = P.Lp;
     a.group = P.group;
@@ -671,11 +789,12 @@ int run_forward(Plan &P, const void *W, const double2 *wphi, double2 *flm, int f
         Stage sg("wigner_adj", st);
         a.tiles = P.tiles_adj;
         a.nplain = P.nadj_plain;
-        S2DW_CHECK_HIP(launch_wig_adj(a, P.K, P.nadj_plain + P.nadj_x, st));
+        S2DW_CHECK_HIP(launch_wig_adj(a, P.K, P.R, P.nadj_plain + P.nadj_x, maps, st));
     }
     {
         Stage sg("syn_final", st);
-        S2DW_CHECK_HIP(launch_syn_final(P.Fpart, f32, P.nblk, P.group, P.Lmax, P.fac, wphi, P.phi, flm, L, P.Lp, st));
+        S2DW_CHECK_HIP(launch_syn_final(w.Fpart, P.s_F, f32, P.nblk, P.group, P.Lmax, P.fac, wphi, P.phi, flm, L,
+                                        P.Lp, maps, st));
     }
     return S2DW_OK;
 }
@@ -713,33 +832,157 @@ int s2dw_wavelet_bytes(const s2dw_params *p, uint64_t *bytes) {
     return S2DW_OK;
 }
 
-int s2dw_analysis(const s2dw_params *p, const double *flm, void *W, double *Wphi_lm, void *stream) {
+int s2dw_analysis_batched(const s2dw_params *p, int32_t count, const double *flm, void *W, double *Wphi_lm,
+                          void *stream) {
     int rc = check_params(p);
     if (rc != S2DW_OK) return rc;
-    if (!flm || !W || !aligned(flm) || !aligned(W) || (Wphi_lm && !aligned(Wphi_lm))) return S2DW_E_ARG;
+    if (count < 1 || !flm || !W || !aligned(flm) || !aligned(W) || (Wphi_lm && !aligned(Wphi_lm))) return S2DW_E_ARG;
     Plan *P = nullptr;
     const int f32 = p->precision == S2DW_MIXED ? 1 : 0;
     rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0);
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    rc = run_inverse(*P, (const double2 *)flm, W, f32, st);
+    const int chunk = std::max(1, std::min<int>(count, P->chunk));
+    Work *w = nullptr;
+    rc = get_work(*P, st, chunk, w);
     if (rc != S2DW_OK) return rc;
-    if (Wphi_lm) {
-        Stage sg("scaling", st);
-        S2DW_CHECK_HIP(launch_scaling((const double2 *)flm, P->phi, (double2 *)Wphi_lm, p->L, st));
+    const size_t L2 = (size_t)p->L * p->L;
+    const size_t wmap = (size_t)P->S * (2 * p->N - 1) * p->L * (2 * (size_t)p->L - 1) * (f32 ? 4 : 8);
+    for (int i0 = 0; i0 < count; i0 += chunk) {
+        const int n = std::min(chunk, count - i0);
+        rc = run_inverse(*P, *w, n, (const double2 *)flm + L2 * i0, (char *)W + wmap * i0, f32, st);
+        if (rc != S2DW_OK) return rc;
+        if (Wphi_lm) {
+            Stage sg("scaling", st);
+            S2DW_CHECK_HIP(launch_scaling((const double2 *)flm + L2 * i0, P->phi, (double2 *)Wphi_lm + L2 * i0, p->L,
+                                          n, st));
+        }
     }
     return S2DW_OK;
 }
 
-int s2dw_synthesis(const s2dw_params *p, const void *W, const double *Wphi_lm, double *flm_out, void *stream) {
+int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, const double *Wphi_lm,
+                           double *flm_out, void *stream) {
     int rc = check_params(p);
     if (rc != S2DW_OK) return rc;
-    if (!W || !flm_out || !aligned(W) || !aligned(flm_out) || (Wphi_lm && !aligned(Wphi_lm))) return S2DW_E_ARG;
+    if (count < 1 || !W || !flm_out || !aligned(W) || !aligned(flm_out) || (Wphi_lm && !aligned(Wphi_lm)))
+        return S2DW_E_ARG;
     Plan *P = nullptr;
     const int f32 = p->precision == S2DW_MIXED ? 1 : 0;
     rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0);
     if (rc != S2DW_OK) return rc;
-    return run_forward(*P, W, (const double2 *)Wphi_lm, (double2 *)flm_out, f32, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    const int chunk = std::max(1, std::min<int>(count, P->chunk));
+    Work *w = nullptr;
+    rc = get_work(*P, st, chunk, w);
+    if (rc != S2DW_OK) return rc;
+    const size_t L2 = (size_t)p->L * p->L;
+    const size_t wmap = (size_t)P->S * (2 * p->N - 1) * p->L * (2 * (size_t)p->L - 1) * (f32 ? 4 : 8);
+    for (int i0 = 0; i0 < count; i0 += chunk) {
+        const int n = std::min(chunk, count - i0);
+        rc = run_forward(*P, *w, n, (const char *)W + wmap * i0, Wphi_lm ? (const double2 *)Wphi_lm + L2 * i0 : nullptr,
+                         (double2 *)flm_out + L2 * i0, f32, st);
+        if (rc != S2DW_OK) return rc;
+    }
+    return S2DW_OK;
+}
+
+int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *slots, int32_t *chunk) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    if (count < 1) return S2DW_E_ARG;
+    Plan *P = nullptr;
+    const int f32 = p->precision == S2DW_MIXED ? 1 : 0;
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0);
+    if (rc != S2DW_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return S2DW_E_DEVICE;
+    int cmax = std::min<int>(count, std::max(default_chunk(*P), 1));
+    // probe buffers (zero coefficients: the kernels have no data-dependent control flow)
+    const size_t L2 = (size_t)p->L * p->L;
+    const size_t wmap = (size_t)P->S * (2 * p->N - 1) * p->L * (2 * (size_t)p->L - 1) * (f32 ? 4 : 8);
+    void *fin = nullptr, *wbuf = nullptr, *fout = nullptr;
+    if (hipMalloc(&fin, 16 * L2 * cmax) != hipSuccess) return S2DW_E_NOMEM;
+    if (hipMalloc(&wbuf, wmap * cmax) != hipSuccess || hipMalloc(&fout, 16 * L2 * cmax) != hipSuccess) {
+        hipFree(fin);
+        if (wbuf) hipFree(wbuf);
+        return S2DW_E_NOMEM;
+    }
+    hipMemset(fin, 0, 16 * L2 * cmax);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    s2dw_params q = *p;
+    // seconds per map of a round trip with tile shape R and batch chunk c
+    auto trial = [&](int R, int c, double &sec) -> int {
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            int r2 = set_slots(*P, R);
+            if (r2 != S2DW_OK) return r2;
+            P->chunk = c;
+        }
+        for (int it = 0; it < 3; ++it) {
+            if (it == 1) hipEventRecord(e0, st);
+            int r2 = s2dw_analysis_batched(&q, c, (const double *)fin, wbuf, nullptr, st);
+            if (r2 == S2DW_OK) r2 = s2dw_synthesis_batched(&q, c, wbuf, nullptr, (double *)fout, st);
+            if (r2 != S2DW_OK) return r2;
+        }
+        hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) return S2DW_E_DEVICE;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        sec = ms * 1e-3 / (2.0 * c);
+        return S2DW_OK;
+    };
+    int Ropt[3];
+    const int nR = wig_slot_options(P->K, Ropt);
+    int bestR = P->R, bestC = cmax;
+    double best = 1e30;
+    for (int i = 0; i < nR && rc == S2DW_OK; ++i) {
+        double sec = 0;
+        rc = trial(Ropt[i], cmax, sec);
+        if (rc == S2DW_OK && sec < best) {
+            best = sec;
+            bestR = Ropt[i];
+        }
+    }
+    best = 1e30;
+    for (int c = 1; c <= cmax && rc == S2DW_OK; c *= 2) {
+        double sec = 0;
+        rc = trial(bestR, c, sec);
+        if (rc == S2DW_OK && sec < best * 0.97) {  // a larger batch must win by 3%
+            best = sec;
+            bestC = c;
+        }
+    }
+    if (rc == S2DW_OK && cmax & (cmax - 1)) {  // the largest chunk when it is not a power of two
+        double sec = 0;
+        rc = trial(bestR, cmax, sec);
+        if (rc == S2DW_OK && sec < best * 0.97) bestC = cmax;
+    }
+    hipStreamSynchronize(st);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(fin);
+    hipFree(wbuf);
+    hipFree(fout);
+    if (rc != S2DW_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        rc = set_slots(*P, bestR);
+        P->chunk = bestC;
+    }
+    if (slots) *slots = bestR;
+    if (chunk) *chunk = bestC;
+    return rc;
+}
+
+int s2dw_analysis(const s2dw_params *p, const double *flm, void *W, double *Wphi_lm, void *stream) {
+    return s2dw_analysis_batched(p, 1, flm, W, Wphi_lm, stream);
+}
+
+int s2dw_synthesis(const s2dw_params *p, const void *W, const double *Wphi_lm, double *flm_out, void *stream) {
+    return s2dw_synthesis_batched(p, 1, W, Wphi_lm, flm_out, stream);
 }
 
 int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, double *Wphi_map, void *stream) {
@@ -751,14 +994,20 @@ int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, doubl
     rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P);
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
+    Work *w = nullptr;
+    rc = get_work(*P, st, 1, w);
+    if (rc != S2DW_OK) return rc;
     double2 *wphi = (double2 *)Wphi_lm;
-    if (!wphi) wphi = P->fpad;  // scratch: L*Lp >= L*L complex
-    S2DW_CHECK_HIP(launch_scaling((const double2 *)flm, P->phi, wphi, p->L, st));
+    if (!wphi) wphi = w->fpad;  // scratch: L*Lp >= L*L complex
+    S2DW_CHECK_HIP(launch_scaling((const double2 *)flm, P->phi, wphi, p->L, 1, st));
     if (Wphi_map) {
         Plan *Q = nullptr;
         rc = get_plan(kShtInverse, p->L, 1, 0.0, 0, Q);
         if (rc != S2DW_OK) return rc;
-        rc = run_inverse(*Q, wphi, Wphi_map, 0, st);
+        Work *wq = nullptr;
+        rc = get_work(*Q, st, 1, wq);
+        if (rc != S2DW_OK) return rc;
+        rc = run_inverse(*Q, *wq, 1, wphi, Wphi_map, 0, st);
     }
     return rc;
 }
@@ -769,7 +1018,10 @@ int s2dw_sht_forward(const s2dw_params *p, const double *f_map, double *flm, voi
     Plan *Q = nullptr;
     int rc = get_plan(kShtForward, p->L, 1, 0.0, 0, Q);
     if (rc != S2DW_OK) return rc;
-    return run_forward(*Q, f_map, nullptr, (double2 *)flm, 0, (hipStream_t)stream);
+    Work *w = nullptr;
+    rc = get_work(*Q, (hipStream_t)stream, 1, w);
+    if (rc != S2DW_OK) return rc;
+    return run_forward(*Q, *w, 1, f_map, nullptr, (double2 *)flm, 0, (hipStream_t)stream);
 }
 
 int s2dw_sht_inverse(const s2dw_params *p, const double *flm, double *f_map, void *stream) {
@@ -778,7 +1030,10 @@ int s2dw_sht_inverse(const s2dw_params *p, const double *flm, double *f_map, voi
     Plan *Q = nullptr;
     int rc = get_plan(kShtInverse, p->L, 1, 0.0, 0, Q);
     if (rc != S2DW_OK) return rc;
-    return run_inverse(*Q, (const double2 *)flm, f_map, 0, (hipStream_t)stream);
+    Work *w = nullptr;
+    rc = get_work(*Q, (hipStream_t)stream, 1, w);
+    if (rc != S2DW_OK) return rc;
+    return run_inverse(*Q, *w, 1, (const double2 *)flm, f_map, 0, (hipStream_t)stream);
 }
 
 int s2dw_wavelet_tables(const s2dw_params *p, double *kappa, double *phi, double *s_ln) {

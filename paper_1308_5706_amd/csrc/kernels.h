@@ -20,6 +20,7 @@ struct WigFwdArgs {
     const int2 *tiles;     // (m0, m'0) per workgroup
     int nplain;            // workgroups [0, nplain) take plain tiles, the rest extended-exponent ones
     double2 *U;            // workspace; scale j at sc.off[j]: [N][Lj][Lj] = [n][m][m']
+    size_t s_fpad, s_U;    // per-map strides (elements) of a batch; map = blockIdx.y
     int L, Lp, N, eoff;    // eoff = 3 when eta_N = i (conj(eta) = i^3), else 0
     int nk[kMaxK];
     SegTab seg;
@@ -37,14 +38,16 @@ struct WigAdjArgs {
     int nplain;
     const void *V;         // scale j at sc.off[j]: [K][2][Lj][Lj] = [k][P|Q][m][m'], double2 or float2
     void *Fpart;           // [L / group][L][Lp] partial sums over each m' group, double2 or float2
+    size_t s_V, s_F;       // per-map strides (complex elements) of a batch; map = blockIdx.y
     int L, Lp, group, f32;
     SegTab seg;
     ScaleTab sc;
 };
 
-int wig_slots(int K);
-hipError_t launch_wig_fwd(const WigFwdArgs &a, int K, int ntiles, hipStream_t st);
-hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int ntiles, hipStream_t st);
+int wig_slots(int K);                        // default m' slots per wave for K carried orders
+int wig_slot_options(int K, int *R);          // compiled slot counts for K (up to 3), returns how many
+hipError_t launch_wig_fwd(const WigFwdArgs &a, int K, int R, int ntiles, int maps, hipStream_t st);
+hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int R, int ntiles, int maps, hipStream_t st);
 
 // ---------------------------------------------------------------- beta / alpha / gamma stages
 // Bluestein stages (stages.hip).  Layouts per scale j (Lj = band-limit of the scale,
@@ -63,14 +66,16 @@ struct StageArgs {
     const void *tw;        // e^{-2 pi i k/P}, k < P
     const void *csq;       // e^{i pi i^2/T}, i < T, T = 2L - 1
     const void *cpp;       // e^{i pi p(p+1)/T} at p + L - 1, |p| < L
+    size_t s_in, s_out;    // per-map strides (complex elements) of a batch; map = blockIdx.y
     int L, Lj, N, Nh, K, eta_imag, f32;
     int nk[kMaxK];
     double scale;
 };
-hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, hipStream_t st);
-hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, hipStream_t st);
-hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, hipStream_t st);
-hipError_t launch_beta_adj_fft(const StageArgs &a, int P, hipStream_t st);
+// Every launcher takes the number of maps of the batch (grid y).
+hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st);
+hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st);
+hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
+hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 
 struct GammaArgs {
     const void *win;       // W read (synthesis): double, or float if f32
@@ -78,17 +83,20 @@ struct GammaArgs {
     const void *in;        // Y (analysis): double2, or float2 if f32
     void *out;             // X (synthesis)
     const void *tg;        // [2N-1][Nh]: (1 or 2) e^{i n gamma_g} (analysis), e^{-i n gamma_g} (synthesis)
+    size_t s_w, s_y;       // per-map strides of W (real elements) and of Y / X (complex); map = blockIdx.y
     int L, T, G, Nh, f32;
 };
-hipError_t launch_gamma_fwd(const GammaArgs &a, hipStream_t st);
-hipError_t launch_gamma_adj(const GammaArgs &a, hipStream_t st);
+hipError_t launch_gamma_fwd(const GammaArgs &a, int maps, hipStream_t st);
+hipError_t launch_gamma_adj(const GammaArgs &a, int maps, hipStream_t st);
 
 // --------------------------------------------------------------------------------- misc
 
-hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, hipStream_t st);
-hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, hipStream_t st);
-hipError_t launch_syn_final(const void *Fpart, int f32, int nblk, int group, int Lmax, const double *fac,
-                            const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, hipStream_t st);
+// maps: number of maps of a batch (grid z); f_lm, W^Phi_lm of map i at i L^2, workspaces at i s_*.
+hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad, int maps, hipStream_t st);
+hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, int maps, hipStream_t st);
+hipError_t launch_syn_final(const void *Fpart, size_t s_F, int f32, int nblk, int group, int Lmax, const double *fac,
+                            const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, int maps,
+                            hipStream_t st);
 hipError_t launch_zero_words(void *p, size_t n, hipStream_t st);
 hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t st);
 

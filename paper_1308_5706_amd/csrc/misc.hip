@@ -6,15 +6,18 @@ namespace s2dw {
 
 // ---------------------------------------------------------------------------------- misc
 
-__global__ void pad_flm_kernel(const double2 *flm, double2 *fpad, int L, int Lp) {
+// Batched small kernels: map = blockIdx.z; f_lm and W^Phi_lm of map i start at i L^2.
+__global__ void pad_flm_kernel(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int l = blockIdx.y;
     if (m >= Lp) return;
+    flm += (size_t)blockIdx.z * L * L;
+    fpad += (size_t)blockIdx.z * s_fpad;
     fpad[(size_t)l * Lp + m] = (m <= l) ? flm[(size_t)l * l + l + m] : make_double2(0.0, 0.0);
 }
 
-hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, hipStream_t st) {
-    hipLaunchKernelGGL(pad_flm_kernel, dim3((Lp + 255) / 256, L), dim3(256), 0, st, flm, fpad, L, Lp);
+hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad, int maps, hipStream_t st) {
+    hipLaunchKernelGGL(pad_flm_kernel, dim3((Lp + 255) / 256, L, maps), dim3(256), 0, st, flm, fpad, L, Lp, s_fpad);
     return hipGetLastError();
 }
 
@@ -23,14 +26,14 @@ __global__ void scaling_kernel(const double2 *flm, const double *phi, double2 *w
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int l = blockIdx.y;
     if (m > 2 * l) return;
-    const size_t i = (size_t)l * l + m;
+    const size_t i = (size_t)blockIdx.z * L * L + (size_t)l * l + m;
     const double c = sqrt(4.0 * 3.14159265358979323846 / (2.0 * l + 1.0)) * phi[l];
     const double2 f = flm[i];
     wphi[i] = make_double2(c * f.x, c * f.y);
 }
 
-hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, hipStream_t st) {
-    hipLaunchKernelGGL(scaling_kernel, dim3((2 * L - 1 + 255) / 256, L), dim3(256), 0, st, flm, phi, wphi, L);
+hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, int maps, hipStream_t st) {
+    hipLaunchKernelGGL(scaling_kernel, dim3((2 * L - 1 + 255) / 256, L, maps), dim3(256), 0, st, flm, phi, wphi, L);
     return hipGetLastError();
 }
 
@@ -39,11 +42,14 @@ hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, 
 // Fpart holds double2 (FP64 path) or float2 (mixed precision) partial sums; the final sum
 // over the m' groups and the harmonic synthesis factor are applied in FP64.
 template <class VC>
-__global__ void syn_final_kernel(const VC *Fpart, int nblk, int group, int Lmax, const double *fac,
+__global__ void syn_final_kernel(const VC *Fpart, size_t s_F, int nblk, int group, int Lmax, const double *fac,
                                  const double2 *wphi, const double *phi, double2 *flm, int L, int Lp) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int l = blockIdx.y;
     if (m > l) return;
+    Fpart += (size_t)blockIdx.z * s_F;
+    flm += (size_t)blockIdx.z * L * L;
+    if (wphi) wphi += (size_t)blockIdx.z * L * L;
     double fr = 0.0, fi = 0.0;
     // no wavelet coefficient reaches l >= Lmax; blocks starting above l hold no term of row l
     const int gmax = (l < Lmax && m < Lmax) ? min(nblk - 1, l / group) : -1;
@@ -67,14 +73,16 @@ __global__ void syn_final_kernel(const VC *Fpart, int nblk, int group, int Lmax,
     }
 }
 
-hipError_t launch_syn_final(const void *Fpart, int f32, int nblk, int group, int Lmax, const double *fac,
-                            const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, hipStream_t st) {
+hipError_t launch_syn_final(const void *Fpart, size_t s_F, int f32, int nblk, int group, int Lmax, const double *fac,
+                            const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, int maps,
+                            hipStream_t st) {
+    const dim3 grid((L + 255) / 256, L, maps);
     if (f32)
-        hipLaunchKernelGGL(syn_final_kernel<float2>, dim3((L + 255) / 256, L), dim3(256), 0, st, (const float2 *)Fpart,
-                           nblk, group, Lmax, fac, wphi, phi, flm, L, Lp);
+        hipLaunchKernelGGL(syn_final_kernel<float2>, grid, dim3(256), 0, st, (const float2 *)Fpart, s_F, nblk, group,
+                           Lmax, fac, wphi, phi, flm, L, Lp);
     else
-        hipLaunchKernelGGL(syn_final_kernel<double2>, dim3((L + 255) / 256, L), dim3(256), 0, st,
-                           (const double2 *)Fpart, nblk, group, Lmax, fac, wphi, phi, flm, L, Lp);
+        hipLaunchKernelGGL(syn_final_kernel<double2>, grid, dim3(256), 0, st, (const double2 *)Fpart, s_F, nblk,
+                           group, Lmax, fac, wphi, phi, flm, L, Lp);
     return hipGetLastError();
 }
 

@@ -74,11 +74,11 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const 
     const int ni = col / Lj, m = col - ni * Lj;
     const int n = 2 * ni - (a.N - 1);
     const bool odd = ((m + n) & 1) != 0;
-    const double2 *__restrict__ Uc = (const double2 *)a.in + (size_t)col * Lj;
+    const double2 *__restrict__ Uc = (const double2 *)a.in + blockIdx.y * a.s_in + (size_t)col * Lj;
     const C *__restrict__ cpp = (const C *)a.cpp + (L - 1);
     const C *__restrict__ csq = (const C *)a.csq;
     const int Na = 2 * Lj - 1;
-    C *__restrict__ out = (C *)a.out + (size_t)col * L;
+    C *__restrict__ out = (C *)a.out + blockIdx.y * a.s_out + (size_t)col * L;
     auto in = [&](int i) {
         if (i >= Na) return zero2<C>();
         const int mp = i - (Lj - 1);
@@ -123,8 +123,8 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const
     const int b = t / Nh, np = t - (t / Nh) * Nh;
     const int ni = (N / 2) + np, nj = N - 1 - ni;  // rows of n >= 0 and of -n
     const bool zero_n = ni == nj;
-    const C *__restrict__ Up = (const C *)a.in + (size_t)ni * Lj * L + b;
-    const C *__restrict__ Um = (const C *)a.in + (size_t)nj * Lj * L + b;
+    const C *__restrict__ Up = (const C *)a.in + blockIdx.y * a.s_in + (size_t)ni * Lj * L + b;
+    const C *__restrict__ Um = (const C *)a.in + blockIdx.y * a.s_in + (size_t)nj * Lj * L + b;
     const C *__restrict__ csq = (const C *)a.csq;
     const int Na = 2 * Lj - 1;
     auto in = [&](int i) {
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const
         }
         return cmul(c, csq[m < 0 ? -m : m]);
     };
-    C *__restrict__ Y = (C *)a.out + ((size_t)np * L + b) * T;
+    C *__restrict__ Y = (C *)a.out + blockIdx.y * a.s_out + ((size_t)np * L + b) * T;
     auto st = [&](int i, C v) {
         const int x = i - (Na - 1);
         if (x >= 0 && x < T) Y[x] = cmul(v, csq[x]);
@@ -157,14 +157,14 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const
     const int b = t / Nh, np = t - (t / Nh) * Nh;
     const int ni = (N / 2) + np, nj = N - 1 - ni;
     const bool zero_n = ni == nj;
-    const C *__restrict__ X = (const C *)a.in + ((size_t)np * L + b) * T;
+    const C *__restrict__ X = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)np * L + b) * T;
     const C *__restrict__ csq = (const C *)a.csq;
     auto in = [&](int i) { return i < T ? cmulc(X[i], csq[i]) : zero2<C>(); };
     // Zh(m), q = m + Lj - 1 < 2Lj - 1, comes out at q + T - 1
     const int Nk = 2 * Lj - 1;
     const real_t<C> s = (real_t<C>)a.scale;
-    C *__restrict__ Gp = (C *)a.out + (size_t)ni * Lj * L + b;
-    C *__restrict__ Gm = (C *)a.out + (size_t)nj * Lj * L + b;
+    C *__restrict__ Gp = (C *)a.out + blockIdx.y * a.s_out + (size_t)ni * Lj * L + b;
+    C *__restrict__ Gm = (C *)a.out + blockIdx.y * a.s_out + (size_t)nj * Lj * L + b;
     auto st = [&](int i, C v) {
         const int q = i - (T - 1);
         if (q >= 0 && q < Nk) {
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) gamma_fwd_kernel(const GammaArgs a) {
     const size_t plane = (size_t)a.L * a.T;
     const size_t e0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * V;
     if (e0 >= plane) return;
-    const C *__restrict__ Y = (const C *)a.in;
+    const C *__restrict__ Y = (const C *)a.in + blockIdx.y * a.s_y;
     const C *__restrict__ tg = (const C *)a.tg;
     C y[kMaxK][V];
 #pragma unroll
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(256) gamma_fwd_kernel(const GammaArgs a) {
 #pragma unroll
             for (int v = 0; v < V; ++v) y[k][v] = nt_load(Y + k * plane + e0 + v);
         }
-    R *__restrict__ W = (R *)a.wout;
+    R *__restrict__ W = (R *)a.wout + blockIdx.y * a.s_w;
     for (int g = 0; g < a.G; ++g) {
         R acc[V];
 #pragma unroll
@@ -252,9 +252,9 @@ __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
     const size_t plane = (size_t)a.L * a.T;
     const size_t e0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * V;
     if (e0 >= plane) return;
-    const R *__restrict__ W = (const R *)a.win;
+    const R *__restrict__ W = (const R *)a.win + blockIdx.y * a.s_w;
     const C *__restrict__ tg = (const C *)a.tg;
-    C *__restrict__ X = (C *)a.out;
+    C *__restrict__ X = (C *)a.out + blockIdx.y * a.s_y;
     C x[kMaxK][V];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
@@ -314,11 +314,11 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
     const int Nk = 2 * Lj - 1;
     const C *__restrict__ csq = (const C *)a.csq;
     const C *__restrict__ cpp = (const C *)a.cpp;
-    C *__restrict__ Po = (C *)a.out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
-    C *__restrict__ Qo = (C *)a.out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
+    C *__restrict__ Po = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
+    C *__restrict__ Qo = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
-        const C *__restrict__ Gc = (const C *)a.in + ((size_t)ni * Lj + m) * L;
+        const C *__restrict__ Gc = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)ni * Lj + m) * L;
         auto in1 = [&](int i) {
             if (i >= T) return zero2<C>();
             C v = i < L ? Gc[i] : Gc[2 * L - 2 - i];
@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
 // ------------------------------------------------------------------------------ launchers
 
 #define S2DW_P_CASE(C, KER, PV, GRID, ARGS) \
-    case PV: hipLaunchKernelGGL((KER<C, PV>), GRID, dim3(PV / kRM), 0, st, ARGS); break;
+    case PV: hipLaunchKernelGGL((KER<C, PV>), dim3(GRID, maps), dim3(PV / kRM), 0, st, ARGS); break;
 
 #define S2DW_P_SWITCH_T(C, P, KER, GRID, ARGS)           \
     switch (P) {                                          \
@@ -410,23 +410,23 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
         S2DW_P_SWITCH_T(double2, P, KER, GRID, ARGS)                         \
     }
 
-hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, hipStream_t st) {
-    S2DW_P_SWITCH(P, beta_fwd_fft_kernel, dim3(a.N * a.Lj), a)
+hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
+    S2DW_P_SWITCH(P, beta_fwd_fft_kernel, a.N * a.Lj, a)
     return hipGetLastError();
 }
 
-hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, hipStream_t st) {
-    S2DW_P_SWITCH(P, alpha_fwd_fft_kernel, dim3(8 * ((a.Nh * a.L + 7) / 8)), a)
+hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
+    S2DW_P_SWITCH(P, alpha_fwd_fft_kernel, 8 * ((a.Nh * a.L + 7) / 8), a)
     return hipGetLastError();
 }
 
-hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, hipStream_t st) {
-    S2DW_P_SWITCH(P, alpha_adj_fft_kernel, dim3(8 * ((a.Nh * a.L + 7) / 8)), a)
+hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
+    S2DW_P_SWITCH(P, alpha_adj_fft_kernel, 8 * ((a.Nh * a.L + 7) / 8), a)
     return hipGetLastError();
 }
 
-hipError_t launch_beta_adj_fft(const StageArgs &a, int P, hipStream_t st) {
-    S2DW_P_SWITCH(P, beta_adj_fft_kernel, dim3(a.K * a.Lj), a)
+hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
+    S2DW_P_SWITCH(P, beta_adj_fft_kernel, a.K * a.Lj, a)
     return hipGetLastError();
 }
 
@@ -434,19 +434,19 @@ hipError_t launch_beta_adj_fft(const StageArgs &a, int P, hipStream_t st) {
     {                                                                                           \
         const size_t plane = (size_t)a.L * a.T;                                                 \
         if (plane % 2 == 0) {                                                                   \
-            const dim3 grid((unsigned)((plane / 2 + 255) / 256));                               \
+            const dim3 grid((unsigned)((plane / 2 + 255) / 256), maps);                               \
             if (a.f32) hipLaunchKernelGGL((KER<float2, 2>), grid, dim3(256), 0, st, a);         \
             else hipLaunchKernelGGL((KER<double2, 2>), grid, dim3(256), 0, st, a);              \
         } else {                                                                                \
-            const dim3 grid((unsigned)((plane + 255) / 256));                                   \
+            const dim3 grid((unsigned)((plane + 255) / 256), maps);                                   \
             if (a.f32) hipLaunchKernelGGL((KER<float2, 1>), grid, dim3(256), 0, st, a);         \
             else hipLaunchKernelGGL((KER<double2, 1>), grid, dim3(256), 0, st, a);              \
         }                                                                                       \
         return hipGetLastError();                                                               \
     }
 
-hipError_t launch_gamma_fwd(const GammaArgs &a, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_fwd_kernel)
+hipError_t launch_gamma_fwd(const GammaArgs &a, int maps, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_fwd_kernel)
 
-hipError_t launch_gamma_adj(const GammaArgs &a, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_adj_kernel)
+hipError_t launch_gamma_adj(const GammaArgs &a, int maps, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_adj_kernel)
 
 }  // namespace s2dw

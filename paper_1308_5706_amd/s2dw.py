@@ -52,7 +52,11 @@ def lib():
                            ("s2dw_synthesis", [cp, vp, vp, vp, vp]),
                            ("s2dw_scaling", [cp, vp, vp, vp, vp]),
                            ("s2dw_sht_forward", [cp, vp, vp, vp]),
-                           ("s2dw_sht_inverse", [cp, vp, vp, vp])]:
+                           ("s2dw_sht_inverse", [cp, vp, vp, vp]),
+                           ("s2dw_analysis_batched", [cp, ctypes.c_int32, vp, vp, vp, vp]),
+                           ("s2dw_synthesis_batched", [cp, ctypes.c_int32, vp, vp, vp, vp]),
+                           ("s2dw_autotune", [cp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)])]:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
@@ -71,6 +75,7 @@ def lib():
 
 
 EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_analysis", "s2dw_synthesis",
+            "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_autotune",
             "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
             "s2dw_profile_read",
             "s2dw_strerror", "s2dw_release_caches"]
@@ -159,6 +164,56 @@ def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: f
                                 ctypes.c_void_p(wp.data_ptr() if wp is not None else None),
                                 ctypes.c_void_p(f.data_ptr()), _stream(stream)), "s2dw_synthesis")
     return f
+
+
+def analysis_batched(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0, *, scaling: bool = True,
+                     out: torch.Tensor | None = None, stream=None, precision: str = "fp64"):
+    """A batch of maps with the same parameters: flm complex128 [B][L*L] -> W [B][S][2N-1][L][2L-1]
+    (float64 or float32) and, if scaling, W^Phi complex128 [B][L*L]."""
+    p = params(L, N, lam, J_min, precision)
+    wdt = _w_dtype(precision)
+    if flm.dim() != 2 or flm.shape[1] != L * L:
+        raise ValueError("flm: expected [B][L*L] complex128")
+    B = flm.shape[0]
+    f = _as_complex(flm, B * L * L, "flm")
+    S = num_scales(L, lam, J_min)
+    W = out if out is not None else torch.empty((B, S, 2 * N - 1, L, 2 * L - 1), dtype=wdt, device=f.device)
+    if W.dtype != wdt or W.numel() != B * S * (2 * N - 1) * L * (2 * L - 1) or not W.is_contiguous():
+        raise ValueError("W: wrong shape, dtype or layout")
+    Wp = torch.empty((B, L * L), dtype=torch.complex128, device=f.device) if scaling else None
+    _check(lib().s2dw_analysis_batched(ctypes.byref(p), B, ctypes.c_void_p(f.data_ptr()),
+                                       ctypes.c_void_p(W.data_ptr()),
+                                       ctypes.c_void_p(Wp.data_ptr() if Wp is not None else None), _stream(stream)),
+           "s2dw_analysis_batched")
+    return W, Wp
+
+
+def synthesis_batched(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0,
+                      J_min: int = 0, *, out: torch.Tensor | None = None, stream=None,
+                      precision: str = "fp64") -> torch.Tensor:
+    """A batch of maps: W [B][S][2N-1][L][2L-1] (+ W^Phi [B][L*L]) -> f_lm complex128 [B][L*L]."""
+    p = params(L, N, lam, J_min, precision)
+    S = num_scales(L, lam, J_min)
+    B = W.shape[0]
+    if W.dtype != _w_dtype(precision) or W.numel() != B * S * (2 * N - 1) * L * (2 * L - 1) or not W.is_cuda:
+        raise ValueError("W: wrong shape or dtype")
+    W = W.contiguous()
+    wp = _as_complex(Wphi, B * L * L, "Wphi") if Wphi is not None else None
+    f = out if out is not None else torch.empty((B, L * L), dtype=torch.complex128, device=W.device)
+    _check(lib().s2dw_synthesis_batched(ctypes.byref(p), B, ctypes.c_void_p(W.data_ptr()),
+                                        ctypes.c_void_p(wp.data_ptr() if wp is not None else None),
+                                        ctypes.c_void_p(f.data_ptr()), _stream(stream)), "s2dw_synthesis_batched")
+    return f
+
+
+def autotune(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1, precision: str = "fp64",
+             stream=None):
+    """Times the compiled Wigner tile shapes and batch chunks for these parameters and keeps
+    the fastest in the library's plan; returns (m' slots per wave, maps per chunk)."""
+    sl, ch = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().s2dw_autotune(ctypes.byref(params(L, N, lam, J_min, precision)), count, _stream(stream),
+                               ctypes.byref(sl), ctypes.byref(ch)), "s2dw_autotune")
+    return sl.value, ch.value
 
 
 def scaling(flm: torch.Tensor, L: int, N: int = 1, lam: float = 2.0, J_min: int = 0, *, sphere_map: bool = False,

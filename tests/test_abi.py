@@ -95,3 +95,15 @@ def test_library_tables_match_oracle_tables(L, N, lam, J_min):
     assert np.array_equal(kap > 0, ok > 0)
     assert np.max(np.abs(phi - tables.phi_table(L, lam, J_min))) < 2e-15
     assert np.max(np.abs(s - tables.directionality(L, N))) < 2e-16
+
+
+def test_batched_and_autotune_argument_errors():
+    lib = s2dw.lib()
+    p = s2dw.params(64, 4, 2.0, 0)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.s2dw_analysis_batched(ctypes.byref(p), 0, fake, fake, None, None) == -1
+    assert lib.s2dw_synthesis_batched(ctypes.byref(p), -2, fake, None, fake, None) == -1
+    assert lib.s2dw_analysis_batched(ctypes.byref(p), 2, None, fake, None, None) == -1
+    assert lib.s2dw_autotune(ctypes.byref(p), 0, None, None, None) == -1
+    bad = s2dw.Params(64, 4, 2.0, 0, 0, 7, 1)  # unknown precision
+    assert lib.s2dw_analysis_batched(ctypes.byref(bad), 1, fake, fake, None, None) == -1
