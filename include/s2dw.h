@@ -135,6 +135,15 @@ int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, c
 int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *slots, int32_t *chunk);
 
 /*
+ * Device memory queries for admission control (serving):
+ *   s2dw_workspace_bytes: bytes of the workspace one stream holds for a batch of `count`
+ *     maps with parameters p (builds the plan of p on first use);
+ *   s2dw_cache_bytes: bytes held now by all plans (tables) and stream workspaces.
+ */
+int s2dw_workspace_bytes(const s2dw_params *p, int32_t count, uint64_t *bytes);
+int s2dw_cache_bytes(uint64_t *bytes);
+
+/*
  * Scaling coefficients (Eq. 3, 31): W^Phi_lm = sqrt(4 pi/(2l+1)) f_lm Phi_l0.
  *   Wphi_lm  out: L*L complex, or NULL.
  *   Wphi_map out: real [L][2L-1] sphere map of the scaling coefficients

@@ -977,6 +977,31 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     return rc;
 }
 
+int s2dw_workspace_bytes(const s2dw_params *p, int32_t count, uint64_t *bytes) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    if (count < 1 || !bytes) return S2DW_E_ARG;
+    Plan *P = nullptr;
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, p->precision == S2DW_MIXED);
+    if (rc != S2DW_OK) return rc;
+    const uint64_t per_map = 16ull * (P->s_fpad + P->s_U + P->s_Ub + P->s_Y + P->s_F);
+    *bytes = per_map * (uint64_t)std::min<int>(count, std::max(P->chunk, 1));
+    return S2DW_OK;
+}
+
+int s2dw_cache_bytes(uint64_t *bytes) {
+    if (!bytes) return S2DW_E_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint64_t b = 0;
+    for (auto &kv : g_plans) {
+        b += kv.second->dev_bytes;
+        for (auto &w : kv.second->work)
+            if (w.second) b += w.second->bytes;
+    }
+    *bytes = b;
+    return S2DW_OK;
+}
+
 int s2dw_analysis(const s2dw_params *p, const double *flm, void *W, double *Wphi_lm, void *stream) {
     return s2dw_analysis_batched(p, 1, flm, W, Wphi_lm, stream);
 }

@@ -66,6 +66,10 @@ def lib():
         L.s2dw_release_caches.restype = None
         L.s2dw_wavelet_tables.argtypes = [cp, vp, vp, vp]
         L.s2dw_wavelet_tables.restype = ctypes.c_int
+        L.s2dw_workspace_bytes.argtypes = [cp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
+        L.s2dw_workspace_bytes.restype = ctypes.c_int
+        L.s2dw_cache_bytes.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
+        L.s2dw_cache_bytes.restype = ctypes.c_int
         L.s2dw_profile.argtypes = [ctypes.c_int]
         L.s2dw_profile.restype = ctypes.c_int
         L.s2dw_profile_read.argtypes = [ctypes.POINTER(StageTime), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
@@ -75,7 +79,8 @@ def lib():
 
 
 EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_analysis", "s2dw_synthesis",
-            "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_autotune",
+            "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_autotune", "s2dw_workspace_bytes",
+            "s2dw_cache_bytes",
             "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
             "s2dw_profile_read",
             "s2dw_strerror", "s2dw_release_caches"]
@@ -247,6 +252,22 @@ def sht_inverse(flm: torch.Tensor, L: int, stream=None) -> torch.Tensor:
     _check(lib().s2dw_sht_inverse(ctypes.byref(params(L, 1)), ctypes.c_void_p(f.data_ptr()),
                                   ctypes.c_void_p(m.data_ptr()), _stream(stream)), "s2dw_sht_inverse")
     return m
+
+
+def workspace_bytes(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1,
+                    precision: str = "fp64") -> int:
+    """Device bytes of one stream's workspace for a batch of `count` maps."""
+    b = ctypes.c_uint64()
+    _check(lib().s2dw_workspace_bytes(ctypes.byref(params(L, N, lam, J_min, precision)), count, ctypes.byref(b)),
+           "s2dw_workspace_bytes")
+    return b.value
+
+
+def cache_bytes() -> int:
+    """Device bytes held by the library's plans and workspaces."""
+    b = ctypes.c_uint64()
+    _check(lib().s2dw_cache_bytes(ctypes.byref(b)), "s2dw_cache_bytes")
+    return b.value
 
 
 def profile(enable: bool) -> None:
