@@ -225,6 +225,17 @@ def main():
     total_coeffs = sum(coeffs_of(L, N, lam, J_min) for L, N in zip(Ls, Ns))
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     for prec in precisions:
+        # the plain GPU path at equal accuracy: each request alone, one after the other
+        for (L, N) in sorted(set(zip(Ls, Ns))):
+            s2dw.analysis(pool[L][0], L, N, lam, J_min, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, (L, N) in enumerate(zip(Ls, Ns)):
+            W, Wp = s2dw.analysis(pool[L][i % len(pool[L])], L, N, lam, J_min, precision=prec)
+            del W, Wp
+        torch.cuda.synchronize()
+        plain = args.requests / (time.perf_counter() - t0)
+        print(f"# {prec}: plain path {plain:.1f} requests/s", file=sys.stderr, flush=True)
         srv = Server(lam=lam, J_min=J_min, precision=prec, streams=args.streams, max_batch=args.max_batch)
         print(f"# {prec}: warming plans and stream workspaces", file=sys.stderr, flush=True)
         srv.warm(sorted(set(zip(Ls, Ns))))
@@ -239,6 +250,7 @@ def main():
                "value": total_coeffs / T, "unit": "SO(3) coeffs/s", "precision": prec,
                "requests": args.requests, "requests_per_s": args.requests / T,
                "saturated_requests_per_s": r_max, "offered_requests_per_s": rate, "load": args.load,
+               "plain_path_requests_per_s": plain,
                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                "streams": args.streams, "max_batch": args.max_batch, "data": "synthetic",
                "mix": {"L": dict(zip(map(str, L_CHOICES), L_WEIGHTS)), "N": N_CHOICES, "lambda": lam,
