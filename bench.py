@@ -145,6 +145,8 @@ def main():
     ap.add_argument("--jmin", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="mixed: W in FP32 and the FFT stages / m'-sum in FP32 (Delta recursion and l-sum FP64)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner pick the Wigner tile shape before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (to scale HBM counters)")
@@ -181,6 +183,11 @@ def main():
                     device=dev)
     fr = torch.empty(L * L, dtype=torch.complex128, device=dev)
     print(f"# workload L={L} N={N} lambda={lam} J_min={J_min} scales={S}", file=sys.stderr, flush=True)
+
+    tuned = None
+    if args.autotune:
+        tuned = s2dw.autotune(L, N, lam, J_min, count=1, precision=prec)
+        print(f"# autotune: {tuned[0]} m' slots per wave, {tuned[1]} maps per chunk", file=sys.stderr, flush=True)
 
     def step():
         _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=W, precision=prec)
@@ -234,7 +241,8 @@ def main():
            "config": {"workload": f"SD wavelet round trip, one map, L={L}, N={N}, lambda={lam}, J_min={J_min}, "
                                   f"{S} scales, grid {2 * N - 1}x{L}x{2 * L - 1}",
                       "L": L, "N": N, "lambda": lam, "J_min": J_min, "scales": S, "coeffs_per_map": coeffs,
-                      "precision": prec, "round_trip_rel_err": rt_err},
+                      "precision": prec, "round_trip_rel_err": rt_err,
+                      "wigner_slots": tuned[0] if tuned else None},
            "roofline": roof,
            "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in per_stage.items()},
            "stages_frac": {k: round(v["frac"], 4) for k, v in stage_roofs.items()},
