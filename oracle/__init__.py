@@ -162,6 +162,34 @@ def analysis(flm, L: int, N: int, lam: float, J_min: int, betas=None, psi=None) 
     return analysis_complex(flm, L, N, lam, J_min, betas=betas, psi=psi).real
 
 
+def analysis_at_complex(flm, L: int, N: int, lam: float, J_min: int, gammas, betas=None,
+                        psi=None) -> np.ndarray:
+    """W^j(alpha_a, beta_b, gamma) by Eq. 20 at arbitrary third Euler angles gamma, complex
+    [S][len(gammas)][nb][2L-1].
+
+    Eq. 20 is a sum over the carried orders n of e^{i n gamma} times a function of (alpha,
+    beta) alone; each of those terms is evaluated at gamma = 0 (Eq. 20 with the single order
+    n) and the factor e^{i n gamma} is applied here, for every gamma asked."""
+    if psi is None:
+        psi = tables.wavelets(L, N, lam, J_min)
+    ps, nl = _psi_cols(psi, N)
+    if betas is None:
+        betas = mw_betas(L)
+    gammas = np.asarray(gammas, dtype=np.float64).reshape(-1)
+    out = None
+    for i, n in enumerate(nl):
+        h = _analysis_raw(flm, np.ascontiguousarray(ps[:, :, i:i + 1]), [n], L, betas, 2 * L - 1, 1, 1)[:, 0]
+        t = np.exp(1j * n * gammas)[None, :, None, None] * h[:, None]
+        out = t if out is None else out + t
+    return out
+
+
+def analysis_at(flm, L: int, N: int, lam: float, J_min: int, gammas, betas=None, psi=None) -> np.ndarray:
+    """Real wavelet coefficients of a real signal at arbitrary gamma, [S][len(gammas)][nb][2L-1]
+    (Eq. 20)."""
+    return analysis_at_complex(flm, L, N, lam, J_min, gammas, betas=betas, psi=psi).real
+
+
 def scaling(flm, L: int, lam: float, J_min: int, phi=None) -> np.ndarray:
     """W^Phi_lm = sqrt(4 pi/(2l+1)) f_lm conj(Phi_l0) (Eq. 31), complex [L*L]."""
     if phi is None:
