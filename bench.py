@@ -234,6 +234,26 @@ def main():
     roof["traffic"] = traffic
     stage_roofs = {k: roofline(k, v, units) for k, v in per_stage.items() if k in units}
 
+    # steering (Eq. 10) of the step's W to Q off-grid angles: a post-step outside the timed
+    # round trip, one launch per call; bytes = W read (S G L T) + steered planes written (S Q L T)
+    Q, reps = 8, 10
+    gam = torch.linspace(0.1, 6.0, Q, dtype=torch.float64, device=dev)
+    Wq = torch.empty((S, Q, L, 2 * L - 1), dtype=W.dtype, device=dev)
+    s2dw.steer(W, gam, L, N, lam, J_min, out=Wq)
+    torch.cuda.synchronize()
+    s2dw.profile(True)
+    for _ in range(reps):
+        s2dw.steer(W, gam, L, N, lam, J_min, out=Wq)
+    sq = s2dw.profile_read()["steer"]
+    s2dw.profile(False)
+    del Wq
+    steer_ms = sq[0] / sq[1]
+    steer_bytes = S * (2 * N - 1 + Q) * L * (2 * L - 1) * W.element_size()
+    steer = {"angles": Q, "ms_per_launch": steer_ms,
+             "roofline": {"bound": "hbm", "achieved": steer_bytes / (steer_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                          "unit": "GB/s", "algorithmic_per_launch": steer_bytes}}
+    steer["roofline"]["frac"] = steer["roofline"]["achieved"] / PEAK_HBM_GBS
+
     out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8; p50/p99 mixed-L",
            "value": value, "unit": "SO(3) coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -246,7 +266,8 @@ def main():
            "roofline": roof,
            "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in per_stage.items()},
            "stages_frac": {k: round(v["frac"], 4) for k, v in stage_roofs.items()},
-           "wigner_terms_per_direction": T}
+           "wigner_terms_per_direction": T,
+           "steer": steer}
     if not args.no_cpu_baseline:
         print("# cpu baseline sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(L, N, lam, J_min)

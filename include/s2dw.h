@@ -126,6 +126,26 @@ int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, c
                            double *flm_out, void *stream);
 
 /*
+ * Steering (steerability of the wavelet coefficients, Eq. 9-10): wavelet coefficients
+ * at arbitrary third Euler angles gamma from the grid samples.  The wavelets carry only
+ * the orders n with |n| < N and n = N-1 (mod 2) (Eq. 11), so W^j(alpha, beta, .) is a
+ * trigonometric polynomial with those frequencies, fixed exactly by its 2N-1 samples:
+ *     W(alpha, beta, gamma) = sum_g z(gamma - gamma_g) W(alpha, beta, gamma_g),
+ *     z(delta) = 1/(2N-1) sum_{n carried} cos(n delta).
+ * (The paper states it with N base orientations on [0, pi); on this grid's 2N-1 samples
+ * the same polynomial takes this kernel.)  Exact up to rounding for W produced by the
+ * analysis; other input is first projected onto the carried orders.
+ *   count    number of maps, >= 1 (W and out hold count maps back to back).
+ *   W        in : [count][S][2N-1][L][2L-1] real, doubles (S2DW_FP64) or floats (S2DW_MIXED).
+ *   n_gamma  number of angles, 0 <= n_gamma <= 65536 (0: nothing is done).
+ *   gamma    in : n_gamma angles in radians, any real values, DEVICE array of doubles.
+ *   out      out: [count][S][n_gamma][L][2L-1], same element type as W; must not overlap W.
+ * Only the kernel launch is asynchronous; no workspace, so it can be captured.
+ */
+int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gamma, const double *gamma, void *out,
+               void *stream);
+
+/*
  * Autotuner: times round trips (analysis + synthesis) of zero-filled probe maps on
  * `stream` for each compiled Wigner tile shape (m' slots per wave, 1, 2 or 4 depending on
  * the number of carried orders) and for batch chunks 1, 2, 4, ... up to min(count, what
@@ -176,8 +196,9 @@ int s2dw_wavelet_tables(const s2dw_params *p, double *kappa, double *phi, double
  * that kernel's device time.  s2dw_profile(1) enables and clears the totals,
  * s2dw_profile(0) disables.  s2dw_profile_read waits for the recorded events and
  * fills up to max entries (host memory) with per-stage totals since the last clear;
- * *n receives the number of stages.  Names: wigner_fwd, beta_fwd, alpha_fwd,
- * alpha_adj, beta_hat, beta_conv, wigner_adj, syn_final, pad, scaling.
+ * *n receives the number of stages.  Names: pad, wigner_fwd, beta_fwd, alpha_fwd,
+ * gamma_fwd (analysis), gamma_adj, alpha_adj, beta_adj, wigner_adj, syn_final
+ * (synthesis), scaling, steer.
  */
 typedef struct s2dw_stage_time {
     char name[24];

@@ -1037,6 +1037,28 @@ int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, doubl
     return rc;
 }
 
+int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gamma, const double *gamma, void *out,
+               void *stream) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    if (count < 1 || n_gamma < 0 || n_gamma > kMaxSteerAngles) return S2DW_E_ARG;
+    if (n_gamma == 0) return S2DW_OK;
+    if (!W || !gamma || !out || !aligned(W) || !aligned(gamma) || !aligned(out)) return S2DW_E_ARG;
+    const int S = jmax_of(p->L, p->lambda) - p->J_min + 1;
+    const size_t P = (size_t)p->L * (2 * p->L - 1);
+    const int f32 = p->precision == S2DW_MIXED;
+    const size_t es = f32 ? 4 : 8;
+    const size_t in_map = (size_t)S * (2 * p->N - 1) * P * es, out_map = (size_t)S * n_gamma * P * es;
+    hipStream_t st = (hipStream_t)stream;
+    Stage sg("steer", st);
+    for (int32_t i = 0; i < count; i += 65535) {
+        const int maps = std::min<int32_t>(65535, count - i);
+        S2DW_CHECK_HIP(launch_steer((const char *)W + i * in_map, gamma, (char *)out + i * out_map, f32, p->N,
+                                    n_gamma, S, P, maps, st));
+    }
+    return S2DW_OK;
+}
+
 int s2dw_sht_forward(const s2dw_params *p, const double *f_map, double *flm, void *stream) {
     if (!p || p->L < 2 || p->L > 4096 || !f_map || !flm || !aligned(f_map) || !aligned(flm)) return S2DW_E_ARG;
     if (p->L > 2048) return S2DW_E_UNSUPPORTED;

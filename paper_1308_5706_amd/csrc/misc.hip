@@ -114,4 +114,92 @@ hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t st
     return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------------------------- steering
+
+// Wavelet coefficients at arbitrary third Euler angles (steerability, Eq. 9-10).  The wavelets
+// carry only the orders n with |n| < N and n = N - 1 (mod 2) (Eq. 11), so W as a function of
+// gamma is a trigonometric polynomial with those frequencies, fixed exactly by its G = 2N - 1
+// grid samples gamma_g = 2 pi g/G:
+//   W(alpha, beta, gamma) = sum_g z(gamma - gamma_g) W(alpha, beta, gamma_g),
+//   z(delta) = (1/G) sum_{n carried} cos(n delta).
+// Block: kSteerQ target angles for 256 x V consecutive (beta, alpha) points of one plane set
+// (map = blockIdx.z, scale = blockIdx.y); blockIdx.x = tile * nqc + q-chunk.  The weights of
+// the block's angles sit in LDS; each point of the G input planes is read once per q-chunk.
+constexpr int kSteerQ = 8;
+constexpr int kSteerG = 31;  // 2N - 1 for N <= 16
+
+template <class E, int V>
+struct SteerVec {
+    typedef E type __attribute__((ext_vector_type(V)));
+};
+
+template <class E, int V>
+__global__ __launch_bounds__(256) void steer_kernel(const E *W, const double *gam, E *out, int N, int Q, int nqc,
+                                                    int S, size_t P) {
+    typedef typename SteerVec<E, V>::type vec;
+    __shared__ E zw[kSteerQ][kSteerG];
+    const int G = 2 * N - 1;
+    const int qc = blockIdx.x % nqc;
+    const size_t tile = blockIdx.x / nqc;
+    const int q0 = qc * kSteerQ;
+    const int qn = min(kSteerQ, Q - q0);
+    for (int t = threadIdx.x; t < qn * G; t += blockDim.x) {
+        const int q = t / G, g = t - q * G;
+        const double d = gam[q0 + q] - 6.283185307179586476925 * (double)g / (double)G;
+        double z = 0.0;
+        for (int n = -(N - 1); n <= N - 1; n += 2) z += cos((double)n * d);
+        zw[q][g] = (E)(z / (double)G);
+    }
+    __syncthreads();
+    const size_t i0 = (tile * blockDim.x + threadIdx.x) * V;
+    if (i0 >= P) return;
+    const size_t set = (size_t)blockIdx.z * S + blockIdx.y;
+    const E *src = W + set * G * P + i0;
+    E *dst = out + (set * Q + q0) * P + i0;
+    vec acc[kSteerQ];
+#pragma unroll
+    for (int q = 0; q < kSteerQ; ++q) acc[q] = (vec)(E)0;
+    for (int g = 0; g < G; ++g) {
+        const vec w = __builtin_nontemporal_load((const vec *)(src + (size_t)g * P));
+#pragma unroll
+        for (int q = 0; q < kSteerQ; ++q) acc[q] += zw[q][g] * w;
+    }
+#pragma unroll
+    for (int q = 0; q < kSteerQ; ++q)
+        if (q < qn) *(vec *)(dst + (size_t)q * P) = acc[q];
+}
+
+hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int Q, int S, size_t P,
+                        int maps, hipStream_t st) {
+    const int nqc = (Q + kSteerQ - 1) / kSteerQ;
+    // vector width: the plane size and both base addresses must be multiples of it
+    const uintptr_t al = (uintptr_t)W | (uintptr_t)out;
+    if (f32) {
+        const int V = (P % 4 == 0 && al % 16 == 0) ? 4 : ((P % 2 == 0 && al % 8 == 0) ? 2 : 1);
+        const size_t tiles = (P + 256 * V - 1) / (256 * V);
+        const dim3 grid((unsigned)(tiles * nqc), S, maps);
+        if (V == 4)
+            hipLaunchKernelGGL((steer_kernel<float, 4>), grid, dim3(256), 0, st, (const float *)W, gam, (float *)out,
+                               N, Q, nqc, S, P);
+        else if (V == 2)
+            hipLaunchKernelGGL((steer_kernel<float, 2>), grid, dim3(256), 0, st, (const float *)W, gam, (float *)out,
+                               N, Q, nqc, S, P);
+        else
+            hipLaunchKernelGGL((steer_kernel<float, 1>), grid, dim3(256), 0, st, (const float *)W, gam, (float *)out,
+                               N, Q, nqc, S, P);
+    } else {
+        const int V = (P % 2 == 0 && al % 16 == 0) ? 2 : 1;
+        const size_t tiles = (P + 256 * V - 1) / (256 * V);
+        const dim3 grid((unsigned)(tiles * nqc), S, maps);
+        if (V == 2)
+            hipLaunchKernelGGL((steer_kernel<double, 2>), grid, dim3(256), 0, st, (const double *)W, gam,
+                               (double *)out, N, Q, nqc, S, P);
+        else
+            hipLaunchKernelGGL((steer_kernel<double, 1>), grid, dim3(256), 0, st, (const double *)W, gam,
+                               (double *)out, N, Q, nqc, S, P);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace s2dw

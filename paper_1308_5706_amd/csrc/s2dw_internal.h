@@ -12,6 +12,7 @@ namespace s2dw {
 constexpr int kMaxScales = 24;
 constexpr int kMaxSegs = 64;
 constexpr int kMaxK = 8;  // nonnegative n carried by the wavelets: ceil(N/2), N <= 16
+constexpr int kMaxSteerAngles = 1 << 16;  // angles per steering call
 
 // l-segments on which the set of active wavelet scales is constant.  At most one
 // even and one odd scale is active on any l (supports of kappa^j and kappa^{j+2} are

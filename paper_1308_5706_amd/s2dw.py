@@ -55,6 +55,7 @@ def lib():
                            ("s2dw_sht_inverse", [cp, vp, vp, vp]),
                            ("s2dw_analysis_batched", [cp, ctypes.c_int32, vp, vp, vp, vp]),
                            ("s2dw_synthesis_batched", [cp, ctypes.c_int32, vp, vp, vp, vp]),
+                           ("s2dw_steer", [cp, ctypes.c_int32, vp, ctypes.c_int32, vp, vp, vp]),
                            ("s2dw_autotune", [cp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32)])]:
             f = getattr(L, name)
@@ -79,7 +80,7 @@ def lib():
 
 
 EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_analysis", "s2dw_synthesis",
-            "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_autotune", "s2dw_workspace_bytes",
+            "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_workspace_bytes",
             "s2dw_cache_bytes",
             "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
             "s2dw_profile_read",
@@ -219,6 +220,35 @@ def autotune(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1
     _check(lib().s2dw_autotune(ctypes.byref(params(L, N, lam, J_min, precision)), count, _stream(stream),
                                ctypes.byref(sl), ctypes.byref(ch)), "s2dw_autotune")
     return sl.value, ch.value
+
+
+def steer(W: torch.Tensor, gammas, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,
+          out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Wavelet coefficients at arbitrary third Euler angles (steerability, Eq. 10).
+
+    W: [S][2N-1][L][2L-1] or [B][S][2N-1][L][2L-1], float64 (or float32: the mixed-precision
+    layout).  gammas: angles in radians (a sequence or a float64 tensor).  Returns
+    [S][Q][L][2L-1] (or [B][S][Q][L][2L-1]) in W's dtype."""
+    if W.dtype not in (torch.float64, torch.float32) or not W.is_cuda:
+        raise ValueError("W: expected a float64 or float32 device tensor")
+    precision = "fp64" if W.dtype == torch.float64 else "mixed"
+    S = num_scales(L, lam, J_min)
+    plane = S * (2 * N - 1) * L * (2 * L - 1)
+    batched = W.dim() == 5
+    if W.numel() % plane != 0 or W.numel() == 0 or W.dim() not in (4, 5):
+        raise ValueError("W: wrong shape")
+    B = W.numel() // plane
+    W = W.contiguous()
+    g = torch.as_tensor(gammas, dtype=torch.float64).reshape(-1).to(W.device).contiguous()
+    Q = g.numel()
+    shape = ((B,) if batched else ()) + (S, Q, L, 2 * L - 1)
+    o = out if out is not None else torch.empty(shape, dtype=W.dtype, device=W.device)
+    if o.dtype != W.dtype or o.numel() != B * S * Q * L * (2 * L - 1) or not o.is_contiguous():
+        raise ValueError("out: wrong shape, dtype or layout")
+    _check(lib().s2dw_steer(ctypes.byref(params(L, N, lam, J_min, precision)), B, ctypes.c_void_p(W.data_ptr()), Q,
+                            ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(o.data_ptr()), _stream(stream)),
+           "s2dw_steer")
+    return o
 
 
 def scaling(flm: torch.Tensor, L: int, N: int = 1, lam: float = 2.0, J_min: int = 0, *, sphere_map: bool = False,

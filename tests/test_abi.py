@@ -107,3 +107,18 @@ def test_batched_and_autotune_argument_errors():
     assert lib.s2dw_autotune(ctypes.byref(p), 0, None, None, None) == -1
     bad = s2dw.Params(64, 4, 2.0, 0, 0, 7, 1)  # unknown precision
     assert lib.s2dw_analysis_batched(ctypes.byref(bad), 1, fake, fake, None, None) == -1
+
+
+def test_steer_argument_errors():
+    lib = s2dw.lib()
+    p = s2dw.params(64, 4, 2.0, 0)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.s2dw_steer(ctypes.byref(p), 0, fake, 1, fake, fake, None) == -1
+    assert lib.s2dw_steer(ctypes.byref(p), 1, fake, -1, fake, fake, None) == -1
+    assert lib.s2dw_steer(ctypes.byref(p), 1, fake, 65537, fake, fake, None) == -1
+    assert lib.s2dw_steer(ctypes.byref(p), 1, None, 2, fake, fake, None) == -1
+    assert lib.s2dw_steer(ctypes.byref(p), 1, fake, 2, None, fake, None) == -1
+    assert lib.s2dw_steer(ctypes.byref(p), 1, fake, 2, fake, ctypes.c_void_p(0x1004), None) == -1
+    assert lib.s2dw_steer(ctypes.byref(p), 1, fake, 0, None, None, None) == 0  # no angles: nothing to do
+    bad = s2dw.Params(64, 17, 2.0, 0, 0, 0, 1)  # N above 16
+    assert lib.s2dw_steer(ctypes.byref(bad), 1, fake, 1, fake, fake, None) == -1

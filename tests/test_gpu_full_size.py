@@ -40,6 +40,15 @@ def test_full_size_rows_and_round_trip(L, N, J_min):
         den = np.max(np.abs(ref[j]))
         err = float(np.max(np.abs(got[j] - ref[j])) / den)
         assert err < TOL, (j, err)
+    print("  steering (Eq. 10) to off-grid angles, two sampled beta rows", flush=True)
+    g = np.array([0.7, -2.1])
+    Ws = s2dw.steer(W, g, L, N, lam, J_min)
+    got = Ws[:, :, rows[:2], :].cpu().numpy()
+    del Ws
+    ref = oracle.analysis_at(f, L, N, lam, J_min, g, betas=oracle.mw_betas(L)[rows[:2]], psi=psi)
+    for j in range(ref.shape[0]):
+        err = float(np.max(np.abs(got[j] - ref[j])) / np.max(np.abs(ref[j])))
+        assert err < TOL, (j, err)
     print("  synthesis on the GPU (round trip)", flush=True)
     fr = s2dw.synthesis(W, Wp, L, N, lam, J_min)
     torch.cuda.synchronize()
