@@ -190,6 +190,51 @@ def analysis_at(flm, L: int, N: int, lam: float, J_min: int, gammas, betas=None,
     return analysis_at_complex(flm, L, N, lam, J_min, gammas, betas=betas, psi=psi).real
 
 
+def scale_bandlimits(L: int, lam: float, J_min: int) -> list[int]:
+    """Band-limit of each wavelet scale: one more than the largest l with kappa^j(l) > 0
+    (0 for a scale with no support).  The wavelet transform of scale j needs no grid finer
+    than this band-limit (Sec. 3.2, closing remarks on the compact support of the wavelets)."""
+    kap = tables.kappa_table(L, lam, J_min)
+    out = []
+    for j in range(kap.shape[0]):
+        nz = np.nonzero(kap[j] > 0.0)[0]
+        out.append(int(nz[-1]) + 1 if len(nz) else 0)
+    return out
+
+
+def analysis_multires(flm, L: int, N: int, lam: float, J_min: int, psi=None) -> list[np.ndarray]:
+    """Multiresolution wavelet coefficients: W^j by Eq. 20 on the equiangular grid of the
+    scale's own band-limit Lj (alpha 2Lj-1, beta Lj, gamma 2N-1 samples), real
+    [2N-1][Lj][2Lj-1] per scale j."""
+    if psi is None:
+        psi = tables.wavelets(L, N, lam, J_min)
+    ps, nl = _psi_cols(psi, N)
+    out = []
+    for j, Lj in enumerate(scale_bandlimits(L, lam, J_min)):
+        if Lj == 0:
+            out.append(np.zeros((2 * N - 1, 0, 0)))
+            continue
+        w = _analysis_raw(flm, np.ascontiguousarray(ps[j:j + 1]), nl, L, mw_betas(Lj), 2 * Lj - 1, 2 * N - 1,
+                          2 * N - 1)
+        out.append(w[0].real)
+    return out
+
+
+def synthesis_multires(Ws, Wphi, L: int, N: int, lam: float, J_min: int, psi=None, phi=None) -> np.ndarray:
+    """Exact synthesis from multiresolution coefficients: each scale's Wigner coefficients
+    (Eq. 23) by the quadratures of its own band-limit-Lj grid (zero for l >= Lj, where
+    kappa^j vanishes), then Eq. 32 and Eq. 41."""
+    bl = scale_bandlimits(L, lam, J_min)
+    nn = len(tables.n_list(N))
+    wig = np.zeros((len(bl), L, 2 * L - 1, nn), dtype=np.complex128)
+    for j, Lj in enumerate(bl):
+        if Lj == 0:
+            continue
+        wj = forward_wigner_mw(np.asarray(Ws[j])[None], Lj, N)[0]
+        wig[j, :Lj, L - Lj:L + Lj - 1, :] = wj
+    return synthesis_from_wigner(wig, Wphi, L, N, lam, J_min, psi=psi, phi=phi)
+
+
 def scaling(flm, L: int, lam: float, J_min: int, phi=None) -> np.ndarray:
     """W^Phi_lm = sqrt(4 pi/(2l+1)) f_lm conj(Phi_l0) (Eq. 31), complex [L*L]."""
     if phi is None:
