@@ -152,8 +152,9 @@ def main():
                     help="only run a plain device-to-device copy of this many GiB (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the transform is single-GPU; a multi-GPU split is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the library runs a "
+              "transform on one GPU; maps and requests are independent, so several GPUs would each take "
+              "their own)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -254,6 +255,28 @@ def main():
                           "unit": "GB/s", "algorithmic_per_launch": steer_bytes}}
     steer["roofline"]["frac"] = steer["roofline"]["achieved"] / PEAK_HBM_GBS
 
+    # the same round trip in the multiresolution layout (each scale on the grid of its own
+    # band-limit): exact as well, with fewer samples; reported beside the full-grid figure
+    Wm = torch.empty(s2dw._w_shape(L, N, lam, J_min, True), dtype=W.dtype, device=dev)
+    frm = torch.empty_like(fr)
+
+    def step_mr():
+        _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=Wm, precision=prec, multires=True)
+        s2dw.synthesis(Wm, Wp, L, N, lam, J_min, out=frm, precision=prec, multires=True)
+
+    for _ in range(max(1, args.warmup)):
+        step_mr()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_mr()
+    torch.cuda.synchronize()
+    ms_mr = (time.perf_counter() - t0) * 1e3 / args.steps
+    multires = {"ms_per_step": ms_mr, "samples_per_map": Wm.numel(),
+                "round_trip_rel_err": float((frm - f).abs().max().item() / f.abs().max().item())}
+    del Wm
+    print(f"# multires round trip {ms_mr:.3f} ms/step", file=sys.stderr, flush=True)
+
     out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8; p50/p99 mixed-L",
            "value": value, "unit": "SO(3) coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -267,7 +290,8 @@ def main():
            "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in per_stage.items()},
            "stages_frac": {k: round(v["frac"], 4) for k, v in stage_roofs.items()},
            "wigner_terms_per_direction": T,
-           "steer": steer}
+           "steer": steer,
+           "multires": multires}
     if not args.no_cpu_baseline:
         print("# cpu baseline sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(L, N, lam, J_min)

@@ -25,6 +25,13 @@
  *    Scale index j = 0 is the highest-frequency wavelet (the paper's
  *    footnote to Eq. 15); S = J + 1.  Elements are doubles for
  *    S2DW_FP64 and floats for S2DW_MIXED.
+ *  - Multiresolution layout (grid = S2DW_GRID_MW_MULTIRES): the kernel of
+ *    scale j vanishes for l >= L_j = min(L, ceil(L lambda^(1-j))) (Eq. 14-15),
+ *    so W^j is band-limited at L_j and needs no finer grid (the closing
+ *    remarks of Sec. 3.2); it is sampled on the equiangular grid of band-limit
+ *    L_j (alpha 2L_j-1, beta L_j, gamma 2N-1) and the scales are stored back to
+ *    back: W = [W^0 (2N-1)xL_0x(2L_0-1)][W^1 ...]...  s2dw_scale_grid gives each
+ *    scale's shape and offset.  Analysis and synthesis stay exact.
  *  - Sphere maps: real [L][2L-1] = [theta_b][phi_a] on the same beta/alpha
  *    samples.
  *  - Only real signals are supported (reality = 1): f_{l,-m} =
@@ -67,7 +74,11 @@ enum {
     S2DW_E_INTERNAL = -5
 };
 
-enum { S2DW_GRID_MW = 0 /* alpha 2L-1, beta L (incl. pi), gamma 2N-1 */ };
+enum {
+    S2DW_GRID_MW = 0,          /* every scale on the grid of band-limit L: alpha 2L-1, beta L
+                                  (incl. pi), gamma 2N-1 */
+    S2DW_GRID_MW_MULTIRES = 1  /* scale j on the grid of its own band-limit L_j (see below) */
+};
 enum { S2DW_FP64 = 0, S2DW_MIXED = 1 };
 
 typedef struct s2dw_params {
@@ -75,7 +86,7 @@ typedef struct s2dw_params {
     int32_t N;         /* azimuthal band-limit of the wavelets, 1 <= N <= min(L, 16) (Eq. 8) */
     double lambda;     /* dilation parameter, finite and > 1 (Eq. 12) */
     int32_t J_min;     /* 0 <= J_min <= J_L(lambda); scales j = 0..J_L(lambda) - J_min */
-    int32_t grid;      /* S2DW_GRID_MW */
+    int32_t grid;      /* S2DW_GRID_MW or S2DW_GRID_MW_MULTIRES */
     int32_t precision; /* S2DW_FP64, or S2DW_MIXED: W stored as floats; the beta, gamma and
                           alpha stages of both directions and the m'-sum of the synthesis
                           contraction (Eq. 34) computed and accumulated in FP32; the
@@ -91,8 +102,13 @@ int s2dw_num_scales(const s2dw_params *p, int32_t *S);
 /* Grid shape {n_gamma, n_beta, n_alpha} = {2N-1, L, 2L-1}. */
 int s2dw_grid_shape(const s2dw_params *p, int32_t shape[3]);
 
-/* Bytes of the wavelet-coefficient array W for all S scales. */
+/* Bytes of the wavelet-coefficient array W of one map (all S scales, either layout). */
 int s2dw_wavelet_bytes(const s2dw_params *p, uint64_t *bytes);
+
+/* Sample grid of scale j: shape {2N-1, L_j, 2L_j-1} ({2N-1, L, 2L-1} for S2DW_GRID_MW)
+ * and the element offset of W^j in the W of one map.  Host-only; shape or offset may be
+ * NULL. */
+int s2dw_scale_grid(const s2dw_params *p, int32_t j, int32_t shape[3], uint64_t *offset);
 
 /*
  * Wavelet analysis (Eq. 20 by the factoring of rotations, Eq. 25-30).
@@ -136,10 +152,12 @@ int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, c
  * the same polynomial takes this kernel.)  Exact up to rounding for W produced by the
  * analysis; other input is first projected onto the carried orders.
  *   count    number of maps, >= 1 (W and out hold count maps back to back).
- *   W        in : [count][S][2N-1][L][2L-1] real, doubles (S2DW_FP64) or floats (S2DW_MIXED).
+ *   W        in : [count][S][2N-1][L][2L-1] real, doubles (S2DW_FP64) or floats (S2DW_MIXED);
+ *                 with S2DW_GRID_MW_MULTIRES, count maps of the multiresolution layout.
  *   n_gamma  number of angles, 0 <= n_gamma <= 65536 (0: nothing is done).
  *   gamma    in : n_gamma angles in radians, any real values, DEVICE array of doubles.
- *   out      out: [count][S][n_gamma][L][2L-1], same element type as W; must not overlap W.
+ *   out      out: [count][S][n_gamma][L][2L-1] (multiresolution: per scale [n_gamma][L_j]
+ *                 [2L_j-1], scales back to back), same element type as W; must not overlap W.
  * Only the kernel launch is asynchronous; no workspace, so it can be captured.
  */
 int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gamma, const double *gamma, void *out,

@@ -163,9 +163,9 @@ def analysis(flm, L: int, N: int, lam: float, J_min: int, betas=None, psi=None) 
 
 
 def analysis_at_complex(flm, L: int, N: int, lam: float, J_min: int, gammas, betas=None,
-                        psi=None) -> np.ndarray:
+                        psi=None, nalpha=None) -> np.ndarray:
     """W^j(alpha_a, beta_b, gamma) by Eq. 20 at arbitrary third Euler angles gamma, complex
-    [S][len(gammas)][nb][2L-1].
+    [S][len(gammas)][nb][na], alpha_a = 2 pi a/na (na = nalpha, default 2L-1).
 
     Eq. 20 is a sum over the carried orders n of e^{i n gamma} times a function of (alpha,
     beta) alone; each of those terms is evaluated at gamma = 0 (Eq. 20 with the single order
@@ -178,16 +178,18 @@ def analysis_at_complex(flm, L: int, N: int, lam: float, J_min: int, gammas, bet
     gammas = np.asarray(gammas, dtype=np.float64).reshape(-1)
     out = None
     for i, n in enumerate(nl):
-        h = _analysis_raw(flm, np.ascontiguousarray(ps[:, :, i:i + 1]), [n], L, betas, 2 * L - 1, 1, 1)[:, 0]
+        h = _analysis_raw(flm, np.ascontiguousarray(ps[:, :, i:i + 1]), [n], L, betas,
+                          nalpha or 2 * L - 1, 1, 1)[:, 0]
         t = np.exp(1j * n * gammas)[None, :, None, None] * h[:, None]
         out = t if out is None else out + t
     return out
 
 
-def analysis_at(flm, L: int, N: int, lam: float, J_min: int, gammas, betas=None, psi=None) -> np.ndarray:
-    """Real wavelet coefficients of a real signal at arbitrary gamma, [S][len(gammas)][nb][2L-1]
+def analysis_at(flm, L: int, N: int, lam: float, J_min: int, gammas, betas=None, psi=None,
+                nalpha=None) -> np.ndarray:
+    """Real wavelet coefficients of a real signal at arbitrary gamma, [S][len(gammas)][nb][na]
     (Eq. 20)."""
-    return analysis_at_complex(flm, L, N, lam, J_min, gammas, betas=betas, psi=psi).real
+    return analysis_at_complex(flm, L, N, lam, J_min, gammas, betas=betas, psi=psi, nalpha=nalpha).real
 
 
 def scale_bandlimits(L: int, lam: float, J_min: int) -> list[int]:

@@ -31,8 +31,21 @@ struct Plan {
     SegTab seg{};
     ScaleTab sc{};
     int eoff = 0;
+    // sample grid of each scale: full resolution (band-limit L for every scale) or
+    // multiresolution (the scale's own band-limit Lj); W of a map holds the scales back to back
+    int grid = S2DW_GRID_MW;
+    int Lg[kMaxScales] = {};                    // grid band-limit: beta Lg, alpha 2Lg - 1 samples
+    size_t woff[kMaxScales + 1] = {};           // element offset of scale j in the W of one map
+    // chirp tables of one grid band-limit (length T = 2Lg - 1) and the spectrum of the first
+    // synthesis beta convolution (transform size PD)
+    struct GridTab {
+        double2 *csq = nullptr, *cpp = nullptr, *hD1 = nullptr;
+        float2 *csqf = nullptr, *cppf = nullptr, *hD1f = nullptr;
+        int PD = 0;
+    };
+    std::map<int, GridTab> gt;
     // device tables
-    double2 *pq = nullptr, *uv = nullptr, *twa = nullptr, *csq = nullptr, *cpp = nullptr;
+    double2 *pq = nullptr, *uv = nullptr;
     double2 *tgf = nullptr, *tga = nullptr;     // gamma pass factors [2N-1][Nh]
     double *kb2 = nullptr, *seed = nullptr, *seedm = nullptr, *phi = nullptr, *fac = nullptr;
     int *seede = nullptr;
@@ -47,14 +60,11 @@ struct Plan {
     std::vector<int> seede_h;                   // start-value exponents [Lp][Lp] (host)
     // Bluestein stages: transform sizes and chirp spectra per scale, twiddles per size
     std::vector<int> PA, PB;                    // beta (analysis), alpha (both directions)
-    int PD = 0;                                 // beta (synthesis)
-    std::vector<double2 *> hA, hB, hC, hD2;     // per scale
-    double2 *hD1 = nullptr;
+    std::vector<double2 *> hA, hB, hC, hD2;     // per scale (hD2 has the size PD of the scale's grid)
     std::map<int, double2 *> twP;               // e^{-2 pi i k/P}
-    // workspaces
     // FP32 copies of the stage tables for the mixed-precision path (built on first use)
     bool f32_ready = false;
-    float2 *csqf = nullptr, *cppf = nullptr, *tgff = nullptr, *tgaf = nullptr, *hD1f = nullptr;
+    float2 *tgff = nullptr, *tgaf = nullptr;
     std::vector<float2 *> hAf, hBf, hCf, hD2f;
     std::map<int, float2 *> twPf;
     float *kb2f = nullptr;
@@ -146,7 +156,7 @@ void prof_collect() {
     g_prof.used = 0;
 }
 
-typedef std::tuple<int, int, int, double, int> PlanKey;
+typedef std::tuple<int, int, int, double, int, int> PlanKey;
 std::mutex g_mu;
 std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
@@ -330,10 +340,34 @@ std::pair<ld, ld> chirp_val(long long d, int T, int sign) {
     return {cosl(a), sinl(a)};
 }
 
-int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
+// Chirp tables of grid band-limit Lg (T = 2Lg - 1) and the spectrum of the first synthesis
+// beta convolution, shared by the scales sampled on that grid.
+int build_grid_tab(Plan &P, int Lg) {
+    if (P.gt.count(Lg)) return S2DW_OK;
+    Plan::GridTab g;
+    const int M = 2 * Lg - 1;
+    std::vector<double2> csq(M), cpp(M);
+    // chirps with the phase reduced exactly modulo 2T
+    for (int i = 0; i < M; ++i) {
+        const long long p = i - (Lg - 1);
+        const long long r2 = ((long long)i * i) % (2LL * M), rp = ((p * (p + 1)) % (2LL * M) + 2LL * M) % (2LL * M);
+        const ld a2 = kPiL * (ld)r2 / (ld)M, ap = kPiL * (ld)rp / (ld)M;
+        csq[i] = make_double2((double)cosl(a2), (double)sinl(a2));
+        cpp[i] = make_double2((double)cosl(ap), (double)sinl(ap));
+    }
+    g.PD = pow2_at_least(2 * M - 1);
+    if (g.PD > 8192) return S2DW_E_UNSUPPORTED;
+    auto hd1 = spectrum(g.PD, 2 * M - 1, (ld)M, [&](int i) { return chirp_val((long long)i - Lg - M + 2, M, +1); });
+    if (!upload(P, g.csq, csq) || !upload(P, g.cpp, cpp) || !upload(P, g.hD1, hd1)) return S2DW_E_NOMEM;
+    P.gt[Lg] = g;
+    return S2DW_OK;
+}
+
+int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&out) {
     std::unique_ptr<Plan> pl(new (std::nothrow) Plan());
     if (!pl) return S2DW_E_NOMEM;
     pl->kind = kind;
+    pl->grid = grid;
     pl->L = L;
     pl->N = N;
     pl->lam = lam;
@@ -396,21 +430,18 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
         }
     Plan &P = *pl;
     const int M = 2 * L - 1;
-    std::vector<double2> twa(M), csq(M), cpp(M);
-    for (int k = 0; k < M; ++k) {
-        long double a = 2.0L * 3.141592653589793238462643383279502884L * k / M;
-        twa[k] = make_double2((double)cosl(a), (double)sinl(a));
-    }
-    // chirps with the phase reduced exactly modulo 2T
-    for (int i = 0; i < M; ++i) {
-        const long long p = i - (L - 1);
-        const long long r2 = ((long long)i * i) % (2LL * M), rp = ((p * (p + 1)) % (2LL * M) + 2LL * M) % (2LL * M);
-        const ld a2 = kPiL * (ld)r2 / (ld)M, ap = kPiL * (ld)rp / (ld)M;
-        csq[i] = make_double2((double)cosl(a2), (double)sinl(a2));
-        cpp[i] = make_double2((double)cosl(ap), (double)sinl(ap));
+    // sample grids and the W layout of one map
+    const int Gn = 2 * t.N - 1;
+    {
+        size_t wo = 0;
+        for (int j = 0; j < t.S; ++j) {
+            const size_t lg = P.Lg[j] = grid == S2DW_GRID_MW_MULTIRES ? P.sc.Lj[j] : L;
+            P.woff[j] = wo;
+            wo += (size_t)Gn * lg * (lg > 0 ? 2 * lg - 1 : 0);
+        }
+        P.woff[t.S] = wo;
     }
     // gamma pass factors for the orders n >= 0, n = 2 ni - (N - 1), ni = N/2 + k
-    const int Gn = 2 * t.N - 1;
     P.Nh = t.N - t.N / 2;
     std::vector<double2> tgf((size_t)Gn * P.Nh), tga((size_t)Gn * P.Nh);
     for (int g = 0; g < Gn; ++g)
@@ -432,45 +463,44 @@ int build_plan(int kind, int L, int N, double lam, int J_min, Plan *&out) {
     P.n_kb2 = kb2.size();
     P.n_tg = tgf.size();
     bool ok = upload(P, P.pq, pqv) && upload(P, P.uv, uvv) && upload(P, P.kb2, kb2) && upload(P, P.seed, dt.seed) &&
-              upload(P, P.seedm, dt.seedm) && upload(P, P.seede, dt.seede) && upload(P, P.twa, twa) &&
-              upload(P, P.csq, csq) && upload(P, P.cpp, cpp) && upload(P, P.tgf, tgf) && upload(P, P.tga, tga) && upload(P, P.fac, fac) &&
-              upload(P, P.phi, t.phi);
+              upload(P, P.seedm, dt.seedm) && upload(P, P.seede, dt.seede) && upload(P, P.tgf, tgf) &&
+              upload(P, P.tga, tga) && upload(P, P.fac, fac) && upload(P, P.phi, t.phi);
     if (!ok) return S2DW_E_NOMEM;
     // tiles
     P.seede_h = dt.seede;
     int rc_t = set_slots(P, wig_slots(K));
     if (rc_t != S2DW_OK) return rc_t;
-    // Bluestein chirp spectra (see stages.hip for the convolution layout)
-    const int T = M;
-    P.PD = pow2_at_least(2 * T - 1);
-    if (P.PD > 8192) return S2DW_E_UNSUPPORTED;
-    {
-        auto hd1 = spectrum(P.PD, 2 * T - 1, (ld)T, [&](int i) { return chirp_val((long long)i - L - T + 2, T, +1); });
-        if (!upload(P, P.hD1, hd1)) return S2DW_E_NOMEM;
-    }
+    // Bluestein chirp spectra per scale, for the scale's grid band-limit Lg (T = 2Lg - 1;
+    // see stages.hip for the convolution layouts)
     P.PA.assign(t.S, 0);
     P.PB.assign(t.S, 0);
     P.hA.assign(t.S, nullptr);
     P.hB.assign(t.S, nullptr);
     P.hC.assign(t.S, nullptr);
     P.hD2.assign(t.S, nullptr);
-    std::vector<int> sizes = {P.PD};
+    std::vector<int> sizes;
     for (int j = 0; j < t.S; ++j) {
         const int Lj = P.sc.Lj[j];
         if (Lj == 0) continue;
-        P.PA[j] = pow2_at_least(2 * Lj + L - 2);
+        const int Lg = P.Lg[j], T = 2 * Lg - 1;
+        int rc_g = build_grid_tab(P, Lg);
+        if (rc_g != S2DW_OK) return rc_g;
+        const int PD = P.gt[Lg].PD;
+        P.PA[j] = pow2_at_least(2 * Lj + Lg - 2);
         P.PB[j] = pow2_at_least(2 * Lj + T - 2);
+        if (P.PA[j] > 8192 || P.PB[j] > 8192) return S2DW_E_UNSUPPORTED;
+        sizes.push_back(PD);
         sizes.push_back(P.PA[j]);
         sizes.push_back(P.PB[j]);
-        auto ha = spectrum(P.PA[j], 2 * Lj + L - 2, 1.0L,
+        auto ha = spectrum(P.PA[j], 2 * Lj + Lg - 2, 1.0L,
                            [&](int i) { return chirp_val((long long)i - Lj + 1, T, -1); });
         auto hb = spectrum(P.PB[j], 2 * Lj + T - 2, 1.0L,
                            [&](int i) { return chirp_val((long long)i - Lj + 1, T, -1); });
         auto hc = spectrum(P.PB[j], 2 * Lj + T - 2, 1.0L,
                            [&](int i) { return chirp_val((long long)i - Lj - T + 2, T, +1); });
-        // w(q) = int_0^pi sin(b) e^{i q b} db at q = Lj + L - 2 - i
-        auto hd2 = spectrum(P.PD, T + 2 * Lj - 2, 1.0L, [&](int i) {
-            const long long q = (long long)Lj + L - 2 - i;
+        // w(q) = int_0^pi sin(b) e^{i q b} db at q = Lj + Lg - 2 - i
+        auto hd2 = spectrum(PD, T + 2 * Lj - 2, 1.0L, [&](int i) {
+            const long long q = (long long)Lj + Lg - 2 - i;
             if (q == 1) return std::pair<ld, ld>(0.0L, kPiL / 2);
             if (q == -1) return std::pair<ld, ld>(0.0L, -kPiL / 2);
             if (q % 2 == 0) return std::pair<ld, ld>(2.0L / (1.0L - (ld)q * (ld)q), 0.0L);
@@ -513,18 +543,24 @@ bool f32_copy(Plan &P, F *&dst, const void *src, size_t n_values) {
 // Builds the FP32 table set of a plan (once; caller holds g_mu).
 int ensure_f32(Plan &P) {
     if (P.f32_ready) return S2DW_OK;
-    const int L = P.L, T = 2 * L - 1, S = P.S;
-    bool ok = f32_copy(P, P.csqf, P.csq, T) && f32_copy(P, P.cppf, P.cpp, T) && f32_copy(P, P.tgff, P.tgf, P.n_tg) &&
-              f32_copy(P, P.tgaf, P.tga, P.n_tg) && f32_copy(P, P.hD1f, P.hD1, P.PD) &&
+    const int S = P.S;
+    bool ok = f32_copy(P, P.tgff, P.tgf, P.n_tg) && f32_copy(P, P.tgaf, P.tga, P.n_tg) &&
               f32_copy(P, P.kb2f, P.kb2, P.n_kb2);
+    for (auto &kv : P.gt) {
+        if (!ok) break;
+        const int T = 2 * kv.first - 1;
+        Plan::GridTab &g = kv.second;
+        ok = f32_copy(P, g.csqf, g.csq, T) && f32_copy(P, g.cppf, g.cpp, T) && f32_copy(P, g.hD1f, g.hD1, g.PD);
+    }
     P.hAf.assign(S, nullptr);
     P.hBf.assign(S, nullptr);
     P.hCf.assign(S, nullptr);
     P.hD2f.assign(S, nullptr);
     for (int j = 0; ok && j < S; ++j) {
         if (P.sc.Lj[j] == 0) continue;
+        const int PD = P.gt[P.Lg[j]].PD;
         ok = f32_copy(P, P.hAf[j], P.hA[j], P.PA[j]) && f32_copy(P, P.hBf[j], P.hB[j], P.PB[j]) &&
-             f32_copy(P, P.hCf[j], P.hC[j], P.PB[j]) && f32_copy(P, P.hD2f[j], P.hD2[j], P.PD);
+             f32_copy(P, P.hCf[j], P.hC[j], P.PB[j]) && f32_copy(P, P.hD2f[j], P.hD2[j], PD);
     }
     for (auto &kv : P.twP) {
         if (!ok) break;
@@ -538,16 +574,17 @@ int ensure_f32(Plan &P) {
     return S2DW_OK;
 }
 
-int get_plan(int kind, int L, int N, double lam, int J_min, Plan *&out, bool f32 = false) {
+int get_plan(int kind, int L, int N, double lam, int J_min, Plan *&out, bool f32 = false, int grid = S2DW_GRID_MW) {
     std::lock_guard<std::mutex> lk(g_mu);
-    PlanKey key(kind, L, kind == kWavelet ? N : 1, kind == kWavelet ? lam : 0.0, kind == kWavelet ? J_min : 0);
+    if (kind != kWavelet) grid = S2DW_GRID_MW;
+    PlanKey key(kind, L, kind == kWavelet ? N : 1, kind == kWavelet ? lam : 0.0, kind == kWavelet ? J_min : 0, grid);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         out = it->second.get();
         return f32 ? ensure_f32(*out) : S2DW_OK;
     }
     Plan *p = nullptr;
-    int rc = build_plan(kind, L, N, lam, J_min, p);
+    int rc = build_plan(kind, L, N, lam, J_min, grid, p);
     if (rc != S2DW_OK) return rc;
     g_plans[key].reset(p);
     out = p;
@@ -598,13 +635,36 @@ int check_params(const s2dw_params *p) {
     if (!(p->lambda > 1.0) || !std::isfinite(p->lambda)) return S2DW_E_ARG;
     int JL = jmax_of(p->L, p->lambda);
     if (p->J_min < 0 || p->J_min > JL || JL - p->J_min + 1 > kMaxScales) return S2DW_E_ARG;
-    if (p->grid != S2DW_GRID_MW) return S2DW_E_ARG;
+    if (p->grid != S2DW_GRID_MW && p->grid != S2DW_GRID_MW_MULTIRES) return S2DW_E_ARG;
     if (p->precision != S2DW_FP64 && p->precision != S2DW_MIXED) return S2DW_E_ARG;
     if (p->reality != 1) return p->reality == 0 ? S2DW_E_UNSUPPORTED : S2DW_E_ARG;
     return S2DW_OK;
 }
 
 bool aligned(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+// Grid band-limit of every scale of a valid parameter set (L for the full-resolution grid,
+// the scale's own band-limit for the multiresolution one); host tables only, cached.
+int grid_limits(const s2dw_params *p, std::vector<int> &Lg) {
+    static std::map<std::tuple<int, int, double, int>, std::vector<int>> cache;
+    std::vector<int> bl;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto key = std::make_tuple(p->L, p->N, p->lambda, p->J_min);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            bl = it->second;
+        } else {
+            HostTables t;
+            if (!build_wavelet_tables(p->L, p->N, p->lambda, p->J_min, t)) return S2DW_E_ARG;
+            for (int j = 0; j < t.S; ++j) bl.push_back(t.hi[j] >= t.lo[j] ? t.hi[j] + 1 : 0);
+            cache[key] = bl;
+        }
+    }
+    Lg.resize(bl.size());
+    for (size_t j = 0; j < bl.size(); ++j) Lg[j] = p->grid == S2DW_GRID_MW_MULTIRES ? bl[j] : p->L;
+    return S2DW_OK;
+}
 
 #define S2DW_CHECK_HIP(x)                               \
     do {                                                \
@@ -644,11 +704,11 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.R, P.nfwd_plain + P.nfwd_x, maps, st));
     }
     const int N = P.ht.N, G = 2 * N - 1;
-    const size_t per_scale = (size_t)G * L * (2 * L - 1);
-    const size_t per_map = per_scale * P.S;
+    const size_t per_map = P.woff[P.S];
     for (int j = 0; j < P.S; ++j) {
-        const int Lj = P.sc.Lj[j];
-        void *Wj = f32 ? (void *)((float *)W + per_scale * j) : (void *)((double *)W + per_scale * j);
+        const int Lj = P.sc.Lj[j], Lg = P.Lg[j];
+        const size_t per_scale = P.woff[j + 1] - P.woff[j];
+        void *Wj = f32 ? (void *)((float *)W + P.woff[j]) : (void *)((double *)W + P.woff[j]);
         if (Lj == 0) {
             for (int i = 0; i < maps; ++i) {
                 void *Wij = f32 ? (void *)((float *)Wj + per_map * i) : (void *)((double *)Wj + per_map * i);
@@ -656,6 +716,7 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
             }
             continue;
         }
+        const Plan::GridTab &gtab = P.gt[Lg];
         StageArgs b{};
         b.f32 = f32;
         b.in = w.U + P.sc.off[j];
@@ -664,9 +725,9 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         b.s_out = P.s_Ub;
         b.hh = f32 ? (const void *)P.hAf[j] : P.hA[j];
         b.tw = f32 ? (const void *)P.twPf[P.PA[j]] : P.twP[P.PA[j]];
-        b.csq = f32 ? (const void *)P.csqf : P.csq;
-        b.cpp = f32 ? (const void *)P.cppf : P.cpp;
-        b.L = L;
+        b.csq = f32 ? (const void *)gtab.csqf : gtab.csq;
+        b.cpp = f32 ? (const void *)gtab.cppf : gtab.cpp;
+        b.L = Lg;
         b.Lj = Lj;
         b.N = N;
         b.Nh = P.Nh;
@@ -691,8 +752,8 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         g.s_w = per_map;
         g.s_y = P.s_Y;
         g.tg = f32 ? (const void *)P.tgff : P.tgf;
-        g.L = L;
-        g.T = 2 * L - 1;
+        g.L = Lg;
+        g.T = 2 * Lg - 1;
         g.G = G;
         g.Nh = P.Nh;
         g.f32 = f32;
@@ -708,21 +769,21 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
 // per-map layout as run_inverse; wphi of map i at wphi + i L^2, or null).
 int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, double2 *flm, int f32,
                 hipStream_t st) {
-    const int L = P.L, M = 2 * L - 1, N = P.ht.N, G = 2 * N - 1;
-    const size_t per_scale = (size_t)G * L * M;
-    const size_t per_map = per_scale * P.S;
+    const int L = P.L, N = P.ht.N, G = 2 * N - 1;
+    const size_t per_map = P.woff[P.S];
     for (int j = 0; j < P.S; ++j) {
-        const int Lj = P.sc.Lj[j];
+        const int Lj = P.sc.Lj[j], Lg = P.Lg[j], M = 2 * Lg - 1;
         if (Lj == 0) continue;
-        const void *Wj = f32 ? (const void *)((const float *)W + per_scale * j)
-                             : (const void *)((const double *)W + per_scale * j);
+        const Plan::GridTab &gtab = P.gt[Lg];
+        const void *Wj = f32 ? (const void *)((const float *)W + P.woff[j])
+                             : (const void *)((const double *)W + P.woff[j]);
         GammaArgs g{};
         g.win = Wj;
         g.out = w.Y;
         g.s_w = per_map;
         g.s_y = P.s_Y;
         g.tg = f32 ? (const void *)P.tgaf : P.tga;
-        g.L = L;
+        g.L = Lg;
         g.T = M;
         g.G = G;
         g.Nh = P.Nh;
@@ -739,9 +800,9 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         c.s_out = P.s_Ub;
         c.hh = f32 ? (const void *)P.hCf[j] : P.hC[j];
         c.tw = f32 ? (const void *)P.twPf[P.PB[j]] : P.twP[P.PB[j]];
-        c.csq = f32 ? (const void *)P.csqf : P.csq;
-        c.cpp = f32 ? (const void *)P.cppf : P.cpp;
-        c.L = L;
+        c.csq = f32 ? (const void *)gtab.csqf : gtab.csq;
+        c.cpp = f32 ? (const void *)gtab.cppf : gtab.cpp;
+        c.L = Lg;
         c.Lj = Lj;
         c.N = N;
         c.Nh = P.Nh;
@@ -758,14 +819,14 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         // Wigner kernel indexes it with the same element type); per-map stride s_U elements
         v.out = f32 ? (void *)((float2 *)w.U + P.sc.off[j]) : (void *)(w.U + P.sc.off[j]);
         v.s_out = P.s_U;
-        v.hh = f32 ? (const void *)P.hD1f : P.hD1;
+        v.hh = f32 ? (const void *)gtab.hD1f : gtab.hD1;
         v.hh2 = f32 ? (const void *)P.hD2f[j] : P.hD2[j];
-        v.tw = f32 ? (const void *)P.twPf[P.PD] : P.twP[P.PD];
+        v.tw = f32 ? (const void *)P.twPf[gtab.PD] : P.twP[gtab.PD];
         for (int k = 0; k < P.K; ++k) v.nk[k] = P.ht.nk[k];
         v.eta_imag = P.ht.eta_imag ? 1 : 0;
         {
             Stage sg("beta_adj", st);
-            S2DW_CHECK_HIP(launch_beta_adj_fft(v, P.PD, maps, st));
+            S2DW_CHECK_HIP(launch_beta_adj_fft(v, gtab.PD, maps, st));
         }
     }
     WigAdjArgs a{};
@@ -822,12 +883,43 @@ int s2dw_grid_shape(const s2dw_params *p, int32_t shape[3]) {
     return S2DW_OK;
 }
 
+int s2dw_scale_grid(const s2dw_params *p, int32_t j, int32_t shape[3], uint64_t *offset) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    std::vector<int> Lg;
+    rc = grid_limits(p, Lg);
+    if (rc != S2DW_OK) return rc;
+    if (j < 0 || j >= (int32_t)Lg.size()) return S2DW_E_ARG;
+    const uint64_t G = 2 * (uint64_t)p->N - 1;
+    uint64_t off = 0;
+    for (int32_t i = 0; i < j; ++i) off += G * Lg[i] * (Lg[i] > 0 ? 2 * (uint64_t)Lg[i] - 1 : 0);
+    if (shape) {
+        shape[0] = (int32_t)G;
+        shape[1] = Lg[j];
+        shape[2] = Lg[j] > 0 ? 2 * Lg[j] - 1 : 0;
+    }
+    if (offset) *offset = off;
+    return S2DW_OK;
+}
+
 int s2dw_wavelet_bytes(const s2dw_params *p, uint64_t *bytes) {
+    if (!bytes) return S2DW_E_ARG;
+    const uint64_t el = p && p->precision == S2DW_MIXED ? 4 : 8;
+    if (p && p->grid == S2DW_GRID_MW_MULTIRES) {
+        int rc = check_params(p);
+        if (rc != S2DW_OK) return rc;
+        std::vector<int> Lg;
+        rc = grid_limits(p, Lg);
+        if (rc != S2DW_OK) return rc;
+        uint64_t n = 0;
+        for (int l : Lg) n += (2 * (uint64_t)p->N - 1) * l * (l > 0 ? 2 * (uint64_t)l - 1 : 0);
+        *bytes = n * el;
+        return S2DW_OK;
+    }
     int32_t S = 0;
     int rc = s2dw_num_scales(p, &S);
     if (rc != S2DW_OK) return rc;
-    if (!bytes || p->N < 1) return S2DW_E_ARG;
-    uint64_t el = p->precision == S2DW_MIXED ? 4 : 8;
+    if (p->N < 1) return S2DW_E_ARG;
     *bytes = (uint64_t)S * (2 * p->N - 1) * p->L * (2 * (uint64_t)p->L - 1) * el;
     return S2DW_OK;
 }
@@ -839,7 +931,7 @@ int s2dw_analysis_batched(const s2dw_params *p, int32_t count, const double *flm
     if (count < 1 || !flm || !W || !aligned(flm) || !aligned(W) || (Wphi_lm && !aligned(Wphi_lm))) return S2DW_E_ARG;
     Plan *P = nullptr;
     const int f32 = p->precision == S2DW_MIXED ? 1 : 0;
-    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0);
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0, p->grid);
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int chunk = std::max(1, std::min<int>(count, P->chunk));
@@ -847,7 +939,7 @@ int s2dw_analysis_batched(const s2dw_params *p, int32_t count, const double *flm
     rc = get_work(*P, st, chunk, w);
     if (rc != S2DW_OK) return rc;
     const size_t L2 = (size_t)p->L * p->L;
-    const size_t wmap = (size_t)P->S * (2 * p->N - 1) * p->L * (2 * (size_t)p->L - 1) * (f32 ? 4 : 8);
+    const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8);
     for (int i0 = 0; i0 < count; i0 += chunk) {
         const int n = std::min(chunk, count - i0);
         rc = run_inverse(*P, *w, n, (const double2 *)flm + L2 * i0, (char *)W + wmap * i0, f32, st);
@@ -869,7 +961,7 @@ int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, c
         return S2DW_E_ARG;
     Plan *P = nullptr;
     const int f32 = p->precision == S2DW_MIXED ? 1 : 0;
-    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0);
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0, p->grid);
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int chunk = std::max(1, std::min<int>(count, P->chunk));
@@ -877,7 +969,7 @@ int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, c
     rc = get_work(*P, st, chunk, w);
     if (rc != S2DW_OK) return rc;
     const size_t L2 = (size_t)p->L * p->L;
-    const size_t wmap = (size_t)P->S * (2 * p->N - 1) * p->L * (2 * (size_t)p->L - 1) * (f32 ? 4 : 8);
+    const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8);
     for (int i0 = 0; i0 < count; i0 += chunk) {
         const int n = std::min(chunk, count - i0);
         rc = run_forward(*P, *w, n, (const char *)W + wmap * i0, Wphi_lm ? (const double2 *)Wphi_lm + L2 * i0 : nullptr,
@@ -893,14 +985,14 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     if (count < 1) return S2DW_E_ARG;
     Plan *P = nullptr;
     const int f32 = p->precision == S2DW_MIXED ? 1 : 0;
-    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0);
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0, p->grid);
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     if (hipStreamSynchronize(st) != hipSuccess) return S2DW_E_DEVICE;
     int cmax = std::min<int>(count, std::max(default_chunk(*P), 1));
     // probe buffers (zero coefficients: the kernels have no data-dependent control flow)
     const size_t L2 = (size_t)p->L * p->L;
-    const size_t wmap = (size_t)P->S * (2 * p->N - 1) * p->L * (2 * (size_t)p->L - 1) * (f32 ? 4 : 8);
+    const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8);
     void *fin = nullptr, *wbuf = nullptr, *fout = nullptr;
     if (hipMalloc(&fin, 16 * L2 * cmax) != hipSuccess) return S2DW_E_NOMEM;
     if (hipMalloc(&wbuf, wmap * cmax) != hipSuccess || hipMalloc(&fout, 16 * L2 * cmax) != hipSuccess) {
@@ -982,7 +1074,7 @@ int s2dw_workspace_bytes(const s2dw_params *p, int32_t count, uint64_t *bytes) {
     if (rc != S2DW_OK) return rc;
     if (count < 1 || !bytes) return S2DW_E_ARG;
     Plan *P = nullptr;
-    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, p->precision == S2DW_MIXED);
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, p->precision == S2DW_MIXED, p->grid);
     if (rc != S2DW_OK) return rc;
     const uint64_t per_map = 16ull * (P->s_fpad + P->s_U + P->s_Ub + P->s_Y + P->s_F);
     *bytes = per_map * (uint64_t)std::min<int>(count, std::max(P->chunk, 1));
@@ -1016,7 +1108,7 @@ int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, doubl
     if (!flm || !aligned(flm) || (Wphi_lm && !aligned(Wphi_lm)) || (Wphi_map && !aligned(Wphi_map))) return S2DW_E_ARG;
     if (!Wphi_lm && !Wphi_map) return S2DW_OK;
     Plan *P = nullptr;
-    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P);
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, false, p->grid);
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     Work *w = nullptr;
@@ -1044,17 +1136,35 @@ int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gam
     if (count < 1 || n_gamma < 0 || n_gamma > kMaxSteerAngles) return S2DW_E_ARG;
     if (n_gamma == 0) return S2DW_OK;
     if (!W || !gamma || !out || !aligned(W) || !aligned(gamma) || !aligned(out)) return S2DW_E_ARG;
-    const int S = jmax_of(p->L, p->lambda) - p->J_min + 1;
-    const size_t P = (size_t)p->L * (2 * p->L - 1);
+    std::vector<int> Lg;
+    rc = grid_limits(p, Lg);
+    if (rc != S2DW_OK) return rc;
+    const int S = (int)Lg.size(), G = 2 * p->N - 1;
     const int f32 = p->precision == S2DW_MIXED;
     const size_t es = f32 ? 4 : 8;
-    const size_t in_map = (size_t)S * (2 * p->N - 1) * P * es, out_map = (size_t)S * n_gamma * P * es;
+    // element offsets of each scale in one map of W and of out
+    std::vector<size_t> oin(S + 1, 0), oout(S + 1, 0);
+    for (int j = 0; j < S; ++j) {
+        const size_t pl = (size_t)Lg[j] * (Lg[j] > 0 ? 2 * Lg[j] - 1 : 0);
+        oin[j + 1] = oin[j] + G * pl;
+        oout[j + 1] = oout[j] + (size_t)n_gamma * pl;
+    }
     hipStream_t st = (hipStream_t)stream;
     Stage sg("steer", st);
     for (int32_t i = 0; i < count; i += 65535) {
         const int maps = std::min<int32_t>(65535, count - i);
-        S2DW_CHECK_HIP(launch_steer((const char *)W + i * in_map, gamma, (char *)out + i * out_map, f32, p->N,
-                                    n_gamma, S, P, maps, st));
+        const char *Wi = (const char *)W + i * oin[S] * es;
+        char *Oi = (char *)out + i * oout[S] * es;
+        if (p->grid == S2DW_GRID_MW) {  // one plane size: all scales in one launch
+            S2DW_CHECK_HIP(launch_steer(Wi, gamma, Oi, f32, p->N, n_gamma, S, (size_t)p->L * (2 * p->L - 1), oin[S],
+                                        oout[S], maps, st));
+            continue;
+        }
+        for (int j = 0; j < S; ++j) {
+            if (Lg[j] == 0) continue;
+            S2DW_CHECK_HIP(launch_steer(Wi + oin[j] * es, gamma, Oi + oout[j] * es, f32, p->N, n_gamma, 1,
+                                        (size_t)Lg[j] * (2 * Lg[j] - 1), oin[S], oout[S], maps, st));
+        }
     }
     return S2DW_OK;
 }

@@ -99,9 +99,10 @@ hipError_t launch_syn_final(const void *Fpart, size_t s_F, int f32, int nblk, in
                             hipStream_t st);
 hipError_t launch_zero_words(void *p, size_t n, hipStream_t st);
 hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t st);
-// W [maps][S][2N-1][P] -> out [maps][S][Q][P] at the Q angles gam (device), P = L (2L-1)
-// points per plane; doubles, or floats if f32; maps <= 65535.
+// W [maps][S][2N-1][P] -> out [maps][S][Q][P] at the Q angles gam (device), P points per
+// plane, map i of W at i s_in and of out at i s_out (elements); doubles, or floats if f32;
+// maps <= 65535.
 hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int Q, int S, size_t P,
-                        int maps, hipStream_t st);
+                        size_t s_in, size_t s_out, int maps, hipStream_t st);
 
 }  // namespace s2dw

@@ -136,7 +136,7 @@ struct SteerVec {
 
 template <class E, int V>
 __global__ __launch_bounds__(256) void steer_kernel(const E *W, const double *gam, E *out, int N, int Q, int nqc,
-                                                    int S, size_t P) {
+                                                    size_t P, size_t s_in, size_t s_out) {
     typedef typename SteerVec<E, V>::type vec;
     __shared__ E zw[kSteerQ][kSteerG];
     const int G = 2 * N - 1;
@@ -154,9 +154,8 @@ __global__ __launch_bounds__(256) void steer_kernel(const E *W, const double *ga
     __syncthreads();
     const size_t i0 = (tile * blockDim.x + threadIdx.x) * V;
     if (i0 >= P) return;
-    const size_t set = (size_t)blockIdx.z * S + blockIdx.y;
-    const E *src = W + set * G * P + i0;
-    E *dst = out + (set * Q + q0) * P + i0;
+    const E *src = W + blockIdx.z * s_in + (size_t)blockIdx.y * G * P + i0;
+    E *dst = out + blockIdx.z * s_out + ((size_t)blockIdx.y * Q + q0) * P + i0;
     vec acc[kSteerQ];
 #pragma unroll
     for (int q = 0; q < kSteerQ; ++q) acc[q] = (vec)(E)0;
@@ -170,34 +169,29 @@ __global__ __launch_bounds__(256) void steer_kernel(const E *W, const double *ga
         if (q < qn) *(vec *)(dst + (size_t)q * P) = acc[q];
 }
 
-hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int Q, int S, size_t P,
-                        int maps, hipStream_t st) {
+template <class E, int V>
+void steer_launch(const void *W, const double *gam, void *out, int N, int Q, int S, size_t P, size_t s_in,
+                  size_t s_out, int maps, hipStream_t st) {
     const int nqc = (Q + kSteerQ - 1) / kSteerQ;
-    // vector width: the plane size and both base addresses must be multiples of it
-    const uintptr_t al = (uintptr_t)W | (uintptr_t)out;
+    const size_t tiles = (P + 256 * V - 1) / (256 * V);
+    hipLaunchKernelGGL((steer_kernel<E, V>), dim3((unsigned)(tiles * nqc), S, maps), dim3(256), 0, st, (const E *)W,
+                       gam, (E *)out, N, Q, nqc, P, s_in, s_out);
+}
+
+hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int Q, int S, size_t P,
+                        size_t s_in, size_t s_out, int maps, hipStream_t st) {
+    // vector width: the plane size, the map strides and both base addresses are multiples of it
+    const size_t es = f32 ? 4 : 8;
+    auto fits = [&](int V) {
+        return P % V == 0 && s_in % V == 0 && s_out % V == 0 && ((uintptr_t)W | (uintptr_t)out) % (V * es) == 0;
+    };
     if (f32) {
-        const int V = (P % 4 == 0 && al % 16 == 0) ? 4 : ((P % 2 == 0 && al % 8 == 0) ? 2 : 1);
-        const size_t tiles = (P + 256 * V - 1) / (256 * V);
-        const dim3 grid((unsigned)(tiles * nqc), S, maps);
-        if (V == 4)
-            hipLaunchKernelGGL((steer_kernel<float, 4>), grid, dim3(256), 0, st, (const float *)W, gam, (float *)out,
-                               N, Q, nqc, S, P);
-        else if (V == 2)
-            hipLaunchKernelGGL((steer_kernel<float, 2>), grid, dim3(256), 0, st, (const float *)W, gam, (float *)out,
-                               N, Q, nqc, S, P);
-        else
-            hipLaunchKernelGGL((steer_kernel<float, 1>), grid, dim3(256), 0, st, (const float *)W, gam, (float *)out,
-                               N, Q, nqc, S, P);
+        if (fits(4)) steer_launch<float, 4>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
+        else if (fits(2)) steer_launch<float, 2>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
+        else steer_launch<float, 1>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
     } else {
-        const int V = (P % 2 == 0 && al % 16 == 0) ? 2 : 1;
-        const size_t tiles = (P + 256 * V - 1) / (256 * V);
-        const dim3 grid((unsigned)(tiles * nqc), S, maps);
-        if (V == 2)
-            hipLaunchKernelGGL((steer_kernel<double, 2>), grid, dim3(256), 0, st, (const double *)W, gam,
-                               (double *)out, N, Q, nqc, S, P);
-        else
-            hipLaunchKernelGGL((steer_kernel<double, 1>), grid, dim3(256), 0, st, (const double *)W, gam,
-                               (double *)out, N, Q, nqc, S, P);
+        if (fits(2)) steer_launch<double, 2>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
+        else steer_launch<double, 1>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
     }
     return hipGetLastError();
 }

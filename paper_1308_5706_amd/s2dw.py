@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libs2dw.so")
 
 FP64, MIXED = 0, 1
-GRID_MW = 0
+GRID_MW, GRID_MW_MULTIRES = 0, 1
 
 _lib = None
 
@@ -65,6 +65,9 @@ def lib():
         L.s2dw_strerror.restype = ctypes.c_char_p
         L.s2dw_release_caches.argtypes = []
         L.s2dw_release_caches.restype = None
+        L.s2dw_scale_grid.argtypes = [cp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_uint64)]
+        L.s2dw_scale_grid.restype = ctypes.c_int
         L.s2dw_wavelet_tables.argtypes = [cp, vp, vp, vp]
         L.s2dw_wavelet_tables.restype = ctypes.c_int
         L.s2dw_workspace_bytes.argtypes = [cp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
@@ -79,7 +82,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_analysis", "s2dw_synthesis",
+EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_scale_grid", "s2dw_analysis", "s2dw_synthesis",
             "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_workspace_bytes",
             "s2dw_cache_bytes",
             "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
@@ -87,8 +90,10 @@ EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_an
             "s2dw_strerror", "s2dw_release_caches"]
 
 
-def params(L: int, N: int, lam: float = 2.0, J_min: int = 0, precision: str = "fp64") -> Params:
-    return Params(L, N, float(lam), J_min, GRID_MW, FP64 if precision == "fp64" else MIXED, 1)
+def params(L: int, N: int, lam: float = 2.0, J_min: int = 0, precision: str = "fp64",
+           multires: bool = False) -> Params:
+    return Params(L, N, float(lam), J_min, GRID_MW_MULTIRES if multires else GRID_MW,
+                  FP64 if precision == "fp64" else MIXED, 1)
 
 
 def _check(rc: int, what: str):
@@ -137,17 +142,55 @@ def _w_dtype(precision: str):
     return torch.float64 if precision == "fp64" else torch.float32
 
 
+def scale_grid(L: int, N: int, lam: float = 2.0, J_min: int = 0, j: int = 0, *, multires: bool = False):
+    """(shape (2N-1, L_j, 2L_j-1), element offset) of scale j in the W of one map."""
+    sh = (ctypes.c_int32 * 3)()
+    off = ctypes.c_uint64()
+    _check(lib().s2dw_scale_grid(ctypes.byref(params(L, N, lam, J_min, multires=multires)), j, sh,
+                                 ctypes.byref(off)), "s2dw_scale_grid")
+    return (sh[0], sh[1], sh[2]), off.value
+
+
+def _w_shape(L, N, lam, J_min, multires):
+    """Shape of the W of one map: [S][2N-1][L][2L-1], or flat for the multiresolution layout."""
+    if not multires:
+        return (num_scales(L, lam, J_min), 2 * N - 1, L, 2 * L - 1)
+    S = num_scales(L, lam, J_min)
+    sh, off = scale_grid(L, N, lam, J_min, S - 1, multires=True)
+    return (off + sh[0] * sh[1] * sh[2],)
+
+
+def split_scales(W: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0) -> list:
+    """Views [(B,) 2N-1, L_j, 2L_j-1] of each scale of multiresolution coefficients W
+    ([total] or [B][total])."""
+    lead = W.shape[:-1]
+    out = []
+    for j in range(num_scales(L, lam, J_min)):
+        sh, off = scale_grid(L, N, lam, J_min, j, multires=True)
+        n = sh[0] * sh[1] * sh[2]
+        out.append(W[..., off:off + n].reshape(lead + sh))
+    return out
+
+
+def _check_w(W, shape, dtype, B, what):
+    n = B
+    for d in shape:
+        n *= d
+    if W.dtype != dtype or W.numel() != n or not W.is_cuda or not W.is_contiguous():
+        raise ValueError(f"{what}: wrong shape, dtype or layout")
+
+
 def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0, *, scaling: bool = True,
-             out: torch.Tensor | None = None, stream=None, precision: str = "fp64"):
-    """Wavelet coefficients W [S][2N-1][L][2L-1] (float64, or float32 with precision="mixed")
-    and, if scaling, the harmonic scaling coefficients W^Phi_lm (complex128 [L*L])."""
-    p = params(L, N, lam, J_min, precision)
+             out: torch.Tensor | None = None, stream=None, precision: str = "fp64", multires: bool = False):
+    """Wavelet coefficients W [S][2N-1][L][2L-1] (float64, or float32 with precision="mixed";
+    flat in the multiresolution layout, see split_scales) and, if scaling, the harmonic
+    scaling coefficients W^Phi_lm (complex128 [L*L])."""
+    p = params(L, N, lam, J_min, precision, multires)
     wdt = _w_dtype(precision)
     f = _as_complex(flm, L * L, "flm")
-    S = num_scales(L, lam, J_min)
-    W = out if out is not None else torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=wdt, device=f.device)
-    if W.dtype != wdt or W.numel() != S * (2 * N - 1) * L * (2 * L - 1) or not W.is_contiguous():
-        raise ValueError("W: wrong shape, dtype or layout")
+    shape = _w_shape(L, N, lam, J_min, multires)
+    W = out if out is not None else torch.empty(shape, dtype=wdt, device=f.device)
+    _check_w(W, shape, wdt, 1, "W")
     Wp = torch.empty(L * L, dtype=torch.complex128, device=f.device) if scaling else None
     _check(lib().s2dw_analysis(ctypes.byref(p), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(W.data_ptr()),
                                ctypes.c_void_p(Wp.data_ptr() if Wp is not None else None), _stream(stream)),
@@ -156,14 +199,13 @@ def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0
 
 
 def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,
-              out: torch.Tensor | None = None, stream=None, precision: str = "fp64") -> torch.Tensor:
+              out: torch.Tensor | None = None, stream=None, precision: str = "fp64",
+              multires: bool = False) -> torch.Tensor:
     """f_lm (complex128 [L*L]) from W (float64, or float32 with precision="mixed") and the
     scaling coefficients (or the wavelet part only)."""
-    p = params(L, N, lam, J_min, precision)
-    S = num_scales(L, lam, J_min)
-    if W.dtype != _w_dtype(precision) or W.numel() != S * (2 * N - 1) * L * (2 * L - 1) or not W.is_cuda:
-        raise ValueError("W: wrong shape or dtype")
+    p = params(L, N, lam, J_min, precision, multires)
     W = W.contiguous()
+    _check_w(W, _w_shape(L, N, lam, J_min, multires), _w_dtype(precision), 1, "W")
     wp = _as_complex(Wphi, L * L, "Wphi") if Wphi is not None else None
     f = out if out is not None else torch.empty(L * L, dtype=torch.complex128, device=W.device)
     _check(lib().s2dw_synthesis(ctypes.byref(p), ctypes.c_void_p(W.data_ptr()),
@@ -173,19 +215,19 @@ def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: f
 
 
 def analysis_batched(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0, *, scaling: bool = True,
-                     out: torch.Tensor | None = None, stream=None, precision: str = "fp64"):
+                     out: torch.Tensor | None = None, stream=None, precision: str = "fp64", multires: bool = False):
     """A batch of maps with the same parameters: flm complex128 [B][L*L] -> W [B][S][2N-1][L][2L-1]
-    (float64 or float32) and, if scaling, W^Phi complex128 [B][L*L]."""
-    p = params(L, N, lam, J_min, precision)
+    (float64 or float32; [B][total] in the multiresolution layout) and, if scaling, W^Phi
+    complex128 [B][L*L]."""
+    p = params(L, N, lam, J_min, precision, multires)
     wdt = _w_dtype(precision)
     if flm.dim() != 2 or flm.shape[1] != L * L:
         raise ValueError("flm: expected [B][L*L] complex128")
     B = flm.shape[0]
     f = _as_complex(flm, B * L * L, "flm")
-    S = num_scales(L, lam, J_min)
-    W = out if out is not None else torch.empty((B, S, 2 * N - 1, L, 2 * L - 1), dtype=wdt, device=f.device)
-    if W.dtype != wdt or W.numel() != B * S * (2 * N - 1) * L * (2 * L - 1) or not W.is_contiguous():
-        raise ValueError("W: wrong shape, dtype or layout")
+    shape = _w_shape(L, N, lam, J_min, multires)
+    W = out if out is not None else torch.empty((B,) + shape, dtype=wdt, device=f.device)
+    _check_w(W, shape, wdt, B, "W")
     Wp = torch.empty((B, L * L), dtype=torch.complex128, device=f.device) if scaling else None
     _check(lib().s2dw_analysis_batched(ctypes.byref(p), B, ctypes.c_void_p(f.data_ptr()),
                                        ctypes.c_void_p(W.data_ptr()),
@@ -196,14 +238,12 @@ def analysis_batched(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min:
 
 def synthesis_batched(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0,
                       J_min: int = 0, *, out: torch.Tensor | None = None, stream=None,
-                      precision: str = "fp64") -> torch.Tensor:
+                      precision: str = "fp64", multires: bool = False) -> torch.Tensor:
     """A batch of maps: W [B][S][2N-1][L][2L-1] (+ W^Phi [B][L*L]) -> f_lm complex128 [B][L*L]."""
-    p = params(L, N, lam, J_min, precision)
-    S = num_scales(L, lam, J_min)
+    p = params(L, N, lam, J_min, precision, multires)
     B = W.shape[0]
-    if W.dtype != _w_dtype(precision) or W.numel() != B * S * (2 * N - 1) * L * (2 * L - 1) or not W.is_cuda:
-        raise ValueError("W: wrong shape or dtype")
     W = W.contiguous()
+    _check_w(W, _w_shape(L, N, lam, J_min, multires), _w_dtype(precision), B, "W")
     wp = _as_complex(Wphi, B * L * L, "Wphi") if Wphi is not None else None
     f = out if out is not None else torch.empty((B, L * L), dtype=torch.complex128, device=W.device)
     _check(lib().s2dw_synthesis_batched(ctypes.byref(p), B, ctypes.c_void_p(W.data_ptr()),
@@ -213,41 +253,46 @@ def synthesis_batched(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int
 
 
 def autotune(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1, precision: str = "fp64",
-             stream=None):
+             stream=None, multires: bool = False):
     """Times the compiled Wigner tile shapes and batch chunks for these parameters and keeps
     the fastest in the library's plan; returns (m' slots per wave, maps per chunk)."""
     sl, ch = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().s2dw_autotune(ctypes.byref(params(L, N, lam, J_min, precision)), count, _stream(stream),
+    _check(lib().s2dw_autotune(ctypes.byref(params(L, N, lam, J_min, precision, multires)), count, _stream(stream),
                                ctypes.byref(sl), ctypes.byref(ch)), "s2dw_autotune")
     return sl.value, ch.value
 
 
 def steer(W: torch.Tensor, gammas, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,
-          out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+          out: torch.Tensor | None = None, stream=None, multires: bool = False) -> torch.Tensor:
     """Wavelet coefficients at arbitrary third Euler angles (steerability, Eq. 10).
 
     W: [S][2N-1][L][2L-1] or [B][S][2N-1][L][2L-1], float64 (or float32: the mixed-precision
-    layout).  gammas: angles in radians (a sequence or a float64 tensor).  Returns
-    [S][Q][L][2L-1] (or [B][S][Q][L][2L-1]) in W's dtype."""
+    layout); with multires, [total] or [B][total].  gammas: angles in radians (a sequence or
+    a float64 tensor).  Returns [(B,) S, Q, L, 2L-1] (multires: [(B,) total_Q] with scale j's
+    [Q][L_j][2L_j-1] block at Q/(2N-1) times its offset in W) in W's dtype."""
     if W.dtype not in (torch.float64, torch.float32) or not W.is_cuda:
         raise ValueError("W: expected a float64 or float32 device tensor")
     precision = "fp64" if W.dtype == torch.float64 else "mixed"
-    S = num_scales(L, lam, J_min)
-    plane = S * (2 * N - 1) * L * (2 * L - 1)
-    batched = W.dim() == 5
-    if W.numel() % plane != 0 or W.numel() == 0 or W.dim() not in (4, 5):
+    shape = _w_shape(L, N, lam, J_min, multires)
+    per = 1
+    for d in shape:
+        per *= d
+    batched = W.dim() == len(shape) + 1
+    if W.numel() == 0 or W.numel() % per != 0 or W.dim() not in (len(shape), len(shape) + 1):
         raise ValueError("W: wrong shape")
-    B = W.numel() // plane
+    B = W.numel() // per
     W = W.contiguous()
     g = torch.as_tensor(gammas, dtype=torch.float64).reshape(-1).to(W.device).contiguous()
     Q = g.numel()
-    shape = ((B,) if batched else ()) + (S, Q, L, 2 * L - 1)
-    o = out if out is not None else torch.empty(shape, dtype=W.dtype, device=W.device)
-    if o.dtype != W.dtype or o.numel() != B * S * Q * L * (2 * L - 1) or not o.is_contiguous():
+    G = 2 * N - 1
+    oshape = (per // G * Q,) if multires else (shape[0], Q, L, 2 * L - 1)
+    oshape = ((B,) if batched else ()) + oshape
+    o = out if out is not None else torch.empty(oshape, dtype=W.dtype, device=W.device)
+    if o.dtype != W.dtype or o.numel() != B * (per // G) * Q or not o.is_contiguous():
         raise ValueError("out: wrong shape, dtype or layout")
-    _check(lib().s2dw_steer(ctypes.byref(params(L, N, lam, J_min, precision)), B, ctypes.c_void_p(W.data_ptr()), Q,
-                            ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(o.data_ptr()), _stream(stream)),
-           "s2dw_steer")
+    _check(lib().s2dw_steer(ctypes.byref(params(L, N, lam, J_min, precision, multires)), B,
+                            ctypes.c_void_p(W.data_ptr()), Q, ctypes.c_void_p(g.data_ptr()),
+                            ctypes.c_void_p(o.data_ptr()), _stream(stream)), "s2dw_steer")
     return o
 
 
@@ -285,10 +330,11 @@ def sht_inverse(flm: torch.Tensor, L: int, stream=None) -> torch.Tensor:
 
 
 def workspace_bytes(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1,
-                    precision: str = "fp64") -> int:
+                    precision: str = "fp64", multires: bool = False) -> int:
     """Device bytes of one stream's workspace for a batch of `count` maps."""
     b = ctypes.c_uint64()
-    _check(lib().s2dw_workspace_bytes(ctypes.byref(params(L, N, lam, J_min, precision)), count, ctypes.byref(b)),
+    _check(lib().s2dw_workspace_bytes(ctypes.byref(params(L, N, lam, J_min, precision, multires)), count,
+                                      ctypes.byref(b)),
            "s2dw_workspace_bytes")
     return b.value
 

@@ -122,3 +122,25 @@ def test_steer_argument_errors():
     assert lib.s2dw_steer(ctypes.byref(p), 1, fake, 0, None, None, None) == 0  # no angles: nothing to do
     bad = s2dw.Params(64, 17, 2.0, 0, 0, 0, 1)  # N above 16
     assert lib.s2dw_steer(ctypes.byref(bad), 1, fake, 1, fake, fake, None) == -1
+
+
+@pytest.mark.parametrize("L,N,lam,J_min", [(64, 4, 2.0, 0), (100, 3, 1.7, 1), (1024, 8, 2.0, 1)])
+def test_multires_layout_queries(L, N, lam, J_min):
+    # per-scale grids of the multiresolution layout follow the band-limits of the kernel (host only)
+    import oracle
+    bl = oracle.scale_bandlimits(L, lam, J_min)
+    off = 0
+    for j, Lj in enumerate(bl):
+        sh, o = s2dw.scale_grid(L, N, lam, J_min, j, multires=True)
+        assert sh == (2 * N - 1, Lj, 2 * Lj - 1 if Lj else 0) and o == off
+        off += sh[0] * sh[1] * sh[2]
+        shf, of = s2dw.scale_grid(L, N, lam, J_min, j)
+        assert shf == (2 * N - 1, L, 2 * L - 1) and of == j * (2 * N - 1) * L * (2 * L - 1)
+    b = ctypes.c_uint64()
+    assert s2dw.lib().s2dw_wavelet_bytes(ctypes.byref(s2dw.params(L, N, lam, J_min, multires=True)),
+                                         ctypes.byref(b)) == 0
+    assert b.value == 8 * off
+    assert s2dw.lib().s2dw_scale_grid(ctypes.byref(s2dw.params(L, N, lam, J_min, multires=True)), len(bl),
+                                      None, None) == -1
+    bad = s2dw.Params(L, N, lam, J_min, 2, 0, 1)  # unknown grid
+    assert s2dw.lib().s2dw_scale_grid(ctypes.byref(bad), 0, None, None) == -1

@@ -57,3 +57,31 @@ def test_full_size_rows_and_round_trip(L, N, J_min):
     del W, Wp, fr
     s2dw.release_caches()
     torch.cuda.empty_cache()
+
+
+def test_full_size_multires_rows_and_round_trip():
+    # the benchmark workload in the multiresolution layout: sampled beta rows of the finest and
+    # of a coarse scale against the oracle, and the exact round trip
+    L, N, J_min, lam = 1024, 8, 1, 2.0
+    print(f"full size multires L={L} N={N} J_min={J_min}", flush=True)
+    f = random_flm(L, 0)
+    fd = torch.as_tensor(f).to("cuda")
+    W, Wp = s2dw.analysis(fd, L, N, lam, J_min, multires=True)
+    scales = s2dw.split_scales(W, L, N, lam, J_min)
+    psi = tables.wavelets(L, N, lam, J_min)
+    for j in [0, 5]:
+        Lj = scales[j].shape[1]
+        rows = [0, Lj - 1]
+        got = scales[j][:, rows, :].cpu().numpy()
+        print(f"  oracle on scale {j} (L_j = {Lj}), rows {rows}", flush=True)
+        ref = oracle.analysis_at(f, L, N, lam, J_min, 2 * np.pi * np.arange(2 * N - 1) / (2 * N - 1),
+                                 betas=oracle.mw_betas(Lj)[rows], psi=psi[j:j + 1], nalpha=2 * Lj - 1)[0]
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        assert err < TOL, (j, err)
+    fr = s2dw.synthesis(W, Wp, L, N, lam, J_min, multires=True)
+    torch.cuda.synchronize()
+    rt = float((fr - fd).abs().max().item() / fd.abs().max().item())
+    assert rt < 1e-12, rt
+    del W, Wp, fr, scales
+    s2dw.release_caches()
+    torch.cuda.empty_cache()
