@@ -257,12 +257,12 @@ def main():
 
     # the same round trip in the multiresolution layout (each scale on the grid of its own
     # band-limit): exact as well, with fewer samples; reported beside the full-grid figure
-    Wm = torch.empty(s2dw._w_shape(L, N, lam, J_min, True), dtype=W.dtype, device=dev)
+    Wm = torch.empty(s2dw._w_shape(L, N, lam, J_min, "multires"), dtype=W.dtype, device=dev)
     frm = torch.empty_like(fr)
 
     def step_mr():
-        _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=Wm, precision=prec, multires=True)
-        s2dw.synthesis(Wm, Wp, L, N, lam, J_min, out=frm, precision=prec, multires=True)
+        _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=Wm, precision=prec, grid="multires")
+        s2dw.synthesis(Wm, Wp, L, N, lam, J_min, out=frm, precision=prec, grid="multires")
 
     for _ in range(max(1, args.warmup)):
         step_mr()
@@ -276,6 +276,30 @@ def main():
                 "round_trip_rel_err": float((frm - f).abs().max().item() / f.abs().max().item())}
     del Wm
     print(f"# multires round trip {ms_mr:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # and on the paper's own Driscoll-Healy grid (2L colatitudes, N base orientations)
+    W = None
+    torch.cuda.empty_cache()
+    Wd = torch.empty(s2dw._w_shape(L, N, lam, J_min, "dh"), dtype=torch.float64 if prec == "fp64" else torch.float32,
+                     device=dev)
+
+    def step_dh():
+        _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=Wd, precision=prec, grid="dh")
+        s2dw.synthesis(Wd, Wp, L, N, lam, J_min, out=frm, precision=prec, grid="dh")
+
+    for _ in range(max(1, args.warmup)):
+        step_dh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_dh()
+    torch.cuda.synchronize()
+    ms_dh = (time.perf_counter() - t0) * 1e3 / args.steps
+    dh_grid = {"ms_per_step": ms_dh, "samples_per_map": Wd.numel(),
+               "coeffs_per_s": Wd.numel() / (ms_dh * 1e-3),
+               "round_trip_rel_err": float((frm - f).abs().max().item() / f.abs().max().item())}
+    del Wd
+    print(f"# Driscoll-Healy round trip {ms_dh:.3f} ms/step", file=sys.stderr, flush=True)
 
     out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8; p50/p99 mixed-L",
            "value": value, "unit": "SO(3) coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -291,7 +315,8 @@ def main():
            "stages_frac": {k: round(v["frac"], 4) for k, v in stage_roofs.items()},
            "wigner_terms_per_direction": T,
            "steer": steer,
-           "multires": multires}
+           "multires": multires,
+           "driscoll_healy": dh_grid}
     if not args.no_cpu_baseline:
         print("# cpu baseline sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(L, N, lam, J_min)

@@ -32,6 +32,12 @@
  *    L_j (alpha 2L_j-1, beta L_j, gamma 2N-1) and the scales are stored back to
  *    back: W = [W^0 (2N-1)xL_0x(2L_0-1)][W^1 ...]...  s2dw_scale_grid gives each
  *    scale's shape and offset.  Analysis and synthesis stay exact.
+ *  - Driscoll-Healy layout (grid = S2DW_GRID_DH), the discretisation of
+ *    Sec. 3.1: W real [S][N][2L][2L-1] = [j][gamma_g][beta_t][alpha_a] with
+ *        alpha_a = 2 pi a/(2L-1),  beta_t = pi (2t+1)/(4L) (t < 2L),
+ *        gamma_g = pi g/N (g < N, the N base orientations on [0, pi)).
+ *    Synthesis integrates beta with the quadrature weights of Eq. 17-18 and
+ *    gamma with weight 2 pi z_n, z_n = 1/N (Eq. 39); both directions are exact.
  *  - Sphere maps: real [L][2L-1] = [theta_b][phi_a] on the same beta/alpha
  *    samples.
  *  - Only real signals are supported (reality = 1): f_{l,-m} =
@@ -77,7 +83,9 @@ enum {
 enum {
     S2DW_GRID_MW = 0,          /* every scale on the grid of band-limit L: alpha 2L-1, beta L
                                   (incl. pi), gamma 2N-1 */
-    S2DW_GRID_MW_MULTIRES = 1  /* scale j on the grid of its own band-limit L_j (see below) */
+    S2DW_GRID_MW_MULTIRES = 1, /* scale j on the grid of its own band-limit L_j (see below) */
+    S2DW_GRID_DH = 2           /* the paper's own grid (Sec. 3.1): alpha 2L-1, beta 2L, gamma N
+                                  on [0, pi) (see below) */
 };
 enum { S2DW_FP64 = 0, S2DW_MIXED = 1 };
 
@@ -86,7 +94,7 @@ typedef struct s2dw_params {
     int32_t N;         /* azimuthal band-limit of the wavelets, 1 <= N <= min(L, 16) (Eq. 8) */
     double lambda;     /* dilation parameter, finite and > 1 (Eq. 12) */
     int32_t J_min;     /* 0 <= J_min <= J_L(lambda); scales j = 0..J_L(lambda) - J_min */
-    int32_t grid;      /* S2DW_GRID_MW or S2DW_GRID_MW_MULTIRES */
+    int32_t grid;      /* S2DW_GRID_MW, S2DW_GRID_MW_MULTIRES or S2DW_GRID_DH */
     int32_t precision; /* S2DW_FP64, or S2DW_MIXED: W stored as floats; the beta, gamma and
                           alpha stages of both directions and the m'-sum of the synthesis
                           contraction (Eq. 34) computed and accumulated in FP32; the
@@ -99,15 +107,16 @@ typedef struct s2dw_params {
 /* Number of wavelet scales S = J_L(lambda) - J_min + 1 (Sec. 2.2). */
 int s2dw_num_scales(const s2dw_params *p, int32_t *S);
 
-/* Grid shape {n_gamma, n_beta, n_alpha} = {2N-1, L, 2L-1}. */
+/* Grid shape {n_gamma, n_beta, n_alpha} of one scale: {2N-1, L, 2L-1}, or {N, 2L, 2L-1}
+ * for S2DW_GRID_DH (the finest scale for S2DW_GRID_MW_MULTIRES). */
 int s2dw_grid_shape(const s2dw_params *p, int32_t shape[3]);
 
 /* Bytes of the wavelet-coefficient array W of one map (all S scales, either layout). */
 int s2dw_wavelet_bytes(const s2dw_params *p, uint64_t *bytes);
 
-/* Sample grid of scale j: shape {2N-1, L_j, 2L_j-1} ({2N-1, L, 2L-1} for S2DW_GRID_MW)
- * and the element offset of W^j in the W of one map.  Host-only; shape or offset may be
- * NULL. */
+/* Sample grid of scale j: shape {2N-1, L_j, 2L_j-1} ({2N-1, L, 2L-1} for S2DW_GRID_MW,
+ * {N, 2L, 2L-1} for S2DW_GRID_DH) and the element offset of W^j in the W of one map.
+ * Host-only; shape or offset may be NULL. */
 int s2dw_scale_grid(const s2dw_params *p, int32_t j, int32_t shape[3], uint64_t *offset);
 
 /*
@@ -148,9 +157,10 @@ int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, c
  * trigonometric polynomial with those frequencies, fixed exactly by its 2N-1 samples:
  *     W(alpha, beta, gamma) = sum_g z(gamma - gamma_g) W(alpha, beta, gamma_g),
  *     z(delta) = 1/(2N-1) sum_{n carried} cos(n delta).
- * (The paper states it with N base orientations on [0, pi); on this grid's 2N-1 samples
- * the same polynomial takes this kernel.)  Exact up to rounding for W produced by the
- * analysis; other input is first projected onto the carried orders.
+ * On the Driscoll-Healy grid the samples are the paper's N base orientations
+ * gamma_g = pi g/N and z(delta) = 1/N sum_{n carried} cos(n delta) (z_n = 1/N).  Exact up
+ * to rounding for W produced by the analysis; other input is first projected onto the
+ * carried orders.
  *   count    number of maps, >= 1 (W and out hold count maps back to back).
  *   W        in : [count][S][2N-1][L][2L-1] real, doubles (S2DW_FP64) or floats (S2DW_MIXED);
  *                 with S2DW_GRID_MW_MULTIRES, count maps of the multiresolution layout.

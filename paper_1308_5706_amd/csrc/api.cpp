@@ -34,7 +34,18 @@ struct Plan {
     // sample grid of each scale: full resolution (band-limit L for every scale) or
     // multiresolution (the scale's own band-limit Lj); W of a map holds the scales back to back
     int grid = S2DW_GRID_MW;
-    int Lg[kMaxScales] = {};                    // grid band-limit: beta Lg, alpha 2Lg - 1 samples
+    int Lg[kMaxScales] = {};                    // grid band-limit: alpha 2Lg - 1 samples
+    int nb = 0, ng = 0;                         // beta rings and gamma samples of the (full) grid:
+                                                // (L, 2N - 1), or (2L, N) on the Driscoll-Healy grid
+    // Driscoll-Healy beta tables: chirps of Tb = 4L (csq t < 2L, cpp at p + L - 1, |p| < L) and
+    // the quadrature weights q_t (Eq. 18); per scale the synthesis beta spectrum (size PE)
+    double2 *dh_csq = nullptr, *dh_cpp = nullptr;
+    double *dh_q = nullptr;
+    float2 *dh_csqf = nullptr, *dh_cppf = nullptr;
+    float *dh_qf = nullptr;
+    std::vector<int> PE;
+    std::vector<double2 *> hE;
+    std::vector<float2 *> hEf;
     size_t woff[kMaxScales + 1] = {};           // element offset of scale j in the W of one map
     // chirp tables of one grid band-limit (length T = 2Lg - 1) and the spectrum of the first
     // synthesis beta convolution (transform size PD)
@@ -431,24 +442,30 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
     Plan &P = *pl;
     const int M = 2 * L - 1;
     // sample grids and the W layout of one map
-    const int Gn = 2 * t.N - 1;
+    const bool dh = grid == S2DW_GRID_DH;
+    const int Gn = dh ? t.N : 2 * t.N - 1;
+    P.nb = dh ? 2 * L : L;
+    P.ng = Gn;
     {
         size_t wo = 0;
         for (int j = 0; j < t.S; ++j) {
             const size_t lg = P.Lg[j] = grid == S2DW_GRID_MW_MULTIRES ? P.sc.Lj[j] : L;
+            const size_t rings = dh ? 2 * lg : lg;
             P.woff[j] = wo;
-            wo += (size_t)Gn * lg * (lg > 0 ? 2 * lg - 1 : 0);
+            wo += (size_t)Gn * rings * (lg > 0 ? 2 * lg - 1 : 0);
         }
         P.woff[t.S] = wo;
     }
-    // gamma pass factors for the orders n >= 0, n = 2 ni - (N - 1), ni = N/2 + k
+    // gamma pass factors for the orders n >= 0, n = 2 ni - (N - 1), ni = N/2 + k, at
+    // gamma_g = 2 pi g/(2N - 1) (equiangular) or pi g/N (Driscoll-Healy, Sec. 3.1)
     P.Nh = t.N - t.N / 2;
     std::vector<double2> tgf((size_t)Gn * P.Nh), tga((size_t)Gn * P.Nh);
+    const int gper = dh ? 2 * Gn : Gn;  // gamma_g = 2 pi g/gper
     for (int g = 0; g < Gn; ++g)
         for (int k = 0; k < P.Nh; ++k) {
             const long long n = 2LL * (t.N / 2 + k) - (t.N - 1);
-            const long long r = (n * g) % Gn;
-            const ld a = 2.0L * kPiL * (ld)r / (ld)Gn;
+            const long long r = (n * g) % gper;
+            const ld a = 2.0L * kPiL * (ld)r / (ld)gper;
             const ld f = n == 0 ? 1.0L : 2.0L;
             tgf[(size_t)g * P.Nh + k] = make_double2((double)(f * cosl(a)), (double)(f * sinl(a)));
             tga[(size_t)g * P.Nh + k] = make_double2((double)cosl(a), (double)-sinl(a));
@@ -479,6 +496,29 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
     P.hC.assign(t.S, nullptr);
     P.hD2.assign(t.S, nullptr);
     std::vector<int> sizes;
+    P.PE.assign(t.S, 0);
+    P.hE.assign(t.S, nullptr);
+    const int Tb = dh ? 4 * L : 0;
+    if (dh) {
+        // Driscoll-Healy beta grid: chirps of Tb = 4L and the weights of Eq. 18
+        std::vector<double2> csq(P.nb), cpp(2 * L - 1);
+        std::vector<double> q(P.nb);
+        for (int i = 0; i < P.nb; ++i) {
+            const std::pair<ld, ld> c = chirp_val(i, Tb, +1);
+            csq[i] = make_double2((double)c.first, (double)c.second);
+            const ld th = kPiL * (2 * i + 1) / (ld)Tb;
+            ld acc = 0.0L;
+            for (int k = 0; k < L; ++k) acc += sinl((2 * k + 1) * th) / (2 * k + 1);
+            q[i] = (double)(2.0L / L * sinl(th) * acc);
+        }
+        for (int i = 0; i < 2 * L - 1; ++i) {
+            const long long p = i - (L - 1);
+            const long long rp = ((p * (p + 1)) % (2LL * Tb) + 2LL * Tb) % (2LL * Tb);
+            const ld a = kPiL * (ld)rp / (ld)Tb;
+            cpp[i] = make_double2((double)cosl(a), (double)sinl(a));
+        }
+        if (!upload(P, P.dh_csq, csq) || !upload(P, P.dh_cpp, cpp) || !upload(P, P.dh_q, q)) return S2DW_E_NOMEM;
+    }
     for (int j = 0; j < t.S; ++j) {
         const int Lj = P.sc.Lj[j];
         if (Lj == 0) continue;
@@ -486,14 +526,24 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
         int rc_g = build_grid_tab(P, Lg);
         if (rc_g != S2DW_OK) return rc_g;
         const int PD = P.gt[Lg].PD;
-        P.PA[j] = pow2_at_least(2 * Lj + Lg - 2);
+        const int nbj = dh ? P.nb : Lg, Tbj = dh ? Tb : T;  // beta rings and beta chirp length
+        P.PA[j] = pow2_at_least(2 * Lj + nbj - 2);
         P.PB[j] = pow2_at_least(2 * Lj + T - 2);
         if (P.PA[j] > 8192 || P.PB[j] > 8192) return S2DW_E_UNSUPPORTED;
         sizes.push_back(PD);
         sizes.push_back(P.PA[j]);
         sizes.push_back(P.PB[j]);
-        auto ha = spectrum(P.PA[j], 2 * Lj + Lg - 2, 1.0L,
-                           [&](int i) { return chirp_val((long long)i - Lj + 1, T, -1); });
+        if (dh) {
+            // synthesis beta sum: kernel e^{i pi d^2/Tb} at d = i - (Lj + nb - 2)
+            P.PE[j] = pow2_at_least(nbj + 2 * Lj - 2);
+            if (P.PE[j] > 8192) return S2DW_E_UNSUPPORTED;
+            sizes.push_back(P.PE[j]);
+            auto he = spectrum(P.PE[j], nbj + 2 * Lj - 2, 1.0L,
+                               [&](int i) { return chirp_val((long long)i - (Lj + nbj - 2), Tb, +1); });
+            if (!upload(P, P.hE[j], he)) return S2DW_E_NOMEM;
+        }
+        auto ha = spectrum(P.PA[j], 2 * Lj + nbj - 2, 1.0L,
+                           [&](int i) { return chirp_val((long long)i - Lj + 1, Tbj, -1); });
         auto hb = spectrum(P.PB[j], 2 * Lj + T - 2, 1.0L,
                            [&](int i) { return chirp_val((long long)i - Lj + 1, T, -1); });
         auto hc = spectrum(P.PB[j], 2 * Lj + T - 2, 1.0L,
@@ -525,8 +575,8 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
     for (int j = 0; j < t.S; ++j) maxLj = std::max(maxLj, P.sc.Lj[j]);
     P.s_fpad = (size_t)L * Lp;
     P.s_U = (size_t)std::max<int64_t>(off, 1);
-    P.s_Ub = (size_t)t.N * L * std::max(maxLj, 1);
-    P.s_Y = (size_t)P.Nh * L * M;
+    P.s_Ub = (size_t)t.N * P.nb * std::max(maxLj, 1);
+    P.s_Y = (size_t)P.Nh * P.nb * M;
     P.chunk = default_chunk(P);
     out = pl.release();
     return S2DW_OK;
@@ -552,15 +602,20 @@ int ensure_f32(Plan &P) {
         Plan::GridTab &g = kv.second;
         ok = f32_copy(P, g.csqf, g.csq, T) && f32_copy(P, g.cppf, g.cpp, T) && f32_copy(P, g.hD1f, g.hD1, g.PD);
     }
+    if (ok && P.grid == S2DW_GRID_DH)
+        ok = f32_copy(P, P.dh_csqf, P.dh_csq, P.nb) && f32_copy(P, P.dh_cppf, P.dh_cpp, 2 * P.L - 1) &&
+             f32_copy(P, P.dh_qf, P.dh_q, P.nb);
     P.hAf.assign(S, nullptr);
     P.hBf.assign(S, nullptr);
     P.hCf.assign(S, nullptr);
     P.hD2f.assign(S, nullptr);
+    P.hEf.assign(S, nullptr);
     for (int j = 0; ok && j < S; ++j) {
         if (P.sc.Lj[j] == 0) continue;
         const int PD = P.gt[P.Lg[j]].PD;
         ok = f32_copy(P, P.hAf[j], P.hA[j], P.PA[j]) && f32_copy(P, P.hBf[j], P.hB[j], P.PB[j]) &&
              f32_copy(P, P.hCf[j], P.hC[j], P.PB[j]) && f32_copy(P, P.hD2f[j], P.hD2[j], PD);
+        if (ok && P.hE[j]) ok = f32_copy(P, P.hEf[j], P.hE[j], P.PE[j]);
     }
     for (auto &kv : P.twP) {
         if (!ok) break;
@@ -635,7 +690,7 @@ int check_params(const s2dw_params *p) {
     if (!(p->lambda > 1.0) || !std::isfinite(p->lambda)) return S2DW_E_ARG;
     int JL = jmax_of(p->L, p->lambda);
     if (p->J_min < 0 || p->J_min > JL || JL - p->J_min + 1 > kMaxScales) return S2DW_E_ARG;
-    if (p->grid != S2DW_GRID_MW && p->grid != S2DW_GRID_MW_MULTIRES) return S2DW_E_ARG;
+    if (p->grid != S2DW_GRID_MW && p->grid != S2DW_GRID_MW_MULTIRES && p->grid != S2DW_GRID_DH) return S2DW_E_ARG;
     if (p->precision != S2DW_FP64 && p->precision != S2DW_MIXED) return S2DW_E_ARG;
     if (p->reality != 1) return p->reality == 0 ? S2DW_E_UNSUPPORTED : S2DW_E_ARG;
     return S2DW_OK;
@@ -703,7 +758,7 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         a.nplain = P.nfwd_plain;
         S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.R, P.nfwd_plain + P.nfwd_x, maps, st));
     }
-    const int N = P.ht.N, G = 2 * N - 1;
+    const int N = P.ht.N;
     const size_t per_map = P.woff[P.S];
     for (int j = 0; j < P.S; ++j) {
         const int Lj = P.sc.Lj[j], Lg = P.Lg[j];
@@ -725,9 +780,11 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         b.s_out = P.s_Ub;
         b.hh = f32 ? (const void *)P.hAf[j] : P.hA[j];
         b.tw = f32 ? (const void *)P.twPf[P.PA[j]] : P.twP[P.PA[j]];
-        b.csq = f32 ? (const void *)gtab.csqf : gtab.csq;
-        b.cpp = f32 ? (const void *)gtab.cppf : gtab.cpp;
+        const bool dh = P.grid == S2DW_GRID_DH;
+        b.csq = dh ? (f32 ? (const void *)P.dh_csqf : P.dh_csq) : (f32 ? (const void *)gtab.csqf : gtab.csq);
+        b.cpp = dh ? (f32 ? (const void *)P.dh_cppf : P.dh_cpp) : (f32 ? (const void *)gtab.cppf : gtab.cpp);
         b.L = Lg;
+        b.nb = dh ? P.nb : Lg;
         b.Lj = Lj;
         b.N = N;
         b.Nh = P.Nh;
@@ -742,6 +799,8 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         c.s_out = P.s_Y;
         c.hh = f32 ? (const void *)P.hBf[j] : P.hB[j];
         c.tw = f32 ? (const void *)P.twPf[P.PB[j]] : P.twP[P.PB[j]];
+        c.csq = f32 ? (const void *)gtab.csqf : gtab.csq;
+        c.cpp = f32 ? (const void *)gtab.cppf : gtab.cpp;
         {
             Stage sg("alpha_fwd", st);
             S2DW_CHECK_HIP(launch_alpha_fwd_fft(c, P.PB[j], maps, st));
@@ -752,9 +811,9 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         g.s_w = per_map;
         g.s_y = P.s_Y;
         g.tg = f32 ? (const void *)P.tgff : P.tgf;
-        g.L = Lg;
+        g.L = b.nb;
         g.T = 2 * Lg - 1;
-        g.G = G;
+        g.G = P.ng;
         g.Nh = P.Nh;
         g.f32 = f32;
         {
@@ -769,7 +828,7 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
 // per-map layout as run_inverse; wphi of map i at wphi + i L^2, or null).
 int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, double2 *flm, int f32,
                 hipStream_t st) {
-    const int L = P.L, N = P.ht.N, G = 2 * N - 1;
+    const int L = P.L, N = P.ht.N;
     const size_t per_map = P.woff[P.S];
     for (int j = 0; j < P.S; ++j) {
         const int Lj = P.sc.Lj[j], Lg = P.Lg[j], M = 2 * Lg - 1;
@@ -782,10 +841,11 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         g.out = w.Y;
         g.s_w = per_map;
         g.s_y = P.s_Y;
+        const bool dh = P.grid == S2DW_GRID_DH;
         g.tg = f32 ? (const void *)P.tgaf : P.tga;
-        g.L = Lg;
+        g.L = dh ? P.nb : Lg;
         g.T = M;
-        g.G = G;
+        g.G = P.ng;
         g.Nh = P.Nh;
         g.f32 = f32;
         {
@@ -803,11 +863,12 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         c.csq = f32 ? (const void *)gtab.csqf : gtab.csq;
         c.cpp = f32 ? (const void *)gtab.cppf : gtab.cpp;
         c.L = Lg;
+        c.nb = g.L;
         c.Lj = Lj;
         c.N = N;
         c.Nh = P.Nh;
         c.K = P.K;
-        c.scale = (2.0 * M_PI / M) * (2.0 * M_PI / G);
+        c.scale = (2.0 * M_PI / M) * (2.0 * M_PI / P.ng);
         {
             Stage sg("alpha_adj", st);
             S2DW_CHECK_HIP(launch_alpha_adj_fft(c, P.PB[j], maps, st));
@@ -819,12 +880,20 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         // Wigner kernel indexes it with the same element type); per-map stride s_U elements
         v.out = f32 ? (void *)((float2 *)w.U + P.sc.off[j]) : (void *)(w.U + P.sc.off[j]);
         v.s_out = P.s_U;
-        v.hh = f32 ? (const void *)gtab.hD1f : gtab.hD1;
-        v.hh2 = f32 ? (const void *)P.hD2f[j] : P.hD2[j];
-        v.tw = f32 ? (const void *)P.twPf[gtab.PD] : P.twP[gtab.PD];
         for (int k = 0; k < P.K; ++k) v.nk[k] = P.ht.nk[k];
         v.eta_imag = P.ht.eta_imag ? 1 : 0;
-        {
+        if (dh) {
+            v.csq = f32 ? (const void *)P.dh_csqf : P.dh_csq;
+            v.cpp = f32 ? (const void *)P.dh_cppf : P.dh_cpp;
+            v.qw = f32 ? (const void *)P.dh_qf : P.dh_q;
+            v.hh = f32 ? (const void *)P.hEf[j] : P.hE[j];
+            v.tw = f32 ? (const void *)P.twPf[P.PE[j]] : P.twP[P.PE[j]];
+            Stage sg("beta_adj", st);
+            S2DW_CHECK_HIP(launch_beta_adj_dh(v, P.PE[j], maps, st));
+        } else {
+            v.hh = f32 ? (const void *)gtab.hD1f : gtab.hD1;
+            v.hh2 = f32 ? (const void *)P.hD2f[j] : P.hD2[j];
+            v.tw = f32 ? (const void *)P.twPf[gtab.PD] : P.twP[gtab.PD];
             Stage sg("beta_adj", st);
             S2DW_CHECK_HIP(launch_beta_adj_fft(v, gtab.PD, maps, st));
         }
@@ -877,8 +946,9 @@ int s2dw_num_scales(const s2dw_params *p, int32_t *S) {
 
 int s2dw_grid_shape(const s2dw_params *p, int32_t shape[3]) {
     if (!p || !shape || p->L < 2 || p->N < 1) return S2DW_E_ARG;
-    shape[0] = 2 * p->N - 1;
-    shape[1] = p->L;
+    const bool dh = p->grid == S2DW_GRID_DH;
+    shape[0] = dh ? p->N : 2 * p->N - 1;
+    shape[1] = dh ? 2 * p->L : p->L;
     shape[2] = 2 * p->L - 1;
     return S2DW_OK;
 }
@@ -890,12 +960,13 @@ int s2dw_scale_grid(const s2dw_params *p, int32_t j, int32_t shape[3], uint64_t 
     rc = grid_limits(p, Lg);
     if (rc != S2DW_OK) return rc;
     if (j < 0 || j >= (int32_t)Lg.size()) return S2DW_E_ARG;
-    const uint64_t G = 2 * (uint64_t)p->N - 1;
+    const bool dh = p->grid == S2DW_GRID_DH;
+    const uint64_t G = dh ? p->N : 2 * (uint64_t)p->N - 1, rf = dh ? 2 : 1;
     uint64_t off = 0;
-    for (int32_t i = 0; i < j; ++i) off += G * Lg[i] * (Lg[i] > 0 ? 2 * (uint64_t)Lg[i] - 1 : 0);
+    for (int32_t i = 0; i < j; ++i) off += G * rf * Lg[i] * (Lg[i] > 0 ? 2 * (uint64_t)Lg[i] - 1 : 0);
     if (shape) {
         shape[0] = (int32_t)G;
-        shape[1] = Lg[j];
+        shape[1] = (int32_t)(rf * Lg[j]);
         shape[2] = Lg[j] > 0 ? 2 * Lg[j] - 1 : 0;
     }
     if (offset) *offset = off;
@@ -920,7 +991,10 @@ int s2dw_wavelet_bytes(const s2dw_params *p, uint64_t *bytes) {
     int rc = s2dw_num_scales(p, &S);
     if (rc != S2DW_OK) return rc;
     if (p->N < 1) return S2DW_E_ARG;
-    *bytes = (uint64_t)S * (2 * p->N - 1) * p->L * (2 * (uint64_t)p->L - 1) * el;
+    int32_t sh[3];
+    rc = s2dw_grid_shape(p, sh);
+    if (rc != S2DW_OK) return rc;
+    *bytes = (uint64_t)S * sh[0] * sh[1] * sh[2] * el;
     return S2DW_OK;
 }
 
@@ -1139,13 +1213,17 @@ int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gam
     std::vector<int> Lg;
     rc = grid_limits(p, Lg);
     if (rc != S2DW_OK) return rc;
-    const int S = (int)Lg.size(), G = 2 * p->N - 1;
+    const bool dh = p->grid == S2DW_GRID_DH;
+    const int S = (int)Lg.size(), G = dh ? p->N : 2 * p->N - 1, rf = dh ? 2 : 1;
+    // gamma samples: gamma_g = 2 pi g/(2N-1), or pi g/N on the Driscoll-Healy grid; in both
+    // cases the interpolation weight is 1/G (z_n = 1/N on the paper's grid, Eq. 10)
+    const double step = dh ? M_PI / p->N : 2.0 * M_PI / G;
     const int f32 = p->precision == S2DW_MIXED;
     const size_t es = f32 ? 4 : 8;
     // element offsets of each scale in one map of W and of out
     std::vector<size_t> oin(S + 1, 0), oout(S + 1, 0);
     for (int j = 0; j < S; ++j) {
-        const size_t pl = (size_t)Lg[j] * (Lg[j] > 0 ? 2 * Lg[j] - 1 : 0);
+        const size_t pl = (size_t)rf * Lg[j] * (Lg[j] > 0 ? 2 * Lg[j] - 1 : 0);
         oin[j + 1] = oin[j] + G * pl;
         oout[j + 1] = oout[j] + (size_t)n_gamma * pl;
     }
@@ -1155,14 +1233,14 @@ int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gam
         const int maps = std::min<int32_t>(65535, count - i);
         const char *Wi = (const char *)W + i * oin[S] * es;
         char *Oi = (char *)out + i * oout[S] * es;
-        if (p->grid == S2DW_GRID_MW) {  // one plane size: all scales in one launch
-            S2DW_CHECK_HIP(launch_steer(Wi, gamma, Oi, f32, p->N, n_gamma, S, (size_t)p->L * (2 * p->L - 1), oin[S],
-                                        oout[S], maps, st));
+        if (p->grid != S2DW_GRID_MW_MULTIRES) {  // one plane size: all scales in one launch
+            S2DW_CHECK_HIP(launch_steer(Wi, gamma, Oi, f32, p->N, G, step, n_gamma, S,
+                                        (size_t)rf * p->L * (2 * p->L - 1), oin[S], oout[S], maps, st));
             continue;
         }
         for (int j = 0; j < S; ++j) {
             if (Lg[j] == 0) continue;
-            S2DW_CHECK_HIP(launch_steer(Wi + oin[j] * es, gamma, Oi + oout[j] * es, f32, p->N, n_gamma, 1,
+            S2DW_CHECK_HIP(launch_steer(Wi + oin[j] * es, gamma, Oi + oout[j] * es, f32, p->N, G, step, n_gamma, 1,
                                         (size_t)Lg[j] * (2 * Lg[j] - 1), oin[S], oout[S], maps, st));
         }
     }

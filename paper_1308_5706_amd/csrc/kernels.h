@@ -51,10 +51,10 @@ hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int R, int ntiles, int map
 
 // ---------------------------------------------------------------- beta / alpha / gamma stages
 // Bluestein stages (stages.hip).  Layouts per scale j (Lj = band-limit of the scale,
-// T = 2L - 1, Nh = ceil(N/2) orders n >= 0):
-//   analysis:  U [N][Lj][Lj] = [n][m][m'] -> Ub [N][Lj][L] = [n][m][b]
-//              -> Y [Nh][L][T] (alpha sums, n >= 0) -> W [2N-1][L][T] (gamma pass)
-//   synthesis: W -> X [Nh][L][T] (gamma pass) -> G [N][Lj][L] = [n][m][b] (alpha sums)
+// T = 2L - 1, nb beta rings, G gamma samples, Nh = ceil(N/2) orders n >= 0):
+//   analysis:  U [N][Lj][Lj] = [n][m][m'] -> Ub [N][Lj][nb] = [n][m][b]
+//              -> Y [Nh][nb][T] (alpha sums, n >= 0) -> W [G][nb][T] (gamma pass)
+//   synthesis: W -> X [Nh][nb][T] (gamma pass) -> G [N][Lj][nb] = [n][m][b] (alpha sums)
 //              -> V [K][2][Lj][Lj] = [k][P|Q][m][m']
 struct StageArgs {
     // Arrays are double2 (FP64 path) or float2 (f32 = 1, mixed precision), except the
@@ -64,10 +64,11 @@ struct StageArgs {
     const void *hh;        // FFT of the stage's chirp (or kernel) sequence, divided by P
     const void *hh2;       // FFT of the w(q) sequence (synthesis beta stage), divided by P
     const void *tw;        // e^{-2 pi i k/P}, k < P
-    const void *csq;       // e^{i pi i^2/T}, i < T, T = 2L - 1
-    const void *cpp;       // e^{i pi p(p+1)/T} at p + L - 1, |p| < L
+    const void *csq;       // e^{i pi i^2/T}, i < T (alpha stages, T = 2L - 1), or i < nb (beta stages, T = Tb)
+    const void *cpp;       // e^{i pi p(p+1)/T} at p + L - 1, |p| < L (T as for csq)
+    const void *qw;        // Driscoll-Healy quadrature weights q_t, t < nb (real; synthesis beta stage)
     size_t s_in, s_out;    // per-map strides (complex elements) of a batch; map = blockIdx.y
-    int L, Lj, N, Nh, K, eta_imag, f32;
+    int L, nb, Lj, N, Nh, K, eta_imag, f32;  // nb: beta rings (L, or 2L on the Driscoll-Healy grid)
     int nk[kMaxK];
     double scale;
 };
@@ -76,6 +77,7 @@ hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t 
 hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
+hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t st);
 
 struct GammaArgs {
     const void *win;       // W read (synthesis): double, or float if f32
@@ -99,10 +101,10 @@ hipError_t launch_syn_final(const void *Fpart, size_t s_F, int f32, int nblk, in
                             hipStream_t st);
 hipError_t launch_zero_words(void *p, size_t n, hipStream_t st);
 hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t st);
-// W [maps][S][2N-1][P] -> out [maps][S][Q][P] at the Q angles gam (device), P points per
-// plane, map i of W at i s_in and of out at i s_out (elements); doubles, or floats if f32;
-// maps <= 65535.
-hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int Q, int S, size_t P,
-                        size_t s_in, size_t s_out, int maps, hipStream_t st);
+// W [maps][S][G][P] (gamma_g = g step) -> out [maps][S][Q][P] at the Q angles gam (device),
+// P points per plane, map i of W at i s_in and of out at i s_out (elements); doubles, or
+// floats if f32; G <= 31, maps <= 65535.
+hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int G, double step, int Q,
+                        int S, size_t P, size_t s_in, size_t s_out, int maps, hipStream_t st);
 
 }  // namespace s2dw

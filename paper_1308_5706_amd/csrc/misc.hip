@@ -119,8 +119,9 @@ hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t st
 
 // Wavelet coefficients at arbitrary third Euler angles (steerability, Eq. 9-10).  The wavelets
 // carry only the orders n with |n| < N and n = N - 1 (mod 2) (Eq. 11), so W as a function of
-// gamma is a trigonometric polynomial with those frequencies, fixed exactly by its G = 2N - 1
-// grid samples gamma_g = 2 pi g/G:
+// gamma is a trigonometric polynomial with those frequencies, fixed exactly by its G grid
+// samples gamma_g = g step (G = 2N - 1, step = 2 pi/G on the equiangular grid; G = N base
+// orientations, step = pi/N, on the Driscoll-Healy grid):
 //   W(alpha, beta, gamma) = sum_g z(gamma - gamma_g) W(alpha, beta, gamma_g),
 //   z(delta) = (1/G) sum_{n carried} cos(n delta).
 // Block: kSteerQ target angles for 256 x V consecutive (beta, alpha) points of one plane set
@@ -135,18 +136,17 @@ struct SteerVec {
 };
 
 template <class E, int V>
-__global__ __launch_bounds__(256) void steer_kernel(const E *W, const double *gam, E *out, int N, int Q, int nqc,
-                                                    size_t P, size_t s_in, size_t s_out) {
+__global__ __launch_bounds__(256) void steer_kernel(const E *W, const double *gam, E *out, int N, int G,
+                                                    double step, int Q, int nqc, size_t P, size_t s_in, size_t s_out) {
     typedef typename SteerVec<E, V>::type vec;
     __shared__ E zw[kSteerQ][kSteerG];
-    const int G = 2 * N - 1;
     const int qc = blockIdx.x % nqc;
     const size_t tile = blockIdx.x / nqc;
     const int q0 = qc * kSteerQ;
     const int qn = min(kSteerQ, Q - q0);
     for (int t = threadIdx.x; t < qn * G; t += blockDim.x) {
         const int q = t / G, g = t - q * G;
-        const double d = gam[q0 + q] - 6.283185307179586476925 * (double)g / (double)G;
+        const double d = gam[q0 + q] - step * (double)g;
         double z = 0.0;
         for (int n = -(N - 1); n <= N - 1; n += 2) z += cos((double)n * d);
         zw[q][g] = (E)(z / (double)G);
@@ -170,28 +170,28 @@ __global__ __launch_bounds__(256) void steer_kernel(const E *W, const double *ga
 }
 
 template <class E, int V>
-void steer_launch(const void *W, const double *gam, void *out, int N, int Q, int S, size_t P, size_t s_in,
-                  size_t s_out, int maps, hipStream_t st) {
+void steer_launch(const void *W, const double *gam, void *out, int N, int G, double step, int Q, int S, size_t P,
+                  size_t s_in, size_t s_out, int maps, hipStream_t st) {
     const int nqc = (Q + kSteerQ - 1) / kSteerQ;
     const size_t tiles = (P + 256 * V - 1) / (256 * V);
     hipLaunchKernelGGL((steer_kernel<E, V>), dim3((unsigned)(tiles * nqc), S, maps), dim3(256), 0, st, (const E *)W,
-                       gam, (E *)out, N, Q, nqc, P, s_in, s_out);
+                       gam, (E *)out, N, G, step, Q, nqc, P, s_in, s_out);
 }
 
-hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int Q, int S, size_t P,
-                        size_t s_in, size_t s_out, int maps, hipStream_t st) {
+hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int G, double step, int Q,
+                        int S, size_t P, size_t s_in, size_t s_out, int maps, hipStream_t st) {
     // vector width: the plane size, the map strides and both base addresses are multiples of it
     const size_t es = f32 ? 4 : 8;
     auto fits = [&](int V) {
         return P % V == 0 && s_in % V == 0 && s_out % V == 0 && ((uintptr_t)W | (uintptr_t)out) % (V * es) == 0;
     };
     if (f32) {
-        if (fits(4)) steer_launch<float, 4>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
-        else if (fits(2)) steer_launch<float, 2>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
-        else steer_launch<float, 1>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
+        if (fits(4)) steer_launch<float, 4>(W, gam, out, N, G, step, Q, S, P, s_in, s_out, maps, st);
+        else if (fits(2)) steer_launch<float, 2>(W, gam, out, N, G, step, Q, S, P, s_in, s_out, maps, st);
+        else steer_launch<float, 1>(W, gam, out, N, G, step, Q, S, P, s_in, s_out, maps, st);
     } else {
-        if (fits(2)) steer_launch<double, 2>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
-        else steer_launch<double, 1>(W, gam, out, N, Q, S, P, s_in, s_out, maps, st);
+        if (fits(2)) steer_launch<double, 2>(W, gam, out, N, G, step, Q, S, P, s_in, s_out, maps, st);
+        else steer_launch<double, 1>(W, gam, out, N, G, step, Q, S, P, s_in, s_out, maps, st);
     }
     return hipGetLastError();
 }

@@ -62,14 +62,16 @@ __device__ __forceinline__ C to_c(double2 v) { return mk<C>((real_t<C>)v.x, (rea
 }  // namespace
 
 // ------------------------------------------------------------------- analysis: beta (Eq. 29)
-// Column (n, m) of scale j: Ub(b) = sum_{|m'|<Lj} U_{m m' n} e^{i m' beta_b}, b < L, with
-// U_{m,-m',n} = (-1)^{m+n} U_{m m' n} (only m' >= 0 is stored).  Since m' beta_b =
-// 2 pi m' b/T + pi m'/T, the chirp input is U e^{i pi m'(m'+1)/T}.
+// Column (n, m) of scale j: Ub(b) = sum_{|m'|<Lj} U_{m m' n} e^{i m' beta_b}, b < nb, with
+// U_{m,-m',n} = (-1)^{m+n} U_{m m' n} (only m' >= 0 is stored) and beta_b = pi (2b+1)/Tb:
+// the equiangular grid has Tb = 2L - 1, nb = L, the Driscoll-Healy grid (Eq. 17) Tb = 4L,
+// nb = 2L.  Since m' beta_b = 2 pi m' b/Tb + pi m'/Tb, the chirp input is
+// U e^{i pi m'(m'+1)/Tb}; the chirp tables of the launch are those of Tb.
 template <class C, int P>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const StageArgs a) {
     __shared__ C buf[fft::padded(P)];
     const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L;
+    const int Lj = a.Lj, L = a.L, nb = a.nb;
     const int col = blockIdx.x;  // ni * Lj + m
     const int ni = col / Lj, m = col - ni * Lj;
     const int n = 2 * ni - (a.N - 1);
@@ -78,7 +80,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const 
     const C *__restrict__ cpp = (const C *)a.cpp + (L - 1);
     const C *__restrict__ csq = (const C *)a.csq;
     const int Na = 2 * Lj - 1;
-    C *__restrict__ out = (C *)a.out + blockIdx.y * a.s_out + (size_t)col * L;
+    C *__restrict__ out = (C *)a.out + blockIdx.y * a.s_out + (size_t)col * nb;
     auto in = [&](int i) {
         if (i >= Na) return zero2<C>();
         const int mp = i - (Lj - 1);
@@ -88,7 +90,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const 
     };
     auto st = [&](int i, C v) {
         const int b = i - (Na - 1);
-        if (b >= 0 && b < L) out[b] = cmul(v, csq[b]);
+        if (b >= 0 && b < nb) out[b] = cmul(v, csq[b]);
     };
     fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
 }
@@ -106,8 +108,9 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const 
 //
 // Column order: blockIdx.x -> t = (b, n') is remapped so that the workgroups that run on
 // one XCD (dispatched round-robin over the 8 XCDs) take consecutive t; the [n][m][b]
-// arrays, read and written with stride L along m, then share L2 lines across neighbouring
-// rings b.
+// arrays, read and written with stride nb along m, then share L2 lines across neighbouring
+// rings b.  nb = number of beta rings (L, or 2L on the Driscoll-Healy grid); alpha has
+// T = 2L - 1 samples on both grids.
 __device__ __forceinline__ int xcd_column(int x, int ncols) {
     const int per = (ncols + 7) >> 3;
     return (x & 7) * per + (x >> 3);
@@ -117,14 +120,14 @@ template <class C, int P>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const StageArgs a) {
     __shared__ C buf[fft::padded(P)];
     const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh;
-    const int t = xcd_column(blockIdx.x, Nh * L);
-    if (t >= Nh * L) return;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh, nb = a.nb;
+    const int t = xcd_column(blockIdx.x, Nh * nb);
+    if (t >= Nh * nb) return;
     const int b = t / Nh, np = t - (t / Nh) * Nh;
     const int ni = (N / 2) + np, nj = N - 1 - ni;  // rows of n >= 0 and of -n
     const bool zero_n = ni == nj;
-    const C *__restrict__ Up = (const C *)a.in + blockIdx.y * a.s_in + (size_t)ni * Lj * L + b;
-    const C *__restrict__ Um = (const C *)a.in + blockIdx.y * a.s_in + (size_t)nj * Lj * L + b;
+    const C *__restrict__ Up = (const C *)a.in + blockIdx.y * a.s_in + (size_t)ni * Lj * nb + b;
+    const C *__restrict__ Um = (const C *)a.in + blockIdx.y * a.s_in + (size_t)nj * Lj * nb + b;
     const C *__restrict__ csq = (const C *)a.csq;
     const int Na = 2 * Lj - 1;
     auto in = [&](int i) {
@@ -132,14 +135,14 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const
         const int m = i - (Lj - 1);
         C c;
         if (m >= 0) {
-            c = Up[(size_t)m * L];
+            c = Up[(size_t)m * nb];
             if (m == 0 && zero_n) c.y = 0.0;
         } else {
-            c = cconj(Um[(size_t)(-m) * L]);
+            c = cconj(Um[(size_t)(-m) * nb]);
         }
         return cmul(c, csq[m < 0 ? -m : m]);
     };
-    C *__restrict__ Y = (C *)a.out + blockIdx.y * a.s_out + ((size_t)np * L + b) * T;
+    C *__restrict__ Y = (C *)a.out + blockIdx.y * a.s_out + ((size_t)np * nb + b) * T;
     auto st = [&](int i, C v) {
         const int x = i - (Na - 1);
         if (x >= 0 && x < T) Y[x] = cmul(v, csq[x]);
@@ -151,27 +154,27 @@ template <class C, int P>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const StageArgs a) {
     __shared__ C buf[fft::padded(P)];
     const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh;
-    const int t = xcd_column(blockIdx.x, Nh * L);
-    if (t >= Nh * L) return;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh, nb = a.nb;
+    const int t = xcd_column(blockIdx.x, Nh * nb);
+    if (t >= Nh * nb) return;
     const int b = t / Nh, np = t - (t / Nh) * Nh;
     const int ni = (N / 2) + np, nj = N - 1 - ni;
     const bool zero_n = ni == nj;
-    const C *__restrict__ X = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)np * L + b) * T;
+    const C *__restrict__ X = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)np * nb + b) * T;
     const C *__restrict__ csq = (const C *)a.csq;
     auto in = [&](int i) { return i < T ? cmulc(X[i], csq[i]) : zero2<C>(); };
     // Zh(m), q = m + Lj - 1 < 2Lj - 1, comes out at q + T - 1
     const int Nk = 2 * Lj - 1;
     const real_t<C> s = (real_t<C>)a.scale;
-    C *__restrict__ Gp = (C *)a.out + blockIdx.y * a.s_out + (size_t)ni * Lj * L + b;
-    C *__restrict__ Gm = (C *)a.out + blockIdx.y * a.s_out + (size_t)nj * Lj * L + b;
+    C *__restrict__ Gp = (C *)a.out + blockIdx.y * a.s_out + (size_t)ni * Lj * nb + b;
+    C *__restrict__ Gm = (C *)a.out + blockIdx.y * a.s_out + (size_t)nj * Lj * nb + b;
     auto st = [&](int i, C v) {
         const int q = i - (T - 1);
         if (q >= 0 && q < Nk) {
             const int m = q - (Lj - 1);
             const C z = cscale(cmulc(v, csq[m < 0 ? -m : m]), s);
-            if (m >= 0) Gp[(size_t)m * L] = z;
-            if (m <= 0 && !zero_n) Gm[(size_t)(-m) * L] = cconj(z);
+            if (m >= 0) Gp[(size_t)m * nb] = z;
+            if (m <= 0 && !zero_n) Gm[(size_t)(-m) * nb] = cconj(z);
         }
     };
     fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
@@ -291,6 +294,45 @@ __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
 }
 
 // ------------------------------------------ synthesis: beta integral and m' folding (Eq. 35, 40)
+// Step (3) of both beta quadratures below, once V(m') of the column pair is known: the fold
+// over +-m' and the even/odd-l combinations P, Q of the two n columns (see the synthesis
+// Wigner kernel).  On entry V of column +n sits in buf[q] (q = m' + Lj - 1) or, with two
+// columns, in the block's output rows Po/Qo, and V of column -n in buf[Nk + q].
+template <class C, int NT>
+__device__ __forceinline__ void fold_pq(C *buf, int tid, int Lj, int m, int n, int ncol, bool odd, int eta, C *Po,
+                                        C *Qo) {
+    const int Nk = 2 * Lj - 1;
+    if (ncol > 1) {
+        for (int q = tid; q < Nk; q += NT) buf[pad(q)] = q < Lj ? Po[q] : Qo[q - Lj];
+        __syncthreads();
+    }
+    for (int mp = tid; mp < Lj; mp += NT) {
+        C tp = buf[pad(mp + Lj - 1)], tm = ncol > 1 ? buf[pad(Nk + mp + Lj - 1)] : zero2<C>();
+        if (mp > 0) {
+            C up = buf[pad(-mp + Lj - 1)], um = ncol > 1 ? buf[pad(Nk - mp + Lj - 1)] : zero2<C>();
+            if (odd) {
+                up = mk<C>(-up.x, -up.y);
+                um = mk<C>(-um.x, -um.y);
+            }
+            tp = cadd(tp, up);
+            tm = cadd(tm, um);
+        }
+        C Pv, Qv;
+        if (n == 0) {
+            Pv = Qv = rot_i(tp, m + eta);
+        } else {
+            const C A = rot_i(tp, -n);
+            C B = rot_i(tm, n);
+            if (mp & 1) B = mk<C>(-B.x, -B.y);
+            Pv = rot_i(cadd(A, B), m + eta);
+            Qv = rot_i(csub(A, B), m + eta);
+        }
+        Po[mp] = Pv;
+        Qo[mp] = Qv;
+    }
+}
+
+// Equiangular grid.
 // Column pair (+n, -n), fixed m.  (1) Fourier coefficients of the samples extended to the
 // full circle (G(2 pi - beta) = (-1)^{m+n} G(beta)):
 //   Gh(p) = (1/T) sum_{t<T} ext_t e^{-i p beta_t},  |p| < L,  beta_t = pi(2t+1)/T;
@@ -353,35 +395,59 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
             fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh2, in2, st2);
         }
     }
-    if (ncol > 1) {
-        for (int q = tid; q < Nk; q += NT) buf[pad(q)] = q < Lj ? Po[q] : Qo[q - Lj];
-        __syncthreads();
-    }
-    const int eta = a.eta_imag ? 1 : 0;
-    for (int mp = tid; mp < Lj; mp += NT) {
-        C tp = buf[pad(mp + Lj - 1)], tm = ncol > 1 ? buf[pad(Nk + mp + Lj - 1)] : zero2<C>();
-        if (mp > 0) {
-            C up = buf[pad(-mp + Lj - 1)], um = ncol > 1 ? buf[pad(Nk - mp + Lj - 1)] : zero2<C>();
-            if (odd) {
-                up = mk<C>(-up.x, -up.y);
-                um = mk<C>(-um.x, -um.y);
-            }
-            tp = cadd(tp, up);
-            tm = cadd(tm, um);
-        }
-        C Pv, Qv;
-        if (n == 0) {
-            Pv = Qv = rot_i(tp, m + eta);
+    fold_pq<C, NT>(buf, tid, Lj, m, n, ncol, odd, a.eta_imag ? 1 : 0, Po, Qo);
+}
+
+// Driscoll-Healy grid (Eq. 17-18 and 40): theta_t = pi (2t+1)/Tb, t < nb, Tb = 4L, nb = 2L,
+// with the quadrature weights q_t of Eq. 18 (sin(theta) included), which integrate the
+// product of the samples and e^{-i m' theta} exactly:
+//   V(m') = sum_{t<nb} q_t G(theta_t) e^{-i m' theta_t},  |m'| < Lj,
+// then the fold (3).  Since m' theta_t = (m'^2 + m' + t^2 - (m' - t)^2) pi/Tb, the sum is one
+// chirp convolution per column: V(m') = conj(cpp(m')) sum_t [q_t G_t conj(csq_t)] e^{i pi (m'-t)^2/Tb}.
+template <class C, int P>
+__global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_dh_kernel(const StageArgs a) {
+    __shared__ C buf[fft::padded(P)];
+    constexpr int NT = P / kRM;
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, L = a.L, N = a.N, nb = a.nb;
+    const int k = blockIdx.x / Lj, m = blockIdx.x - (blockIdx.x / Lj) * Lj;
+    int n = 0;
+#pragma unroll
+    for (int kk = 0; kk < kMaxK; ++kk)
+        if (kk == k) n = a.nk[kk];
+    const int ncol = n == 0 ? 1 : 2;
+    const bool odd = ((m + n) & 1) != 0;
+    const int Nk = 2 * Lj - 1;
+    const C *__restrict__ csq = (const C *)a.csq;
+    const C *__restrict__ cpp = (const C *)a.cpp + (L - 1);
+    const real_t<C> *__restrict__ qw = (const real_t<C> *)a.qw;
+    C *__restrict__ Po = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
+    C *__restrict__ Qo = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
+    for (int c = 0; c < ncol; ++c) {
+        const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
+        const C *__restrict__ Gc = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)ni * Lj + m) * nb;
+        auto in = [&](int i) { return i < nb ? cscale(cmulc(Gc[i], csq[i]), qw[i]) : zero2<C>(); };
+        // V(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + nb - 1
+        if (c == 0 && ncol > 1) {
+            auto st = [&](int i, C v) {
+                const int q = i - (nb - 1);
+                if (q >= 0 && q < Nk) {
+                    v = cmulc(v, cpp[q - (Lj - 1)]);
+                    if (q < Lj) Po[q] = v;
+                    else Qo[q - Lj] = v;
+                }
+            };
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
         } else {
-            const C A = rot_i(tp, -n);
-            C B = rot_i(tm, n);
-            if (mp & 1) B = mk<C>(-B.x, -B.y);
-            Pv = rot_i(cadd(A, B), m + eta);
-            Qv = rot_i(csub(A, B), m + eta);
+            const int sh = c * Nk;
+            auto st = [&](int i, C v) {
+                const int q = i - (nb - 1);
+                if (q >= 0 && q < Nk) buf[pad(sh + q)] = cmulc(v, cpp[q - (Lj - 1)]);
+            };
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
         }
-        Po[mp] = Pv;
-        Qo[mp] = Qv;
     }
+    fold_pq<C, NT>(buf, tid, Lj, m, n, ncol, odd, a.eta_imag ? 1 : 0, Po, Qo);
 }
 
 // ------------------------------------------------------------------------------ launchers
@@ -416,17 +482,22 @@ hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t 
 }
 
 hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
-    S2DW_P_SWITCH(P, alpha_fwd_fft_kernel, 8 * ((a.Nh * a.L + 7) / 8), a)
+    S2DW_P_SWITCH(P, alpha_fwd_fft_kernel, 8 * ((a.Nh * a.nb + 7) / 8), a)
     return hipGetLastError();
 }
 
 hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
-    S2DW_P_SWITCH(P, alpha_adj_fft_kernel, 8 * ((a.Nh * a.L + 7) / 8), a)
+    S2DW_P_SWITCH(P, alpha_adj_fft_kernel, 8 * ((a.Nh * a.nb + 7) / 8), a)
     return hipGetLastError();
 }
 
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
     S2DW_P_SWITCH(P, beta_adj_fft_kernel, a.K * a.Lj, a)
+    return hipGetLastError();
+}
+
+hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t st) {
+    S2DW_P_SWITCH(P, beta_adj_dh_kernel, a.K * a.Lj, a)
     return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libs2dw.so")
 
 FP64, MIXED = 0, 1
-GRID_MW, GRID_MW_MULTIRES = 0, 1
+GRID_MW, GRID_MW_MULTIRES, GRID_DH = 0, 1, 2
+GRIDS = {"mw": GRID_MW, "multires": GRID_MW_MULTIRES, "dh": GRID_DH}
 
 _lib = None
 
@@ -91,9 +92,12 @@ EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_sc
 
 
 def params(L: int, N: int, lam: float = 2.0, J_min: int = 0, precision: str = "fp64",
-           multires: bool = False) -> Params:
-    return Params(L, N, float(lam), J_min, GRID_MW_MULTIRES if multires else GRID_MW,
-                  FP64 if precision == "fp64" else MIXED, 1)
+           grid: str = "mw") -> Params:
+    """grid: "mw" (equiangular, every scale at band-limit L), "multires" (each scale on the
+    equiangular grid of its own band-limit) or "dh" (the Driscoll-Healy grid of Sec. 3.1)."""
+    if grid not in GRIDS:
+        raise ValueError(f"grid must be one of {sorted(GRIDS)}, not {grid!r}")
+    return Params(L, N, float(lam), J_min, GRIDS[grid], FP64 if precision == "fp64" else MIXED, 1)
 
 
 def _check(rc: int, what: str):
@@ -142,21 +146,22 @@ def _w_dtype(precision: str):
     return torch.float64 if precision == "fp64" else torch.float32
 
 
-def scale_grid(L: int, N: int, lam: float = 2.0, J_min: int = 0, j: int = 0, *, multires: bool = False):
-    """(shape (2N-1, L_j, 2L_j-1), element offset) of scale j in the W of one map."""
+def scale_grid(L: int, N: int, lam: float = 2.0, J_min: int = 0, j: int = 0, *, grid: str = "mw"):
+    """(shape (n_gamma, n_beta, n_alpha), element offset) of scale j in the W of one map."""
     sh = (ctypes.c_int32 * 3)()
     off = ctypes.c_uint64()
-    _check(lib().s2dw_scale_grid(ctypes.byref(params(L, N, lam, J_min, multires=multires)), j, sh,
+    _check(lib().s2dw_scale_grid(ctypes.byref(params(L, N, lam, J_min, grid=grid)), j, sh,
                                  ctypes.byref(off)), "s2dw_scale_grid")
     return (sh[0], sh[1], sh[2]), off.value
 
 
-def _w_shape(L, N, lam, J_min, multires):
-    """Shape of the W of one map: [S][2N-1][L][2L-1], or flat for the multiresolution layout."""
-    if not multires:
-        return (num_scales(L, lam, J_min), 2 * N - 1, L, 2 * L - 1)
+def _w_shape(L, N, lam, J_min, grid):
+    """Shape of the W of one map: [S][n_gamma][n_beta][n_alpha], or flat for the
+    multiresolution layout."""
     S = num_scales(L, lam, J_min)
-    sh, off = scale_grid(L, N, lam, J_min, S - 1, multires=True)
+    sh, off = scale_grid(L, N, lam, J_min, S - 1, grid=grid)
+    if grid != "multires":
+        return (S,) + sh
     return (off + sh[0] * sh[1] * sh[2],)
 
 
@@ -166,7 +171,7 @@ def split_scales(W: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int =
     lead = W.shape[:-1]
     out = []
     for j in range(num_scales(L, lam, J_min)):
-        sh, off = scale_grid(L, N, lam, J_min, j, multires=True)
+        sh, off = scale_grid(L, N, lam, J_min, j, grid="multires")
         n = sh[0] * sh[1] * sh[2]
         out.append(W[..., off:off + n].reshape(lead + sh))
     return out
@@ -181,14 +186,14 @@ def _check_w(W, shape, dtype, B, what):
 
 
 def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0, *, scaling: bool = True,
-             out: torch.Tensor | None = None, stream=None, precision: str = "fp64", multires: bool = False):
+             out: torch.Tensor | None = None, stream=None, precision: str = "fp64", grid: str = "mw"):
     """Wavelet coefficients W [S][2N-1][L][2L-1] (float64, or float32 with precision="mixed";
     flat in the multiresolution layout, see split_scales) and, if scaling, the harmonic
     scaling coefficients W^Phi_lm (complex128 [L*L])."""
-    p = params(L, N, lam, J_min, precision, multires)
+    p = params(L, N, lam, J_min, precision, grid)
     wdt = _w_dtype(precision)
     f = _as_complex(flm, L * L, "flm")
-    shape = _w_shape(L, N, lam, J_min, multires)
+    shape = _w_shape(L, N, lam, J_min, grid)
     W = out if out is not None else torch.empty(shape, dtype=wdt, device=f.device)
     _check_w(W, shape, wdt, 1, "W")
     Wp = torch.empty(L * L, dtype=torch.complex128, device=f.device) if scaling else None
@@ -200,12 +205,12 @@ def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0
 
 def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,
               out: torch.Tensor | None = None, stream=None, precision: str = "fp64",
-              multires: bool = False) -> torch.Tensor:
+              grid: str = "mw") -> torch.Tensor:
     """f_lm (complex128 [L*L]) from W (float64, or float32 with precision="mixed") and the
     scaling coefficients (or the wavelet part only)."""
-    p = params(L, N, lam, J_min, precision, multires)
+    p = params(L, N, lam, J_min, precision, grid)
     W = W.contiguous()
-    _check_w(W, _w_shape(L, N, lam, J_min, multires), _w_dtype(precision), 1, "W")
+    _check_w(W, _w_shape(L, N, lam, J_min, grid), _w_dtype(precision), 1, "W")
     wp = _as_complex(Wphi, L * L, "Wphi") if Wphi is not None else None
     f = out if out is not None else torch.empty(L * L, dtype=torch.complex128, device=W.device)
     _check(lib().s2dw_synthesis(ctypes.byref(p), ctypes.c_void_p(W.data_ptr()),
@@ -215,17 +220,17 @@ def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: f
 
 
 def analysis_batched(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0, *, scaling: bool = True,
-                     out: torch.Tensor | None = None, stream=None, precision: str = "fp64", multires: bool = False):
+                     out: torch.Tensor | None = None, stream=None, precision: str = "fp64", grid: str = "mw"):
     """A batch of maps with the same parameters: flm complex128 [B][L*L] -> W [B][S][2N-1][L][2L-1]
     (float64 or float32; [B][total] in the multiresolution layout) and, if scaling, W^Phi
     complex128 [B][L*L]."""
-    p = params(L, N, lam, J_min, precision, multires)
+    p = params(L, N, lam, J_min, precision, grid)
     wdt = _w_dtype(precision)
     if flm.dim() != 2 or flm.shape[1] != L * L:
         raise ValueError("flm: expected [B][L*L] complex128")
     B = flm.shape[0]
     f = _as_complex(flm, B * L * L, "flm")
-    shape = _w_shape(L, N, lam, J_min, multires)
+    shape = _w_shape(L, N, lam, J_min, grid)
     W = out if out is not None else torch.empty((B,) + shape, dtype=wdt, device=f.device)
     _check_w(W, shape, wdt, B, "W")
     Wp = torch.empty((B, L * L), dtype=torch.complex128, device=f.device) if scaling else None
@@ -238,12 +243,12 @@ def analysis_batched(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min:
 
 def synthesis_batched(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0,
                       J_min: int = 0, *, out: torch.Tensor | None = None, stream=None,
-                      precision: str = "fp64", multires: bool = False) -> torch.Tensor:
+                      precision: str = "fp64", grid: str = "mw") -> torch.Tensor:
     """A batch of maps: W [B][S][2N-1][L][2L-1] (+ W^Phi [B][L*L]) -> f_lm complex128 [B][L*L]."""
-    p = params(L, N, lam, J_min, precision, multires)
+    p = params(L, N, lam, J_min, precision, grid)
     B = W.shape[0]
     W = W.contiguous()
-    _check_w(W, _w_shape(L, N, lam, J_min, multires), _w_dtype(precision), B, "W")
+    _check_w(W, _w_shape(L, N, lam, J_min, grid), _w_dtype(precision), B, "W")
     wp = _as_complex(Wphi, B * L * L, "Wphi") if Wphi is not None else None
     f = out if out is not None else torch.empty((B, L * L), dtype=torch.complex128, device=W.device)
     _check(lib().s2dw_synthesis_batched(ctypes.byref(p), B, ctypes.c_void_p(W.data_ptr()),
@@ -253,17 +258,17 @@ def synthesis_batched(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int
 
 
 def autotune(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1, precision: str = "fp64",
-             stream=None, multires: bool = False):
+             stream=None, grid: str = "mw"):
     """Times the compiled Wigner tile shapes and batch chunks for these parameters and keeps
     the fastest in the library's plan; returns (m' slots per wave, maps per chunk)."""
     sl, ch = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().s2dw_autotune(ctypes.byref(params(L, N, lam, J_min, precision, multires)), count, _stream(stream),
+    _check(lib().s2dw_autotune(ctypes.byref(params(L, N, lam, J_min, precision, grid)), count, _stream(stream),
                                ctypes.byref(sl), ctypes.byref(ch)), "s2dw_autotune")
     return sl.value, ch.value
 
 
 def steer(W: torch.Tensor, gammas, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,
-          out: torch.Tensor | None = None, stream=None, multires: bool = False) -> torch.Tensor:
+          out: torch.Tensor | None = None, stream=None, grid: str = "mw") -> torch.Tensor:
     """Wavelet coefficients at arbitrary third Euler angles (steerability, Eq. 10).
 
     W: [S][2N-1][L][2L-1] or [B][S][2N-1][L][2L-1], float64 (or float32: the mixed-precision
@@ -273,7 +278,7 @@ def steer(W: torch.Tensor, gammas, L: int, N: int, lam: float = 2.0, J_min: int 
     if W.dtype not in (torch.float64, torch.float32) or not W.is_cuda:
         raise ValueError("W: expected a float64 or float32 device tensor")
     precision = "fp64" if W.dtype == torch.float64 else "mixed"
-    shape = _w_shape(L, N, lam, J_min, multires)
+    shape = _w_shape(L, N, lam, J_min, grid)
     per = 1
     for d in shape:
         per *= d
@@ -284,13 +289,13 @@ def steer(W: torch.Tensor, gammas, L: int, N: int, lam: float = 2.0, J_min: int 
     W = W.contiguous()
     g = torch.as_tensor(gammas, dtype=torch.float64).reshape(-1).to(W.device).contiguous()
     Q = g.numel()
-    G = 2 * N - 1
-    oshape = (per // G * Q,) if multires else (shape[0], Q, L, 2 * L - 1)
+    G = N if grid == "dh" else 2 * N - 1
+    oshape = (per // G * Q,) if grid == "multires" else (shape[0], Q) + shape[2:]
     oshape = ((B,) if batched else ()) + oshape
     o = out if out is not None else torch.empty(oshape, dtype=W.dtype, device=W.device)
     if o.dtype != W.dtype or o.numel() != B * (per // G) * Q or not o.is_contiguous():
         raise ValueError("out: wrong shape, dtype or layout")
-    _check(lib().s2dw_steer(ctypes.byref(params(L, N, lam, J_min, precision, multires)), B,
+    _check(lib().s2dw_steer(ctypes.byref(params(L, N, lam, J_min, precision, grid)), B,
                             ctypes.c_void_p(W.data_ptr()), Q, ctypes.c_void_p(g.data_ptr()),
                             ctypes.c_void_p(o.data_ptr()), _stream(stream)), "s2dw_steer")
     return o
@@ -330,10 +335,10 @@ def sht_inverse(flm: torch.Tensor, L: int, stream=None) -> torch.Tensor:
 
 
 def workspace_bytes(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1,
-                    precision: str = "fp64", multires: bool = False) -> int:
+                    precision: str = "fp64", grid: str = "mw") -> int:
     """Device bytes of one stream's workspace for a batch of `count` maps."""
     b = ctypes.c_uint64()
-    _check(lib().s2dw_workspace_bytes(ctypes.byref(params(L, N, lam, J_min, precision, multires)), count,
+    _check(lib().s2dw_workspace_bytes(ctypes.byref(params(L, N, lam, J_min, precision, grid)), count,
                                       ctypes.byref(b)),
            "s2dw_workspace_bytes")
     return b.value

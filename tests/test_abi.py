@@ -131,16 +131,21 @@ def test_multires_layout_queries(L, N, lam, J_min):
     bl = oracle.scale_bandlimits(L, lam, J_min)
     off = 0
     for j, Lj in enumerate(bl):
-        sh, o = s2dw.scale_grid(L, N, lam, J_min, j, multires=True)
+        sh, o = s2dw.scale_grid(L, N, lam, J_min, j, grid="multires")
         assert sh == (2 * N - 1, Lj, 2 * Lj - 1 if Lj else 0) and o == off
         off += sh[0] * sh[1] * sh[2]
         shf, of = s2dw.scale_grid(L, N, lam, J_min, j)
         assert shf == (2 * N - 1, L, 2 * L - 1) and of == j * (2 * N - 1) * L * (2 * L - 1)
     b = ctypes.c_uint64()
-    assert s2dw.lib().s2dw_wavelet_bytes(ctypes.byref(s2dw.params(L, N, lam, J_min, multires=True)),
+    assert s2dw.lib().s2dw_wavelet_bytes(ctypes.byref(s2dw.params(L, N, lam, J_min, grid="multires")),
                                          ctypes.byref(b)) == 0
     assert b.value == 8 * off
-    assert s2dw.lib().s2dw_scale_grid(ctypes.byref(s2dw.params(L, N, lam, J_min, multires=True)), len(bl),
+    assert s2dw.lib().s2dw_scale_grid(ctypes.byref(s2dw.params(L, N, lam, J_min, grid="multires")), len(bl),
                                       None, None) == -1
-    bad = s2dw.Params(L, N, lam, J_min, 2, 0, 1)  # unknown grid
+    bad = s2dw.Params(L, N, lam, J_min, 3, 0, 1)  # unknown grid
     assert s2dw.lib().s2dw_scale_grid(ctypes.byref(bad), 0, None, None) == -1
+    # the Driscoll-Healy grid of Sec. 3.1: N gamma, 2L beta, 2L-1 alpha samples per scale
+    sh, o = s2dw.scale_grid(L, N, lam, J_min, 1, grid="dh")
+    assert sh == (N, 2 * L, 2 * L - 1) and o == N * 2 * L * (2 * L - 1)
+    assert s2dw.lib().s2dw_wavelet_bytes(ctypes.byref(s2dw.params(L, N, lam, J_min, grid="dh")), ctypes.byref(b)) == 0
+    assert b.value == 8 * len(bl) * N * 2 * L * (2 * L - 1)

@@ -66,7 +66,7 @@ def test_full_size_multires_rows_and_round_trip():
     print(f"full size multires L={L} N={N} J_min={J_min}", flush=True)
     f = random_flm(L, 0)
     fd = torch.as_tensor(f).to("cuda")
-    W, Wp = s2dw.analysis(fd, L, N, lam, J_min, multires=True)
+    W, Wp = s2dw.analysis(fd, L, N, lam, J_min, grid="multires")
     scales = s2dw.split_scales(W, L, N, lam, J_min)
     psi = tables.wavelets(L, N, lam, J_min)
     for j in [0, 5]:
@@ -78,10 +78,34 @@ def test_full_size_multires_rows_and_round_trip():
                                  betas=oracle.mw_betas(Lj)[rows], psi=psi[j:j + 1], nalpha=2 * Lj - 1)[0]
         err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
         assert err < TOL, (j, err)
-    fr = s2dw.synthesis(W, Wp, L, N, lam, J_min, multires=True)
+    fr = s2dw.synthesis(W, Wp, L, N, lam, J_min, grid="multires")
     torch.cuda.synchronize()
     rt = float((fr - fd).abs().max().item() / fd.abs().max().item())
     assert rt < 1e-12, rt
     del W, Wp, fr, scales
+    s2dw.release_caches()
+    torch.cuda.empty_cache()
+
+
+def test_full_size_driscoll_healy_rows_and_round_trip():
+    # the benchmark workload on the paper's own grid (Sec. 3.1): 2L colatitudes, N base
+    # orientations; sampled beta rows against the oracle and the exact round trip
+    L, N, J_min, lam = 1024, 8, 1, 2.0
+    print(f"full size Driscoll-Healy L={L} N={N} J_min={J_min}", flush=True)
+    f = random_flm(L, 0)
+    fd = torch.as_tensor(f).to("cuda")
+    W, Wp = s2dw.analysis(fd, L, N, lam, J_min, grid="dh")
+    rows = [0, L, 2 * L - 1]
+    got = W[:, :, rows, :].cpu().numpy()
+    print("  oracle on the sampled beta rows", flush=True)
+    ref = oracle.analysis_at(f, L, N, lam, J_min, np.pi * np.arange(N) / N, betas=oracle.dh_betas(L)[rows])
+    for j in range(ref.shape[0]):
+        err = float(np.max(np.abs(got[j] - ref[j])) / np.max(np.abs(ref[j])))
+        assert err < TOL, (j, err)
+    fr = s2dw.synthesis(W, Wp, L, N, lam, J_min, grid="dh")
+    torch.cuda.synchronize()
+    rt = float((fr - fd).abs().max().item() / fd.abs().max().item())
+    assert rt < 1e-12, rt
+    del W, Wp, fr
     s2dw.release_caches()
     torch.cuda.empty_cache()

@@ -46,7 +46,7 @@ def test_band_limits_match_the_oracle():
     for L, N, J_min, lam in CASES:
         bl = oracle.scale_bandlimits(L, lam, J_min)
         for j, Lj in enumerate(bl):
-            sh, _ = s2dw.scale_grid(L, N, lam, J_min, j, multires=True)
+            sh, _ = s2dw.scale_grid(L, N, lam, J_min, j, grid="multires")
             assert sh == (2 * N - 1, Lj, 2 * Lj - 1 if Lj else 0)
 
 
@@ -55,7 +55,7 @@ def test_multires_analysis_matches_oracle(L, N, J_min, lam):
     print(f"multires analysis L={L} N={N} J_min={J_min} lambda={lam}", flush=True)
     f = random_flm(L, 600 + L)
     ref = oracle.analysis_multires(f, L, N, lam, J_min)
-    W, Wp = s2dw.analysis(dev(f), L, N, lam, J_min, multires=True)
+    W, Wp = s2dw.analysis(dev(f), L, N, lam, J_min, grid="multires")
     got = [w.cpu().numpy() for w in s2dw.split_scales(W, L, N, lam, J_min)]
     for j in range(len(ref)):
         assert got[j].shape == ref[j].shape
@@ -71,15 +71,15 @@ def test_multires_synthesis_matches_oracle_on_arbitrary_samples(L, N, J_min, lam
     Ws = [random_wavelet_samples(1, 2 * N - 1, Lj, max(2 * Lj - 1, 0), 700 + j)[0] for j, Lj in enumerate(bl)]
     Wphi = oracle.scaling(random_flm(L, 701), L, lam, J_min)
     ref = oracle.synthesis_multires(Ws, Wphi, L, N, lam, J_min)
-    got = s2dw.synthesis(dev(flat(Ws)), dev(Wphi), L, N, lam, J_min, multires=True).cpu().numpy()
+    got = s2dw.synthesis(dev(flat(Ws)), dev(Wphi), L, N, lam, J_min, grid="multires").cpu().numpy()
     assert rel(got, ref) < TOL, rel(got, ref)
 
 
 @pytest.mark.parametrize("L,N,J_min,lam", CASES)
 def test_multires_round_trip(L, N, J_min, lam):
     f = random_flm(L, 800 + L)
-    W, Wp = s2dw.analysis(dev(f), L, N, lam, J_min, multires=True)
-    fr = s2dw.synthesis(W, Wp, L, N, lam, J_min, multires=True).cpu().numpy()
+    W, Wp = s2dw.analysis(dev(f), L, N, lam, J_min, grid="multires")
+    fr = s2dw.synthesis(W, Wp, L, N, lam, J_min, grid="multires").cpu().numpy()
     assert rel(fr, f) < 1e-12
 
 
@@ -88,7 +88,7 @@ def test_multires_medium_configuration_and_size():
     print("multires medium configuration", flush=True)
     f = random_flm(L, 0)
     ref = oracle.analysis_multires(f, L, N, 2.0, J_min)
-    W, Wp = s2dw.analysis(dev(f), L, N, 2.0, J_min, multires=True)
+    W, Wp = s2dw.analysis(dev(f), L, N, 2.0, J_min, grid="multires")
     assert W.numel() == sum(r.size for r in ref)
     full = s2dw.num_scales(L, 2.0, J_min) * (2 * N - 1) * L * (2 * L - 1)
     assert W.numel() < 0.4 * full
@@ -96,19 +96,19 @@ def test_multires_medium_configuration_and_size():
     for j in range(len(ref)):
         assert rel(got[j], ref[j]) < TOL, j
     refs = oracle.synthesis_multires(ref, oracle.scaling(f, L, 2.0, J_min), L, N, 2.0, J_min)
-    assert rel(s2dw.synthesis(W, Wp, L, N, 2.0, J_min, multires=True).cpu().numpy(), refs) < TOL
+    assert rel(s2dw.synthesis(W, Wp, L, N, 2.0, J_min, grid="multires").cpu().numpy(), refs) < TOL
 
 
 def test_multires_mixed_precision():
     L, N, J_min = 64, 4, 1
     f = random_flm(L, 9)
     ref = oracle.analysis_multires(f, L, N, 2.0, J_min)
-    W, Wp = s2dw.analysis(dev(f), L, N, 2.0, J_min, multires=True, precision="mixed")
+    W, Wp = s2dw.analysis(dev(f), L, N, 2.0, J_min, grid="multires", precision="mixed")
     assert W.dtype == torch.float32
     got = [w.cpu().numpy().astype(np.float64) for w in s2dw.split_scales(W, L, N, 2.0, J_min)]
     for j in range(len(ref)):
         assert rel(got[j], ref[j]) < 1e-5, j
-    fr = s2dw.synthesis(W, Wp, L, N, 2.0, J_min, multires=True, precision="mixed").cpu().numpy()
+    fr = s2dw.synthesis(W, Wp, L, N, 2.0, J_min, grid="multires", precision="mixed").cpu().numpy()
     assert rel(fr, f) < 1e-5
 
 
@@ -116,12 +116,12 @@ def test_multires_mixed_precision():
 def test_multires_batched_equals_single(precision):
     L, N, J_min, B = 40, 4, 1, 3
     F = torch.stack([dev(random_flm(L, 50 + i)) for i in range(B)])
-    W, Wp = s2dw.analysis_batched(F, L, N, 2.0, J_min, precision=precision, multires=True)
-    fr = s2dw.synthesis_batched(W, Wp, L, N, 2.0, J_min, precision=precision, multires=True)
+    W, Wp = s2dw.analysis_batched(F, L, N, 2.0, J_min, precision=precision, grid="multires")
+    fr = s2dw.synthesis_batched(W, Wp, L, N, 2.0, J_min, precision=precision, grid="multires")
     for i in range(B):
-        Wi, Wpi = s2dw.analysis(F[i], L, N, 2.0, J_min, precision=precision, multires=True)
+        Wi, Wpi = s2dw.analysis(F[i], L, N, 2.0, J_min, precision=precision, grid="multires")
         assert torch.equal(W[i], Wi), i
-        fi = s2dw.synthesis(Wi, Wpi, L, N, 2.0, J_min, precision=precision, multires=True)
+        fi = s2dw.synthesis(Wi, Wpi, L, N, 2.0, J_min, precision=precision, grid="multires")
         assert torch.equal(fr[i], fi), i
 
 
@@ -129,8 +129,8 @@ def test_multires_steer_matches_oracle():
     L, N, J_min = 48, 5, 1
     f = random_flm(L, 11)
     g = np.array([0.3, -1.9, 7.5, 0.0])
-    W, _ = s2dw.analysis(dev(f), L, N, 2.0, J_min, scaling=False, multires=True)
-    Ws = s2dw.steer(W, g, L, N, 2.0, J_min, multires=True).cpu().numpy()
+    W, _ = s2dw.analysis(dev(f), L, N, 2.0, J_min, scaling=False, grid="multires")
+    Ws = s2dw.steer(W, g, L, N, 2.0, J_min, grid="multires").cpu().numpy()
     psi = tables.wavelets(L, N, 2.0, J_min)
     off = 0
     for j, Lj in enumerate(oracle.scale_bandlimits(L, 2.0, J_min)):
