@@ -13,6 +13,9 @@ Layout conventions (the same ones the library's C ABI documents):
     beta_b = pi(2b+1)/(2L-1), gamma_g = 2 pi g/(2N-1).  Scale j = 0 is the
     highest-frequency wavelet.
   * Scaling coefficients: complex harmonic W^Phi_lm, [L*L] (Eq. 31).
+  * Complex (non-real) signals: every sum runs over all m and n as written, so
+    ``analysis_complex`` gives their complex coefficients and the synthesis
+    functions accept complex samples.
 
 Synthesis of samples that are not band-limited: the beta integral is taken of the
 unique trigonometric polynomial of degree < L through the samples extended to the

@@ -8,6 +8,7 @@ Signals are band-limited harmonic coefficients f_lm (index l*l + l + m) of a
 real signal on the sphere: for l < L and 0 <= m <= l a complex Gaussian with
 variance C_l = 1/(l+1)^2 (real and imaginary parts each of variance C_l/2),
 the imaginary part of f_l0 set to zero, and f_{l,-m} = (-1)^m conj(f_lm).
+Complex (non-real) signals draw every m in -l..l independently with the same variance.
 """
 from __future__ import annotations
 
@@ -44,6 +45,23 @@ def random_flm_uniform(L: int, seed: int) -> np.ndarray:
         m = np.arange(1, el + 1)
         f[base - m] = ((-1.0) ** m) * np.conj(z[1:])
     return f
+
+
+def random_flm_complex(L: int, seed: int) -> np.ndarray:
+    """Complex128 [L*L] coefficients of a complex band-limited signal (no symmetry)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = np.zeros(L * L, dtype=np.complex128)
+    for el in range(L):
+        sd = np.sqrt(1.0 / (el + 1) ** 2 / 2.0)
+        n = 2 * el + 1
+        f[el * el: el * el + n] = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * sd
+    return f
+
+
+def random_wavelet_samples_complex(S: int, ng: int, nb: int, na: int, seed: int) -> np.ndarray:
+    """Arbitrary complex samples on the SO(3) grid, [S][ng][nb][na]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((S, ng, nb, na)) + 1j * rng.standard_normal((S, ng, nb, na))
 
 
 def random_real_map(nb: int, na: int, seed: int) -> np.ndarray:
