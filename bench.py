@@ -301,6 +301,29 @@ def main():
     del Wd
     print(f"# Driscoll-Healy round trip {ms_dh:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # a complex (non-real) signal on the equiangular grid: complex W, two real maps' work
+    from paper_1308_5706_amd.inputs import random_flm_complex
+    fc = torch.as_tensor(random_flm_complex(L, 0)).to(dev)
+    Wc = torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=torch.complex128 if prec == "fp64" else torch.complex64,
+                     device=dev)
+
+    def step_cx():
+        _, Wp = s2dw.analysis(fc, L, N, lam, J_min, out=Wc, precision=prec, reality=False)
+        s2dw.synthesis(Wc, Wp, L, N, lam, J_min, out=frm, precision=prec, reality=False)
+
+    for _ in range(max(1, args.warmup)):
+        step_cx()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_cx()
+    torch.cuda.synchronize()
+    ms_cx = (time.perf_counter() - t0) * 1e3 / args.steps
+    complex_signal = {"ms_per_step": ms_cx, "complex_coeffs_per_s": Wc.numel() / (ms_cx * 1e-3),
+                      "round_trip_rel_err": float((frm - fc).abs().max().item() / fc.abs().max().item())}
+    del Wc
+    print(f"# complex-signal round trip {ms_cx:.3f} ms/step", file=sys.stderr, flush=True)
+
     out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8; p50/p99 mixed-L",
            "value": value, "unit": "SO(3) coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -316,7 +339,8 @@ def main():
            "wigner_terms_per_direction": T,
            "steer": steer,
            "multires": multires,
-           "driscoll_healy": dh_grid}
+           "driscoll_healy": dh_grid,
+           "complex_signal": complex_signal}
     if not args.no_cpu_baseline:
         print("# cpu baseline sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(L, N, lam, J_min)

@@ -40,9 +40,13 @@
  *    gamma with weight 2 pi z_n, z_n = 1/N (Eq. 39); both directions are exact.
  *  - Sphere maps: real [L][2L-1] = [theta_b][phi_a] on the same beta/alpha
  *    samples.
- *  - Only real signals are supported (reality = 1): f_{l,-m} =
- *    (-1)^m conj(f_lm), which makes W real.  The library reads f_lm for
- *    m >= 0 only and writes all m on output.
+ *  - Real signals (reality = 1): f_{l,-m} = (-1)^m conj(f_lm), which makes W
+ *    real.  The library reads f_lm for m >= 0 only and writes all m on output.
+ *  - Complex signals (reality = 0): all f_lm are read and written; W is
+ *    complex, stored as (re, im) pairs (doubles, or floats for S2DW_MIXED) in
+ *    the same layout.  A complex signal runs through the real path as its real
+ *    and imaginary parts on the sphere (Eq. 1 is linear in f), two real maps in
+ *    the same kernel launches, so it costs two real transforms.
  *
  * Memory and execution
  *  - Every data pointer is a DEVICE pointer owned by the caller (usually a
@@ -76,7 +80,7 @@ enum {
     S2DW_E_ARG = -1,         /* invalid argument (value, null or misaligned pointer) */
     S2DW_E_NOMEM = -2,       /* device or host allocation failed */
     S2DW_E_DEVICE = -3,      /* a HIP call failed */
-    S2DW_E_UNSUPPORTED = -4, /* valid but not implemented (e.g. complex signals) */
+    S2DW_E_UNSUPPORTED = -4, /* valid but not implemented (e.g. the sphere map of complex scaling coefficients) */
     S2DW_E_INTERNAL = -5
 };
 
@@ -101,7 +105,7 @@ typedef struct s2dw_params {
                           Delta recursion, the analysis l-sum (Eq. 27) and the final
                           harmonic synthesis (Eq. 32) stay FP64.  Error against the FP64
                           result: about 1e-6 relative (tests bound it by 1e-5). */
-    int32_t reality;   /* must be 1 (real signal) */
+    int32_t reality;   /* 1: real signal (real W), 0: complex signal (complex W) */
 } s2dw_params;
 
 /* Number of wavelet scales S = J_L(lambda) - J_min + 1 (Sec. 2.2). */
@@ -195,7 +199,8 @@ int s2dw_cache_bytes(uint64_t *bytes);
  * Scaling coefficients (Eq. 3, 31): W^Phi_lm = sqrt(4 pi/(2l+1)) f_lm Phi_l0.
  *   Wphi_lm  out: L*L complex, or NULL.
  *   Wphi_map out: real [L][2L-1] sphere map of the scaling coefficients
- *                 (the inverse spherical-harmonic transform of W^Phi), or NULL.
+ *                 (the inverse spherical-harmonic transform of W^Phi), or NULL
+ *                 (real signals only: S2DW_E_UNSUPPORTED for reality = 0).
  */
 int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, double *Wphi_map, void *stream);
 

@@ -692,7 +692,7 @@ int check_params(const s2dw_params *p) {
     if (p->J_min < 0 || p->J_min > JL || JL - p->J_min + 1 > kMaxScales) return S2DW_E_ARG;
     if (p->grid != S2DW_GRID_MW && p->grid != S2DW_GRID_MW_MULTIRES && p->grid != S2DW_GRID_DH) return S2DW_E_ARG;
     if (p->precision != S2DW_FP64 && p->precision != S2DW_MIXED) return S2DW_E_ARG;
-    if (p->reality != 1) return p->reality == 0 ? S2DW_E_UNSUPPORTED : S2DW_E_ARG;
+    if (p->reality != 0 && p->reality != 1) return S2DW_E_ARG;
     return S2DW_OK;
 }
 
@@ -728,11 +728,15 @@ int grid_limits(const s2dw_params *p, std::vector<int> &Lg) {
 
 // Wigner-stage analysis + beta/alpha/gamma sums for a batch of `maps` maps: f_lm of map i at
 // flm + i L^2, its W at W + i S (2N-1) L (2L-1) (elements of the W type).
-int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32, hipStream_t st) {
+// With cx (complex signals), flm holds maps / 2 complex signals, each run as the two real maps
+// 2z, 2z + 1 (real and imaginary part on the sphere), and W holds maps / 2 complex arrays
+// ((re, im) pairs, same per-map layout).
+int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32, hipStream_t st, bool cx = false) {
     const int L = P.L;
     {
         Stage sg("pad", st);
-        S2DW_CHECK_HIP(launch_pad_flm(flm, w.fpad, L, P.Lp, P.s_fpad, maps, st));
+        if (cx) S2DW_CHECK_HIP(launch_pad_flm_complex(flm, w.fpad, L, P.Lp, P.s_fpad, maps / 2, st));
+        else S2DW_CHECK_HIP(launch_pad_flm(flm, w.fpad, L, P.Lp, P.s_fpad, maps, st));
     }
     WigFwdArgs a{};
     a.fpad = w.fpad;
@@ -759,16 +763,16 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.R, P.nfwd_plain + P.nfwd_x, maps, st));
     }
     const int N = P.ht.N;
-    const size_t per_map = P.woff[P.S];
+    const size_t per_map = P.woff[P.S];  // elements of one W (complex ones with cx)
+    const size_t ew = (f32 ? 4 : 8) * (cx ? 2 : 1);
+    const int wmaps = cx ? maps / 2 : maps;
     for (int j = 0; j < P.S; ++j) {
         const int Lj = P.sc.Lj[j], Lg = P.Lg[j];
         const size_t per_scale = P.woff[j + 1] - P.woff[j];
-        void *Wj = f32 ? (void *)((float *)W + P.woff[j]) : (void *)((double *)W + P.woff[j]);
+        void *Wj = (char *)W + P.woff[j] * ew;
         if (Lj == 0) {
-            for (int i = 0; i < maps; ++i) {
-                void *Wij = f32 ? (void *)((float *)Wj + per_map * i) : (void *)((double *)Wj + per_map * i);
-                S2DW_CHECK_HIP(launch_zero_words(Wij, per_scale * (f32 ? 1 : 2), st));
-            }
+            for (int i = 0; i < wmaps; ++i)
+                S2DW_CHECK_HIP(launch_zero_words((char *)Wj + per_map * ew * i, per_scale * ew / 4, st));
             continue;
         }
         const Plan::GridTab &gtab = P.gt[Lg];
@@ -818,7 +822,8 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         g.f32 = f32;
         {
             Stage sg("gamma_fwd", st);
-            S2DW_CHECK_HIP(launch_gamma_fwd(g, maps, st));
+            if (cx) S2DW_CHECK_HIP(launch_gamma_fwd_cx(g, wmaps, st));
+            else S2DW_CHECK_HIP(launch_gamma_fwd(g, maps, st));
         }
     }
     return S2DW_OK;
@@ -826,16 +831,18 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
 
 // gamma/alpha/beta quadratures + Wigner-stage contraction for a batch: W -> f_lm (same
 // per-map layout as run_inverse; wphi of map i at wphi + i L^2, or null).
+// With cx, W holds maps / 2 complex arrays; real map 2z (2z + 1) is the real (imaginary) part
+// of complex array z, and f_lm of real map k goes to flm + k L^2.
 int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, double2 *flm, int f32,
-                hipStream_t st) {
+                hipStream_t st, bool cx = false) {
     const int L = P.L, N = P.ht.N;
     const size_t per_map = P.woff[P.S];
+    const size_t ew = (f32 ? 4 : 8) * (cx ? 2 : 1);
     for (int j = 0; j < P.S; ++j) {
         const int Lj = P.sc.Lj[j], Lg = P.Lg[j], M = 2 * Lg - 1;
         if (Lj == 0) continue;
         const Plan::GridTab &gtab = P.gt[Lg];
-        const void *Wj = f32 ? (const void *)((const float *)W + P.woff[j])
-                             : (const void *)((const double *)W + P.woff[j]);
+        const void *Wj = (const char *)W + P.woff[j] * ew;
         GammaArgs g{};
         g.win = Wj;
         g.out = w.Y;
@@ -850,7 +857,8 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         g.f32 = f32;
         {
             Stage sg("gamma_adj", st);
-            S2DW_CHECK_HIP(launch_gamma_adj(g, maps, st));
+            if (cx) S2DW_CHECK_HIP(launch_gamma_adj_cx(g, maps / 2, st));
+            else S2DW_CHECK_HIP(launch_gamma_adj(g, maps, st));
         }
         StageArgs c{};
         c.f32 = f32;
@@ -975,7 +983,7 @@ int s2dw_scale_grid(const s2dw_params *p, int32_t j, int32_t shape[3], uint64_t 
 
 int s2dw_wavelet_bytes(const s2dw_params *p, uint64_t *bytes) {
     if (!bytes) return S2DW_E_ARG;
-    const uint64_t el = p && p->precision == S2DW_MIXED ? 4 : 8;
+    const uint64_t el = (p && p->precision == S2DW_MIXED ? 4 : 8) * (p && p->reality == 0 ? 2 : 1);
     if (p && p->grid == S2DW_GRID_MW_MULTIRES) {
         int rc = check_params(p);
         if (rc != S2DW_OK) return rc;
@@ -1008,15 +1016,17 @@ int s2dw_analysis_batched(const s2dw_params *p, int32_t count, const double *flm
     rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0, p->grid);
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    const int chunk = std::max(1, std::min<int>(count, P->chunk));
+    const bool cx = p->reality == 0;
+    const int per = cx ? 2 : 1;  // real maps per signal
+    const int chunk = std::max(1, std::min<int>(count, P->chunk / per));
     Work *w = nullptr;
-    rc = get_work(*P, st, chunk, w);
+    rc = get_work(*P, st, chunk * per, w);
     if (rc != S2DW_OK) return rc;
     const size_t L2 = (size_t)p->L * p->L;
-    const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8);
+    const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8) * per;
     for (int i0 = 0; i0 < count; i0 += chunk) {
         const int n = std::min(chunk, count - i0);
-        rc = run_inverse(*P, *w, n, (const double2 *)flm + L2 * i0, (char *)W + wmap * i0, f32, st);
+        rc = run_inverse(*P, *w, n * per, (const double2 *)flm + L2 * i0, (char *)W + wmap * i0, f32, st, cx);
         if (rc != S2DW_OK) return rc;
         if (Wphi_lm) {
             Stage sg("scaling", st);
@@ -1038,17 +1048,28 @@ int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, c
     rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, f32 != 0, p->grid);
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    const int chunk = std::max(1, std::min<int>(count, P->chunk));
+    const bool cx = p->reality == 0;
+    const int per = cx ? 2 : 1;
+    const int chunk = std::max(1, std::min<int>(count, P->chunk / per));
     Work *w = nullptr;
-    rc = get_work(*P, st, chunk, w);
+    rc = get_work(*P, st, chunk * per, w);
     if (rc != S2DW_OK) return rc;
     const size_t L2 = (size_t)p->L * p->L;
-    const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8);
+    const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8) * per;
     for (int i0 = 0; i0 < count; i0 += chunk) {
         const int n = std::min(chunk, count - i0);
-        rc = run_forward(*P, *w, n, (const char *)W + wmap * i0, Wphi_lm ? (const double2 *)Wphi_lm + L2 * i0 : nullptr,
-                         (double2 *)flm_out + L2 * i0, f32, st);
+        const double2 *wphi = Wphi_lm ? (const double2 *)Wphi_lm + L2 * i0 : nullptr;
+        if (!cx) {
+            rc = run_forward(*P, *w, n, (const char *)W + wmap * i0, wphi, (double2 *)flm_out + L2 * i0, f32, st);
+            if (rc != S2DW_OK) return rc;
+            continue;
+        }
+        // the real and imaginary parts' syntheses land in the (free) padded-input workspace,
+        // map k at k L^2, and are combined with the scaling part
+        rc = run_forward(*P, *w, 2 * n, (const char *)W + wmap * i0, nullptr, w->fpad, f32, st, true);
         if (rc != S2DW_OK) return rc;
+        Stage sg("syn_final", st);
+        S2DW_CHECK_HIP(launch_merge_complex(w->fpad, L2, wphi, P->phi, (double2 *)flm_out + L2 * i0, p->L, n, st));
     }
     return S2DW_OK;
 }
@@ -1066,7 +1087,7 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     int cmax = std::min<int>(count, std::max(default_chunk(*P), 1));
     // probe buffers (zero coefficients: the kernels have no data-dependent control flow)
     const size_t L2 = (size_t)p->L * p->L;
-    const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8);
+    const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8) * (p->reality == 0 ? 2 : 1);
     void *fin = nullptr, *wbuf = nullptr, *fout = nullptr;
     if (hipMalloc(&fin, 16 * L2 * cmax) != hipSuccess) return S2DW_E_NOMEM;
     if (hipMalloc(&wbuf, wmap * cmax) != hipSuccess || hipMalloc(&fout, 16 * L2 * cmax) != hipSuccess) {
@@ -1151,7 +1172,8 @@ int s2dw_workspace_bytes(const s2dw_params *p, int32_t count, uint64_t *bytes) {
     rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, p->precision == S2DW_MIXED, p->grid);
     if (rc != S2DW_OK) return rc;
     const uint64_t per_map = 16ull * (P->s_fpad + P->s_U + P->s_Ub + P->s_Y + P->s_F);
-    *bytes = per_map * (uint64_t)std::min<int>(count, std::max(P->chunk, 1));
+    const int per = p->reality == 0 ? 2 : 1;  // real maps per signal
+    *bytes = per_map * per * (uint64_t)std::min<int>(count, std::max(P->chunk / per, 1));
     return S2DW_OK;
 }
 
@@ -1180,6 +1202,7 @@ int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, doubl
     int rc = check_params(p);
     if (rc != S2DW_OK) return rc;
     if (!flm || !aligned(flm) || (Wphi_lm && !aligned(Wphi_lm)) || (Wphi_map && !aligned(Wphi_map))) return S2DW_E_ARG;
+    if (Wphi_map && p->reality == 0) return S2DW_E_UNSUPPORTED;  // the sphere maps are real
     if (!Wphi_lm && !Wphi_map) return S2DW_OK;
     Plan *P = nullptr;
     rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, false, p->grid);
@@ -1220,10 +1243,12 @@ int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gam
     const double step = dh ? M_PI / p->N : 2.0 * M_PI / G;
     const int f32 = p->precision == S2DW_MIXED;
     const size_t es = f32 ? 4 : 8;
+    // complex coefficients (complex signals): (re, im) pairs steer as one plane of twice the size
+    const size_t cf = p->reality == 0 ? 2 : 1;
     // element offsets of each scale in one map of W and of out
     std::vector<size_t> oin(S + 1, 0), oout(S + 1, 0);
     for (int j = 0; j < S; ++j) {
-        const size_t pl = (size_t)rf * Lg[j] * (Lg[j] > 0 ? 2 * Lg[j] - 1 : 0);
+        const size_t pl = cf * rf * Lg[j] * (Lg[j] > 0 ? 2 * Lg[j] - 1 : 0);
         oin[j + 1] = oin[j] + G * pl;
         oout[j + 1] = oout[j] + (size_t)n_gamma * pl;
     }
@@ -1235,13 +1260,13 @@ int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gam
         char *Oi = (char *)out + i * oout[S] * es;
         if (p->grid != S2DW_GRID_MW_MULTIRES) {  // one plane size: all scales in one launch
             S2DW_CHECK_HIP(launch_steer(Wi, gamma, Oi, f32, p->N, G, step, n_gamma, S,
-                                        (size_t)rf * p->L * (2 * p->L - 1), oin[S], oout[S], maps, st));
+                                        cf * rf * p->L * (2 * p->L - 1), oin[S], oout[S], maps, st));
             continue;
         }
         for (int j = 0; j < S; ++j) {
             if (Lg[j] == 0) continue;
             S2DW_CHECK_HIP(launch_steer(Wi + oin[j] * es, gamma, Oi + oout[j] * es, f32, p->N, G, step, n_gamma, 1,
-                                        (size_t)Lg[j] * (2 * Lg[j] - 1), oin[S], oout[S], maps, st));
+                                        cf * Lg[j] * (2 * Lg[j] - 1), oin[S], oout[S], maps, st));
         }
     }
     return S2DW_OK;

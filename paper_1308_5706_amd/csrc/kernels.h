@@ -85,17 +85,28 @@ struct GammaArgs {
     const void *in;        // Y (analysis): double2, or float2 if f32
     void *out;             // X (synthesis)
     const void *tg;        // [2N-1][Nh]: (1 or 2) e^{i n gamma_g} (analysis), e^{-i n gamma_g} (synthesis)
-    size_t s_w, s_y;       // per-map strides of W (real elements) and of Y / X (complex); map = blockIdx.y
+    size_t s_w, s_y;       // per-map strides of W (real elements; complex ones for the _cx kernels) and of
+                           // Y / X (complex); map = blockIdx.y
     int L, T, G, Nh, f32;
 };
 hipError_t launch_gamma_fwd(const GammaArgs &a, int maps, hipStream_t st);
 hipError_t launch_gamma_adj(const GammaArgs &a, int maps, hipStream_t st);
+// Complex signals: complex map z of W (s_w complex elements per map, (re, im) pairs) from /
+// to the real maps 2z and 2z + 1 of Y / X; cmaps complex maps.
+hipError_t launch_gamma_fwd_cx(const GammaArgs &a, int cmaps, hipStream_t st);
+hipError_t launch_gamma_adj_cx(const GammaArgs &a, int cmaps, hipStream_t st);
 
 // --------------------------------------------------------------------------------- misc
 
 // maps: number of maps of a batch (grid z); f_lm, W^Phi_lm of map i at i L^2, workspaces at i s_*.
 hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad, int maps, hipStream_t st);
 hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, int maps, hipStream_t st);
+// Complex signals as two real ones: cmaps complex f_lm -> real maps 2z, 2z + 1 of fpad, and
+// back: f = a + i b (+ the scaling part) from the syntheses of those maps (each L^2 at k s_fab).
+hipError_t launch_pad_flm_complex(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad, int cmaps,
+                                  hipStream_t st);
+hipError_t launch_merge_complex(const double2 *fab, size_t s_fab, const double2 *wphi, const double *phi,
+                                double2 *flm, int L, int cmaps, hipStream_t st);
 hipError_t launch_syn_final(const void *Fpart, size_t s_F, int f32, int nblk, int group, int Lmax, const double *fac,
                             const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, int maps,
                             hipStream_t st);

@@ -21,6 +21,63 @@ hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, size
     return hipGetLastError();
 }
 
+// Complex (non-real) signals run through the real path as two real signals: complex map z of
+// a batch becomes real maps 2z (the real part of f on the sphere) and 2z + 1 (the imaginary
+// part), since Eq. 1 is linear in f.  Their coefficients, for 0 <= m <= l, are
+//   a_lm = (f_lm + (-1)^m conj f_{l,-m}) / 2,   b_lm = (f_lm - (-1)^m conj f_{l,-m}) / (2i).
+__global__ void pad_flm_complex_kernel(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (m >= Lp) return;
+    flm += (size_t)blockIdx.z * L * L;
+    double2 *pa = fpad + (size_t)(2 * blockIdx.z) * s_fpad + (size_t)l * Lp + m;
+    double2 *pb = pa + s_fpad;
+    if (m > l) {
+        *pa = make_double2(0.0, 0.0);
+        *pb = make_double2(0.0, 0.0);
+        return;
+    }
+    const double2 f = flm[(size_t)l * l + l + m], g = flm[(size_t)l * l + l - m];
+    const double sg = (m & 1) ? -1.0 : 1.0;
+    const double cr = sg * g.x, ci = -sg * g.y;  // (-1)^m conj f_{l,-m}
+    *pa = make_double2(0.5 * (f.x + cr), 0.5 * (f.y + ci));
+    *pb = make_double2(0.5 * (f.y - ci), -0.5 * (f.x - cr));
+}
+
+hipError_t launch_pad_flm_complex(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad, int cmaps,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(pad_flm_complex_kernel, dim3((Lp + 255) / 256, L, cmaps), dim3(256), 0, st, flm, fpad, L, Lp,
+                       s_fpad);
+    return hipGetLastError();
+}
+
+// Synthesis of complex signals: f_lm = a_lm + i b_lm + sqrt((2l+1)/(4 pi)) W^Phi_lm Phi_l0
+// (Eq. 41) for all m, from the real-signal syntheses a (map 2z) and b (map 2z + 1) at
+// fab + k s_fab (k = 2z, 2z + 1), each L^2 complex.
+__global__ void merge_complex_kernel(const double2 *fab, size_t s_fab, const double2 *wphi, const double *phi,
+                                     double2 *flm, int L) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (i > 2 * l) return;
+    const size_t k = (size_t)l * l + i;
+    const double2 a = fab[(size_t)(2 * blockIdx.z) * s_fab + k], b = fab[(size_t)(2 * blockIdx.z + 1) * s_fab + k];
+    double re = a.x - b.y, im = a.y + b.x;
+    if (wphi) {
+        const double c = sqrt((2.0 * l + 1.0) / (4.0 * 3.14159265358979323846)) * phi[l];
+        const double2 w = wphi[(size_t)blockIdx.z * L * L + k];
+        re += c * w.x;
+        im += c * w.y;
+    }
+    flm[(size_t)blockIdx.z * L * L + k] = make_double2(re, im);
+}
+
+hipError_t launch_merge_complex(const double2 *fab, size_t s_fab, const double2 *wphi, const double *phi,
+                                double2 *flm, int L, int cmaps, hipStream_t st) {
+    hipLaunchKernelGGL(merge_complex_kernel, dim3((2 * L - 1 + 255) / 256, L, cmaps), dim3(256), 0, st, fab, s_fab,
+                       wphi, phi, flm, L);
+    return hipGetLastError();
+}
+
 // W^Phi_lm = sqrt(4 pi/(2l+1)) f_lm Phi_l0 (Eq. 31); Phi is real.
 __global__ void scaling_kernel(const double2 *flm, const double *phi, double2 *wphi, int L) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;

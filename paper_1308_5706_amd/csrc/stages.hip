@@ -293,6 +293,73 @@ __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
         }
 }
 
+// Complex signals: complex map z = real maps 2z (real part of f) and 2z + 1 (imaginary part);
+// W = W_2z + i W_2z+1 (Eq. 1 is linear in f) is written as (re, im) pairs, one point per
+// thread, and read back the same way in the synthesis.
+template <class C>
+__global__ void __launch_bounds__(256) gamma_fwd_cx_kernel(const GammaArgs a) {
+    using R = real_t<C>;
+    const size_t plane = (size_t)a.L * a.T;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= plane) return;
+    const C *__restrict__ Ya = (const C *)a.in + (size_t)(2 * blockIdx.y) * a.s_y + e;
+    const C *__restrict__ Yb = Ya + a.s_y;
+    const C *__restrict__ tg = (const C *)a.tg;
+    C ya[kMaxK], yb[kMaxK];
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+        if (k < a.Nh) {
+            ya[k] = nt_load(Ya + k * plane);
+            yb[k] = nt_load(Yb + k * plane);
+        }
+    C *__restrict__ W = (C *)a.wout + blockIdx.y * a.s_w + e;
+    for (int g = 0; g < a.G; ++g) {
+        R ra = 0, rb = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k) {
+            if (k < a.Nh) {
+                const C w = tg[g * a.Nh + k];
+                ra = fma(ya[k].x, w.x, fma(-ya[k].y, w.y, ra));
+                rb = fma(yb[k].x, w.x, fma(-yb[k].y, w.y, rb));
+            }
+        }
+        nt_store(mk<C>(ra, rb), W + g * plane);
+    }
+}
+
+template <class C>
+__global__ void __launch_bounds__(256) gamma_adj_cx_kernel(const GammaArgs a) {
+    const size_t plane = (size_t)a.L * a.T;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= plane) return;
+    const C *__restrict__ W = (const C *)a.win + blockIdx.y * a.s_w + e;
+    const C *__restrict__ tg = (const C *)a.tg;
+    C xa[kMaxK], xb[kMaxK];
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) xa[k] = xb[k] = zero2<C>();
+    for (int g = 0; g < a.G; ++g) {
+        const C w = nt_load(W + g * plane);
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k) {
+            if (k < a.Nh) {
+                const C t = tg[g * a.Nh + k];
+                xa[k].x = fma(w.x, t.x, xa[k].x);
+                xa[k].y = fma(w.x, t.y, xa[k].y);
+                xb[k].x = fma(w.y, t.x, xb[k].x);
+                xb[k].y = fma(w.y, t.y, xb[k].y);
+            }
+        }
+    }
+    C *__restrict__ Xa = (C *)a.out + (size_t)(2 * blockIdx.y) * a.s_y + e;
+    C *__restrict__ Xb = Xa + a.s_y;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+        if (k < a.Nh) {
+            nt_store(xa[k], Xa + k * plane);
+            nt_store(xb[k], Xb + k * plane);
+        }
+}
+
 // ------------------------------------------ synthesis: beta integral and m' folding (Eq. 35, 40)
 // Step (3) of both beta quadratures below, once V(m') of the column pair is known: the fold
 // over +-m' and the even/odd-l combinations P, Q of the two n columns (see the synthesis
@@ -519,5 +586,18 @@ hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t s
 hipError_t launch_gamma_fwd(const GammaArgs &a, int maps, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_fwd_kernel)
 
 hipError_t launch_gamma_adj(const GammaArgs &a, int maps, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_adj_kernel)
+
+#define S2DW_GAMMA_CX_LAUNCH(KER)                                                                 \
+    {                                                                                             \
+        const size_t plane = (size_t)a.L * a.T;                                                   \
+        const dim3 grid((unsigned)((plane + 255) / 256), cmaps);                                  \
+        if (a.f32) hipLaunchKernelGGL((KER<float2>), grid, dim3(256), 0, st, a);                  \
+        else hipLaunchKernelGGL((KER<double2>), grid, dim3(256), 0, st, a);                       \
+        return hipGetLastError();                                                                 \
+    }
+
+hipError_t launch_gamma_fwd_cx(const GammaArgs &a, int cmaps, hipStream_t st) S2DW_GAMMA_CX_LAUNCH(gamma_fwd_cx_kernel)
+
+hipError_t launch_gamma_adj_cx(const GammaArgs &a, int cmaps, hipStream_t st) S2DW_GAMMA_CX_LAUNCH(gamma_adj_cx_kernel)
 
 }  // namespace s2dw

@@ -83,8 +83,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_scale_grid", "s2dw_analysis", "s2dw_synthesis",
-            "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_workspace_bytes",
+EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_scale_grid", "s2dw_analysis",
+            "s2dw_synthesis", "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_workspace_bytes",
             "s2dw_cache_bytes",
             "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
             "s2dw_profile_read",
@@ -92,12 +92,14 @@ EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_sc
 
 
 def params(L: int, N: int, lam: float = 2.0, J_min: int = 0, precision: str = "fp64",
-           grid: str = "mw") -> Params:
+           grid: str = "mw", reality: bool = True) -> Params:
     """grid: "mw" (equiangular, every scale at band-limit L), "multires" (each scale on the
-    equiangular grid of its own band-limit) or "dh" (the Driscoll-Healy grid of Sec. 3.1)."""
+    equiangular grid of its own band-limit) or "dh" (the Driscoll-Healy grid of Sec. 3.1);
+    reality: real signal (real W) or complex signal (complex W)."""
     if grid not in GRIDS:
         raise ValueError(f"grid must be one of {sorted(GRIDS)}, not {grid!r}")
-    return Params(L, N, float(lam), J_min, GRIDS[grid], FP64 if precision == "fp64" else MIXED, 1)
+    return Params(L, N, float(lam), J_min, GRIDS[grid], FP64 if precision == "fp64" else MIXED,
+                  1 if reality else 0)
 
 
 def _check(rc: int, what: str):
@@ -140,10 +142,12 @@ def _as_complex(x: torch.Tensor, n: int, what: str) -> torch.Tensor:
     return x.contiguous()
 
 
-def _w_dtype(precision: str):
+def _w_dtype(precision: str, reality: bool = True):
     if precision not in ("fp64", "mixed"):
         raise ValueError(f"precision must be 'fp64' or 'mixed', not {precision!r}")
-    return torch.float64 if precision == "fp64" else torch.float32
+    if reality:
+        return torch.float64 if precision == "fp64" else torch.float32
+    return torch.complex128 if precision == "fp64" else torch.complex64
 
 
 def scale_grid(L: int, N: int, lam: float = 2.0, J_min: int = 0, j: int = 0, *, grid: str = "mw"):
@@ -186,12 +190,14 @@ def _check_w(W, shape, dtype, B, what):
 
 
 def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0, *, scaling: bool = True,
-             out: torch.Tensor | None = None, stream=None, precision: str = "fp64", grid: str = "mw"):
+             out: torch.Tensor | None = None, stream=None, precision: str = "fp64", grid: str = "mw",
+             reality: bool = True):
     """Wavelet coefficients W [S][2N-1][L][2L-1] (float64, or float32 with precision="mixed";
-    flat in the multiresolution layout, see split_scales) and, if scaling, the harmonic
-    scaling coefficients W^Phi_lm (complex128 [L*L])."""
-    p = params(L, N, lam, J_min, precision, grid)
-    wdt = _w_dtype(precision)
+    complex128 / complex64 for a complex signal, reality=False; flat in the multiresolution
+    layout, see split_scales) and, if scaling, the harmonic scaling coefficients W^Phi_lm
+    (complex128 [L*L])."""
+    p = params(L, N, lam, J_min, precision, grid, reality)
+    wdt = _w_dtype(precision, reality)
     f = _as_complex(flm, L * L, "flm")
     shape = _w_shape(L, N, lam, J_min, grid)
     W = out if out is not None else torch.empty(shape, dtype=wdt, device=f.device)
@@ -205,12 +211,12 @@ def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0
 
 def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,
               out: torch.Tensor | None = None, stream=None, precision: str = "fp64",
-              grid: str = "mw") -> torch.Tensor:
+              grid: str = "mw", reality: bool = True) -> torch.Tensor:
     """f_lm (complex128 [L*L]) from W (float64, or float32 with precision="mixed") and the
     scaling coefficients (or the wavelet part only)."""
-    p = params(L, N, lam, J_min, precision, grid)
+    p = params(L, N, lam, J_min, precision, grid, reality)
     W = W.contiguous()
-    _check_w(W, _w_shape(L, N, lam, J_min, grid), _w_dtype(precision), 1, "W")
+    _check_w(W, _w_shape(L, N, lam, J_min, grid), _w_dtype(precision, reality), 1, "W")
     wp = _as_complex(Wphi, L * L, "Wphi") if Wphi is not None else None
     f = out if out is not None else torch.empty(L * L, dtype=torch.complex128, device=W.device)
     _check(lib().s2dw_synthesis(ctypes.byref(p), ctypes.c_void_p(W.data_ptr()),
@@ -220,12 +226,13 @@ def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: f
 
 
 def analysis_batched(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0, *, scaling: bool = True,
-                     out: torch.Tensor | None = None, stream=None, precision: str = "fp64", grid: str = "mw"):
+                     out: torch.Tensor | None = None, stream=None, precision: str = "fp64", grid: str = "mw",
+                     reality: bool = True):
     """A batch of maps with the same parameters: flm complex128 [B][L*L] -> W [B][S][2N-1][L][2L-1]
     (float64 or float32; [B][total] in the multiresolution layout) and, if scaling, W^Phi
     complex128 [B][L*L]."""
-    p = params(L, N, lam, J_min, precision, grid)
-    wdt = _w_dtype(precision)
+    p = params(L, N, lam, J_min, precision, grid, reality)
+    wdt = _w_dtype(precision, reality)
     if flm.dim() != 2 or flm.shape[1] != L * L:
         raise ValueError("flm: expected [B][L*L] complex128")
     B = flm.shape[0]
@@ -243,12 +250,12 @@ def analysis_batched(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min:
 
 def synthesis_batched(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0,
                       J_min: int = 0, *, out: torch.Tensor | None = None, stream=None,
-                      precision: str = "fp64", grid: str = "mw") -> torch.Tensor:
+                      precision: str = "fp64", grid: str = "mw", reality: bool = True) -> torch.Tensor:
     """A batch of maps: W [B][S][2N-1][L][2L-1] (+ W^Phi [B][L*L]) -> f_lm complex128 [B][L*L]."""
-    p = params(L, N, lam, J_min, precision, grid)
+    p = params(L, N, lam, J_min, precision, grid, reality)
     B = W.shape[0]
     W = W.contiguous()
-    _check_w(W, _w_shape(L, N, lam, J_min, grid), _w_dtype(precision), B, "W")
+    _check_w(W, _w_shape(L, N, lam, J_min, grid), _w_dtype(precision, reality), B, "W")
     wp = _as_complex(Wphi, B * L * L, "Wphi") if Wphi is not None else None
     f = out if out is not None else torch.empty((B, L * L), dtype=torch.complex128, device=W.device)
     _check(lib().s2dw_synthesis_batched(ctypes.byref(p), B, ctypes.c_void_p(W.data_ptr()),
@@ -258,11 +265,11 @@ def synthesis_batched(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int
 
 
 def autotune(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1, precision: str = "fp64",
-             stream=None, grid: str = "mw"):
+             stream=None, grid: str = "mw", reality: bool = True):
     """Times the compiled Wigner tile shapes and batch chunks for these parameters and keeps
     the fastest in the library's plan; returns (m' slots per wave, maps per chunk)."""
     sl, ch = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().s2dw_autotune(ctypes.byref(params(L, N, lam, J_min, precision, grid)), count, _stream(stream),
+    _check(lib().s2dw_autotune(ctypes.byref(params(L, N, lam, J_min, precision, grid, reality)), count, _stream(stream),
                                ctypes.byref(sl), ctypes.byref(ch)), "s2dw_autotune")
     return sl.value, ch.value
 
@@ -275,9 +282,10 @@ def steer(W: torch.Tensor, gammas, L: int, N: int, lam: float = 2.0, J_min: int 
     layout); with multires, [total] or [B][total].  gammas: angles in radians (a sequence or
     a float64 tensor).  Returns [(B,) S, Q, L, 2L-1] (multires: [(B,) total_Q] with scale j's
     [Q][L_j][2L_j-1] block at Q/(2N-1) times its offset in W) in W's dtype."""
-    if W.dtype not in (torch.float64, torch.float32) or not W.is_cuda:
-        raise ValueError("W: expected a float64 or float32 device tensor")
-    precision = "fp64" if W.dtype == torch.float64 else "mixed"
+    if W.dtype not in (torch.float64, torch.float32, torch.complex128, torch.complex64) or not W.is_cuda:
+        raise ValueError("W: expected a float64, float32, complex128 or complex64 device tensor")
+    precision = "fp64" if W.dtype in (torch.float64, torch.complex128) else "mixed"
+    reality = not W.is_complex()
     shape = _w_shape(L, N, lam, J_min, grid)
     per = 1
     for d in shape:
@@ -295,7 +303,7 @@ def steer(W: torch.Tensor, gammas, L: int, N: int, lam: float = 2.0, J_min: int 
     o = out if out is not None else torch.empty(oshape, dtype=W.dtype, device=W.device)
     if o.dtype != W.dtype or o.numel() != B * (per // G) * Q or not o.is_contiguous():
         raise ValueError("out: wrong shape, dtype or layout")
-    _check(lib().s2dw_steer(ctypes.byref(params(L, N, lam, J_min, precision, grid)), B,
+    _check(lib().s2dw_steer(ctypes.byref(params(L, N, lam, J_min, precision, grid, reality)), B,
                             ctypes.c_void_p(W.data_ptr()), Q, ctypes.c_void_p(g.data_ptr()),
                             ctypes.c_void_p(o.data_ptr()), _stream(stream)), "s2dw_steer")
     return o
@@ -335,10 +343,10 @@ def sht_inverse(flm: torch.Tensor, L: int, stream=None) -> torch.Tensor:
 
 
 def workspace_bytes(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1,
-                    precision: str = "fp64", grid: str = "mw") -> int:
+                    precision: str = "fp64", grid: str = "mw", reality: bool = True) -> int:
     """Device bytes of one stream's workspace for a batch of `count` maps."""
     b = ctypes.c_uint64()
-    _check(lib().s2dw_workspace_bytes(ctypes.byref(params(L, N, lam, J_min, precision, grid)), count,
+    _check(lib().s2dw_workspace_bytes(ctypes.byref(params(L, N, lam, J_min, precision, grid, reality)), count,
                                       ctypes.byref(b)),
            "s2dw_workspace_bytes")
     return b.value

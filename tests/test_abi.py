@@ -69,11 +69,18 @@ def test_null_and_misaligned_pointers():
     assert lib.s2dw_analysis(None, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None, None) == -1
 
 
-def test_complex_signals_are_reported_unsupported():
+def test_reality_flag_and_complex_sizes():
     lib = s2dw.lib()
-    p = s2dw.Params(64, 4, 2.0, 0, 0, 0, 0)
     fake = ctypes.c_void_p(0x1000)
-    assert lib.s2dw_analysis(ctypes.byref(p), fake, fake, None, None) == -4
+    bad = s2dw.Params(64, 4, 2.0, 0, 0, 0, 2)  # reality must be 0 or 1
+    assert lib.s2dw_analysis(ctypes.byref(bad), fake, fake, None, None) == -1
+    # complex signals: complex W, twice the bytes of the real layout
+    br, bc = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.s2dw_wavelet_bytes(ctypes.byref(s2dw.params(64, 4, 2.0, 0)), ctypes.byref(br)) == 0
+    assert lib.s2dw_wavelet_bytes(ctypes.byref(s2dw.params(64, 4, 2.0, 0, reality=False)), ctypes.byref(bc)) == 0
+    assert bc.value == 2 * br.value
+    # the sphere map of complex scaling coefficients is not offered (the maps are real)
+    assert lib.s2dw_scaling(ctypes.byref(s2dw.params(64, 4, 2.0, 0, reality=False)), fake, None, fake, None) == -4
 
 
 def test_strerror():

@@ -109,3 +109,28 @@ def test_full_size_driscoll_healy_rows_and_round_trip():
     del W, Wp, fr
     s2dw.release_caches()
     torch.cuda.empty_cache()
+
+
+def test_full_size_complex_signal_rows_and_round_trip():
+    # a complex signal at the benchmark workload: complex coefficients on sampled beta rows
+    # against the oracle, and the exact round trip
+    from paper_1308_5706_amd.inputs import random_flm_complex
+    L, N, J_min, lam = 1024, 8, 1, 2.0
+    print(f"full size complex signal L={L} N={N} J_min={J_min}", flush=True)
+    f = random_flm_complex(L, 0)
+    fd = torch.as_tensor(f).to("cuda")
+    W, Wp = s2dw.analysis(fd, L, N, lam, J_min, reality=False)
+    rows = [0, L - 1]
+    got = W[:, :, rows, :].cpu().numpy()
+    print("  oracle on the sampled beta rows", flush=True)
+    ref = oracle.analysis_complex(f, L, N, lam, J_min, betas=oracle.mw_betas(L)[rows])
+    for j in range(ref.shape[0]):
+        err = float(np.max(np.abs(got[j] - ref[j])) / np.max(np.abs(ref[j])))
+        assert err < TOL, (j, err)
+    fr = s2dw.synthesis(W, Wp, L, N, lam, J_min, reality=False)
+    torch.cuda.synchronize()
+    rt = float((fr - fd).abs().max().item() / fd.abs().max().item())
+    assert rt < 1e-12, rt
+    del W, Wp, fr
+    s2dw.release_caches()
+    torch.cuda.empty_cache()
