@@ -50,8 +50,8 @@ struct Plan {
     // chirp tables of one grid band-limit (length T = 2Lg - 1) and the spectrum of the first
     // synthesis beta convolution (transform size PD)
     struct GridTab {
-        double2 *csq = nullptr, *cpp = nullptr, *hD1 = nullptr;
-        float2 *csqf = nullptr, *cppf = nullptr, *hD1f = nullptr;
+        double2 *csq = nullptr, *cpp = nullptr, *hD1 = nullptr, *eph = nullptr;
+        float2 *csqf = nullptr, *cppf = nullptr, *hD1f = nullptr, *ephf = nullptr;
         int PD = 0;
     };
     std::map<int, GridTab> gt;
@@ -71,6 +71,11 @@ struct Plan {
     std::vector<int> seede_h;                   // start-value exponents [Lp][Lp] (host)
     // Bluestein stages: transform sizes and chirp spectra per scale, twiddles per size
     std::vector<int> PA, PB;                    // beta (analysis), alpha (both directions)
+    // blocked alpha transforms (scales with few coefficients): nblk blocks of B samples, each
+    // a convolution of size PBb; nblk = 0 where the single convolution of size PB is used
+    std::vector<int> PBb, Bb, nblkb;
+    std::vector<double2 *> hBb, hCb;
+    std::vector<float2 *> hBbf, hCbf;
     std::vector<double2 *> hA, hB, hC, hD2;     // per scale (hD2 has the size PD of the scale's grid)
     std::map<int, double2 *> twP;               // e^{-2 pi i k/P}
     // FP32 copies of the stage tables for the mixed-precision path (built on first use)
@@ -357,7 +362,11 @@ int build_grid_tab(Plan &P, int Lg) {
     if (P.gt.count(Lg)) return S2DW_OK;
     Plan::GridTab g;
     const int M = 2 * Lg - 1;
-    std::vector<double2> csq(M), cpp(M);
+    std::vector<double2> csq(M), cpp(M), eph(M);
+    for (int r = 0; r < M; ++r) {
+        const ld a = 2.0L * kPiL * (ld)r / (ld)M;
+        eph[r] = make_double2((double)cosl(a), (double)sinl(a));
+    }
     // chirps with the phase reduced exactly modulo 2T
     for (int i = 0; i < M; ++i) {
         const long long p = i - (Lg - 1);
@@ -369,7 +378,8 @@ int build_grid_tab(Plan &P, int Lg) {
     g.PD = pow2_at_least(2 * M - 1);
     if (g.PD > 8192) return S2DW_E_UNSUPPORTED;
     auto hd1 = spectrum(g.PD, 2 * M - 1, (ld)M, [&](int i) { return chirp_val((long long)i - Lg - M + 2, M, +1); });
-    if (!upload(P, g.csq, csq) || !upload(P, g.cpp, cpp) || !upload(P, g.hD1, hd1)) return S2DW_E_NOMEM;
+    if (!upload(P, g.csq, csq) || !upload(P, g.cpp, cpp) || !upload(P, g.hD1, hd1) || !upload(P, g.eph, eph))
+        return S2DW_E_NOMEM;
     P.gt[Lg] = g;
     return S2DW_OK;
 }
@@ -498,6 +508,11 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
     std::vector<int> sizes;
     P.PE.assign(t.S, 0);
     P.hE.assign(t.S, nullptr);
+    P.PBb.assign(t.S, 0);
+    P.Bb.assign(t.S, 0);
+    P.nblkb.assign(t.S, 0);
+    P.hBb.assign(t.S, nullptr);
+    P.hCb.assign(t.S, nullptr);
     const int Tb = dh ? 4 * L : 0;
     if (dh) {
         // Driscoll-Healy beta grid: chirps of Tb = 4L and the weights of Eq. 18
@@ -541,6 +556,35 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
             auto he = spectrum(P.PE[j], nbj + 2 * Lj - 2, 1.0L,
                                [&](int i) { return chirp_val((long long)i - (Lj + nbj - 2), Tb, +1); });
             if (!upload(P, P.hE[j], he)) return S2DW_E_NOMEM;
+        }
+        {
+            // blocked alpha transforms: the cheapest of one convolution of size PB and nblk of
+            // size Q in {512, 1024, 2048} over B = Q - 2Lj + 2 samples each (cost ~ count
+            // Q log2 Q), taken when it saves at least 30% (measured: the looped short
+            // convolutions reach about 0.1-0.2 less than this model predicts)
+            auto cost = [](int Q) { return (double)Q * std::log2((double)Q); };
+            double best = 0.7 * cost(P.PB[j]);
+            for (int Q = 512; Q <= 2048; Q *= 2) {
+                const int B = Q - 2 * Lj + 2;
+                if (B < 64) continue;
+                const int nbk = (T + B - 1) / B;
+                if (nbk < 2) continue;
+                if (nbk * cost(Q) < best) {
+                    best = nbk * cost(Q);
+                    P.PBb[j] = Q;
+                    P.Bb[j] = B;
+                    P.nblkb[j] = nbk;
+                }
+            }
+            if (P.nblkb[j] > 1) {
+                const int Q = P.PBb[j], B = P.Bb[j];
+                sizes.push_back(Q);
+                auto hb = spectrum(Q, 2 * Lj + B - 2, 1.0L,
+                                   [&](int i) { return chirp_val((long long)i - Lj + 1, T, -1); });
+                auto hc = spectrum(Q, 2 * Lj + B - 2, 1.0L,
+                                   [&](int i) { return chirp_val((long long)i - Lj - B + 2, T, +1); });
+                if (!upload(P, P.hBb[j], hb) || !upload(P, P.hCb[j], hc)) return S2DW_E_NOMEM;
+            }
         }
         auto ha = spectrum(P.PA[j], 2 * Lj + nbj - 2, 1.0L,
                            [&](int i) { return chirp_val((long long)i - Lj + 1, Tbj, -1); });
@@ -600,7 +644,8 @@ int ensure_f32(Plan &P) {
         if (!ok) break;
         const int T = 2 * kv.first - 1;
         Plan::GridTab &g = kv.second;
-        ok = f32_copy(P, g.csqf, g.csq, T) && f32_copy(P, g.cppf, g.cpp, T) && f32_copy(P, g.hD1f, g.hD1, g.PD);
+        ok = f32_copy(P, g.csqf, g.csq, T) && f32_copy(P, g.cppf, g.cpp, T) && f32_copy(P, g.hD1f, g.hD1, g.PD) &&
+             f32_copy(P, g.ephf, g.eph, T);
     }
     if (ok && P.grid == S2DW_GRID_DH)
         ok = f32_copy(P, P.dh_csqf, P.dh_csq, P.nb) && f32_copy(P, P.dh_cppf, P.dh_cpp, 2 * P.L - 1) &&
@@ -610,12 +655,16 @@ int ensure_f32(Plan &P) {
     P.hCf.assign(S, nullptr);
     P.hD2f.assign(S, nullptr);
     P.hEf.assign(S, nullptr);
+    P.hBbf.assign(S, nullptr);
+    P.hCbf.assign(S, nullptr);
     for (int j = 0; ok && j < S; ++j) {
         if (P.sc.Lj[j] == 0) continue;
         const int PD = P.gt[P.Lg[j]].PD;
         ok = f32_copy(P, P.hAf[j], P.hA[j], P.PA[j]) && f32_copy(P, P.hBf[j], P.hB[j], P.PB[j]) &&
              f32_copy(P, P.hCf[j], P.hC[j], P.PB[j]) && f32_copy(P, P.hD2f[j], P.hD2[j], PD);
         if (ok && P.hE[j]) ok = f32_copy(P, P.hEf[j], P.hE[j], P.PE[j]);
+        if (ok && P.hBb[j])
+            ok = f32_copy(P, P.hBbf[j], P.hBb[j], P.PBb[j]) && f32_copy(P, P.hCbf[j], P.hCb[j], P.PBb[j]);
     }
     for (auto &kv : P.twP) {
         if (!ok) break;
@@ -805,7 +854,15 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         c.tw = f32 ? (const void *)P.twPf[P.PB[j]] : P.twP[P.PB[j]];
         c.csq = f32 ? (const void *)gtab.csqf : gtab.csq;
         c.cpp = f32 ? (const void *)gtab.cppf : gtab.cpp;
-        {
+        if (P.nblkb[j] > 1) {
+            c.hh = f32 ? (const void *)P.hBbf[j] : P.hBb[j];
+            c.tw = f32 ? (const void *)P.twPf[P.PBb[j]] : P.twP[P.PBb[j]];
+            c.eph = f32 ? (const void *)gtab.ephf : gtab.eph;
+            c.nblk = P.nblkb[j];
+            c.B = P.Bb[j];
+            Stage sg("alpha_fwd", st);
+            S2DW_CHECK_HIP(launch_alpha_fwd_blk(c, P.PBb[j], maps, st));
+        } else {
             Stage sg("alpha_fwd", st);
             S2DW_CHECK_HIP(launch_alpha_fwd_fft(c, P.PB[j], maps, st));
         }
@@ -877,7 +934,16 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         c.Nh = P.Nh;
         c.K = P.K;
         c.scale = (2.0 * M_PI / M) * (2.0 * M_PI / P.ng);
-        {
+        if (P.nblkb[j] > 1) {
+            StageArgs cb = c;
+            cb.hh = f32 ? (const void *)P.hCbf[j] : P.hCb[j];
+            cb.tw = f32 ? (const void *)P.twPf[P.PBb[j]] : P.twP[P.PBb[j]];
+            cb.eph = f32 ? (const void *)gtab.ephf : gtab.eph;
+            cb.nblk = P.nblkb[j];
+            cb.B = P.Bb[j];
+            Stage sg("alpha_adj", st);
+            S2DW_CHECK_HIP(launch_alpha_adj_blk(cb, P.PBb[j], maps, st));
+        } else {
             Stage sg("alpha_adj", st);
             S2DW_CHECK_HIP(launch_alpha_adj_fft(c, P.PB[j], maps, st));
         }

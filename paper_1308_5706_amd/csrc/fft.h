@@ -42,8 +42,11 @@ template <class C> __device__ __forceinline__ C cmulc(C a, C b) {  // a * conj(b
 template <class C> __device__ __forceinline__ C cconj(C a) { return mk<C>(a.x, -a.y); }
 template <class C> __device__ __forceinline__ C cscale(C a, real_t<C> s) { return mk<C>(a.x * s, a.y * s); }
 
-__host__ __device__ constexpr int padded(int P) { return P + P / 16; }
-__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+#ifndef S2DW_LDS_PAD_SHIFT
+#define S2DW_LDS_PAD_SHIFT 4
+#endif
+__host__ __device__ constexpr int padded(int P) { return P + (P >> S2DW_LDS_PAD_SHIFT); }
+__device__ __forceinline__ int pad(int i) { return i + (i >> S2DW_LDS_PAD_SHIFT); }
 
 // a * (SIGN i)
 template <int SIGN, class C>
@@ -133,12 +136,12 @@ __device__ __forceinline__ void dft_reg(C *v) {
 template <class C>
 struct LdsIn {
     const C *buf;
-    __device__ __forceinline__ C operator()(int i) const { return buf[pad(i)]; }
+    __device__ __forceinline__ C operator()(int i, int = 0) const { return buf[pad(i)]; }
 };
 template <class C>
 struct LdsOut {
     C *buf;
-    __device__ __forceinline__ void operator()(int i, C v) const { buf[pad(i)] = v; }
+    __device__ __forceinline__ void operator()(int i, C v, int = 0) const { buf[pad(i)] = v; }
 };
 
 // log2 of a power of two, at compile time
@@ -167,7 +170,10 @@ __device__ __forceinline__ void twiddle_powers(C *w) {
 }
 
 // One Stockham pass of radix R and span Ns over a column of P values held by NT threads:
-// inputs come from `in` (LDS or a loader), outputs go to `out` (LDS or a storer).
+// inputs come from `in` (LDS or a loader), outputs go to `out` (LDS or a storer).  Both are
+// called with the element index and the thread's slot q R + r (q < P/(R NT), r < R), a
+// compile-time constant once the loops are unrolled, so that a loader or storer can keep
+// per-thread values in registers; every pass gives a thread P/NT slots.
 // tw[t] = e^{-2 pi i t/P} (the inverse transform, SIGN = +1, uses its conjugate).  The
 // pass is in place: all reads, a barrier, all writes, a barrier.  The twiddle entry is
 // requested before the reads so that its latency overlaps them.
@@ -191,7 +197,7 @@ __device__ __forceinline__ void pass(int Ns, int tid0, const C *__restrict__ tw,
     for (int q = 0; q < PER; ++q) {
         const int j = tid + q * NT;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = in(j + r * NB);
+        for (int r = 0; r < R; ++r) v[q][r] = in(j + r * NB, q * R + r);
     }
     __syncthreads();
 #pragma unroll
@@ -206,7 +212,7 @@ __device__ __forceinline__ void pass(int Ns, int tid0, const C *__restrict__ tw,
         dft_reg<R, SIGN>(v[q]);
         const int base = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) out(base + r * Ns, v[q][out_pos<R>(r)]);
+        for (int r = 0; r < R; ++r) out(base + r * Ns, v[q][out_pos<R>(r)], q * R + r);
     }
     __syncthreads();
 }
@@ -229,7 +235,7 @@ __device__ __forceinline__ void mid_pass(int tid0, const C *__restrict__ tw, con
         const int j = tid + q * NT;
         w[q][1] = tw[j];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = in(j + r * NB);
+        for (int r = 0; r < R; ++r) v[q][r] = in(j + r * NB, q * R + r);
     }
     __syncthreads();
 #pragma unroll
@@ -244,7 +250,7 @@ __device__ __forceinline__ void mid_pass(int tid0, const C *__restrict__ tw, con
         for (int r = 0; r < R; ++r) x[r] = cmul(v[q][out_pos<R>(r)], hh[j + r * NB]);
         dft_reg<R, +1>(x);
 #pragma unroll
-        for (int r = 0; r < R; ++r) out(j * R + r, x[out_pos<R>(r)]);
+        for (int r = 0; r < R; ++r) out(j * R + r, x[out_pos<R>(r)], q * R + r);
     }
     __syncthreads();
 }

@@ -67,6 +67,8 @@ struct StageArgs {
     const void *csq;       // e^{i pi i^2/T}, i < T (alpha stages, T = 2L - 1), or i < nb (beta stages, T = Tb)
     const void *cpp;       // e^{i pi p(p+1)/T} at p + L - 1, |p| < L (T as for csq)
     const void *qw;        // Driscoll-Healy quadrature weights q_t, t < nb (real; synthesis beta stage)
+    const void *eph;       // e^{2 pi i r/T}, r < T (blocked alpha stages)
+    int nblk, B;           // blocked alpha stages: nblk blocks of B samples
     size_t s_in, s_out;    // per-map strides (complex elements) of a batch; map = blockIdx.y
     int L, nb, Lj, N, Nh, K, eta_imag, f32;  // nb: beta rings (L, or 2L on the Driscoll-Healy grid)
     int nk[kMaxK];
@@ -76,6 +78,8 @@ struct StageArgs {
 hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
+hipError_t launch_alpha_fwd_blk(const StageArgs &a, int P, int maps, hipStream_t st);
+hipError_t launch_alpha_adj_blk(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t st);
 

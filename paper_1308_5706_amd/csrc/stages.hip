@@ -81,14 +81,14 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const 
     const C *__restrict__ csq = (const C *)a.csq;
     const int Na = 2 * Lj - 1;
     C *__restrict__ out = (C *)a.out + blockIdx.y * a.s_out + (size_t)col * nb;
-    auto in = [&](int i) {
+    auto in = [&](int i, int = 0) {
         if (i >= Na) return zero2<C>();
         const int mp = i - (Lj - 1);
         C v = to_c<C>(Uc[mp < 0 ? -mp : mp]);
         if (mp < 0 && odd) v = mk<C>(-v.x, -v.y);
         return cmul(v, cpp[mp]);
     };
-    auto st = [&](int i, C v) {
+    auto st = [&](int i, C v, int = 0) {
         const int b = i - (Na - 1);
         if (b >= 0 && b < nb) out[b] = cmul(v, csq[b]);
     };
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const
     const C *__restrict__ Um = (const C *)a.in + blockIdx.y * a.s_in + (size_t)nj * Lj * nb + b;
     const C *__restrict__ csq = (const C *)a.csq;
     const int Na = 2 * Lj - 1;
-    auto in = [&](int i) {
+    auto in = [&](int i, int = 0) {
         if (i >= Na) return zero2<C>();
         const int m = i - (Lj - 1);
         C c;
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const
         return cmul(c, csq[m < 0 ? -m : m]);
     };
     C *__restrict__ Y = (C *)a.out + blockIdx.y * a.s_out + ((size_t)np * nb + b) * T;
-    auto st = [&](int i, C v) {
+    auto st = [&](int i, C v, int = 0) {
         const int x = i - (Na - 1);
         if (x >= 0 && x < T) Y[x] = cmul(v, csq[x]);
     };
@@ -162,13 +162,13 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const
     const bool zero_n = ni == nj;
     const C *__restrict__ X = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)np * nb + b) * T;
     const C *__restrict__ csq = (const C *)a.csq;
-    auto in = [&](int i) { return i < T ? cmulc(X[i], csq[i]) : zero2<C>(); };
+    auto in = [&](int i, int = 0) { return i < T ? cmulc(X[i], csq[i]) : zero2<C>(); };
     // Zh(m), q = m + Lj - 1 < 2Lj - 1, comes out at q + T - 1
     const int Nk = 2 * Lj - 1;
     const real_t<C> s = (real_t<C>)a.scale;
     C *__restrict__ Gp = (C *)a.out + blockIdx.y * a.s_out + (size_t)ni * Lj * nb + b;
     C *__restrict__ Gm = (C *)a.out + blockIdx.y * a.s_out + (size_t)nj * Lj * nb + b;
-    auto st = [&](int i, C v) {
+    auto st = [&](int i, C v, int = 0) {
         const int q = i - (T - 1);
         if (q >= 0 && q < Nk) {
             const int m = q - (Lj - 1);
@@ -178,6 +178,117 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const
         }
     };
     fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+}
+
+// Blocked alpha sums for scales with few coefficients (2Lj - 1 well below T): the T samples
+// are taken in nblk blocks of B consecutive ones, each through a short chirp convolution of
+// size P >= B + 2Lj - 2 instead of one of size >= T + 2Lj - 2.  With a = a0 + a' (a0 = k B),
+//   sum_m C(m) e^{2 pi i m a/T} = sum_m [C(m) e^{2 pi i m a0/T}] e^{2 pi i m a'/T},
+// so every block uses the same chirp spectrum and only the modulation e^{2 pi i m a0/T} =
+// eph[(m a0) mod T] changes.  The workgroup loops over the blocks; in the synthesis the
+// block results are summed in registers (the storer's slots are the same in every block).
+template <class C, int P>
+__global__ void __launch_bounds__(P / kRM) alpha_fwd_blk_kernel(const StageArgs a) {
+    static_assert(fft::Plan<P, kRM>::NPASS >= 2, "the first pass reads element tid + r NT into slot r");
+    __shared__ C buf[fft::padded(P)];
+    constexpr int NT = P / kRM;
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh, nb = a.nb, B = a.B;
+    const int t = xcd_column(blockIdx.x, Nh * nb);
+    if (t >= Nh * nb) return;
+    const int b = t / Nh, np = t - (t / Nh) * Nh;
+    const int ni = (N / 2) + np, nj = N - 1 - ni;
+    const bool zero_n = ni == nj;
+    const C *__restrict__ Up = (const C *)a.in + blockIdx.y * a.s_in + (size_t)ni * Lj * nb + b;
+    const C *__restrict__ Um = (const C *)a.in + blockIdx.y * a.s_in + (size_t)nj * Lj * nb + b;
+    const C *__restrict__ csq = (const C *)a.csq;
+    const C *__restrict__ eph = (const C *)a.eph;
+    const int Na = 2 * Lj - 1;
+    // this thread's chirped inputs, element tid + s NT in slot s, kept across the blocks
+    C base[kRM];
+#pragma unroll
+    for (int s = 0; s < kRM; ++s) {
+        const int i = tid + s * NT;
+        C c = zero2<C>();
+        if (i < Na) {
+            const int m = i - (Lj - 1);
+            if (m >= 0) {
+                c = Up[(size_t)m * nb];
+                if (m == 0 && zero_n) c.y = 0.0;
+            } else {
+                c = cconj(Um[(size_t)(-m) * nb]);
+            }
+            c = cmul(c, csq[m < 0 ? -m : m]);
+        }
+        base[s] = c;
+    }
+    C *__restrict__ Y = (C *)a.out + blockIdx.y * a.s_out + ((size_t)np * nb + b) * T;
+    for (int k = 0; k < a.nblk; ++k) {
+        const int a0 = k * B;
+        auto in = [&](int i, int s) {
+            int r = ((i - (Lj - 1)) * a0) % T;
+            if (r < 0) r += T;
+            return cmul(base[s], eph[r]);
+        };
+        auto st = [&](int i, C v, int = 0) {
+            const int x = i - (Na - 1);
+            if (x >= 0 && x < B && a0 + x < T) Y[a0 + x] = cmul(v, csq[x]);
+        };
+        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+    }
+}
+
+// Synthesis: Gs(m) = sum_k e^{-2 pi i m a0/T} sum_{a' < B} X(a0 + a') e^{-2 pi i m a'/T}.
+template <class C, int P>
+__global__ void __launch_bounds__(P / kRM) alpha_adj_blk_kernel(const StageArgs a) {
+    __shared__ C buf[fft::padded(P)];
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N, Nh = a.Nh, nb = a.nb, B = a.B;
+    const int t = xcd_column(blockIdx.x, Nh * nb);
+    if (t >= Nh * nb) return;
+    const int b = t / Nh, np = t - (t / Nh) * Nh;
+    const int ni = (N / 2) + np, nj = N - 1 - ni;
+    const bool zero_n = ni == nj;
+    const C *__restrict__ X = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)np * nb + b) * T;
+    const C *__restrict__ csq = (const C *)a.csq;
+    const C *__restrict__ eph = (const C *)a.eph;
+    const int Nk = 2 * Lj - 1;
+    C acc[kRM];
+    int qs[kRM];
+#pragma unroll
+    for (int s = 0; s < kRM; ++s) {
+        acc[s] = zero2<C>();
+        qs[s] = -1;
+    }
+    for (int k = 0; k < a.nblk; ++k) {
+        const int a0 = k * B;
+        auto in = [&](int i, int = 0) { return (i < B && a0 + i < T) ? cmulc(X[a0 + i], csq[i]) : zero2<C>(); };
+        // the block's part of Zh(m), q = m + Lj - 1 < 2Lj - 1, comes out at q + B - 1
+        auto st = [&](int i, C v, int s) {
+            const int q = i - (B - 1);
+            qs[s] = q;
+            if (q >= 0 && q < Nk) {
+                const int m = q - (Lj - 1);
+                int r = (-m * a0) % T;
+                if (r < 0) r += T;
+                acc[s] = cadd(acc[s], cmul(cmulc(v, csq[m < 0 ? -m : m]), eph[r]));
+            }
+        };
+        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+    }
+    const real_t<C> sc = (real_t<C>)a.scale;
+    C *__restrict__ Gp = (C *)a.out + blockIdx.y * a.s_out + (size_t)ni * Lj * nb + b;
+    C *__restrict__ Gm = (C *)a.out + blockIdx.y * a.s_out + (size_t)nj * Lj * nb + b;
+#pragma unroll
+    for (int s = 0; s < kRM; ++s) {
+        const int q = qs[s];
+        if (q >= 0 && q < Nk) {
+            const int m = q - (Lj - 1);
+            const C z = cscale(acc[s], sc);
+            if (m >= 0) Gp[(size_t)m * nb] = z;
+            if (m <= 0 && !zero_n) Gm[(size_t)(-m) * nb] = cconj(z);
+        }
+    }
 }
 
 typedef double nt_double2 __attribute__((ext_vector_type(2)));
@@ -428,24 +539,24 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
         const C *__restrict__ Gc = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)ni * Lj + m) * L;
-        auto in1 = [&](int i) {
+        auto in1 = [&](int i, int = 0) {
             if (i >= T) return zero2<C>();
             C v = i < L ? Gc[i] : Gc[2 * L - 2 - i];
             if (i >= L && odd) v = mk<C>(-v.x, -v.y);
             return cmulc(v, csq[i]);
         };
         // Gh(p), q = p + L - 1 < T, comes out at q + T - 1 (1/T is folded into the spectrum)
-        auto st1 = [&](int i, C v) {
+        auto st1 = [&](int i, C v, int = 0) {
             const int q = i - (T - 1);
             if (q >= 0 && q < T) buf[pad(q)] = cmulc(v, cpp[q]);
         };
         fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in1, st1);
-        auto in2 = [&](int i) { return i < T ? buf[pad(i)] : zero2<C>(); };
+        auto in2 = [&](int i, int = 0) { return i < T ? buf[pad(i)] : zero2<C>(); };
         // V(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + T - 1.  With two columns the
         // first one waits in this block's own output rows (2 Lj slots) while the second one
         // uses the whole buffer; the second one goes to slots Nk + q.
         if (c == 0 && ncol > 1) {
-            auto st2 = [&](int i, C v) {
+            auto st2 = [&](int i, C v, int = 0) {
                 const int q = i - (T - 1);
                 if (q >= 0 && q < Nk) {
                     if (q < Lj) Po[q] = v;
@@ -455,7 +566,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
             fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh2, in2, st2);
         } else {
             const int sh = c * Nk;
-            auto st2 = [&](int i, C v) {
+            auto st2 = [&](int i, C v, int = 0) {
                 const int q = i - (T - 1);
                 if (q >= 0 && q < Nk) buf[pad(sh + q)] = v;
             };
@@ -493,10 +604,10 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_dh_kernel(const S
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
         const C *__restrict__ Gc = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)ni * Lj + m) * nb;
-        auto in = [&](int i) { return i < nb ? cscale(cmulc(Gc[i], csq[i]), qw[i]) : zero2<C>(); };
+        auto in = [&](int i, int = 0) { return i < nb ? cscale(cmulc(Gc[i], csq[i]), qw[i]) : zero2<C>(); };
         // V(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + nb - 1
         if (c == 0 && ncol > 1) {
-            auto st = [&](int i, C v) {
+            auto st = [&](int i, C v, int = 0) {
                 const int q = i - (nb - 1);
                 if (q >= 0 && q < Nk) {
                     v = cmulc(v, cpp[q - (Lj - 1)]);
@@ -507,7 +618,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_dh_kernel(const S
             fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
         } else {
             const int sh = c * Nk;
-            auto st = [&](int i, C v) {
+            auto st = [&](int i, C v, int = 0) {
                 const int q = i - (nb - 1);
                 if (q >= 0 && q < Nk) buf[pad(sh + q)] = cmulc(v, cpp[q - (Lj - 1)]);
             };
@@ -555,6 +666,16 @@ hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t
 
 hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
     S2DW_P_SWITCH(P, alpha_adj_fft_kernel, 8 * ((a.Nh * a.nb + 7) / 8), a)
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha_fwd_blk(const StageArgs &a, int P, int maps, hipStream_t st) {
+    S2DW_P_SWITCH(P, alpha_fwd_blk_kernel, 8 * ((a.Nh * a.nb + 7) / 8), a)
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha_adj_blk(const StageArgs &a, int P, int maps, hipStream_t st) {
+    S2DW_P_SWITCH(P, alpha_adj_blk_kernel, 8 * ((a.Nh * a.nb + 7) / 8), a)
     return hipGetLastError();
 }
 

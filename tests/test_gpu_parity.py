@@ -157,3 +157,28 @@ def test_mixed_precision_against_oracle(L, N, J_min, seed):
     e_rt = rel(fr, f)
     print(f"  synthesis rel. error {e_syn:.1e}, round trip {e_rt:.1e}", flush=True)
     assert e_syn < MIXED_TOL and e_rt < MIXED_TOL
+
+
+def test_blocked_alpha_scales_against_oracle():
+    # L = 600: the coarse scales (L_j <= 57) take the blocked alpha transforms; analysis rows of
+    # every scale and the synthesis of arbitrary samples on sampled m columns against the oracle
+    L, N, J_min = 600, 2, 0
+    print(f"blocked alpha scales L={L} N={N}", flush=True)
+    lam = 2.0
+    f = random_flm(L, 12)
+    rows = [0, 299, L - 1]
+    W, _ = s2dw.analysis(dev(f), L, N, lam, J_min, scaling=False)
+    got = host(W[:, :, rows, :])
+    psi = tables.wavelets(L, N, lam, J_min)
+    ref = oracle.analysis(f, L, N, lam, J_min, betas=oracle.mw_betas(L)[rows], psi=psi)
+    for j in range(ref.shape[0]):
+        assert rel(got[j], ref[j]) < TOL, (j, rel(got[j], ref[j]))
+    S = ref.shape[0]
+    Wr = random_wavelet_samples(S, 2 * N - 1, L, 2 * L - 1, 13)
+    fs = host(s2dw.synthesis(dev(Wr), None, L, N, lam, J_min))
+    Gt = oracle.alpha_gamma_rules_mw(Wr, L, N)  # the alpha and gamma rules once, then beta per column
+    for m in [0, 7, 450]:
+        wig = oracle.beta_wigner_mw(Gt, L, N, (m, m))
+        fr = oracle.synthesis_from_wigner(wig, None, L, N, lam, J_min, psi=psi)
+        idx = [el * el + el + m for el in range(m, L)]
+        assert rel(fs[idx], fr[idx]) < TOL, (m, rel(fs[idx], fr[idx]))
