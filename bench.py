@@ -82,12 +82,13 @@ def cpu_baseline(L, N, lam, J_min, budget_rows=None, budget_cols=None):
 
 
 def stage_units(kappa, L, N, T):
-    """Algorithmic work of one launch of each stage, averaged over the launches of a step.
+    """Algorithmic work of each stage per step (one map), summed over the scales.
 
     Wigner stages (one launch per direction): 5 FLOP per term of the l-sum / m'-contraction
     over the m >= 0, m' >= 0 quarter (1 multiply for Delta Delta, 2 FMA for the complex
-    product).  Bluestein and gamma stages (one launch per scale j): bytes of the arrays the
-    stage must read and write, T = 2L - 1, G = 2N - 1, Nh = ceil(N/2), Lj = band-limit:
+    product).  Bluestein and gamma stages (one launch per scale j, the coarse scales of the
+    synthesis beta stage in one shared launch): bytes of the arrays the stage must read and
+    write per scale, T = 2L - 1, G = 2N - 1, Nh = ceil(N/2), Lj = band-limit:
       beta_fwd  U quarter 16 N Lj^2 in,      Ub 16 N Lj L out
       alpha_fwd Ub 16 N Lj L in,             Y 16 Nh L T out
       gamma_fwd Y 16 Nh L T in,              W 8 G L T out
@@ -110,14 +111,18 @@ def stage_units(kappa, L, N, T):
         "alpha_adj": [16 * Nh * L * Tg + 16 * N * Lj * L for Lj in Ljs],
         "beta_adj": [16 * N * Lj * L + 32 * Nh * Lj * Lj for Lj in Ljs],
     }
-    units = {k: ("hbm", sum(v) / len(v)) for k, v in per.items() if v}
+    units = {k: ("hbm", float(sum(v))) for k, v in per.items() if v}
     units["wigner_fwd"] = ("alu", 5.0 * T)
     units["wigner_adj"] = ("alu", 5.0 * T)
     return units
 
 
 def roofline(stage, ps, units):
-    kind, per_launch = units.get(stage, ("hbm", 0.0))
+    """Achieved rate of a stage: its algorithmic work per step (all scales; several scales
+    may share a launch) over its device time per step, i.e. the work of an average launch
+    over the average launch duration."""
+    kind, per_step = units.get(stage, ("hbm", 0.0))
+    per_launch = per_step / ps["launches_per_step"]
     sec = ps["ms_per_launch"] * 1e-3
     if kind == "alu":
         achieved = per_launch / sec / 1e12

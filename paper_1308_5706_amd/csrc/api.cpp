@@ -46,6 +46,12 @@ struct Plan {
     std::vector<int> PE;
     std::vector<double2 *> hE;
     std::vector<float2 *> hEf;
+    // the coarse scales j >= mj0 of the synthesis beta stage run in one launch (equiangular
+    // full grid): their G arrays sit at goff[j] in the beta-stage workspace; mtab / mtabf
+    // describe them to the kernel (mns scales, mnwg workgroups per map)
+    int mj0 = -1, mns = 0, mnwg = 0;
+    size_t goff[kMaxScales] = {};
+    BetaAdjScale *mtab = nullptr, *mtabf = nullptr;
     size_t woff[kMaxScales + 1] = {};           // element offset of scale j in the W of one map
     // chirp tables of one grid band-limit (length T = 2Lg - 1) and the spectrum of the first
     // synthesis beta convolution (transform size PD)
@@ -603,6 +609,31 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
         if (!upload(P, P.hA[j], ha) || !upload(P, P.hB[j], hb) || !upload(P, P.hC[j], hc) || !upload(P, P.hD2[j], hd2))
             return S2DW_E_NOMEM;
     }
+    if (grid == S2DW_GRID_MW && kind == kWavelet) {
+        // coarse scales (at most 256 column pairs each) at the end of the scale list, as many
+        // as the beta-stage workspace holds side by side (sum of their Lj <= the largest Lj)
+        int maxL = 0;
+        for (int j = 0; j < t.S; ++j) maxL = std::max(maxL, P.sc.Lj[j]);
+        int j0 = t.S, sumL = 0;
+        while (j0 > 0 && P.K * P.sc.Lj[j0 - 1] <= 256 && sumL + P.sc.Lj[j0 - 1] <= maxL) sumL += P.sc.Lj[--j0];
+        std::vector<BetaAdjScale> tab;
+        size_t go = 0;
+        int nwg = 0;
+        for (int j = j0; j < t.S; ++j) {
+            const int Lj = P.sc.Lj[j];
+            if (Lj == 0) continue;
+            P.goff[j] = go;
+            tab.push_back(BetaAdjScale{nwg, Lj, (long long)go, (long long)P.sc.off[j], (const void *)P.hD2[j]});
+            go += (size_t)t.N * Lj * L;
+            nwg += P.K * Lj;
+        }
+        if (tab.size() >= 2) {
+            if (!upload(P, P.mtab, tab)) return S2DW_E_NOMEM;
+            P.mj0 = j0;
+            P.mns = (int)tab.size();
+            P.mnwg = nwg;
+        }
+    }
     for (int Psz : sizes) {
         if (P.twP.count(Psz)) continue;
         std::vector<double2> tw(Psz);
@@ -665,6 +696,13 @@ int ensure_f32(Plan &P) {
         if (ok && P.hE[j]) ok = f32_copy(P, P.hEf[j], P.hE[j], P.PE[j]);
         if (ok && P.hBb[j])
             ok = f32_copy(P, P.hBbf[j], P.hBb[j], P.PBb[j]) && f32_copy(P, P.hCbf[j], P.hCb[j], P.PBb[j]);
+    }
+    if (ok && P.mj0 >= 0) {
+        std::vector<BetaAdjScale> tab(P.mns);
+        ok = hipMemcpy(tab.data(), P.mtab, sizeof(BetaAdjScale) * P.mns, hipMemcpyDeviceToHost) == hipSuccess;
+        for (int i = 0, j = P.mj0; ok && j < P.S; ++j)
+            if (P.sc.Lj[j] > 0) tab[i++].hh2 = P.hD2f[j];
+        ok = ok && upload(P, P.mtabf, tab);
     }
     for (auto &kv : P.twP) {
         if (!ok) break;
@@ -917,10 +955,12 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
             if (cx) S2DW_CHECK_HIP(launch_gamma_adj_cx(g, maps / 2, st));
             else S2DW_CHECK_HIP(launch_gamma_adj(g, maps, st));
         }
+        const bool merged = P.mj0 >= 0 && j >= P.mj0;  // synthesis beta stage in the coarse-scale launch
         StageArgs c{};
         c.f32 = f32;
         c.in = w.Y;
-        c.out = w.Ub;
+        c.out = !merged ? (void *)w.Ub
+                        : (f32 ? (void *)((float2 *)w.Ub + P.goff[j]) : (void *)(w.Ub + P.goff[j]));
         c.s_in = P.s_Y;
         c.s_out = P.s_Ub;
         c.hh = f32 ? (const void *)P.hCf[j] : P.hC[j];
@@ -947,6 +987,7 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
             Stage sg("alpha_adj", st);
             S2DW_CHECK_HIP(launch_alpha_adj_fft(c, P.PB[j], maps, st));
         }
+        if (merged) continue;
         StageArgs v = c;
         v.in = w.Ub;
         v.s_in = P.s_Ub;
@@ -971,6 +1012,28 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
             Stage sg("beta_adj", st);
             S2DW_CHECK_HIP(launch_beta_adj_fft(v, gtab.PD, maps, st));
         }
+    }
+    if (P.mj0 >= 0) {
+        const Plan::GridTab &gtab = P.gt[L];
+        StageArgs v{};
+        v.f32 = f32;
+        v.in = w.Ub;
+        v.out = w.U;
+        v.s_in = P.s_Ub;
+        v.s_out = P.s_U;
+        v.csq = f32 ? (const void *)gtab.csqf : gtab.csq;
+        v.cpp = f32 ? (const void *)gtab.cppf : gtab.cpp;
+        v.hh = f32 ? (const void *)gtab.hD1f : gtab.hD1;
+        v.tw = f32 ? (const void *)P.twPf[gtab.PD] : P.twP[gtab.PD];
+        v.L = L;
+        v.nb = L;
+        v.N = N;
+        v.Nh = P.Nh;
+        v.K = P.K;
+        for (int k = 0; k < P.K; ++k) v.nk[k] = P.ht.nk[k];
+        v.eta_imag = P.ht.eta_imag ? 1 : 0;
+        Stage sg("beta_adj", st);
+        S2DW_CHECK_HIP(launch_beta_adj_multi(v, f32 ? P.mtabf : P.mtab, P.mns, P.mnwg, gtab.PD, maps, st));
     }
     WigAdjArgs a{};
     a.pq = P.pq;

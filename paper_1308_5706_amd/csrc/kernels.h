@@ -7,7 +7,10 @@ namespace s2dw {
 
 constexpr int kAdjWaves = 8;                 // waves per synthesis Wigner workgroup
 constexpr int kAdjThreads = kAdjWaves * 64;
-constexpr int kAdjWin = 8;                   // l-window reduced in LDS across the workgroup (fixed order)
+#ifndef S2DW_ADJ_WIN
+#define S2DW_ADJ_WIN 16
+#endif
+constexpr int kAdjWin = S2DW_ADJ_WIN;        // l-window reduced in LDS across the workgroup (fixed order)
 
 struct WigFwdArgs {
     const double2 *fpad;   // [L][Lp]   f_lm for m <= l (0 elsewhere)
@@ -82,6 +85,15 @@ hipError_t launch_alpha_fwd_blk(const StageArgs &a, int P, int maps, hipStream_t
 hipError_t launch_alpha_adj_blk(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t st);
+// One scale of a multi-scale synthesis beta launch: its first workgroup, band-limit, the
+// offsets (complex elements) of its G and V in the stage arrays, and its w(q) spectrum.
+struct BetaAdjScale {
+    int first, Lj;
+    long long in_off, out_off;
+    const void *hh2;
+};
+hipError_t launch_beta_adj_multi(const StageArgs &a, const BetaAdjScale *tab, int ns, int nwg, int P, int maps,
+                                 hipStream_t st);
 
 struct GammaArgs {
     const void *win;       // W read (synthesis): double, or float if f32

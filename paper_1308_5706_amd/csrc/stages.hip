@@ -518,13 +518,15 @@ __device__ __forceinline__ void fold_pq(C *buf, int tid, int Lj, int m, int n, i
 // (2/(1-q^2) for even q, +-i pi/2 for q = +-1, else 0): the exact beta integral of the
 // interpolant against e^{-i m' beta}; (3) the fold over +-m' and the even/odd-l
 // combinations P, Q of the two n columns (see the synthesis Wigner kernel).
+// Column pair col = k Lj + m of a scale of band-limit Lj; in / out: the scale's G and V of
+// the map, hh2: the scale's w(q) spectrum.
 template <class C, int P>
-__global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const StageArgs a) {
-    __shared__ C buf[fft::padded(P)];
+__device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int col, int Lj, const C *in, C *out,
+                                              const C *hh2) {
     constexpr int NT = P / kRM;
     const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L, T = 2 * L - 1, N = a.N;
-    const int k = blockIdx.x / Lj, m = blockIdx.x - (blockIdx.x / Lj) * Lj;
+    const int L = a.L, T = 2 * L - 1, N = a.N;
+    const int k = col / Lj, m = col - (col / Lj) * Lj;
     int n = 0;  // a.nk[k] without a dynamically indexed copy of the argument block
 #pragma unroll
     for (int kk = 0; kk < kMaxK; ++kk)
@@ -534,11 +536,11 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
     const int Nk = 2 * Lj - 1;
     const C *__restrict__ csq = (const C *)a.csq;
     const C *__restrict__ cpp = (const C *)a.cpp;
-    C *__restrict__ Po = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
-    C *__restrict__ Qo = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
+    C *__restrict__ Po = out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
+    C *__restrict__ Qo = out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
-        const C *__restrict__ Gc = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)ni * Lj + m) * L;
+        const C *__restrict__ Gc = in + ((size_t)ni * Lj + m) * L;
         auto in1 = [&](int i, int = 0) {
             if (i >= T) return zero2<C>();
             C v = i < L ? Gc[i] : Gc[2 * L - 2 - i];
@@ -563,17 +565,38 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const 
                     else Qo[q - Lj] = v;
                 }
             };
-            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh2, in2, st2);
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, hh2, in2, st2);
         } else {
             const int sh = c * Nk;
             auto st2 = [&](int i, C v, int = 0) {
                 const int q = i - (T - 1);
                 if (q >= 0 && q < Nk) buf[pad(sh + q)] = v;
             };
-            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh2, in2, st2);
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, hh2, in2, st2);
         }
     }
     fold_pq<C, NT>(buf, tid, Lj, m, n, ncol, odd, a.eta_imag ? 1 : 0, Po, Qo);
+}
+
+template <class C, int P>
+__global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const StageArgs a) {
+    __shared__ C buf[fft::padded(P)];
+    beta_adj_body<C, P>(a, buf, blockIdx.x, a.Lj, (const C *)a.in + blockIdx.y * a.s_in,
+                        (C *)a.out + blockIdx.y * a.s_out, (const C *)a.hh2);
+}
+
+// The coarse scales of a map in one launch (each alone would fill only a few workgroups):
+// workgroups [tab[s].first, tab[s + 1].first) take scale s.
+template <class C, int P>
+__global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_multi_kernel(const StageArgs a,
+                                                                              const BetaAdjScale *tab, int ns) {
+    __shared__ C buf[fft::padded(P)];
+    int s = 0;
+    for (int i = 1; i < ns; ++i)
+        if ((int)blockIdx.x >= tab[i].first) s = i;
+    const BetaAdjScale e = tab[s];
+    beta_adj_body<C, P>(a, buf, blockIdx.x - e.first, e.Lj, (const C *)a.in + blockIdx.y * a.s_in + e.in_off,
+                        (C *)a.out + blockIdx.y * a.s_out + e.out_off, (const C *)e.hh2);
 }
 
 // Driscoll-Healy grid (Eq. 17-18 and 40): theta_t = pi (2t+1)/Tb, t < nb, Tb = 4L, nb = 2L,
@@ -681,6 +704,29 @@ hipError_t launch_alpha_adj_blk(const StageArgs &a, int P, int maps, hipStream_t
 
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
     S2DW_P_SWITCH(P, beta_adj_fft_kernel, a.K * a.Lj, a)
+    return hipGetLastError();
+}
+
+hipError_t launch_beta_adj_multi(const StageArgs &a, const BetaAdjScale *tab, int ns, int nwg, int P, int maps,
+                                 hipStream_t st) {
+#define S2DW_MULTI_CASE(C, PV)                                                                                \
+    case PV:                                                                                                  \
+        hipLaunchKernelGGL((beta_adj_multi_kernel<C, PV>), dim3(nwg, maps), dim3(PV / kRM), 0, st, a, tab, ns); \
+        break;
+#define S2DW_MULTI_SWITCH(C)                                                                    \
+    switch (P) {                                                                                \
+        S2DW_MULTI_CASE(C, 32) S2DW_MULTI_CASE(C, 64) S2DW_MULTI_CASE(C, 128)                    \
+        S2DW_MULTI_CASE(C, 256) S2DW_MULTI_CASE(C, 512) S2DW_MULTI_CASE(C, 1024)                 \
+        S2DW_MULTI_CASE(C, 2048) S2DW_MULTI_CASE(C, 4096) S2DW_MULTI_CASE(C, 8192)               \
+        default: return hipErrorInvalidValue;                                                   \
+    }
+    if (a.f32) {
+        S2DW_MULTI_SWITCH(float2)
+    } else {
+        S2DW_MULTI_SWITCH(double2)
+    }
+#undef S2DW_MULTI_SWITCH
+#undef S2DW_MULTI_CASE
     return hipGetLastError();
 }
 
