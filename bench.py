@@ -139,107 +139,9 @@ def roofline(stage, ps, units):
     return r
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--L", type=int, default=1024)
-    ap.add_argument("--N", type=int, default=8)
-    ap.add_argument("--lam", type=float, default=2.0)
-    ap.add_argument("--jmin", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
-                    help="mixed: W in FP32 and the FFT stages / m'-sum in FP32 (Delta recursion and l-sum FP64)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="let the library's autotuner pick the Wigner tile shape before timing")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
-                    help="only run a plain device-to-device copy of this many GiB (to scale HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the library runs a "
-              "transform on one GPU; maps and requests are independent, so several GPUs would each take "
-              "their own)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    from paper_1308_5706_amd import s2dw
-    from paper_1308_5706_amd.inputs import random_flm
-
-    if args.copy_calibration > 0:
-        n = int(args.copy_calibration * (1 << 30)) // 8
-        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
-        y = torch.empty_like(x)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": n * 8, "copies": 3}), flush=True)
-        return
-
-    L, N, lam, J_min = args.L, args.N, args.lam, args.jmin
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    S = s2dw.num_scales(L, lam, J_min)
-    f_host = random_flm(L, 0)
-    f = torch.as_tensor(f_host).to(dev)
-    prec = args.precision
-    W = torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=torch.float64 if prec == "fp64" else torch.float32,
-                    device=dev)
-    fr = torch.empty(L * L, dtype=torch.complex128, device=dev)
-    print(f"# workload L={L} N={N} lambda={lam} J_min={J_min} scales={S}", file=sys.stderr, flush=True)
-
-    tuned = None
-    if args.autotune:
-        tuned = s2dw.autotune(L, N, lam, J_min, count=1, precision=prec)
-        print(f"# autotune: {tuned[0]} m' slots per wave, {tuned[1]} maps per chunk", file=sys.stderr, flush=True)
-
-    def step():
-        _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=W, precision=prec)
-        s2dw.synthesis(W, Wp, L, N, lam, J_min, out=fr, precision=prec)
-
-    for i in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        print(f"# warmup step {i} done", file=sys.stderr, flush=True)
-    rt_err = float((fr - f).abs().max().item() / f.abs().max().item())
-
-    s2dw.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages = s2dw.profile_read()
-    s2dw.profile(False)
-    print(f"# timed {args.steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
-
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    coeffs = S * (2 * N - 1) * L * (2 * L - 1)
-    value = coeffs / (ms_step * 1e-3)
-
-    # roofline of the kernel with the largest device time per step (one stage = one kernel
-    # launch per scale, or per direction for the Wigner stages), timed with HIP events
-    kappa, _, _ = s2dw.wavelet_tables(L, N, lam, J_min)
-    T = wigner_terms(kappa, N)
-    per_stage = {k: {"ms_per_launch": v[0] / v[1], "launches_per_step": v[1] / args.steps,
-                     "ms_per_step": v[0] / args.steps} for k, v in stages.items()}
-    units = stage_units(kappa, L, N, T)
-    dom = max(per_stage, key=lambda k: per_stage[k]["ms_per_step"])
-    roof = roofline(dom, per_stage[dom], units)
-    traffic = None
-    try:
-        from paper_1308_5706_amd import profiling
-        st = profiling.read_stage_traffic(f"round_trip_L{L}_N{N}")
-        if st and dom in st:
-            traffic = st[dom]["bytes_per_dispatch"]
-    except Exception as e:  # a missing or unreadable summary leaves traffic unknown
-        print(f"# traffic summary not used: {e}", file=sys.stderr)
-    roof["traffic"] = traffic
-    stage_roofs = {k: roofline(k, v, units) for k, v in per_stage.items() if k in units}
-
+def extra_legs(args, s2dw, torch, dev, f, W, fr, L, N, lam, J_min, S, prec):
+    """Features measured beside the headline round trip (outside its timed region): steering,
+    the multiresolution layout, the Driscoll-Healy grid and a complex signal."""
     # steering (Eq. 10) of the step's W to Q off-grid angles: a post-step outside the timed
     # round trip, one launch per call; bytes = W read (S G L T) + steered planes written (S Q L T)
     Q, reps = 8, 10
@@ -328,6 +230,115 @@ def main():
                       "round_trip_rel_err": float((frm - fc).abs().max().item() / fc.abs().max().item())}
     del Wc
     print(f"# complex-signal round trip {ms_cx:.3f} ms/step", file=sys.stderr, flush=True)
+    return {"steer": steer, "multires": multires, "driscoll_healy": dh_grid, "complex_signal": complex_signal}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=1024)
+    ap.add_argument("--N", type=int, default=8)
+    ap.add_argument("--lam", type=float, default=2.0)
+    ap.add_argument("--jmin", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="mixed: W in FP32 and the FFT stages / m'-sum in FP32 (Delta recursion and l-sum FP64)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner pick the Wigner tile shape before timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline round trip (no steering / multiresolution / Driscoll-Healy / "
+                         "complex-signal legs), e.g. under a profiler")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device-to-device copy of this many GiB (to scale HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the library runs a "
+              "transform on one GPU; maps and requests are independent, so several GPUs would each take "
+              "their own)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1308_5706_amd import s2dw
+    from paper_1308_5706_amd.inputs import random_flm
+
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "copies": 3}), flush=True)
+        return
+
+    L, N, lam, J_min = args.L, args.N, args.lam, args.jmin
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S = s2dw.num_scales(L, lam, J_min)
+    f_host = random_flm(L, 0)
+    f = torch.as_tensor(f_host).to(dev)
+    prec = args.precision
+    W = torch.empty((S, 2 * N - 1, L, 2 * L - 1), dtype=torch.float64 if prec == "fp64" else torch.float32,
+                    device=dev)
+    fr = torch.empty(L * L, dtype=torch.complex128, device=dev)
+    print(f"# workload L={L} N={N} lambda={lam} J_min={J_min} scales={S}", file=sys.stderr, flush=True)
+
+    tuned = None
+    if args.autotune:
+        tuned = s2dw.autotune(L, N, lam, J_min, count=1, precision=prec)
+        print(f"# autotune: {tuned[0]} m' slots per wave, {tuned[1]} maps per chunk", file=sys.stderr, flush=True)
+
+    def step():
+        _, Wp = s2dw.analysis(f, L, N, lam, J_min, out=W, precision=prec)
+        s2dw.synthesis(W, Wp, L, N, lam, J_min, out=fr, precision=prec)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"# warmup step {i} done", file=sys.stderr, flush=True)
+    rt_err = float((fr - f).abs().max().item() / f.abs().max().item())
+
+    s2dw.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = s2dw.profile_read()
+    s2dw.profile(False)
+    print(f"# timed {args.steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    coeffs = S * (2 * N - 1) * L * (2 * L - 1)
+    value = coeffs / (ms_step * 1e-3)
+
+    # roofline of the kernel with the largest device time per step (one stage = one kernel
+    # launch per scale, or per direction for the Wigner stages), timed with HIP events
+    kappa, _, _ = s2dw.wavelet_tables(L, N, lam, J_min)
+    T = wigner_terms(kappa, N)
+    per_stage = {k: {"ms_per_launch": v[0] / v[1], "launches_per_step": v[1] / args.steps,
+                     "ms_per_step": v[0] / args.steps} for k, v in stages.items()}
+    units = stage_units(kappa, L, N, T)
+    dom = max(per_stage, key=lambda k: per_stage[k]["ms_per_step"])
+    roof = roofline(dom, per_stage[dom], units)
+    traffic = None
+    try:
+        from paper_1308_5706_amd import profiling
+        st = profiling.read_stage_traffic(f"round_trip_L{L}_N{N}")
+        if st and dom in st:
+            traffic = st[dom]["bytes_per_dispatch"]
+    except Exception as e:  # a missing or unreadable summary leaves traffic unknown
+        print(f"# traffic summary not used: {e}", file=sys.stderr)
+    roof["traffic"] = traffic
+    stage_roofs = {k: roofline(k, v, units) for k, v in per_stage.items() if k in units}
+
+    extras = {} if args.no_extras else extra_legs(args, s2dw, torch, dev, f, W, fr, L, N, lam, J_min, S, prec)
+    W = None
 
     out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8; p50/p99 mixed-L",
            "value": value, "unit": "SO(3) coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -341,11 +352,8 @@ def main():
            "roofline": roof,
            "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in per_stage.items()},
            "stages_frac": {k: round(v["frac"], 4) for k, v in stage_roofs.items()},
-           "wigner_terms_per_direction": T,
-           "steer": steer,
-           "multires": multires,
-           "driscoll_healy": dh_grid,
-           "complex_signal": complex_signal}
+           "wigner_terms_per_direction": T}
+    out.update(extras)
     if not args.no_cpu_baseline:
         print("# cpu baseline sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(L, N, lam, J_min)

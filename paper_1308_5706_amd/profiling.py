@@ -31,17 +31,17 @@ ROOT = os.path.dirname(HERE)
 
 # library stage name -> substring of the kernel symbol (demangled) that implements it
 STAGE_KERNELS = {
-    "wigner_fwd": "wig_fwd_kernel",
-    "wigner_adj": "wig_adj_kernel",
-    "beta_fwd": "beta_fwd_fft_kernel",
-    "alpha_fwd": "alpha_fwd_fft_kernel",
-    "gamma_fwd": "gamma_fwd_kernel",
-    "gamma_adj": "gamma_adj_kernel",
-    "alpha_adj": "alpha_adj_fft_kernel",
-    "beta_adj": "beta_adj_fft_kernel",
-    "syn_final": "syn_final_kernel",
-    "pad": "pad_flm_kernel",
-    "scaling": "scaling_kernel",
+    "wigner_fwd": ("wig_fwd_kernel",),
+    "wigner_adj": ("wig_adj_kernel",),
+    "beta_fwd": ("beta_fwd_fft_kernel",),
+    "alpha_fwd": ("alpha_fwd_fft_kernel", "alpha_fwd_blk_kernel"),
+    "gamma_fwd": ("gamma_fwd_kernel",),
+    "gamma_adj": ("gamma_adj_kernel",),
+    "alpha_adj": ("alpha_adj_fft_kernel", "alpha_adj_blk_kernel"),
+    "beta_adj": ("beta_adj_fft_kernel", "beta_adj_multi_kernel"),
+    "syn_final": ("syn_final_kernel",),
+    "pad": ("pad_flm_kernel",),
+    "scaling": ("scaling_kernel",),
 }
 
 
@@ -57,8 +57,8 @@ def kernel_sources_hash() -> str:
 
 
 def stage_of(kernel_name: str):
-    for st, sub in STAGE_KERNELS.items():
-        if sub in kernel_name:
+    for st, subs in STAGE_KERNELS.items():
+        if any(sub in kernel_name for sub in subs):
             return st
     return None
 
@@ -145,6 +145,17 @@ def write_profiles(d: str, name: str, commands: str, copy_bytes: int, out_dir: s
         lines.append(f"| `{k[:90]}` | {v['dispatches']} | {v['total_ns'] / 1e6:.3f} | {v['avg_ns'] / 1e3:.2f} | "
                      f"{stage_of(k) or ''} | {'' if fr is None else f'{fr / 1e6:.1f}'} | "
                      f"{'' if wr is None else f'{wr / 1e6:.1f}'} |")
+    # per stage (a stage may use several kernels, e.g. the blocked alpha transforms of the
+    # coarse scales): the average launch duration the benchmark's live timing reports
+    per_stage = defaultdict(lambda: [0, 0.0])
+    for k, v in kernels.items():
+        st = stage_of(k)
+        if st:
+            per_stage[st][0] += v["dispatches"]
+            per_stage[st][1] += v["total_ns"]
+    lines += ["", "| stage | dispatches | total ms | avg us per launch |", "|---|---:|---:|---:|"]
+    for st, (n, tot) in sorted(per_stage.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| {st} | {n} | {tot / 1e6:.3f} | {tot / max(n, 1) / 1e3:.2f} |")
     lines += ["", f"HBM counters scaled by a {copy_bytes / 2**30:.0f} GiB device copy: FETCH_SIZE x "
               f"{cal['FETCH_SIZE'] / 1024:.4f}, WRITE_SIZE x {cal['WRITE_SIZE'] / 1024:.4f} (KiB counted -> KiB moved).", ""]
     with open(os.path.join(out_dir, f"{name}_kernels.md"), "w") as f:
