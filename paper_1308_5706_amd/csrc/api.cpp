@@ -233,8 +233,51 @@ bool build_segments(const HostTables &t, SegTab &seg) {
     return true;
 }
 
-// Tile lists for the Wigner kernels: (m0, m'0) pairs, heaviest first; tiles holding a
-// start value below 2^-1000 go to the extended-exponent list.
+// Dispatch order of a tile list for L2 reuse.  Workgroups are handed to the 8 XCDs
+// round-robin, so list position i runs on XCD (phase + i) mod 8.  The tiles of one m' group
+// read the same m' rows of the wave-uniform tables (kappa sigma Delta, u, v) at every l;
+// keeping a group on one XCD lets those rows come from that XCD's L2.  Groups go to the XCD
+// with the least work so far (heaviest group first), each as a run of its tiles, heaviest
+// first; positions whose XCD has no tile left take one from the fullest XCD.
+std::vector<int2> xcd_order(const std::vector<std::pair<long, int2>> &tiles, int phase) {
+    std::map<int, std::vector<std::pair<long, int2>>> groups;  // by m'0
+    for (const auto &e : tiles) groups[e.second.y].push_back(e);
+    std::vector<std::pair<long, int>> gw;
+    for (auto &g : groups) {
+        std::stable_sort(g.second.begin(), g.second.end(),
+                         [](const std::pair<long, int2> &u, const std::pair<long, int2> &v) { return u.first > v.first; });
+        long w = 0;
+        for (const auto &e : g.second) w += e.first;
+        gw.push_back({w, g.first});
+    }
+    std::stable_sort(gw.begin(), gw.end(),
+                     [](const std::pair<long, int> &u, const std::pair<long, int> &v) { return u.first > v.first; });
+    std::vector<std::vector<int2>> bins(8);
+    long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (const auto &g : gw) {
+        const int x = (int)(std::min_element(load, load + 8) - load);
+        load[x] += g.first;
+        for (const auto &e : groups[g.second]) bins[x].push_back(e.second);
+    }
+    std::vector<int2> out;
+    size_t pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    while (out.size() < tiles.size()) {
+        int x = (int)((phase + out.size()) % 8);
+        if (pos[x] >= bins[x].size()) {
+            size_t best = 0;
+            for (int y = 0; y < 8; ++y)
+                if (bins[y].size() - pos[y] > best) {
+                    best = bins[y].size() - pos[y];
+                    x = y;
+                }
+        }
+        out.push_back(bins[x][pos[x]++]);
+    }
+    return out;
+}
+
+// Tile lists for the Wigner kernels: (m0, m'0) pairs in XCD-aware order (above); tiles holding
+// a start value below 2^-1000 go to the extended-exponent list, launched after the others.
 void build_tiles(const Plan &pl, const std::vector<int> &seede, int Lp, int mgroup, std::vector<int2> &plain,
                  std::vector<int2> &xn) {
     std::vector<std::pair<long, int2>> a, b;
@@ -251,13 +294,8 @@ void build_tiles(const Plan &pl, const std::vector<int> &seede, int Lp, int mgro
                     }
             (x ? b : a).push_back({work, make_int2(m0, p0)});
         }
-    auto cmp = [](const std::pair<long, int2> &u, const std::pair<long, int2> &v) { return u.first > v.first; };
-    std::stable_sort(a.begin(), a.end(), cmp);
-    std::stable_sort(b.begin(), b.end(), cmp);
-    plain.clear();
-    xn.clear();
-    for (auto &e : a) plain.push_back(e.second);
-    for (auto &e : b) xn.push_back(e.second);
+    plain = xcd_order(a, 0);
+    xn = xcd_order(b, (int)(a.size() % 8));
 }
 
 // Selects the Wigner tile shape: R m' slots per wave (the analysis workgroup covers 4R
