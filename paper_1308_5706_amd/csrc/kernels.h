@@ -7,10 +7,6 @@ namespace s2dw {
 
 constexpr int kAdjWaves = 8;                 // waves per synthesis Wigner workgroup
 constexpr int kAdjThreads = kAdjWaves * 64;
-#ifndef S2DW_ADJ_WIN
-#define S2DW_ADJ_WIN 16
-#endif
-constexpr int kAdjWin = S2DW_ADJ_WIN;        // l-window reduced in LDS across the workgroup (fixed order)
 
 struct WigFwdArgs {
     const double2 *fpad;   // [L][Lp]   f_lm for m <= l (0 elsewhere)
