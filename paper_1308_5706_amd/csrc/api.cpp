@@ -62,7 +62,8 @@ struct Plan {
     };
     std::map<int, GridTab> gt;
     // device tables
-    double2 *pq = nullptr, *uv = nullptr;
+    double *pq = nullptr, *uv = nullptr;        // rescaled recurrence factors pt_l(m), ut_l(m')
+    double *gsc = nullptr;                      // [L][Lp] g_l(m): D = Delta / (g_l(m) h_l(m'))
     double2 *tgf = nullptr, *tga = nullptr;     // gamma pass factors [2N-1][Nh]
     double *kb2 = nullptr, *seed = nullptr, *seedm = nullptr, *phi = nullptr, *fac = nullptr;
     int *seede = nullptr;
@@ -488,9 +489,11 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
             for (int s = 0; s < 2; ++s) {
                 if (js[s] < 0) continue;
                 const double kap = t.kappa[(size_t)js[s] * L + l];
+                // h_l(m') of the rescaled recurrence folded in (the g_l(m) side goes with f_lm)
+                const double hh = dt.h[(size_t)mp * L + l];
                 for (int k = 0; k < K; ++k)
                     kb2[(((size_t)mp * L + l) * 2 + s) * K + k] =
-                        kap * t.sig[(size_t)l * K + k] * ncol[((size_t)mp * L + l) * K + k];
+                        kap * t.sig[(size_t)l * K + k] * ncol[((size_t)mp * L + l) * K + k] * hh;
             }
         }
     Plan &P = *pl;
@@ -528,17 +531,14 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
     for (int l = 0; l < L; ++l)
         fac[l] = kind == kShtForward ? std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) / (2.0 * M_PI)
                                      : (2.0 * l + 1.0) / (8.0 * M_PI * M_PI);
-    std::vector<double2> pqv((size_t)L * Lp), uvv((size_t)Lp * L);
-    memcpy(pqv.data(), dt.pq.data(), pqv.size() * sizeof(double2));
-    memcpy(uvv.data(), dt.uv.data(), uvv.size() * sizeof(double2));
     P.n_kb2 = kb2.size();
     P.n_tg = tgf.size();
-    bool ok = upload(P, P.pq, pqv) && upload(P, P.uv, uvv) && upload(P, P.kb2, kb2) && upload(P, P.seed, dt.seed) &&
-              upload(P, P.seedm, dt.seedm) && upload(P, P.seede, dt.seede) && upload(P, P.tgf, tgf) &&
-              upload(P, P.tga, tga) && upload(P, P.fac, fac) && upload(P, P.phi, t.phi);
+    bool ok = upload(P, P.pq, dt.pt) && upload(P, P.uv, dt.ut) && upload(P, P.gsc, dt.g) && upload(P, P.kb2, kb2) &&
+              upload(P, P.seed, dt.seedt) && upload(P, P.seedm, dt.seedtm) && upload(P, P.seede, dt.seedte) &&
+              upload(P, P.tgf, tgf) && upload(P, P.tga, tga) && upload(P, P.fac, fac) && upload(P, P.phi, t.phi);
     if (!ok) return S2DW_E_NOMEM;
     // tiles
-    P.seede_h = dt.seede;
+    P.seede_h = dt.seedte;
     int rc_t = set_slots(P, wig_slots(K));
     if (rc_t != S2DW_OK) return rc_t;
     // Bluestein chirp spectra per scale, for the scale's grid band-limit Lg (T = 2Lg - 1;
@@ -860,8 +860,8 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
     const int L = P.L;
     {
         Stage sg("pad", st);
-        if (cx) S2DW_CHECK_HIP(launch_pad_flm_complex(flm, w.fpad, L, P.Lp, P.s_fpad, maps / 2, st));
-        else S2DW_CHECK_HIP(launch_pad_flm(flm, w.fpad, L, P.Lp, P.s_fpad, maps, st));
+        if (cx) S2DW_CHECK_HIP(launch_pad_flm_complex(flm, P.gsc, w.fpad, L, P.Lp, P.s_fpad, maps / 2, st));
+        else S2DW_CHECK_HIP(launch_pad_flm(flm, P.gsc, w.fpad, L, P.Lp, P.s_fpad, maps, st));
     }
     WigFwdArgs a{};
     a.fpad = w.fpad;
@@ -1098,8 +1098,8 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
     }
     {
         Stage sg("syn_final", st);
-        S2DW_CHECK_HIP(launch_syn_final(w.Fpart, P.s_F, f32, P.nblk, P.group, P.Lmax, P.fac, wphi, P.phi, flm, L,
-                                        P.Lp, maps, st));
+        S2DW_CHECK_HIP(launch_syn_final(w.Fpart, P.s_F, f32, P.nblk, P.group, P.Lmax, P.fac, P.gsc, wphi, P.phi, flm,
+                                        L, P.Lp, maps, st));
     }
     return S2DW_OK;
 }

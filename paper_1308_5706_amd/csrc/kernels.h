@@ -9,11 +9,14 @@ constexpr int kAdjWaves = 8;                 // waves per synthesis Wigner workg
 constexpr int kAdjThreads = kAdjWaves * 64;
 
 struct WigFwdArgs {
-    const double2 *fpad;   // [L][Lp]   f_lm for m <= l (0 elsewhere)
-    const double2 *pq;     // [L][Lp]   (p_l(m), q_l(m))
-    const double2 *uv;     // [Lp][L]   (u_l(m'), v_l(m'))
-    const double *kb2;     // [Lp][L][2][K]  kappa^{j(slot,l)}(l) sigma_{l,n_k} Delta^l_{m' n_k}
-    const double *seed;    // [Lp][Lp]  Delta^{max(m',m)}_{m'm}
+    // The l-recurrence runs on D_l = Delta^l_{m'm} / (g_l(m) h_l(m')) (rescaled so that its
+    // Delta^{l-1} coefficient is 1: D_{l+1} = -(ut_l(m') pt_l(m)) D_l - D_{l-1}); g goes with
+    // f_lm and h with the kb2 table.
+    const double2 *fpad;   // [L][Lp]   g_l(m) f_lm for m <= l (0 elsewhere)
+    const double *pq;      // [L][Lp]   pt_l(m)
+    const double *uv;      // [Lp][L]   ut_l(m')
+    const double *kb2;     // [Lp][L][2][K]  kappa^{j(slot,l)}(l) sigma_{l,n_k} Delta^l_{m' n_k} h_l(m')
+    const double *seed;    // [Lp][Lp]  D at l0 = max(m',m)
     const double *seedm;   // [Lp][Lp]  its mantissa (extended-exponent variant)
     const int *seede;      // [Lp][Lp]  its exponent
     const int2 *tiles;     // (m0, m'0) per workgroup
@@ -27,8 +30,8 @@ struct WigFwdArgs {
 };
 
 struct WigAdjArgs {
-    const double2 *pq;
-    const double2 *uv;
+    const double *pq;      // as in WigFwdArgs; the partial sums come out divided by g_l(m)
+    const double *uv;
     const void *kb2;       // double, or float if f32 (same layout as in WigFwdArgs)
     const double *seed;
     const double *seedm;
@@ -111,17 +114,20 @@ hipError_t launch_gamma_adj_cx(const GammaArgs &a, int cmaps, hipStream_t st);
 // --------------------------------------------------------------------------------- misc
 
 // maps: number of maps of a batch (grid z); f_lm, W^Phi_lm of map i at i L^2, workspaces at i s_*.
-hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad, int maps, hipStream_t st);
+// The padded copy carries the factor g_l(m) ([L][Lp]) of the rescaled Wigner recurrence.
+hipError_t launch_pad_flm(const double2 *flm, const double *g, double2 *fpad, int L, int Lp, size_t s_fpad, int maps,
+                          hipStream_t st);
 hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, int maps, hipStream_t st);
 // Complex signals as two real ones: cmaps complex f_lm -> real maps 2z, 2z + 1 of fpad, and
 // back: f = a + i b (+ the scaling part) from the syntheses of those maps (each L^2 at k s_fab).
-hipError_t launch_pad_flm_complex(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad, int cmaps,
-                                  hipStream_t st);
+hipError_t launch_pad_flm_complex(const double2 *flm, const double *g, double2 *fpad, int L, int Lp, size_t s_fpad,
+                                  int cmaps, hipStream_t st);
 hipError_t launch_merge_complex(const double2 *fab, size_t s_fab, const double2 *wphi, const double *phi,
                                 double2 *flm, int L, int cmaps, hipStream_t st);
+// g: the factor g_l(m) ([L][Lp]) the partial sums of the rescaled recurrence lack.
 hipError_t launch_syn_final(const void *Fpart, size_t s_F, int f32, int nblk, int group, int Lmax, const double *fac,
-                            const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, int maps,
-                            hipStream_t st);
+                            const double *g, const double2 *wphi, const double *phi, double2 *flm, int L, int Lp,
+                            int maps, hipStream_t st);
 hipError_t launch_zero_words(void *p, size_t n, hipStream_t st);
 hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t st);
 // W [maps][S][G][P] (gamma_g = g step) -> out [maps][S][Q][P] at the Q angles gam (device),

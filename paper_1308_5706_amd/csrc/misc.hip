@@ -7,17 +7,26 @@ namespace s2dw {
 // ---------------------------------------------------------------------------------- misc
 
 // Batched small kernels: map = blockIdx.z; f_lm and W^Phi_lm of map i start at i L^2.
-__global__ void pad_flm_kernel(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad) {
+// fpad = g_l(m) f_lm, m <= l: the Wigner stage's rescaled recurrence takes the factor g here.
+__global__ void pad_flm_kernel(const double2 *flm, const double *g, double2 *fpad, int L, int Lp, size_t s_fpad) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int l = blockIdx.y;
     if (m >= Lp) return;
     flm += (size_t)blockIdx.z * L * L;
     fpad += (size_t)blockIdx.z * s_fpad;
-    fpad[(size_t)l * Lp + m] = (m <= l) ? flm[(size_t)l * l + l + m] : make_double2(0.0, 0.0);
+    double2 v = make_double2(0.0, 0.0);
+    if (m <= l) {
+        const double2 f = flm[(size_t)l * l + l + m];
+        const double c = g[(size_t)l * Lp + m];
+        v = make_double2(c * f.x, c * f.y);
+    }
+    fpad[(size_t)l * Lp + m] = v;
 }
 
-hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad, int maps, hipStream_t st) {
-    hipLaunchKernelGGL(pad_flm_kernel, dim3((Lp + 255) / 256, L, maps), dim3(256), 0, st, flm, fpad, L, Lp, s_fpad);
+hipError_t launch_pad_flm(const double2 *flm, const double *g, double2 *fpad, int L, int Lp, size_t s_fpad, int maps,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(pad_flm_kernel, dim3((Lp + 255) / 256, L, maps), dim3(256), 0, st, flm, g, fpad, L, Lp,
+                       s_fpad);
     return hipGetLastError();
 }
 
@@ -25,7 +34,8 @@ hipError_t launch_pad_flm(const double2 *flm, double2 *fpad, int L, int Lp, size
 // a batch becomes real maps 2z (the real part of f on the sphere) and 2z + 1 (the imaginary
 // part), since Eq. 1 is linear in f.  Their coefficients, for 0 <= m <= l, are
 //   a_lm = (f_lm + (-1)^m conj f_{l,-m}) / 2,   b_lm = (f_lm - (-1)^m conj f_{l,-m}) / (2i).
-__global__ void pad_flm_complex_kernel(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad) {
+__global__ void pad_flm_complex_kernel(const double2 *flm, const double *g, double2 *fpad, int L, int Lp,
+                                       size_t s_fpad) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int l = blockIdx.y;
     if (m >= Lp) return;
@@ -37,17 +47,18 @@ __global__ void pad_flm_complex_kernel(const double2 *flm, double2 *fpad, int L,
         *pb = make_double2(0.0, 0.0);
         return;
     }
-    const double2 f = flm[(size_t)l * l + l + m], g = flm[(size_t)l * l + l - m];
+    const double2 f = flm[(size_t)l * l + l + m], fm = flm[(size_t)l * l + l - m];
     const double sg = (m & 1) ? -1.0 : 1.0;
-    const double cr = sg * g.x, ci = -sg * g.y;  // (-1)^m conj f_{l,-m}
-    *pa = make_double2(0.5 * (f.x + cr), 0.5 * (f.y + ci));
-    *pb = make_double2(0.5 * (f.y - ci), -0.5 * (f.x - cr));
+    const double cr = sg * fm.x, ci = -sg * fm.y;  // (-1)^m conj f_{l,-m}
+    const double c = 0.5 * g[(size_t)l * Lp + m];  // with the factor g_l(m) (see pad_flm_kernel)
+    *pa = make_double2(c * (f.x + cr), c * (f.y + ci));
+    *pb = make_double2(c * (f.y - ci), -c * (f.x - cr));
 }
 
-hipError_t launch_pad_flm_complex(const double2 *flm, double2 *fpad, int L, int Lp, size_t s_fpad, int cmaps,
-                                  hipStream_t st) {
-    hipLaunchKernelGGL(pad_flm_complex_kernel, dim3((Lp + 255) / 256, L, cmaps), dim3(256), 0, st, flm, fpad, L, Lp,
-                       s_fpad);
+hipError_t launch_pad_flm_complex(const double2 *flm, const double *g, double2 *fpad, int L, int Lp, size_t s_fpad,
+                                  int cmaps, hipStream_t st) {
+    hipLaunchKernelGGL(pad_flm_complex_kernel, dim3((Lp + 255) / 256, L, cmaps), dim3(256), 0, st, flm, g, fpad, L,
+                       Lp, s_fpad);
     return hipGetLastError();
 }
 
@@ -94,13 +105,15 @@ hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, 
     return hipGetLastError();
 }
 
-// f_lm = fac_l sum_g Fpart[g][l][m] + sqrt((2l+1)/(4 pi)) W^Phi_lm Phi_l0   (Eq. 32, 41), m >= 0;
+// f_lm = fac_l g_l(m) sum_grp Fpart[grp][l][m] + sqrt((2l+1)/(4 pi)) W^Phi_lm Phi_l0   (Eq. 32,
+// 41), m >= 0 (g_l(m): the factor the rescaled Wigner recurrence leaves out of the sums);
 // f_{l,-m} = (-1)^m conj(f_lm).
 // Fpart holds double2 (FP64 path) or float2 (mixed precision) partial sums; the final sum
 // over the m' groups and the harmonic synthesis factor are applied in FP64.
 template <class VC>
 __global__ void syn_final_kernel(const VC *Fpart, size_t s_F, int nblk, int group, int Lmax, const double *fac,
-                                 const double2 *wphi, const double *phi, double2 *flm, int L, int Lp) {
+                                 const double *gsc, const double2 *wphi, const double *phi, double2 *flm, int L,
+                                 int Lp) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int l = blockIdx.y;
     if (m > l) return;
@@ -115,8 +128,9 @@ __global__ void syn_final_kernel(const VC *Fpart, size_t s_F, int nblk, int grou
         fr += (double)v.x;
         fi += (double)v.y;
     }
-    fr *= fac[l];
-    fi *= fac[l];
+    const double cg = fac[l] * gsc[(size_t)l * Lp + m];
+    fr *= cg;
+    fi *= cg;
     if (wphi) {
         const double c = sqrt((2.0 * l + 1.0) / (4.0 * 3.14159265358979323846)) * phi[l];
         const double2 w = wphi[(size_t)l * l + l + m];
@@ -131,15 +145,15 @@ __global__ void syn_final_kernel(const VC *Fpart, size_t s_F, int nblk, int grou
 }
 
 hipError_t launch_syn_final(const void *Fpart, size_t s_F, int f32, int nblk, int group, int Lmax, const double *fac,
-                            const double2 *wphi, const double *phi, double2 *flm, int L, int Lp, int maps,
-                            hipStream_t st) {
+                            const double *g, const double2 *wphi, const double *phi, double2 *flm, int L, int Lp,
+                            int maps, hipStream_t st) {
     const dim3 grid((L + 255) / 256, L, maps);
     if (f32)
         hipLaunchKernelGGL(syn_final_kernel<float2>, grid, dim3(256), 0, st, (const float2 *)Fpart, s_F, nblk, group,
-                           Lmax, fac, wphi, phi, flm, L, Lp);
+                           Lmax, fac, g, wphi, phi, flm, L, Lp);
     else
         hipLaunchKernelGGL(syn_final_kernel<double2>, grid, dim3(256), 0, st, (const double2 *)Fpart, s_F, nblk,
-                           group, Lmax, fac, wphi, phi, flm, L, Lp);
+                           group, Lmax, fac, g, wphi, phi, flm, L, Lp);
     return hipGetLastError();
 }
 

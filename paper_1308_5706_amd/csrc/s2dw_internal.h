@@ -54,8 +54,18 @@ struct DeltaTables {
     std::vector<double> pq;      // [L][Lp][2]   per-column factors p_l(x), q_l(x)
     std::vector<double> uv;      // [Lp][L][2]   per-row factors u_l(x), v_l(x)
     std::vector<double> seed;    // [Lp][Lp]     Delta^{max(m',m)}_{m'm} (0 where it underflows)
-    std::vector<double> seedm;   // [Lp][Lp]     its mantissa in [0.5, 1) with sign
-    std::vector<int> seede;      // [Lp][Lp]     its binary exponent
+    // The same recurrence for the rescaled values D_l = Delta^l_{m'm} / (g_l(m) h_l(m')),
+    // with g_{l+1}(x) = q_l(x) g_{l-1}(x) from g_x = g_{x+1} = 1 and h_{l+1}(x) = v_l(x)
+    // h_{l-1}(x) from h_x = h_{x+1} = 1: the Delta^{l-1} coefficient becomes 1,
+    //   D_{l+1} = -(ut_l(m') pt_l(m)) D_l - D_{l-1},
+    //   pt_l(x) = p_l(x) g_l(x)/g_{l+1}(x),  ut_l(x) = u_l(x) h_l(x)/h_{l+1}(x).
+    std::vector<double> pt;      // [L][Lp]      pt_l(x)
+    std::vector<double> ut;      // [Lp][L]      ut_l(x)
+    std::vector<double> g;       // [L][Lp]      g_l(x), x <= l (0 elsewhere)
+    std::vector<double> h;       // [Lp][L]      h_l(x), x <= l (0 elsewhere)
+    std::vector<double> seedt;   // [Lp][Lp]     D at l0 = max(m',m) (0 where it underflows)
+    std::vector<double> seedtm;  // [Lp][Lp]     its mantissa in [0.5, 1) with sign
+    std::vector<int> seedte;     // [Lp][Lp]     its binary exponent
 };
 void build_delta_tables(int L, DeltaTables &d);
 

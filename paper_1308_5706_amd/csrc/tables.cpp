@@ -206,27 +206,64 @@ void build_delta_tables(int L, DeltaTables &d) {
             }
         }
     }
+    // rescaling factors g_l(x) (the q side) and h_l(x) (the v side), l = x .. L, in long
+    // double; they stay within a few powers of L of 1
+    std::vector<ld> gq((size_t)(L + 1) * L, 0.0L), hv((size_t)L * (L + 1), 0.0L);
+    auto Sf = [](ld l, int x) { return sqrtl((l - x) * (l + x)); };
+    for (int x = 0; x < L; ++x) {
+        ld *gx = &gq[(size_t)x * (L + 1)], *hx = &hv[(size_t)x * (L + 1)];
+        gx[x] = 1.0L;
+        hx[x] = 1.0L;
+        if (x + 1 <= L) gx[x + 1] = hx[x + 1] = 1.0L;
+        for (int l = x + 1; l + 1 <= L; ++l) {
+            const ld q = Sf((ld)l, x) / Sf((ld)l + 1, x);         // q_l(x), l > x
+            const ld v = ((ld)l + 1) / (ld)l * q;                  // v_l(x), l >= 1
+            gx[l + 1] = q * gx[l - 1];
+            hx[l + 1] = v * hx[l - 1];
+        }
+    }
+    d.pt.assign((size_t)L * Lp, 0.0);
+    d.ut.assign((size_t)Lp * L, 0.0);
+    d.g.assign((size_t)L * Lp, 0.0);
+    d.h.assign((size_t)Lp * L, 0.0);
+    for (int x = 0; x < L; ++x) {
+        const ld *gx = &gq[(size_t)x * (L + 1)], *hx = &hv[(size_t)x * (L + 1)];
+        for (int l = x; l < L; ++l) {
+            const ld s1 = Sf((ld)l + 1, x);
+            const ld p = (ld)x / s1;                                // p_l(x)
+            d.pt[(size_t)l * Lp + x] = (double)(p * gx[l] / gx[l + 1]);
+            if (l > 0) d.ut[(size_t)x * L + l] = (double)((2.0L * l + 1.0L) / (ld)l * p * hx[l] / hx[l + 1]);
+            d.g[(size_t)l * Lp + x] = (double)gx[l];
+            d.h[(size_t)x * L + l] = (double)hx[l];
+        }
+    }
     // corner values T(a, b) = sqrt(C(2a, a+b)) 2^-a for 0 <= b <= a < L, built from
     // T(a, a) = 2^-a downwards with T(a, b-1) = T(a, b) sqrt((a+b)/(a-b+1))
     d.seed.assign((size_t)Lp * Lp, 0.0);
-    d.seedm.assign((size_t)Lp * Lp, 0.0);
-    d.seede.assign((size_t)Lp * Lp, 0);
+    d.seedt.assign((size_t)Lp * Lp, 0.0);
+    d.seedtm.assign((size_t)Lp * Lp, 0.0);
+    d.seedte.assign((size_t)Lp * Lp, 0);
     std::vector<ld> T(L);
     for (int a = 0; a < L; ++a) {
         T[a] = ldexpl(1.0L, -a);
         for (int b = a; b > 0; --b) T[b - 1] = T[b] * sqrtl((ld)(a + b) / (ld)(a - b + 1));
         for (int b = 0; b <= a; ++b) {
             // row m' = a, column m = b <= a: (-1)^{a-b} T(a, b);  row m' = b, column m = a: T(a, b)
-            ld v1 = ((a - b) & 1) ? -T[b] : T[b];
-            ld v2 = T[b];
-            int e;
-            size_t i1 = (size_t)a * Lp + b, i2 = (size_t)b * Lp + a;
-            d.seedm[i1] = (double)frexpl(v1, &e);
-            d.seede[i1] = e;
+            const ld v1 = ((a - b) & 1) ? -T[b] : T[b];
+            const ld v2 = T[b];
+            const size_t i1 = (size_t)a * Lp + b, i2 = (size_t)b * Lp + a;
             d.seed[i1] = (double)v1;
-            d.seedm[i2] = (double)frexpl(v2, &e);
-            d.seede[i2] = e;
             d.seed[i2] = (double)v2;
+            // rescaled: c_{l0} = g_{l0}(m) h_{l0}(m') with l0 = a
+            const ld t1 = v1 / (gq[(size_t)b * (L + 1) + a] * hv[(size_t)a * (L + 1) + a]);  // m' = a, m = b
+            const ld t2 = v2 / (gq[(size_t)a * (L + 1) + a] * hv[(size_t)b * (L + 1) + a]);  // m' = b, m = a
+            int e;
+            d.seedtm[i1] = (double)frexpl(t1, &e);
+            d.seedte[i1] = e;
+            d.seedt[i1] = (double)t1;
+            d.seedtm[i2] = (double)frexpl(t2, &e);
+            d.seedte[i2] = e;
+            d.seedt[i2] = (double)t2;
         }
     }
 }
