@@ -480,7 +480,9 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
     std::vector<double> ncol;
     build_delta_ncols(dt, t.nk, ncol);
     const int K = t.K, Lp = dt.Lp;
-    std::vector<double> kb2((size_t)Lp * L * 2 * K, 0.0);
+    // one record of padding at the end: the analysis kernel reads the entries of step l + 1
+    // ahead of step l, also after the last step of the last row
+    std::vector<double> kb2((size_t)Lp * L * 2 * K + 2 * K, 0.0);
     for (int mp = 0; mp < L; ++mp)
         for (int l = 0; l < L; ++l) {
             int si = 0;
@@ -533,6 +535,7 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
                                      : (2.0 * l + 1.0) / (8.0 * M_PI * M_PI);
     P.n_kb2 = kb2.size();
     P.n_tg = tgf.size();
+    dt.ut.resize(dt.ut.size() + 1, 0.0);  // one padding entry (as for kb2)
     bool ok = upload(P, P.pq, dt.pt) && upload(P, P.uv, dt.ut) && upload(P, P.gsc, dt.g) && upload(P, P.kb2, kb2) &&
               upload(P, P.seed, dt.seedt) && upload(P, P.seedm, dt.seedtm) && upload(P, P.seede, dt.seedte) &&
               upload(P, P.tgf, tgf) && upload(P, P.tga, tga) && upload(P, P.fac, fac) && upload(P, P.phi, t.phi);
