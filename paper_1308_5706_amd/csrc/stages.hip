@@ -474,16 +474,12 @@ __global__ void __launch_bounds__(256) gamma_adj_cx_kernel(const GammaArgs a) {
 // ------------------------------------------ synthesis: beta integral and m' folding (Eq. 35, 40)
 // Step (3) of both beta quadratures below, once V(m') of the column pair is known: the fold
 // over +-m' and the even/odd-l combinations P, Q of the two n columns (see the synthesis
-// Wigner kernel).  On entry V of column +n sits in buf[q] (q = m' + Lj - 1) or, with two
-// columns, in the block's output rows Po/Qo, and V of column -n in buf[Nk + q].
+// Wigner kernel).  On entry V of column +n sits in buf[q] (q = m' + Lj - 1) and, with two
+// columns, V of column -n in buf[Nk + q].
 template <class C, int NT>
 __device__ __forceinline__ void fold_pq(C *buf, int tid, int Lj, int m, int n, int ncol, bool odd, int eta, C *Po,
                                         C *Qo) {
     const int Nk = 2 * Lj - 1;
-    if (ncol > 1) {
-        for (int q = tid; q < Nk; q += NT) buf[pad(q)] = q < Lj ? Po[q] : Qo[q - Lj];
-        __syncthreads();
-    }
     for (int mp = tid; mp < Lj; mp += NT) {
         C tp = buf[pad(mp + Lj - 1)], tm = ncol > 1 ? buf[pad(Nk + mp + Lj - 1)] : zero2<C>();
         if (mp > 0) {
@@ -538,6 +534,8 @@ __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int co
     const C *__restrict__ cpp = (const C *)a.cpp;
     C *__restrict__ Po = out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
     C *__restrict__ Qo = out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
+    C keep[kRM];  // V of column +n by storer slot (two columns), and its index q (or -1)
+    int kq[kRM];
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
         const C *__restrict__ Gc = in + ((size_t)ni * Lj + m) * L;
@@ -555,15 +553,13 @@ __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int co
         fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in1, st1);
         auto in2 = [&](int i, int = 0) { return i < T ? buf[pad(i)] : zero2<C>(); };
         // V(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + T - 1.  With two columns the
-        // first one waits in this block's own output rows (2 Lj slots) while the second one
-        // uses the whole buffer; the second one goes to slots Nk + q.
+        // first one waits in registers (each thread keeps the outputs of its storer slots)
+        // while the second one uses the whole buffer; the second one goes to slots Nk + q.
         if (c == 0 && ncol > 1) {
-            auto st2 = [&](int i, C v, int = 0) {
+            auto st2 = [&](int i, C v, int slot) {
                 const int q = i - (T - 1);
-                if (q >= 0 && q < Nk) {
-                    if (q < Lj) Po[q] = v;
-                    else Qo[q - Lj] = v;
-                }
+                kq[slot] = (q >= 0 && q < Nk) ? q : -1;
+                keep[slot] = v;
             };
             fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, hh2, in2, st2);
         } else {
@@ -575,6 +571,12 @@ __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int co
             fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, hh2, in2, st2);
         }
     }
+    if (ncol > 1) {
+#pragma unroll
+        for (int r = 0; r < kRM; ++r)
+            if (kq[r] >= 0) buf[pad(kq[r])] = keep[r];
+    }
+    __syncthreads();
     fold_pq<C, NT>(buf, tid, Lj, m, n, ncol, odd, a.eta_imag ? 1 : 0, Po, Qo);
 }
 
@@ -624,19 +626,19 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_dh_kernel(const S
     const real_t<C> *__restrict__ qw = (const real_t<C> *)a.qw;
     C *__restrict__ Po = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
     C *__restrict__ Qo = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
+    C keep[kRM];  // V of column +n by storer slot (two columns), and its index q (or -1)
+    int kq[kRM];
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
         const C *__restrict__ Gc = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)ni * Lj + m) * nb;
         auto in = [&](int i, int = 0) { return i < nb ? cscale(cmulc(Gc[i], csq[i]), qw[i]) : zero2<C>(); };
         // V(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + nb - 1
         if (c == 0 && ncol > 1) {
-            auto st = [&](int i, C v, int = 0) {
+            auto st = [&](int i, C v, int slot) {
                 const int q = i - (nb - 1);
-                if (q >= 0 && q < Nk) {
-                    v = cmulc(v, cpp[q - (Lj - 1)]);
-                    if (q < Lj) Po[q] = v;
-                    else Qo[q - Lj] = v;
-                }
+                const bool ok = q >= 0 && q < Nk;
+                kq[slot] = ok ? q : -1;
+                keep[slot] = ok ? cmulc(v, cpp[q - (Lj - 1)]) : v;
             };
             fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
         } else {
@@ -648,6 +650,12 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_dh_kernel(const S
             fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
         }
     }
+    if (ncol > 1) {
+#pragma unroll
+        for (int r = 0; r < kRM; ++r)
+            if (kq[r] >= 0) buf[pad(kq[r])] = keep[r];
+    }
+    __syncthreads();
     fold_pq<C, NT>(buf, tid, Lj, m, n, ncol, odd, a.eta_imag ? 1 : 0, Po, Qo);
 }
 
