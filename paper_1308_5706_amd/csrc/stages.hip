@@ -130,17 +130,18 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const
     const C *__restrict__ Um = (const C *)a.in + blockIdx.y * a.s_in + (size_t)nj * Lj * nb + b;
     const C *__restrict__ csq = (const C *)a.csq;
     const int Na = 2 * Lj - 1;
+    // The alpha loaders are branch-free: an index past the end is clamped, so that the load
+    // stays in bounds and is issued with the thread's others (all in flight together), and
+    // its value is then replaced by zero.
     auto in = [&](int i, int = 0) {
-        if (i >= Na) return zero2<C>();
-        const int m = i - (Lj - 1);
-        C c;
-        if (m >= 0) {
-            c = Up[(size_t)m * nb];
-            if (m == 0 && zero_n) c.y = 0.0;
-        } else {
-            c = cconj(Um[(size_t)(-m) * nb]);
-        }
-        return cmul(c, csq[m < 0 ? -m : m]);
+        const bool ok = i < Na;
+        const int m = (ok ? i : Na - 1) - (Lj - 1), am = m < 0 ? -m : m;
+        C c = (m >= 0 ? Up : Um)[(size_t)am * nb];
+        const C w = csq[am];
+        if (m < 0) c = cconj(c);
+        if (m == 0 && zero_n) c.y = 0.0;
+        c = cmul(c, w);
+        return ok ? c : zero2<C>();
     };
     C *__restrict__ Y = (C *)a.out + blockIdx.y * a.s_out + ((size_t)np * nb + b) * T;
     auto st = [&](int i, C v, int = 0) {
@@ -162,7 +163,12 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const
     const bool zero_n = ni == nj;
     const C *__restrict__ X = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)np * nb + b) * T;
     const C *__restrict__ csq = (const C *)a.csq;
-    auto in = [&](int i, int = 0) { return i < T ? cmulc(X[i], csq[i]) : zero2<C>(); };
+    auto in = [&](int i, int = 0) {  // branch-free (see alpha_fwd_fft_kernel)
+        const bool ok = i < T;
+        const int ic = ok ? i : T - 1;
+        const C v = cmulc(X[ic], csq[ic]);
+        return ok ? v : zero2<C>();
+    };
     // Zh(m), q = m + Lj - 1 < 2Lj - 1, comes out at q + T - 1
     const int Nk = 2 * Lj - 1;
     const real_t<C> s = (real_t<C>)a.scale;
@@ -207,20 +213,16 @@ __global__ void __launch_bounds__(P / kRM) alpha_fwd_blk_kernel(const StageArgs 
     // this thread's chirped inputs, element tid + s NT in slot s, kept across the blocks
     C base[kRM];
 #pragma unroll
-    for (int s = 0; s < kRM; ++s) {
+    for (int s = 0; s < kRM; ++s) {  // branch-free (see alpha_fwd_fft_kernel)
         const int i = tid + s * NT;
-        C c = zero2<C>();
-        if (i < Na) {
-            const int m = i - (Lj - 1);
-            if (m >= 0) {
-                c = Up[(size_t)m * nb];
-                if (m == 0 && zero_n) c.y = 0.0;
-            } else {
-                c = cconj(Um[(size_t)(-m) * nb]);
-            }
-            c = cmul(c, csq[m < 0 ? -m : m]);
-        }
-        base[s] = c;
+        const bool ok = i < Na;
+        const int m = (ok ? i : Na - 1) - (Lj - 1), am = m < 0 ? -m : m;
+        C c = (m >= 0 ? Up : Um)[(size_t)am * nb];
+        const C w = csq[am];
+        if (m < 0) c = cconj(c);
+        if (m == 0 && zero_n) c.y = 0.0;
+        c = cmul(c, w);
+        base[s] = ok ? c : zero2<C>();
     }
     C *__restrict__ Y = (C *)a.out + blockIdx.y * a.s_out + ((size_t)np * nb + b) * T;
     for (int k = 0; k < a.nblk; ++k) {
@@ -262,7 +264,12 @@ __global__ void __launch_bounds__(P / kRM) alpha_adj_blk_kernel(const StageArgs 
     }
     for (int k = 0; k < a.nblk; ++k) {
         const int a0 = k * B;
-        auto in = [&](int i, int = 0) { return (i < B && a0 + i < T) ? cmulc(X[a0 + i], csq[i]) : zero2<C>(); };
+        auto in = [&](int i, int = 0) {  // branch-free (see alpha_fwd_fft_kernel)
+            const bool ok = i < B && a0 + i < T;
+            const int ic = ok ? i : 0;
+            const C v = cmulc(X[a0 + ic], csq[ic]);
+            return ok ? v : zero2<C>();
+        };
         // the block's part of Zh(m), q = m + Lj - 1 < 2Lj - 1, comes out at q + B - 1
         auto st = [&](int i, C v, int s) {
             const int q = i - (B - 1);
