@@ -1,0 +1,65 @@
+"""Host checks of the roofline accounting in bench.py (no device work): the algorithmic work
+per stage follows the stated formulas, and a stage with both a byte and a FLOP count is
+placed under the roof it comes closer to."""
+import importlib.util
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import tables
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_wigner_terms_brute_force(bench):
+    # count (l, m, m', n) terms of the quarter m, m' >= 0 directly on a tiny case
+    L, N, lam, J_min = 12, 3, 2.0, 0
+    kappa = tables.kappa_table(L, lam, J_min)
+    nl = [n for n in range(-(N - 1), N) if (N + n) % 2 == 1]
+    brute = 0
+    for j in range(kappa.shape[0]):
+        for el in range(L):
+            if kappa[j, el] > 0:
+                for m in range(el + 1):
+                    for mp in range(el + 1):
+                        brute += sum(1 for n in nl if abs(n) <= el)
+    assert bench.wigner_terms(kappa, N) == brute
+
+
+def test_stage_units_formulas(bench):
+    L, N, lam, J_min = 64, 4, 2.0, 1
+    kappa = tables.kappa_table(L, lam, J_min)
+    T = bench.wigner_terms(kappa, N)
+    u = bench.stage_units(kappa, L, N, T)
+    Ljs = [max(np.nonzero(kappa[j] > 0)[0]) + 1 for j in range(kappa.shape[0]) if np.any(kappa[j] > 0)]
+    Tg, Nh = 2 * L - 1, N - N // 2
+    dft = 5.0 * Tg * math.log2(Tg)
+    by = dict(u["beta_adj"])
+    assert by["hbm"] == sum(16 * N * Lj * L + 32 * Nh * Lj * Lj for Lj in Ljs)
+    conv = [10.0 * (Tg + 2 * Lj - 2) * math.log2(Tg + 2 * Lj - 2) + 6.0 * (Tg + 2 * Lj - 2) for Lj in Ljs]
+    assert by["alu"] == pytest.approx(sum(N * Lj * (dft + c) for Lj, c in zip(Ljs, conv)))
+    assert dict(u["alpha_adj"])["alu"] == pytest.approx(len(Ljs) * Nh * L * dft)
+    assert dict(u["gamma_fwd"]) == {"hbm": float(len(Ljs) * (16 * Nh * L * Tg + 8 * (2 * N - 1) * L * Tg))}
+    assert u["wigner_fwd"] == [("alu", 5.0 * T)]
+
+
+def test_roofline_takes_the_nearer_roof(bench):
+    units = {"s": [("hbm", 8e9), ("alu", 1e10)]}   # per step
+    ps = {"ms_per_launch": 1.0, "launches_per_step": 2.0}
+    r = bench.roofline("s", ps, units)
+    # per launch 4e9 B and 5e9 FLOP in 1 ms: 4000 GB/s (50 %) against 5 TFLOP/s (6.4 %)
+    assert r["bound"] == "hbm" and r["achieved"] == pytest.approx(4000.0) and r["frac"] == pytest.approx(0.5)
+    assert r["other"]["bound"] == "alu" and r["other"]["frac"] == pytest.approx(5.0 / bench.PEAK_FP64_TFLOPS)
+    units = {"s": [("hbm", 8e8), ("alu", 1e11)]}
+    r = bench.roofline("s", ps, units)
+    assert r["bound"] == "alu" and r["frac"] == pytest.approx(50.0 / bench.PEAK_FP64_TFLOPS)
