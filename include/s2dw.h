@@ -241,6 +241,16 @@ typedef struct s2dw_stage_time {
 int s2dw_profile(int enable);
 int s2dw_profile_read(s2dw_stage_time *out, int32_t max, int32_t *n);
 
+/*
+ * Restricts stage timing to the named stages: names is a comma-separated list of the
+ * stage names above (host string, read during the call); NULL or "" times every stage
+ * (the default).  Each timed launch costs two event records on the stream, which the
+ * device executes between kernels, so timing only the stage of interest keeps the
+ * timed sequence close to an untimed one.  Returns S2DW_E_ARG, and keeps the previous
+ * selection, if a name is not a stage name.  Needs no GPU.
+ */
+int s2dw_profile_stages(const char *names);
+
 /* Human-readable text of a status code. */
 const char *s2dw_strerror(int code);
 

@@ -8,6 +8,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <tuple>
 
@@ -132,6 +133,7 @@ struct Prof {
     };
     std::vector<Rec> recs;
     std::map<std::string, std::pair<double, int64_t>> totals;
+    std::set<std::string> only;  // stages timed while on; empty: every stage
 };
 Prof g_prof;
 
@@ -152,6 +154,7 @@ struct Stage {
     Stage(const char *n, hipStream_t s) : st(s), name(n) {
         if (!g_prof.on) return;
         std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (!g_prof.only.empty() && !g_prof.only.count(n)) return;
         a = prof_event();
         if (a) hipEventRecord(a, st);
     }
@@ -1494,6 +1497,31 @@ int s2dw_profile(int enable) {
     prof_collect();
     g_prof.totals.clear();
     g_prof.on = enable != 0;
+    return S2DW_OK;
+}
+
+int s2dw_profile_stages(const char *names) {
+    static const char *const known[] = {"pad",       "wigner_fwd", "beta_fwd",  "alpha_fwd", "gamma_fwd", "gamma_adj",
+                                        "alpha_adj", "beta_adj",   "wigner_adj", "syn_final", "scaling",  "steer"};
+    std::set<std::string> sel;
+    if (names) {
+        const std::string all(names);
+        size_t i = 0;
+        while (i <= all.size()) {
+            size_t j = all.find(',', i);
+            if (j == std::string::npos) j = all.size();
+            const std::string w = all.substr(i, j - i);
+            if (!w.empty()) {
+                bool ok = false;
+                for (const char *k : known) ok = ok || w == k;
+                if (!ok) return S2DW_E_ARG;
+                sel.insert(w);
+            }
+            i = j + 1;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.only.swap(sel);
     return S2DW_OK;
 }
 

@@ -79,6 +79,8 @@ def lib():
         L.s2dw_profile.restype = ctypes.c_int
         L.s2dw_profile_read.argtypes = [ctypes.POINTER(StageTime), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.s2dw_profile_read.restype = ctypes.c_int
+        L.s2dw_profile_stages.argtypes = [ctypes.c_char_p]
+        L.s2dw_profile_stages.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -87,7 +89,7 @@ EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_sc
             "s2dw_synthesis", "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_workspace_bytes",
             "s2dw_cache_bytes",
             "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
-            "s2dw_profile_read",
+            "s2dw_profile_read", "s2dw_profile_stages",
             "s2dw_strerror", "s2dw_release_caches"]
 
 
@@ -362,6 +364,12 @@ def cache_bytes() -> int:
 def profile(enable: bool) -> None:
     """Turn per-kernel stage timing on (clearing totals) or off."""
     _check(lib().s2dw_profile(1 if enable else 0), "s2dw_profile")
+
+
+def profile_stages(names=None) -> None:
+    """Time only the named stages while timing is on (None or empty: every stage)."""
+    arg = ",".join(names).encode() if names else None
+    _check(lib().s2dw_profile_stages(arg), "s2dw_profile_stages")
 
 
 def profile_read() -> dict:

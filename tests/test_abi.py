@@ -156,3 +156,11 @@ def test_multires_layout_queries(L, N, lam, J_min):
     assert sh == (N, 2 * L, 2 * L - 1) and o == N * 2 * L * (2 * L - 1)
     assert s2dw.lib().s2dw_wavelet_bytes(ctypes.byref(s2dw.params(L, N, lam, J_min, grid="dh")), ctypes.byref(b)) == 0
     assert b.value == 8 * len(bl) * N * 2 * L * (2 * L - 1)
+
+
+def test_profile_stage_selection_checks_names():
+    lib = s2dw.lib()
+    assert lib.s2dw_profile_stages(b"beta_adj,wigner_fwd") == 0
+    assert lib.s2dw_profile_stages(b"beta_adj,nosuchstage") == -1
+    assert lib.s2dw_profile_stages(b"") == 0
+    assert lib.s2dw_profile_stages(None) == 0

@@ -133,6 +133,36 @@ def test_repeat_calls_are_bitwise_stable():
     assert torch.equal(r1, r2)
 
 
+def test_stage_timing_selection():
+    L, N, J_min = 48, 4, 0
+    S = s2dw.num_scales(L, 2.0, J_min)
+    f = dev(random_flm(L, 14))
+    W, Wp = s2dw.analysis(f, L, N, 2.0, J_min)
+    ref = host(s2dw.synthesis(W, Wp, L, N, 2.0, J_min))
+    try:
+        s2dw.profile_stages(None)
+        s2dw.profile(True)
+        W, Wp = s2dw.analysis(f, L, N, 2.0, J_min)
+        out = s2dw.synthesis(W, Wp, L, N, 2.0, J_min)
+        every = s2dw.profile_read()
+        s2dw.profile_stages(["beta_adj", "wigner_fwd"])
+        s2dw.profile(True)
+        W, Wp = s2dw.analysis(f, L, N, 2.0, J_min)
+        out2 = s2dw.synthesis(W, Wp, L, N, 2.0, J_min)
+        some = s2dw.profile_read()
+    finally:
+        s2dw.profile(False)
+        s2dw.profile_stages(None)
+    assert {"wigner_fwd", "beta_fwd", "alpha_fwd", "gamma_fwd", "gamma_adj", "alpha_adj", "beta_adj",
+            "wigner_adj"} <= set(every)
+    assert every["wigner_fwd"][1] == 1 and every["gamma_fwd"][1] == S
+    assert set(some) == {"beta_adj", "wigner_fwd"}
+    assert some["wigner_fwd"][1] == 1 and some["beta_adj"][1] == every["beta_adj"][1]
+    assert all(v[0] > 0 for v in some.values())
+    # timing changes nothing in the results
+    assert np.array_equal(host(out), ref) and np.array_equal(host(out2), ref)
+
+
 MIXED_TOL = 1e-5  # FP32 stages: bound on the relative max-error against the FP64 oracle
 
 
