@@ -230,7 +230,8 @@ int s2dw_wavelet_tables(const s2dw_params *p, double *kappa, double *phi, double
  * s2dw_profile(0) disables.  s2dw_profile_read waits for the recorded events and
  * fills up to max entries (host memory) with per-stage totals since the last clear;
  * *n receives the number of stages.  Names: pad, wigner_fwd, beta_fwd, alpha_fwd,
- * gamma_fwd (analysis), gamma_adj, alpha_adj, beta_adj, wigner_adj, syn_final
+ * gamma_fwd, alpha_gamma_fwd (analysis; the last is the fused alpha and gamma pass that
+ * coarse scales take in FP64), gamma_adj, alpha_adj, beta_adj, wigner_adj, syn_final
  * (synthesis), scaling, steer.
  */
 typedef struct s2dw_stage_time {

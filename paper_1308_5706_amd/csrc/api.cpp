@@ -857,6 +857,15 @@ int grid_limits(const s2dw_params *p, std::vector<int> &Lg) {
         if ((x) != hipSuccess) return S2DW_E_DEVICE;    \
     } while (0)
 
+// Coarse scales of the analysis (FP64, real signals) take the fused alpha and gamma pass
+// while its Nh (2Lj - 1) complex multiply-adds per sample stay within 9 G, G the number of
+// W values the sample writes: the pass then costs little more than its W writes, against a
+// blocked alpha transform plus a gamma pass that writes and reads Y (at L = 1024, N = 8:
+// 65-73 us per scale for Lj = 4, 8, 16 against about 130 us).
+bool direct_alpha_gamma(int Nh, int G, int Lj, int f32, bool cx) {
+    return !f32 && !cx && Nh * (2 * Lj - 1) <= 9 * G && 2 * Nh * Lj <= kAlphaGammaCoeffs;
+}
+
 // Wigner-stage analysis + beta/alpha/gamma sums for a batch of `maps` maps: f_lm of map i at
 // flm + i L^2, its W at W + i S (2N-1) L (2L-1) (elements of the W type).
 // With cx (complex signals), flm holds maps / 2 complex signals, each run as the two real maps
@@ -926,6 +935,24 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
         {
             Stage sg("beta_fwd", st);
             S2DW_CHECK_HIP(launch_beta_fwd_fft(b, P.PA[j], maps, st));
+        }
+        if (direct_alpha_gamma(P.Nh, P.ng, Lj, f32, cx)) {
+            AlphaGammaArgs d{};
+            d.in = w.Ub;
+            d.wout = Wj;
+            d.tg = P.tgf;
+            d.eph = gtab.eph;
+            d.s_in = P.s_Ub;
+            d.s_w = per_map;
+            d.nb = b.nb;
+            d.T = 2 * Lg - 1;
+            d.Lj = Lj;
+            d.N = N;
+            d.Nh = P.Nh;
+            d.G = P.ng;
+            Stage sg("alpha_gamma_fwd", st);
+            S2DW_CHECK_HIP(launch_alpha_gamma_fwd(d, maps, st));
+            continue;
         }
         StageArgs c = b;
         c.in = w.Ub;
@@ -1501,8 +1528,9 @@ int s2dw_profile(int enable) {
 }
 
 int s2dw_profile_stages(const char *names) {
-    static const char *const known[] = {"pad",       "wigner_fwd", "beta_fwd",  "alpha_fwd", "gamma_fwd", "gamma_adj",
-                                        "alpha_adj", "beta_adj",   "wigner_adj", "syn_final", "scaling",  "steer"};
+    static const char *const known[] = {"pad",       "wigner_fwd", "beta_fwd",   "alpha_fwd", "gamma_fwd",
+                                        "alpha_gamma_fwd", "gamma_adj", "alpha_adj", "beta_adj", "wigner_adj",
+                                        "syn_final", "scaling", "steer"};
     std::set<std::string> sel;
     if (names) {
         const std::string all(names);

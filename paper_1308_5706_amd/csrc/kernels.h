@@ -105,6 +105,20 @@ struct GammaArgs {
     int L, T, G, Nh, f32;
 };
 hipError_t launch_gamma_fwd(const GammaArgs &a, int maps, hipStream_t st);
+// Analysis alpha and gamma sums of one coarse scale in one pass (FP64, real signals): Ub
+// [N][Lj][nb] (the beta stage's output, per-map stride s_in complex elements) -> W
+// [G][nb][T] (per-map stride s_w real elements); eph = e^{2 pi i r/T}, r < T; tg as for
+// the gamma pass.
+constexpr int kAlphaGammaCoeffs = 1024;  // 2 Nh Lj complex coefficients of a ring at most
+struct AlphaGammaArgs {
+    const void *in;
+    void *wout;
+    const void *tg;
+    const void *eph;
+    size_t s_in, s_w;
+    int nb, T, Lj, N, Nh, G;
+};
+hipError_t launch_alpha_gamma_fwd(const AlphaGammaArgs &a, int maps, hipStream_t st);
 hipError_t launch_gamma_adj(const GammaArgs &a, int maps, hipStream_t st);
 // Complex signals: complex map z of W (s_w complex elements per map, (re, im) pairs) from /
 // to the real maps 2z and 2z + 1 of Y / X; cmaps complex maps.

@@ -411,6 +411,93 @@ __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
         }
 }
 
+// Coarse scales of the analysis: both sums at once, sample by sample, without Y:
+//   W(g, b, a) = sum_{n'} Re(tg[g][n'] Y_n'(b, a)),  Y_n(b, a) = sum_{|m|<Lj} C_n(b, m) z^m,
+// z = e^{i alpha_a}.  With C_n(b, -m) = conj(Ub[-n][m][b]) and |z| = 1, Y_n = p(z) + conj(q(z)),
+// p(z) = sum_{m>=0} Ub[n][m][b] z^m and q(z) = sum_{m>=1} Ub[-n][m][b] z^m, both by Horner's
+// rule.  That is Nh (2Lj - 1) complex multiply-adds per sample instead of a blocked chirp
+// transform and a pass over Y, worth it while Nh (2Lj - 1) is small next to the G values
+// written per sample.  A row of workgroups per ring b; the ring's coefficients (stride nb
+// apart in Ub) are staged in LDS once per workgroup and then read by every lane at the same
+// address.  PAIR (plane and map stride even, W 16-byte aligned): a thread takes two
+// consecutive samples and writes them with one 16-byte store; T being odd, element (b, 0)
+// sits at an even offset exactly when b is even, so the pairs of ring b start at
+// a = -(b & 1) and the ring's one unpaired sample (first or last) is written alone.
+// Otherwise one sample per thread.  NH = Nh (a template parameter, so that the Y values
+// of a thread take only the registers they need).
+template <bool PAIR, int NH>
+__global__ void __launch_bounds__(256) alpha_gamma_fwd_kernel(const AlphaGammaArgs a) {
+    constexpr int V = PAIR ? 2 : 1;
+    __shared__ double2 cs[kAlphaGammaCoeffs];  // [k][side][m]: side 0 row n, side 1 row -n
+    constexpr int Nh = NH;
+    const int b = blockIdx.y, Lj = a.Lj, nb = a.nb, N = a.N, T = a.T;
+    const double2 *__restrict__ U = (const double2 *)a.in + blockIdx.z * a.s_in + b;
+    for (int i = threadIdx.x; i < 2 * Nh * Lj; i += 256) {
+        const int k = i / (2 * Lj), r = i - k * 2 * Lj, side = r >= Lj ? 1 : 0, m = r - side * Lj;
+        const int ni = N / 2 + k, row = side ? N - 1 - ni : ni;
+        cs[i] = U[((size_t)row * Lj + m) * nb];
+    }
+    __syncthreads();
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int x0 = PAIR ? 2 * t - (b & 1) : t;
+    bool ok[V];
+    ok[0] = x0 >= 0 && x0 < T;
+    if constexpr (PAIR) ok[1] = x0 + 1 < T;
+    if (!ok[0] && !ok[V - 1]) return;
+    const double2 *__restrict__ eph = (const double2 *)a.eph;
+    double2 z[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) z[v] = eph[ok[v] ? x0 + v : 0];
+    double2 y[NH][V];
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+        const double2 *cp = cs + k * 2 * Lj, *cm = cp + Lj;
+        {
+            double2 p[V], q[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) p[v] = q[v] = zero2<double2>();
+#pragma unroll 2
+            for (int m = Lj - 1; m >= 1; --m) {
+                const double2 up = cp[m], um = cm[m];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    p[v] = cadd(cmul(p[v], z[v]), up);
+                    q[v] = cadd(cmul(q[v], z[v]), um);
+                }
+            }
+            double2 c0 = cp[0];
+            if (k == 0 && (N & 1)) c0.y = 0.0;  // the row n = 0 (N odd): C_0(b, 0) is real
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const double2 pv = cadd(cmul(p[v], z[v]), c0), qv = cmul(q[v], z[v]);
+                y[k][v] = mk<double2>(pv.x + qv.x, pv.y - qv.y);
+            }
+        }
+    }
+    const size_t plane = (size_t)nb * T;
+    double *__restrict__ W = (double *)a.wout + blockIdx.z * a.s_w + (size_t)b * T + x0;
+    const double2 *__restrict__ tg = (const double2 *)a.tg;
+    for (int g = 0; g < a.G; ++g) {
+        double acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            const double2 w = tg[g * Nh + k];
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] = fma(y[k][v].x, w.x, fma(-y[k][v].y, w.y, acc[v]));
+        }
+        double *dst = W + g * plane;
+        if (PAIR && ok[0] && ok[V - 1]) {
+            nt_store(make_double2(acc[0], acc[V - 1]), (double2 *)dst);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (ok[v]) __builtin_nontemporal_store(acc[v], dst + v);
+        }
+    }
+}
+
 // Complex signals: complex map z = real maps 2z (real part of f) and 2z + 1 (imaginary part);
 // W = W_2z + i W_2z+1 (Eq. 1 is linear in f) is written as (re, im) pairs, one point per
 // thread, and read back the same way in the synthesis.
@@ -768,6 +855,31 @@ hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t s
 hipError_t launch_gamma_fwd(const GammaArgs &a, int maps, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_fwd_kernel)
 
 hipError_t launch_gamma_adj(const GammaArgs &a, int maps, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_adj_kernel)
+
+hipError_t launch_alpha_gamma_fwd(const AlphaGammaArgs &a, int maps, hipStream_t st) {
+    if (a.Nh < 1 || a.Nh > kMaxK || a.Lj < 1 || 2 * a.Nh * a.Lj > kAlphaGammaCoeffs || a.T < 1 || a.nb < 1 || maps < 1)
+        return hipErrorInvalidValue;
+    const size_t plane = (size_t)a.nb * a.T;
+    const bool pair = a.T % 2 == 1 && plane % 2 == 0 && (maps == 1 || a.s_w % 2 == 0) &&
+                      ((uintptr_t)a.wout & 15) == 0;
+    const dim3 grid((unsigned)(((pair ? a.T / 2 + 1 : a.T) + 255) / 256), (unsigned)a.nb, (unsigned)maps);
+    switch (a.Nh * 2 + (pair ? 1 : 0)) {
+#define S2DW_AG_CASE(NH)                                                                           \
+    case 2 * NH: hipLaunchKernelGGL((alpha_gamma_fwd_kernel<false, NH>), grid, dim3(256), 0, st, a); break; \
+    case 2 * NH + 1: hipLaunchKernelGGL((alpha_gamma_fwd_kernel<true, NH>), grid, dim3(256), 0, st, a); break;
+        S2DW_AG_CASE(1)
+        S2DW_AG_CASE(2)
+        S2DW_AG_CASE(3)
+        S2DW_AG_CASE(4)
+        S2DW_AG_CASE(5)
+        S2DW_AG_CASE(6)
+        S2DW_AG_CASE(7)
+        S2DW_AG_CASE(8)
+#undef S2DW_AG_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 #define S2DW_GAMMA_CX_LAUNCH(KER)                                                                 \
     {                                                                                             \

@@ -49,7 +49,17 @@ def test_stage_units_formulas(bench):
     conv = [10.0 * (Tg + 2 * Lj - 2) * math.log2(Tg + 2 * Lj - 2) + 6.0 * (Tg + 2 * Lj - 2) for Lj in Ljs]
     assert by["alu"] == pytest.approx(sum(N * Lj * (dft + c) for Lj, c in zip(Ljs, conv)))
     assert dict(u["alpha_adj"])["alu"] == pytest.approx(len(Ljs) * Nh * L * dft)
-    assert dict(u["gamma_fwd"]) == {"hbm": float(len(Ljs) * (16 * Nh * L * Tg + 8 * (2 * N - 1) * L * Tg))}
+    two = [Lj for Lj in Ljs if Nh * (2 * Lj - 1) > 9 * (2 * N - 1)]
+    one = [Lj for Lj in Ljs if Nh * (2 * Lj - 1) <= 9 * (2 * N - 1)]
+    assert two and one
+    assert dict(u["gamma_fwd"]) == {"hbm": float(len(two) * (16 * Nh * L * Tg + 8 * (2 * N - 1) * L * Tg))}
+    assert dict(u["alpha_fwd"])["alu"] == pytest.approx(len(two) * Nh * L * dft)
+    assert dict(u["alpha_gamma_fwd"]) == {"hbm": float(sum(16 * N * Lj * L + 8 * (2 * N - 1) * L * Tg
+                                                             for Lj in one))}
+    # without the fused pass (mixed precision) every scale has an alpha and a gamma pass
+    u2 = bench.stage_units(kappa, L, N, T, fused=False)
+    assert "alpha_gamma_fwd" not in u2
+    assert dict(u2["gamma_fwd"]) == {"hbm": float(len(Ljs) * (16 * Nh * L * Tg + 8 * (2 * N - 1) * L * Tg))}
     assert u["wigner_fwd"] == [("alu", 5.0 * T)]
 
 
