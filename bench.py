@@ -86,7 +86,7 @@ def direct_alpha_gamma(N, Lj):
     signals on the equiangular grid; the library's rule: Nh (2Lj - 1) complex multiply-adds
     per sample at most 9 G, G = 2N - 1 the W values written per sample)."""
     Nh = N - N // 2
-    return Nh * (2 * Lj - 1) <= 9 * (2 * N - 1) and 2 * Nh * Lj <= 1024
+    return Nh * (2 * Lj - 1) <= min(9 * (2 * N - 1), 256) and 2 * Nh * Lj <= 1024
 
 
 def stage_units(kappa, L, N, T, fused=True):
@@ -105,6 +105,8 @@ def stage_units(kappa, L, N, T, fused=True):
       beta_adj  G 16 N Lj L in,              V 32 Nh Lj^2 out
       alpha_gamma_fwd (coarse scales of an FP64 analysis, fused = True; they leave
                 alpha_fwd and gamma_fwd)  Ub 16 N Lj L in,  W 8 G L T out
+      gamma_alpha_adj (the same scales of the synthesis; they leave gamma_adj and
+                alpha_adj)  W 8 G L T in,  G 16 N Lj L out
     and, for the four Fourier stages, FLOP with a length-n complex DFT counted as an FFT,
     5 n log2 n, whatever way it is computed:
       beta_fwd  N Lj columns, one length-T DFT each
@@ -129,8 +131,9 @@ def stage_units(kappa, L, N, T, fused=True):
         "alpha_fwd": [16 * N * Lj * L + 16 * Nh * L * Tg for Lj in two],
         "gamma_fwd": [16 * Nh * L * Tg + 8 * G * L * Tg for Lj in two],
         "alpha_gamma_fwd": [16 * N * Lj * L + 8 * G * L * Tg for Lj in one],
-        "gamma_adj": [8 * G * L * Tg + 16 * Nh * L * Tg for Lj in Ljs],
-        "alpha_adj": [16 * Nh * L * Tg + 16 * N * Lj * L for Lj in Ljs],
+        "gamma_adj": [8 * G * L * Tg + 16 * Nh * L * Tg for Lj in two],
+        "alpha_adj": [16 * Nh * L * Tg + 16 * N * Lj * L for Lj in two],
+        "gamma_alpha_adj": [8 * G * L * Tg + 16 * N * Lj * L for Lj in one],
         "beta_adj": [16 * N * Lj * L + 32 * Nh * Lj * Lj for Lj in Ljs],
     }
     dft = 5.0 * Tg * math.log2(Tg)
@@ -142,7 +145,7 @@ def stage_units(kappa, L, N, T, fused=True):
     flops = {
         "beta_fwd": sum(N * Lj * dft for Lj in Ljs),
         "alpha_fwd": len(two) * Nh * L * dft,
-        "alpha_adj": len(Ljs) * Nh * L * dft,
+        "alpha_adj": len(two) * Nh * L * dft,
         "beta_adj": sum(N * Lj * (dft + conv(Lj)) for Lj in Ljs),
     }
     units = {k: [("hbm", float(sum(v)))] for k, v in per.items() if v}

@@ -857,13 +857,16 @@ int grid_limits(const s2dw_params *p, std::vector<int> &Lg) {
         if ((x) != hipSuccess) return S2DW_E_DEVICE;    \
     } while (0)
 
-// Coarse scales of the analysis (FP64, real signals) take the fused alpha and gamma pass
-// while its Nh (2Lj - 1) complex multiply-adds per sample stay within 9 G, G the number of
-// W values the sample writes: the pass then costs little more than its W writes, against a
-// blocked alpha transform plus a gamma pass that writes and reads Y (at L = 1024, N = 8:
-// 65-73 us per scale for Lj = 4, 8, 16 against about 130 us).
+// Coarse scales (FP64, real signals) take the fused alpha and gamma passes of the analysis
+// and the synthesis while Nh (2Lj - 1) stays within 9 G and 256 (the outputs of a ring in
+// the synthesis pass, at most one per thread).  Nh (2Lj - 1) is the number of complex
+// multiply-adds per sample, G the number of W values a sample writes or reads: the passes
+// then cost little more than their W traffic, against a blocked alpha transform plus a
+// gamma pass that also writes and reads Y or X (at L = 1024, N = 8, for Lj = 4, 8, 16:
+// analysis 65-73 us per scale, synthesis 57-113 us, against about 130 us each).
 bool direct_alpha_gamma(int Nh, int G, int Lj, int f32, bool cx) {
-    return !f32 && !cx && Nh * (2 * Lj - 1) <= 9 * G && 2 * Nh * Lj <= kAlphaGammaCoeffs;
+    const int terms = Nh * (2 * Lj - 1);
+    return !f32 && !cx && terms <= 9 * G && terms <= 256 && 2 * Nh * Lj <= kAlphaGammaCoeffs;
 }
 
 // Wigner-stage analysis + beta/alpha/gamma sums for a batch of `maps` maps: f_lm of map i at
@@ -1021,17 +1024,37 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         g.G = P.ng;
         g.Nh = P.Nh;
         g.f32 = f32;
-        {
+        const bool merged = P.mj0 >= 0 && j >= P.mj0;  // synthesis beta stage in the coarse-scale launch
+        void *gout = !merged ? (void *)w.Ub
+                             : (f32 ? (void *)((float2 *)w.Ub + P.goff[j]) : (void *)(w.Ub + P.goff[j]));
+        const double qscale = (2.0 * M_PI / M) * (2.0 * M_PI / P.ng);  // alpha and gamma quadrature weights
+        const bool fused = direct_alpha_gamma(P.Nh, P.ng, Lj, f32, cx);
+        if (fused) {
+            GammaAlphaArgs d{};
+            d.win = Wj;
+            d.out = gout;
+            d.tg = P.tga;
+            d.eph = gtab.eph;
+            d.s_w = per_map;
+            d.s_out = P.s_Ub;
+            d.nb = g.L;
+            d.T = M;
+            d.Lj = Lj;
+            d.N = N;
+            d.Nh = P.Nh;
+            d.G = P.ng;
+            d.scale = qscale;
+            Stage sg("gamma_alpha_adj", st);
+            S2DW_CHECK_HIP(launch_gamma_alpha_adj(d, maps, st));
+        } else {
             Stage sg("gamma_adj", st);
             if (cx) S2DW_CHECK_HIP(launch_gamma_adj_cx(g, maps / 2, st));
             else S2DW_CHECK_HIP(launch_gamma_adj(g, maps, st));
         }
-        const bool merged = P.mj0 >= 0 && j >= P.mj0;  // synthesis beta stage in the coarse-scale launch
         StageArgs c{};
         c.f32 = f32;
         c.in = w.Y;
-        c.out = !merged ? (void *)w.Ub
-                        : (f32 ? (void *)((float2 *)w.Ub + P.goff[j]) : (void *)(w.Ub + P.goff[j]));
+        c.out = gout;
         c.s_in = P.s_Y;
         c.s_out = P.s_Ub;
         c.hh = f32 ? (const void *)P.hCf[j] : P.hC[j];
@@ -1044,8 +1067,10 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         c.N = N;
         c.Nh = P.Nh;
         c.K = P.K;
-        c.scale = (2.0 * M_PI / M) * (2.0 * M_PI / P.ng);
-        if (P.nblkb[j] > 1) {
+        c.scale = qscale;
+        if (fused) {
+            // the alpha quadrature ran in the fused pass above
+        } else if (P.nblkb[j] > 1) {
             StageArgs cb = c;
             cb.hh = f32 ? (const void *)P.hCbf[j] : P.hCb[j];
             cb.tw = f32 ? (const void *)P.twPf[P.PBb[j]] : P.twP[P.PBb[j]];
@@ -1528,9 +1553,10 @@ int s2dw_profile(int enable) {
 }
 
 int s2dw_profile_stages(const char *names) {
-    static const char *const known[] = {"pad",       "wigner_fwd", "beta_fwd",   "alpha_fwd", "gamma_fwd",
-                                        "alpha_gamma_fwd", "gamma_adj", "alpha_adj", "beta_adj", "wigner_adj",
-                                        "syn_final", "scaling", "steer"};
+    static const char *const known[] = {"pad",       "wigner_fwd",      "beta_fwd",  "alpha_fwd",
+                                        "gamma_fwd", "alpha_gamma_fwd", "gamma_adj", "gamma_alpha_adj",
+                                        "alpha_adj", "beta_adj",        "wigner_adj", "syn_final",
+                                        "scaling",   "steer"};
     std::set<std::string> sel;
     if (names) {
         const std::string all(names);

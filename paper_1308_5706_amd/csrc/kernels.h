@@ -119,6 +119,20 @@ struct AlphaGammaArgs {
     int nb, T, Lj, N, Nh, G;
 };
 hipError_t launch_alpha_gamma_fwd(const AlphaGammaArgs &a, int maps, hipStream_t st);
+// Synthesis gamma and alpha quadratures of one coarse scale in one pass (FP64, real
+// signals): W [G][nb][T] (per-map stride s_w real elements) -> G [N][Lj][nb] (per-map stride
+// s_out complex elements); tg = e^{-i n gamma_g} [G][Nh]; eph = e^{2 pi i r/T}, r < T;
+// scale = the product of the two quadrature weights.  Nh (2Lj - 1) <= 256.
+struct GammaAlphaArgs {
+    const void *win;
+    void *out;
+    const void *tg;
+    const void *eph;
+    size_t s_w, s_out;
+    int nb, T, Lj, N, Nh, G;
+    double scale;
+};
+hipError_t launch_gamma_alpha_adj(const GammaAlphaArgs &a, int maps, hipStream_t st);
 hipError_t launch_gamma_adj(const GammaArgs &a, int maps, hipStream_t st);
 // Complex signals: complex map z of W (s_w complex elements per map, (re, im) pairs) from /
 // to the real maps 2z and 2z + 1 of Y / X; cmaps complex maps.

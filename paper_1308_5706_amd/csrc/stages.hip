@@ -498,6 +498,93 @@ __global__ void __launch_bounds__(256) alpha_gamma_fwd_kernel(const AlphaGammaAr
     }
 }
 
+// Coarse scales of the synthesis: both quadratures at once, ring by ring, without X:
+//   Gs_n(b, m) = scale sum_a X_n(b, a) e^{-i m alpha_a},  X_n(b, a) = sum_g W(g, b, a) tg[g][n],
+// for n >= 0 and |m| < Lj.  One workgroup per ring b; the T samples go in chunks of 256:
+// the workgroup forms X of the chunk in LDS (one sample per thread, the gamma sum), then
+// each output (n, m) is summed over the chunk by H = 256 / (Nh (2Lj - 1)) threads, each
+// over a contiguous run of the chunk as a polynomial in rho = e^{-i m alpha_1} (Horner's
+// rule, at most 256 terms) times rho^s0 from the exact table at the run's start s0; the H
+// partial sums are added in a fixed order at the end.  The outputs
+// are stored as the alpha stage stores them: Gs_n(b, m) in row n for m >= 0 and conj Gs_n
+// (b, m) in row -n at -m for m <= 0 (not for the row n = 0 of odd N).
+template <int NH>
+__global__ void __launch_bounds__(256) gamma_alpha_adj_kernel(const GammaAlphaArgs a) {
+    constexpr int NT = 256;
+    __shared__ double2 xs[NH][NT];
+    __shared__ double2 red[NT];
+    const int tid = threadIdx.x, b = blockIdx.x, T = a.T, Lj = a.Lj, N = a.N, G = a.G;
+    const int nm = 2 * Lj - 1, nouts = NH * nm, H = NT / nouts;
+    const int o = tid % nouts, h = tid / nouts;
+    const bool act = h < H;
+    const int k = o / nm, m = o - k * nm - (Lj - 1);
+    const int mm = m < 0 ? m + T : m;  // m mod T
+    const double2 *__restrict__ eph = (const double2 *)a.eph;
+    const double2 rho = cconj(eph[mm]);  // e^{-i m alpha_1}
+    const int len = (NT + H - 1) / H;
+    const size_t plane = (size_t)a.nb * T;
+    const double *__restrict__ Wr = (const double *)a.win + blockIdx.y * a.s_w + (size_t)b * T;
+    const double2 *__restrict__ tg = (const double2 *)a.tg;
+    // W of the next chunk waits in registers (G <= GMAX = 4 NH - 1, since N <= 2 NH): its
+    // loads are issued before the alpha sums of the current chunk
+    constexpr int GMAX = 4 * NH - 1;
+    double wn[GMAX];
+    auto load_chunk = [&](int a0) {
+        const int x = a0 + tid;
+#pragma unroll
+        for (int g = 0; g < GMAX; ++g)
+            wn[g] = (g < G && x < T) ? __builtin_nontemporal_load(Wr + g * plane + (x < T ? x : 0)) : 0.0;
+    };
+    load_chunk(0);
+    double2 acc = zero2<double2>();
+    for (int a0 = 0; a0 < T; a0 += NT) {
+        {
+            double2 xv[NH];
+#pragma unroll
+            for (int kk = 0; kk < NH; ++kk) xv[kk] = zero2<double2>();
+#pragma unroll
+            for (int g = 0; g < GMAX; ++g) {
+                if (g < G) {
+#pragma unroll
+                    for (int kk = 0; kk < NH; ++kk) {
+                        const double2 t = tg[g * NH + kk];
+                        xv[kk].x = fma(wn[g], t.x, xv[kk].x);
+                        xv[kk].y = fma(wn[g], t.y, xv[kk].y);
+                    }
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < NH; ++kk) xs[kk][tid] = xv[kk];
+        }
+        if (a0 + NT < T) load_chunk(a0 + NT);
+        __syncthreads();
+        if (act) {
+            // sum_{x in [s0, s1)} X(x) rho^x = rho^s0 sum_j X(s0 + j) rho^j, by Horner's rule in rho
+            const int s0 = a0 + h * len, s1 = min(min(s0 + len, a0 + NT), T);
+            if (s0 < s1) {
+                double2 hs = zero2<double2>();
+                for (int x = s1 - 1; x >= s0; --x) {
+                    const double2 xv = xs[k][x - a0];
+                    hs = mk<double2>(fma(hs.x, rho.x, fma(-hs.y, rho.y, xv.x)), fma(hs.x, rho.y, fma(hs.y, rho.x, xv.y)));
+                }
+                acc = cadd(acc, cmul(hs, cconj(eph[(int)(((long long)mm * s0) % T)])));
+            }
+        }
+        __syncthreads();
+    }
+    red[tid] = act ? acc : zero2<double2>();
+    __syncthreads();
+    if (tid < nouts) {
+        double2 tot = red[tid];
+        for (int hh = 1; hh < H; ++hh) tot = cadd(tot, red[hh * nouts + tid]);
+        const double2 z = cscale(tot, a.scale);
+        const int ni = N / 2 + k, nj = N - 1 - ni;
+        double2 *__restrict__ Gout = (double2 *)a.out + blockIdx.y * a.s_out + b;
+        if (m >= 0) Gout[((size_t)ni * Lj + m) * a.nb] = z;
+        if (m <= 0 && ni != nj) Gout[((size_t)nj * Lj + (size_t)(-m)) * a.nb] = cconj(z);
+    }
+}
+
 // Complex signals: complex map z = real maps 2z (real part of f) and 2z + 1 (imaginary part);
 // W = W_2z + i W_2z+1 (Eq. 1 is linear in f) is written as (re, im) pairs, one point per
 // thread, and read back the same way in the synthesis.
@@ -855,6 +942,28 @@ hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t s
 hipError_t launch_gamma_fwd(const GammaArgs &a, int maps, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_fwd_kernel)
 
 hipError_t launch_gamma_adj(const GammaArgs &a, int maps, hipStream_t st) S2DW_GAMMA_LAUNCH(gamma_adj_kernel)
+
+hipError_t launch_gamma_alpha_adj(const GammaAlphaArgs &a, int maps, hipStream_t st) {
+    if (a.Nh < 1 || a.Nh > kMaxK || a.Lj < 1 || a.Nh * (2 * a.Lj - 1) > 256 || a.T < 1 || a.nb < 1 || a.G < 1 ||
+        a.G > 4 * a.Nh - 1 || maps < 1)
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)a.nb, (unsigned)maps);
+    switch (a.Nh) {
+#define S2DW_GA_CASE(NH) \
+    case NH: hipLaunchKernelGGL((gamma_alpha_adj_kernel<NH>), grid, dim3(256), 0, st, a); break;
+        S2DW_GA_CASE(1)
+        S2DW_GA_CASE(2)
+        S2DW_GA_CASE(3)
+        S2DW_GA_CASE(4)
+        S2DW_GA_CASE(5)
+        S2DW_GA_CASE(6)
+        S2DW_GA_CASE(7)
+        S2DW_GA_CASE(8)
+#undef S2DW_GA_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_alpha_gamma_fwd(const AlphaGammaArgs &a, int maps, hipStream_t st) {
     if (a.Nh < 1 || a.Nh > kMaxK || a.Lj < 1 || 2 * a.Nh * a.Lj > kAlphaGammaCoeffs || a.T < 1 || a.nb < 1 || maps < 1)

@@ -48,7 +48,6 @@ def test_stage_units_formulas(bench):
     assert by["hbm"] == sum(16 * N * Lj * L + 32 * Nh * Lj * Lj for Lj in Ljs)
     conv = [10.0 * (Tg + 2 * Lj - 2) * math.log2(Tg + 2 * Lj - 2) + 6.0 * (Tg + 2 * Lj - 2) for Lj in Ljs]
     assert by["alu"] == pytest.approx(sum(N * Lj * (dft + c) for Lj, c in zip(Ljs, conv)))
-    assert dict(u["alpha_adj"])["alu"] == pytest.approx(len(Ljs) * Nh * L * dft)
     two = [Lj for Lj in Ljs if Nh * (2 * Lj - 1) > 9 * (2 * N - 1)]
     one = [Lj for Lj in Ljs if Nh * (2 * Lj - 1) <= 9 * (2 * N - 1)]
     assert two and one
@@ -56,6 +55,9 @@ def test_stage_units_formulas(bench):
     assert dict(u["alpha_fwd"])["alu"] == pytest.approx(len(two) * Nh * L * dft)
     assert dict(u["alpha_gamma_fwd"]) == {"hbm": float(sum(16 * N * Lj * L + 8 * (2 * N - 1) * L * Tg
                                                              for Lj in one))}
+    assert dict(u["gamma_alpha_adj"]) == {"hbm": float(sum(8 * (2 * N - 1) * L * Tg + 16 * N * Lj * L
+                                                             for Lj in one))}
+    assert dict(u["alpha_adj"])["alu"] == pytest.approx(len(two) * Nh * L * dft)
     # without the fused pass (mixed precision) every scale has an alpha and a gamma pass
     u2 = bench.stage_units(kappa, L, N, T, fused=False)
     assert "alpha_gamma_fwd" not in u2

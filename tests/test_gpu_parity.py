@@ -153,11 +153,12 @@ def test_stage_timing_selection():
     finally:
         s2dw.profile(False)
         s2dw.profile_stages(None)
-    assert {"wigner_fwd", "beta_fwd", "alpha_fwd", "gamma_fwd", "gamma_adj", "alpha_adj", "beta_adj",
-            "wigner_adj"} <= set(every)
+    assert {"wigner_fwd", "beta_fwd", "alpha_fwd", "gamma_fwd", "alpha_gamma_fwd", "gamma_adj", "alpha_adj",
+            "gamma_alpha_adj", "beta_adj", "wigner_adj"} <= set(every)
     # one gamma pass per scale, fused with the alpha sums on the coarse scales
     assert every["wigner_fwd"][1] == 1
-    assert every["gamma_fwd"][1] + every["alpha_gamma_fwd"][1] == S and every["gamma_adj"][1] == S
+    assert every["gamma_fwd"][1] + every["alpha_gamma_fwd"][1] == S
+    assert every["gamma_adj"][1] + every["gamma_alpha_adj"][1] == S
     assert set(some) == {"beta_adj", "wigner_fwd"}
     assert some["wigner_fwd"][1] == 1 and some["beta_adj"][1] == every["beta_adj"][1]
     assert all(v[0] > 0 for v in some.values())
@@ -193,10 +194,10 @@ def test_mixed_precision_against_oracle(L, N, J_min, seed):
 
 @pytest.mark.parametrize("N", [2, 8])
 def test_blocked_alpha_scales_against_oracle(N):
-    # L = 600: the coarse scales (L_j <= 57) take the blocked alpha transforms, except in the
-    # analysis those with Nh (2 L_j - 1) <= 9 (2N - 1), which take the fused alpha and gamma
-    # pass (L_j <= 10 at N = 2 and at N = 8); analysis rows of every scale and (N = 2) the
-    # synthesis of arbitrary samples on sampled m columns against the oracle
+    # L = 600: the coarse scales (L_j <= 57) take the blocked alpha transforms, except those
+    # with Nh (2 L_j - 1) <= 9 (2N - 1), which take the fused alpha and gamma passes (L_j <= 10
+    # at N = 2 and at N = 8); analysis rows of every scale and (N = 2) the synthesis of
+    # arbitrary samples on sampled m columns against the oracle
     L, J_min = 600, 0
     print(f"blocked alpha scales L={L} N={N}", flush=True)
     lam = 2.0
