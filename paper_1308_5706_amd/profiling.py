@@ -30,7 +30,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
 # library stage name -> substring of the kernel symbol (demangled) that implements it
-STAGE_KERNELS = {
+STAGE_KERNELS = {  # first match wins: the fused passes before the gamma passes they contain
+    "alpha_gamma_fwd": ("alpha_gamma_fwd_kernel",),
+    "gamma_alpha_adj": ("gamma_alpha_adj_kernel",),
     "wigner_fwd": ("wig_fwd_kernel",),
     "wigner_adj": ("wig_adj_kernel",),
     "beta_fwd": ("beta_fwd_fft_kernel",),

@@ -75,3 +75,19 @@ def test_roofline_takes_the_nearer_roof(bench):
     units = {"s": [("hbm", 8e8), ("alu", 1e11)]}
     r = bench.roofline("s", ps, units)
     assert r["bound"] == "alu" and r["frac"] == pytest.approx(50.0 / bench.PEAK_FP64_TFLOPS)
+
+
+def test_profile_kernel_names_map_to_stages():
+    from paper_1308_5706_amd import profiling
+    cases = {
+        "void s2dw::gamma_fwd_kernel<HIP_vector_type<double, 2u>, 2>(s2dw::GammaArgs)": "gamma_fwd",
+        "void s2dw::alpha_gamma_fwd_kernel<true, 4>(s2dw::AlphaGammaArgs)": "alpha_gamma_fwd",
+        "void s2dw::gamma_alpha_adj_kernel<4>(s2dw::GammaAlphaArgs)": "gamma_alpha_adj",
+        "void s2dw::gamma_adj_kernel<HIP_vector_type<double, 2u>, 2>(s2dw::GammaArgs)": "gamma_adj",
+        "void s2dw::alpha_adj_blk_kernel<HIP_vector_type<double, 2u>, 512>(s2dw::StageArgs)": "alpha_adj",
+        "void s2dw::beta_adj_multi_kernel<HIP_vector_type<double, 2u>, 4096>(s2dw::StageArgs, s2dw::": "beta_adj",
+        "void s2dw::wig_adj_kernel<2, 2, double>(s2dw::WigAdjArgs)": "wigner_adj",
+        "__amd_rocclr_copyBuffer": None,
+    }
+    for name, stage in cases.items():
+        assert profiling.stage_of(name) == stage, name
