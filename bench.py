@@ -282,6 +282,52 @@ def extra_legs(args, s2dw, torch, dev, f, W, fr, L, N, lam, J_min, S, prec):
     return {"steer": steer, "multires": multires, "driscoll_healy": dh_grid, "complex_signal": complex_signal}
 
 
+def paper_sweep(args):
+    """Analogue of the paper's numerical experiment (Sec. 3.4, Fig. 3): round trips of random
+    band-limited signals whose f_lm have real and imaginary parts uniform in [-1, 1], N = 3,
+    lambda = 2, all scales (J_min = 0), ten signals per band-limit L, on the equiangular grid
+    and on the paper's Driscoll-Healy grid.  The error is the largest absolute difference
+    between the reconstructed and the original f_lm (mean and worst over the ten signals);
+    the time is the median device round trip (analysis with scaling, then synthesis) of one
+    signal.  The slope of log time against log L over the three largest L is reported next to
+    the paper's O(L^3)."""
+    import numpy as np
+    import torch
+    from paper_1308_5706_amd import s2dw
+    from paper_1308_5706_amd.inputs import random_flm_uniform
+
+    N, lam, J_min, runs = 3, 2.0, 0, 10
+    Ls = [int(x) for x in args.sweep_L.split(",")]
+    out = {}
+    for grid in ("mw", "dh"):
+        rows = []
+        for L in Ls:
+            errs, times = [], []
+            for r in range(runs):
+                f = torch.as_tensor(random_flm_uniform(L, 100 + r)).to("cuda")
+                if r == 0:  # plan and workspaces
+                    W, Wp = s2dw.analysis(f, L, N, lam, J_min, grid=grid)
+                    s2dw.synthesis(W, Wp, L, N, lam, J_min, grid=grid)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                W, Wp = s2dw.analysis(f, L, N, lam, J_min, grid=grid)
+                fr = s2dw.synthesis(W, Wp, L, N, lam, J_min, grid=grid)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                errs.append(float((fr - f).abs().max().item()))
+                W = Wp = fr = None
+            rows.append({"L": L, "err_mean": float(np.mean(errs)), "err_max": float(np.max(errs)),
+                         "ms": 1e3 * float(np.median(times))})
+            print(f"# sweep {grid} L={L}: error {rows[-1]['err_mean']:.2e}, {rows[-1]['ms']:.3f} ms", file=sys.stderr,
+                  flush=True)
+        big = rows[-3:]
+        slope = float(np.polyfit(np.log([q["L"] for q in big]), np.log([q["ms"] for q in big]), 1)[0])
+        out[grid] = {"rows": rows, "time_slope_vs_L": slope}
+    print(json.dumps({"paper_sweep": out, "N": N, "lambda": lam, "J_min": J_min, "signals_per_L": runs,
+                      "signal": "f_lm real and imaginary parts uniform in [-1, 1] (real signal)",
+                      "data": "synthetic"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +345,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline round trip (no steering / multiresolution / Driscoll-Healy / "
                          "complex-signal legs), e.g. under a profiler")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="only run the analogue of the paper's accuracy and timing experiment (Fig. 3): "
+                         "N = 3, all scales, ten uniform random signals per band-limit, both grids")
+    ap.add_argument("--sweep-L", default="64,128,256,512,1024,2048", help="band-limits of --paper-sweep")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -307,6 +357,10 @@ def main():
               "transform on one GPU; maps and requests are independent, so several GPUs would each take "
               "their own)", file=sys.stderr)
         sys.exit(2)
+
+    if args.paper_sweep:
+        paper_sweep(args)
+        return
 
     import numpy as np
     import torch
