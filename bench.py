@@ -82,14 +82,14 @@ def cpu_baseline(L, N, lam, J_min, budget_rows=None, budget_cols=None):
 
 
 def direct_alpha_gamma(N, Lj):
-    """Whether the analysis of a scale takes the fused alpha and gamma pass (FP64 real
-    signals on the equiangular grid; the library's rule: Nh (2Lj - 1) complex multiply-adds
-    per sample at most 9 G, G = 2N - 1 the W values written per sample)."""
+    """Whether a scale takes the fused alpha and gamma passes (real signals on the
+    equiangular grid; the library's rule: Nh (2Lj - 1) complex multiply-adds per sample at
+    most 9 G and 256, G = 2N - 1 the W values written or read per sample)."""
     Nh = N - N // 2
     return Nh * (2 * Lj - 1) <= min(9 * (2 * N - 1), 256) and 2 * Nh * Lj <= 1024
 
 
-def stage_units(kappa, L, N, T, fused=True):
+def stage_units(kappa, L, N, T, fused=True, fused_adj=True):
     """Algorithmic work of each stage per step (one map), summed over the scales.
 
     Wigner stages (one launch per direction): 5 FLOP per term of the l-sum / m'-contraction
@@ -103,10 +103,10 @@ def stage_units(kappa, L, N, T, fused=True):
       gamma_adj W 8 G L T in,                X 16 Nh L T out
       alpha_adj X 16 Nh L T in,              G 16 N Lj L out
       beta_adj  G 16 N Lj L in,              V 32 Nh Lj^2 out
-      alpha_gamma_fwd (coarse scales of an FP64 analysis, fused = True; they leave
+      alpha_gamma_fwd (coarse scales of the analysis, fused = True; they leave
                 alpha_fwd and gamma_fwd)  Ub 16 N Lj L in,  W 8 G L T out
-      gamma_alpha_adj (the same scales of the synthesis; they leave gamma_adj and
-                alpha_adj)  W 8 G L T in,  G 16 N Lj L out
+      gamma_alpha_adj (the same scales of an FP64 synthesis, fused_adj = True; they leave
+                gamma_adj and alpha_adj)  W 8 G L T in,  G 16 N Lj L out
     and, for the four Fourier stages, FLOP with a length-n complex DFT counted as an FFT,
     5 n log2 n, whatever way it is computed:
       beta_fwd  N Lj columns, one length-T DFT each
@@ -126,14 +126,16 @@ def stage_units(kappa, L, N, T, fused=True):
             Ljs.append(max(nz) + 1)
     two = [Lj for Lj in Ljs if not (fused and direct_alpha_gamma(N, Lj))]
     one = [Lj for Lj in Ljs if fused and direct_alpha_gamma(N, Lj)]
+    two_adj = [Lj for Lj in Ljs if not (fused_adj and direct_alpha_gamma(N, Lj))]
+    one_adj = [Lj for Lj in Ljs if fused_adj and direct_alpha_gamma(N, Lj)]
     per = {
         "beta_fwd": [16 * N * Lj * Lj + 16 * N * Lj * L for Lj in Ljs],
         "alpha_fwd": [16 * N * Lj * L + 16 * Nh * L * Tg for Lj in two],
         "gamma_fwd": [16 * Nh * L * Tg + 8 * G * L * Tg for Lj in two],
         "alpha_gamma_fwd": [16 * N * Lj * L + 8 * G * L * Tg for Lj in one],
-        "gamma_adj": [8 * G * L * Tg + 16 * Nh * L * Tg for Lj in two],
-        "alpha_adj": [16 * Nh * L * Tg + 16 * N * Lj * L for Lj in two],
-        "gamma_alpha_adj": [8 * G * L * Tg + 16 * N * Lj * L for Lj in one],
+        "gamma_adj": [8 * G * L * Tg + 16 * Nh * L * Tg for Lj in two_adj],
+        "alpha_adj": [16 * Nh * L * Tg + 16 * N * Lj * L for Lj in two_adj],
+        "gamma_alpha_adj": [8 * G * L * Tg + 16 * N * Lj * L for Lj in one_adj],
         "beta_adj": [16 * N * Lj * L + 32 * Nh * Lj * Lj for Lj in Ljs],
     }
     dft = 5.0 * Tg * math.log2(Tg)
@@ -145,7 +147,7 @@ def stage_units(kappa, L, N, T, fused=True):
     flops = {
         "beta_fwd": sum(N * Lj * dft for Lj in Ljs),
         "alpha_fwd": len(two) * Nh * L * dft,
-        "alpha_adj": len(two) * Nh * L * dft,
+        "alpha_adj": len(two_adj) * Nh * L * dft,
         "beta_adj": sum(N * Lj * (dft + conv(Lj)) for Lj in Ljs),
     }
     units = {k: [("hbm", float(sum(v)))] for k, v in per.items() if v}
@@ -441,7 +443,7 @@ def main():
     # roofline of that kernel, timed with HIP events during the timed steps
     kappa, _, _ = s2dw.wavelet_tables(L, N, lam, J_min)
     T = wigner_terms(kappa, N)
-    units = stage_units(kappa, L, N, T, fused=prec == "fp64")
+    units = stage_units(kappa, L, N, T, fused_adj=prec == "fp64")
     roof = roofline(dom, live[dom], units)
     traffic = None
     try:

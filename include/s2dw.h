@@ -231,8 +231,9 @@ int s2dw_wavelet_tables(const s2dw_params *p, double *kappa, double *phi, double
  * fills up to max entries (host memory) with per-stage totals since the last clear;
  * *n receives the number of stages.  Names: pad, wigner_fwd, beta_fwd, alpha_fwd,
  * gamma_fwd, alpha_gamma_fwd (analysis; the last is the fused alpha and gamma pass that
- * coarse scales take in FP64), gamma_adj, gamma_alpha_adj (its synthesis counterpart),
- * alpha_adj, beta_adj, wigner_adj, syn_final (synthesis), scaling, steer.
+ * the coarse scales of real signals take), gamma_adj, gamma_alpha_adj (its synthesis
+ * counterpart, FP64), alpha_adj, beta_adj, wigner_adj, syn_final (synthesis), scaling,
+ * steer.
  */
 typedef struct s2dw_stage_time {
     char name[24];

@@ -857,16 +857,17 @@ int grid_limits(const s2dw_params *p, std::vector<int> &Lg) {
         if ((x) != hipSuccess) return S2DW_E_DEVICE;    \
     } while (0)
 
-// Coarse scales (FP64, real signals) take the fused alpha and gamma passes of the analysis
-// and the synthesis while Nh (2Lj - 1) stays within 9 G and 256 (the outputs of a ring in
-// the synthesis pass, at most one per thread).  Nh (2Lj - 1) is the number of complex
+// Coarse scales of real signals take the fused alpha and gamma passes (the analysis one
+// in both precisions: it computes in FP64 and reads and writes Ub and W in the plan's
+// precision; the synthesis one in FP64) while Nh (2Lj - 1) stays within 9 G and 256 (the
+// outputs of a ring in the synthesis pass, at most one per thread).  Nh (2Lj - 1) is the number of complex
 // multiply-adds per sample, G the number of W values a sample writes or reads: the passes
 // then cost little more than their W traffic, against a blocked alpha transform plus a
 // gamma pass that also writes and reads Y or X (at L = 1024, N = 8, for Lj = 4, 8, 16:
 // analysis 65-73 us per scale, synthesis 57-113 us, against about 130 us each).
-bool direct_alpha_gamma(int Nh, int G, int Lj, int f32, bool cx) {
+bool direct_alpha_gamma(int Nh, int G, int Lj, bool cx) {
     const int terms = Nh * (2 * Lj - 1);
-    return !f32 && !cx && terms <= 9 * G && terms <= 256 && 2 * Nh * Lj <= kAlphaGammaCoeffs;
+    return !cx && terms <= 9 * G && terms <= 256 && 2 * Nh * Lj <= kAlphaGammaCoeffs;
 }
 
 // Wigner-stage analysis + beta/alpha/gamma sums for a batch of `maps` maps: f_lm of map i at
@@ -939,7 +940,7 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
             Stage sg("beta_fwd", st);
             S2DW_CHECK_HIP(launch_beta_fwd_fft(b, P.PA[j], maps, st));
         }
-        if (direct_alpha_gamma(P.Nh, P.ng, Lj, f32, cx)) {
+        if (direct_alpha_gamma(P.Nh, P.ng, Lj, cx)) {
             AlphaGammaArgs d{};
             d.in = w.Ub;
             d.wout = Wj;
@@ -953,6 +954,7 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
             d.N = N;
             d.Nh = P.Nh;
             d.G = P.ng;
+            d.f32 = f32;
             Stage sg("alpha_gamma_fwd", st);
             S2DW_CHECK_HIP(launch_alpha_gamma_fwd(d, maps, st));
             continue;
@@ -1028,7 +1030,9 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
         void *gout = !merged ? (void *)w.Ub
                              : (f32 ? (void *)((float2 *)w.Ub + P.goff[j]) : (void *)(w.Ub + P.goff[j]));
         const double qscale = (2.0 * M_PI / M) * (2.0 * M_PI / P.ng);  // alpha and gamma quadrature weights
-        const bool fused = direct_alpha_gamma(P.Nh, P.ng, Lj, f32, cx);
+        // FP64 only: the fused pass computes in FP64 and is bound by its arithmetic at the
+        // larger Lj, where the FP32 passes of the mixed path are cheaper
+        const bool fused = direct_alpha_gamma(P.Nh, P.ng, Lj, cx) && !f32;
         if (fused) {
             GammaAlphaArgs d{};
             d.win = Wj;
@@ -1044,6 +1048,7 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
             d.Nh = P.Nh;
             d.G = P.ng;
             d.scale = qscale;
+            d.f32 = f32;
             Stage sg("gamma_alpha_adj", st);
             S2DW_CHECK_HIP(launch_gamma_alpha_adj(d, maps, st));
         } else {

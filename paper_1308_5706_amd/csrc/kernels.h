@@ -105,10 +105,10 @@ struct GammaArgs {
     int L, T, G, Nh, f32;
 };
 hipError_t launch_gamma_fwd(const GammaArgs &a, int maps, hipStream_t st);
-// Analysis alpha and gamma sums of one coarse scale in one pass (FP64, real signals): Ub
+// Analysis alpha and gamma sums of one coarse scale in one pass (real signals): Ub
 // [N][Lj][nb] (the beta stage's output, per-map stride s_in complex elements) -> W
-// [G][nb][T] (per-map stride s_w real elements); eph = e^{2 pi i r/T}, r < T; tg as for
-// the gamma pass.
+// [G][nb][T] (per-map stride s_w real elements), both FP32 with f32; eph = e^{2 pi i r/T},
+// r < T, and tg (as for the FP64 gamma pass) in FP64.
 constexpr int kAlphaGammaCoeffs = 1024;  // 2 Nh Lj complex coefficients of a ring at most
 struct AlphaGammaArgs {
     const void *in;
@@ -116,20 +116,21 @@ struct AlphaGammaArgs {
     const void *tg;
     const void *eph;
     size_t s_in, s_w;
-    int nb, T, Lj, N, Nh, G;
+    int nb, T, Lj, N, Nh, G, f32;
 };
 hipError_t launch_alpha_gamma_fwd(const AlphaGammaArgs &a, int maps, hipStream_t st);
-// Synthesis gamma and alpha quadratures of one coarse scale in one pass (FP64, real
-// signals): W [G][nb][T] (per-map stride s_w real elements) -> G [N][Lj][nb] (per-map stride
-// s_out complex elements); tg = e^{-i n gamma_g} [G][Nh]; eph = e^{2 pi i r/T}, r < T;
-// scale = the product of the two quadrature weights.  Nh (2Lj - 1) <= 256.
+// Synthesis gamma and alpha quadratures of one coarse scale in one pass (real signals): W
+// [G][nb][T] (per-map stride s_w real elements) -> G [N][Lj][nb] (per-map stride s_out
+// complex elements), both FP32 with f32; tg = e^{-i n gamma_g} [G][Nh] and eph =
+// e^{2 pi i r/T}, r < T, in FP64; scale = the product of the two quadrature weights.
+// Nh (2Lj - 1) <= 256.
 struct GammaAlphaArgs {
     const void *win;
     void *out;
     const void *tg;
     const void *eph;
     size_t s_w, s_out;
-    int nb, T, Lj, N, Nh, G;
+    int nb, T, Lj, N, Nh, G, f32;
     double scale;
 };
 hipError_t launch_gamma_alpha_adj(const GammaAlphaArgs &a, int maps, hipStream_t st);

@@ -411,7 +411,8 @@ __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
         }
 }
 
-// Coarse scales of the analysis: both sums at once, sample by sample, without Y:
+// Coarse scales of the analysis: both sums at once, sample by sample, without Y (FP64
+// arithmetic; C = double2 with FP64 arrays, float2 with the FP32 Ub and W of the mixed path):
 //   W(g, b, a) = sum_{n'} Re(tg[g][n'] Y_n'(b, a)),  Y_n(b, a) = sum_{|m|<Lj} C_n(b, m) z^m,
 // z = e^{i alpha_a}.  With C_n(b, -m) = conj(Ub[-n][m][b]) and |z| = 1, Y_n = p(z) + conj(q(z)),
 // p(z) = sum_{m>=0} Ub[n][m][b] z^m and q(z) = sum_{m>=1} Ub[-n][m][b] z^m, both by Horner's
@@ -425,17 +426,19 @@ __global__ void __launch_bounds__(256) gamma_adj_kernel(const GammaArgs a) {
 // a = -(b & 1) and the ring's one unpaired sample (first or last) is written alone.
 // Otherwise one sample per thread.  NH = Nh (a template parameter, so that the Y values
 // of a thread take only the registers they need).
-template <bool PAIR, int NH>
+template <bool PAIR, int NH, class C>
 __global__ void __launch_bounds__(256) alpha_gamma_fwd_kernel(const AlphaGammaArgs a) {
+    using R = real_t<C>;
     constexpr int V = PAIR ? 2 : 1;
     __shared__ double2 cs[kAlphaGammaCoeffs];  // [k][side][m]: side 0 row n, side 1 row -n
     constexpr int Nh = NH;
     const int b = blockIdx.y, Lj = a.Lj, nb = a.nb, N = a.N, T = a.T;
-    const double2 *__restrict__ U = (const double2 *)a.in + blockIdx.z * a.s_in + b;
+    const C *__restrict__ U = (const C *)a.in + blockIdx.z * a.s_in + b;
     for (int i = threadIdx.x; i < 2 * Nh * Lj; i += 256) {
         const int k = i / (2 * Lj), r = i - k * 2 * Lj, side = r >= Lj ? 1 : 0, m = r - side * Lj;
         const int ni = N / 2 + k, row = side ? N - 1 - ni : ni;
-        cs[i] = U[((size_t)row * Lj + m) * nb];
+        const C u = U[((size_t)row * Lj + m) * nb];
+        cs[i] = make_double2((double)u.x, (double)u.y);
     }
     __syncthreads();
     const int t = blockIdx.x * 256 + threadIdx.x;
@@ -475,7 +478,7 @@ __global__ void __launch_bounds__(256) alpha_gamma_fwd_kernel(const AlphaGammaAr
         }
     }
     const size_t plane = (size_t)nb * T;
-    double *__restrict__ W = (double *)a.wout + blockIdx.z * a.s_w + (size_t)b * T + x0;
+    R *__restrict__ W = (R *)a.wout + blockIdx.z * a.s_w + (size_t)b * T + x0;
     const double2 *__restrict__ tg = (const double2 *)a.tg;
     for (int g = 0; g < a.G; ++g) {
         double acc[V];
@@ -487,18 +490,19 @@ __global__ void __launch_bounds__(256) alpha_gamma_fwd_kernel(const AlphaGammaAr
 #pragma unroll
             for (int v = 0; v < V; ++v) acc[v] = fma(y[k][v].x, w.x, fma(-y[k][v].y, w.y, acc[v]));
         }
-        double *dst = W + g * plane;
+        R *dst = W + g * plane;
         if (PAIR && ok[0] && ok[V - 1]) {
-            nt_store(make_double2(acc[0], acc[V - 1]), (double2 *)dst);
+            nt_store(mk<C>((R)acc[0], (R)acc[V - 1]), (C *)dst);
         } else {
 #pragma unroll
             for (int v = 0; v < V; ++v)
-                if (ok[v]) __builtin_nontemporal_store(acc[v], dst + v);
+                if (ok[v]) __builtin_nontemporal_store((R)acc[v], dst + v);
         }
     }
 }
 
-// Coarse scales of the synthesis: both quadratures at once, ring by ring, without X:
+// Coarse scales of the synthesis: both quadratures at once, ring by ring, without X (FP64
+// arithmetic; C = double2 with FP64 arrays, float2 with the FP32 W and G of the mixed path):
 //   Gs_n(b, m) = scale sum_a X_n(b, a) e^{-i m alpha_a},  X_n(b, a) = sum_g W(g, b, a) tg[g][n],
 // for n >= 0 and |m| < Lj.  One workgroup per ring b; the T samples go in chunks of 256:
 // the workgroup forms X of the chunk in LDS (one sample per thread, the gamma sum), then
@@ -508,8 +512,9 @@ __global__ void __launch_bounds__(256) alpha_gamma_fwd_kernel(const AlphaGammaAr
 // partial sums are added in a fixed order at the end.  The outputs
 // are stored as the alpha stage stores them: Gs_n(b, m) in row n for m >= 0 and conj Gs_n
 // (b, m) in row -n at -m for m <= 0 (not for the row n = 0 of odd N).
-template <int NH>
+template <int NH, class C>
 __global__ void __launch_bounds__(256) gamma_alpha_adj_kernel(const GammaAlphaArgs a) {
+    using R = real_t<C>;
     constexpr int NT = 256;
     __shared__ double2 xs[NH][NT];
     __shared__ double2 red[NT];
@@ -523,7 +528,7 @@ __global__ void __launch_bounds__(256) gamma_alpha_adj_kernel(const GammaAlphaAr
     const double2 rho = cconj(eph[mm]);  // e^{-i m alpha_1}
     const int len = (NT + H - 1) / H;
     const size_t plane = (size_t)a.nb * T;
-    const double *__restrict__ Wr = (const double *)a.win + blockIdx.y * a.s_w + (size_t)b * T;
+    const R *__restrict__ Wr = (const R *)a.win + blockIdx.y * a.s_w + (size_t)b * T;
     const double2 *__restrict__ tg = (const double2 *)a.tg;
     // W of the next chunk waits in registers (G <= GMAX = 4 NH - 1, since N <= 2 NH): its
     // loads are issued before the alpha sums of the current chunk
@@ -533,7 +538,7 @@ __global__ void __launch_bounds__(256) gamma_alpha_adj_kernel(const GammaAlphaAr
         const int x = a0 + tid;
 #pragma unroll
         for (int g = 0; g < GMAX; ++g)
-            wn[g] = (g < G && x < T) ? __builtin_nontemporal_load(Wr + g * plane + (x < T ? x : 0)) : 0.0;
+            wn[g] = (g < G && x < T) ? (double)__builtin_nontemporal_load(Wr + g * plane + x) : 0.0;
     };
     load_chunk(0);
     double2 acc = zero2<double2>();
@@ -577,9 +582,9 @@ __global__ void __launch_bounds__(256) gamma_alpha_adj_kernel(const GammaAlphaAr
     if (tid < nouts) {
         double2 tot = red[tid];
         for (int hh = 1; hh < H; ++hh) tot = cadd(tot, red[hh * nouts + tid]);
-        const double2 z = cscale(tot, a.scale);
+        const C z = mk<C>((R)(tot.x * a.scale), (R)(tot.y * a.scale));
         const int ni = N / 2 + k, nj = N - 1 - ni;
-        double2 *__restrict__ Gout = (double2 *)a.out + blockIdx.y * a.s_out + b;
+        C *__restrict__ Gout = (C *)a.out + blockIdx.y * a.s_out + b;
         if (m >= 0) Gout[((size_t)ni * Lj + m) * a.nb] = z;
         if (m <= 0 && ni != nj) Gout[((size_t)nj * Lj + (size_t)(-m)) * a.nb] = cconj(z);
     }
@@ -948,9 +953,10 @@ hipError_t launch_gamma_alpha_adj(const GammaAlphaArgs &a, int maps, hipStream_t
         a.G > 4 * a.Nh - 1 || maps < 1)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)a.nb, (unsigned)maps);
-    switch (a.Nh) {
-#define S2DW_GA_CASE(NH) \
-    case NH: hipLaunchKernelGGL((gamma_alpha_adj_kernel<NH>), grid, dim3(256), 0, st, a); break;
+    switch (a.Nh * 2 + (a.f32 ? 1 : 0)) {
+#define S2DW_GA_CASE(NH)                                                                                    \
+    case 2 * NH: hipLaunchKernelGGL((gamma_alpha_adj_kernel<NH, double2>), grid, dim3(256), 0, st, a); break; \
+    case 2 * NH + 1: hipLaunchKernelGGL((gamma_alpha_adj_kernel<NH, float2>), grid, dim3(256), 0, st, a); break;
         S2DW_GA_CASE(1)
         S2DW_GA_CASE(2)
         S2DW_GA_CASE(3)
@@ -969,13 +975,16 @@ hipError_t launch_alpha_gamma_fwd(const AlphaGammaArgs &a, int maps, hipStream_t
     if (a.Nh < 1 || a.Nh > kMaxK || a.Lj < 1 || 2 * a.Nh * a.Lj > kAlphaGammaCoeffs || a.T < 1 || a.nb < 1 || maps < 1)
         return hipErrorInvalidValue;
     const size_t plane = (size_t)a.nb * a.T;
+    const size_t pair_bytes = a.f32 ? 8 : 16;
     const bool pair = a.T % 2 == 1 && plane % 2 == 0 && (maps == 1 || a.s_w % 2 == 0) &&
-                      ((uintptr_t)a.wout & 15) == 0;
+                      ((uintptr_t)a.wout % pair_bytes) == 0;
     const dim3 grid((unsigned)(((pair ? a.T / 2 + 1 : a.T) + 255) / 256), (unsigned)a.nb, (unsigned)maps);
-    switch (a.Nh * 2 + (pair ? 1 : 0)) {
-#define S2DW_AG_CASE(NH)                                                                           \
-    case 2 * NH: hipLaunchKernelGGL((alpha_gamma_fwd_kernel<false, NH>), grid, dim3(256), 0, st, a); break; \
-    case 2 * NH + 1: hipLaunchKernelGGL((alpha_gamma_fwd_kernel<true, NH>), grid, dim3(256), 0, st, a); break;
+    switch (a.Nh * 4 + (pair ? 2 : 0) + (a.f32 ? 1 : 0)) {
+#define S2DW_AG_CASE(NH)                                                                               \
+    case 4 * NH: hipLaunchKernelGGL((alpha_gamma_fwd_kernel<false, NH, double2>), grid, dim3(256), 0, st, a); break; \
+    case 4 * NH + 1: hipLaunchKernelGGL((alpha_gamma_fwd_kernel<false, NH, float2>), grid, dim3(256), 0, st, a); break; \
+    case 4 * NH + 2: hipLaunchKernelGGL((alpha_gamma_fwd_kernel<true, NH, double2>), grid, dim3(256), 0, st, a); break; \
+    case 4 * NH + 3: hipLaunchKernelGGL((alpha_gamma_fwd_kernel<true, NH, float2>), grid, dim3(256), 0, st, a); break;
         S2DW_AG_CASE(1)
         S2DW_AG_CASE(2)
         S2DW_AG_CASE(3)

@@ -58,9 +58,12 @@ def test_stage_units_formulas(bench):
     assert dict(u["gamma_alpha_adj"]) == {"hbm": float(sum(8 * (2 * N - 1) * L * Tg + 16 * N * Lj * L
                                                              for Lj in one))}
     assert dict(u["alpha_adj"])["alu"] == pytest.approx(len(two) * Nh * L * dft)
-    # without the fused pass (mixed precision) every scale has an alpha and a gamma pass
-    u2 = bench.stage_units(kappa, L, N, T, fused=False)
-    assert "alpha_gamma_fwd" not in u2
+    # without the fused passes every scale has an alpha and a gamma pass
+    u2 = bench.stage_units(kappa, L, N, T, fused=False, fused_adj=False)
+    assert "alpha_gamma_fwd" not in u2 and "gamma_alpha_adj" not in u2
+    u3 = bench.stage_units(kappa, L, N, T, fused_adj=False)  # mixed precision: the analysis pass only
+    assert u3["alpha_gamma_fwd"] == u["alpha_gamma_fwd"] and "gamma_alpha_adj" not in u3
+    assert dict(u3["gamma_adj"]) == dict(u2["gamma_adj"])
     assert dict(u2["gamma_fwd"]) == {"hbm": float(len(Ljs) * (16 * Nh * L * Tg + 8 * (2 * N - 1) * L * Tg))}
     assert u["wigner_fwd"] == [("alu", 5.0 * T)]
 
