@@ -135,7 +135,7 @@ def write_profiles(d: str, name: str, commands: str, copy_bytes: int, out_dir: s
     os.makedirs(out_dir, exist_ok=True)
     kernels, traffic, stages, cal = summarize(d, copy_bytes)
     src = kernel_sources_hash()
-    lines = [f"# rocprofv3 kernel trace: {name}", "", "Commands (from the repository root on the GPU box):", "",
+    lines = [f"# rocprofv3 kernel trace: {name}", "", "Commands (run from the repository root):", "",
              "```", commands.strip(), "```", "",
              f"Kernel sources sha256: `{src}`", "",
              "| kernel | dispatches | total ms | avg us | stage | HBM read MB/dispatch | HBM write MB/dispatch |",
