@@ -76,13 +76,11 @@ __device__ __forceinline__ void dft4(C *v) {
     dft4s<SIGN>(v[0], v[1], v[2], v[3]);
 }
 
+// Second half of dft8: the twiddles w8^{n2 k1} and the DFT2 over n2.
 template <int SIGN, class C>
-__device__ __forceinline__ void dft8(C *v) {
-    // n = 2 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle w8^{n2 k1}, DFT2 over n2
+__device__ __forceinline__ void dft8_tail(C *v) {
     using R = real_t<C>;
     constexpr R c = (R)0.70710678118654752440;
-    dft4s<SIGN>(v[0], v[2], v[4], v[6]);
-    dft4s<SIGN>(v[1], v[3], v[5], v[7]);
     v[3] = cmul(v[3], mk<C>(c, SIGN * c));
     v[5] = mul_si<SIGN>(v[5]);
     v[7] = cmul(v[7], mk<C>(-c, SIGN * c));
@@ -94,6 +92,29 @@ __device__ __forceinline__ void dft8(C *v) {
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = o[i];
+}
+
+template <int SIGN, class C>
+__device__ __forceinline__ void dft8(C *v) {
+    // n = 2 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle w8^{n2 k1}, DFT2 over n2
+    dft4s<SIGN>(v[0], v[2], v[4], v[6]);
+    dft4s<SIGN>(v[1], v[3], v[5], v[7]);
+    dft8_tail<SIGN>(v);
+}
+
+// dft8 of inputs whose upper half v[4..7] is zero (v[4..7] are not read): the DFT4s over n1
+// then see two zero inputs each.
+template <int SIGN, class C>
+__device__ __forceinline__ void dft8_low(C *v) {
+#pragma unroll
+    for (int n2 = 0; n2 < 2; ++n2) {
+        const C x0 = v[n2], x1 = v[2 + n2], d = mul_si<SIGN>(x1);
+        v[n2] = cadd(x0, x1);
+        v[4 + n2] = csub(x0, x1);
+        v[2 + n2] = cadd(x0, d);
+        v[6 + n2] = csub(x0, d);
+    }
+    dft8_tail<SIGN>(v);
 }
 
 template <int SIGN, class C>
@@ -217,6 +238,32 @@ __device__ __forceinline__ void pass(int Ns, int tid0, const C *__restrict__ tw,
     __syncthreads();
 }
 
+// The first forward pass (span 1, no twiddles) of radix 8 when the column has at most P/2
+// nonzero inputs: inputs j + r P/8 with r >= 4 lie at or beyond P/2, so they are zero and
+// are neither read nor added (dft8_low).  Same outputs as pass() up to the sign of zeros.
+template <int P, int NT, int SIGN, class C, class In, class Out>
+__device__ __forceinline__ void pass_first_low(int tid0, In in, Out out) {
+    constexpr int R = 8, NB = P / R, PER = NB / NT;
+    int tid = tid0;
+    __asm__ volatile("" : "+v"(tid));
+    C v[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * NT;
+#pragma unroll
+        for (int r = 0; r < R / 2; ++r) v[q][r] = in(j + r * NB, q * R + r);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * NT;
+        dft8_low<SIGN>(v[q]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) out(j * R + r, v[q][r], q * R + r);
+    }
+    __syncthreads();
+}
+
 // The last forward pass, the product with the spectrum and the first inverse pass, fused
 // in registers.  With the partial pass of radix R = P / (P/R) taken last in the forward
 // transform and first in the inverse one, butterfly j of the forward pass produces
@@ -259,9 +306,11 @@ __device__ __forceinline__ void mid_pass(int tid0, const C *__restrict__ tw, con
 // by the spectrum hh, transformed back and written by `out` (unnormalised: hh carries 1/P).
 // Forward passes: radix RM (span 1, RM, ...), then the partial radix last; inverse passes:
 // the partial radix first, then radix RM.  The pass at the junction is fused (mid_pass).
+// n_in: `in` returns zero at every index >= n_in (with RM = 8 and n_in <= P/2 the first
+// pass skips the zero half).
 template <int P, int RM, class C, class In, class Out>
 __device__ __forceinline__ void convolve_io(C *buf, int tid, const C *__restrict__ tw, const C *__restrict__ hh,
-                                            In in, Out out) {
+                                            In in, Out out, int n_in = P) {
     static_assert(P >= 32 && (P & (P - 1)) == 0, "power of two >= 32");
     using PL = Plan<P, RM>;
     constexpr int NT = PL::NT;
@@ -272,8 +321,16 @@ __device__ __forceinline__ void convolve_io(C *buf, int tid, const C *__restrict
     int Ns = 1;
 #pragma unroll
     for (int s = 0; s < NSIDE; ++s) {
-        if (s == 0) pass<P, NT, RM, -1>(Ns, tid, tw, in, lo);
-        else pass<P, NT, RM, -1>(Ns, tid, tw, li, lo);
+        if (s == 0) {
+            if constexpr (RM == 8) {
+                if (n_in <= P / 2) pass_first_low<P, NT, -1, C>(tid, in, lo);
+                else pass<P, NT, RM, -1>(Ns, tid, tw, in, lo);
+            } else {
+                pass<P, NT, RM, -1>(Ns, tid, tw, in, lo);
+            }
+        } else {
+            pass<P, NT, RM, -1>(Ns, tid, tw, li, lo);
+        }
         Ns *= RM;
     }
     if constexpr (NSIDE == 0) mid_pass<P, NT, RJ>(tid, tw, hh, in, out);

@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const 
         const int b = i - (Na - 1);
         if (b >= 0 && b < nb) out[b] = cmul(v, csq[b]);
     };
-    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, Na);
 }
 
 // ------------------------------------------------------------------ alpha and gamma stages
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_fwd_fft_kernel(const
         const int x = i - (Na - 1);
         if (x >= 0 && x < T) Y[x] = cmul(v, csq[x]);
     };
-    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, Na);
 }
 
 template <class C, int P>
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const
             if (m <= 0 && !zero_n) Gm[(size_t)(-m) * nb] = cconj(z);
         }
     };
-    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, T);
 }
 
 // Blocked alpha sums for scales with few coefficients (2Lj - 1 well below T): the T samples
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(P / kRM) alpha_fwd_blk_kernel(const StageArgs 
             const int x = i - (Na - 1);
             if (x >= 0 && x < B && a0 + x < T) Y[a0 + x] = cmul(v, csq[x]);
         };
-        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, Na);
     }
 }
 
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(P / kRM) alpha_adj_blk_kernel(const StageArgs 
                 acc[s] = cadd(acc[s], cmul(cmulc(v, csq[m < 0 ? -m : m]), eph[r]));
             }
         };
-        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, B);
     }
     const real_t<C> sc = (real_t<C>)a.scale;
     C *__restrict__ Gp = (C *)a.out + blockIdx.y * a.s_out + (size_t)ni * Lj * nb + b;
@@ -736,7 +736,7 @@ __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int co
             const int q = i - (T - 1);
             if (q >= 0 && q < T) buf[pad(q)] = cmulc(v, cpp[q]);
         };
-        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in1, st1);
+        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in1, st1, T);
         auto in2 = [&](int i, int = 0) { return i < T ? buf[pad(i)] : zero2<C>(); };
         // V(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + T - 1.  With two columns the
         // first one waits in registers (each thread keeps the outputs of its storer slots)
@@ -747,14 +747,14 @@ __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int co
                 kq[slot] = (q >= 0 && q < Nk) ? q : -1;
                 keep[slot] = v;
             };
-            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, hh2, in2, st2);
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, hh2, in2, st2, T);
         } else {
             const int sh = c * Nk;
             auto st2 = [&](int i, C v, int = 0) {
                 const int q = i - (T - 1);
                 if (q >= 0 && q < Nk) buf[pad(sh + q)] = v;
             };
-            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, hh2, in2, st2);
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, hh2, in2, st2, T);
         }
     }
     if (ncol > 1) {
@@ -826,14 +826,14 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_dh_kernel(const S
                 kq[slot] = ok ? q : -1;
                 keep[slot] = ok ? cmulc(v, cpp[q - (Lj - 1)]) : v;
             };
-            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, nb);
         } else {
             const int sh = c * Nk;
             auto st = [&](int i, C v, int = 0) {
                 const int q = i - (nb - 1);
                 if (q >= 0 && q < Nk) buf[pad(sh + q)] = cmulc(v, cpp[q - (Lj - 1)]);
             };
-            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st);
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, nb);
         }
     }
     if (ncol > 1) {
