@@ -40,6 +40,8 @@ CASES = [  # (L, N, J_min, seed)
     (64, 8, 1, 3),
     (70, 5, 2, 4),
     (130, 2, 3, 5),  # several m tiles with a ragged tail
+    (40, 16, 0, 6),  # the most carried orders (8 with n >= 0): the widest fused coarse-scale passes
+    (36, 15, 0, 7),  # odd N with 8 orders n >= 0, the row n = 0 among them
 ]
 
 
