@@ -35,6 +35,7 @@ CASES = [  # (L, N, J_min)
     (40, 8, 1),
     (64, 1, 2),   # axisymmetric: one base orientation
     (70, 5, 2),
+    (40, 16, 0),  # eight carried orders n >= 0 with the N = 16 base orientations of the grid
 ]
 
 

@@ -171,7 +171,7 @@ def test_stage_timing_selection():
 MIXED_TOL = 1e-5  # FP32 stages: bound on the relative max-error against the FP64 oracle
 
 
-@pytest.mark.parametrize("L,N,J_min,seed", [(32, 4, 0, 0), (70, 5, 2, 4), (130, 2, 3, 5)])
+@pytest.mark.parametrize("L,N,J_min,seed", [(32, 4, 0, 0), (70, 5, 2, 4), (130, 2, 3, 5), (40, 16, 0, 6)])
 def test_mixed_precision_against_oracle(L, N, J_min, seed):
     print(f"mixed precision L={L} N={N} J_min={J_min}", flush=True)
     lam = 2.0
