@@ -506,10 +506,11 @@ __global__ void __launch_bounds__(256) alpha_gamma_fwd_kernel(const AlphaGammaAr
 //   Gs_n(b, m) = scale sum_a X_n(b, a) e^{-i m alpha_a},  X_n(b, a) = sum_g W(g, b, a) tg[g][n],
 // for n >= 0 and |m| < Lj.  One workgroup per ring b; the T samples go in chunks of 256:
 // the workgroup forms X of the chunk in LDS (one sample per thread, the gamma sum), then
-// each output (n, m) is summed over the chunk by H = 256 / (Nh (2Lj - 1)) threads, each
-// over a contiguous run of the chunk as a polynomial in rho = e^{-i m alpha_1} (Horner's
-// rule, at most 256 terms) times rho^s0 from the exact table at the run's start s0; the H
-// partial sums are added in a fixed order at the end.  The outputs
+// each output (n, m) is summed over the chunk by H = 256 / ceil(Nh (2Lj - 1) / 2) threads
+// (a thread carries two outputs), each over a contiguous run of the chunk as a polynomial
+// in rho = e^{-i m alpha_1} (Horner's rule, at most 256 terms) times rho^s0 from the exact
+// table at the run's start s0; the H partial sums are added in a fixed order at the end.
+// The outputs
 // are stored as the alpha stage stores them: Gs_n(b, m) in row n for m >= 0 and conj Gs_n
 // (b, m) in row -n at -m for m <= 0 (not for the row n = 0 of odd N).
 template <int NH, class C>
@@ -517,15 +518,20 @@ __global__ void __launch_bounds__(256) gamma_alpha_adj_kernel(const GammaAlphaAr
     using R = real_t<C>;
     constexpr int NT = 256;
     __shared__ double2 xs[NH][NT];
-    __shared__ double2 red[NT];
+    __shared__ double2 red[2][NT];
     const int tid = threadIdx.x, b = blockIdx.x, T = a.T, Lj = a.Lj, N = a.N, G = a.G;
-    const int nm = 2 * Lj - 1, nouts = NH * nm, H = NT / nouts;
-    const int o = tid % nouts, h = tid / nouts;
+    // a thread takes the outputs o and o + np (np = ceil(nouts / 2)) over the same run of
+    // samples: two independent Horner chains (the second a copy of the first when o + np
+    // is past the end, its result unused)
+    const int nm = 2 * Lj - 1, nouts = NH * nm, np = (nouts + 1) >> 1, H = NT / np;
+    const int p = tid % np, h = tid / np;
     const bool act = h < H;
-    const int k = o / nm, m = o - k * nm - (Lj - 1);
-    const int mm = m < 0 ? m + T : m;  // m mod T
+    const int o2 = p + np < nouts ? p + np : p;
+    const int k1 = p / nm, m1 = p - k1 * nm - (Lj - 1);
+    const int k2 = o2 / nm, m2 = o2 - k2 * nm - (Lj - 1);
+    const int mm1 = m1 < 0 ? m1 + T : m1, mm2 = m2 < 0 ? m2 + T : m2;  // m mod T
     const double2 *__restrict__ eph = (const double2 *)a.eph;
-    const double2 rho = cconj(eph[mm]);  // e^{-i m alpha_1}
+    const double2 rho1 = cconj(eph[mm1]), rho2 = cconj(eph[mm2]);  // e^{-i m alpha_1}
     const int len = (NT + H - 1) / H;
     const size_t plane = (size_t)a.nb * T;
     const R *__restrict__ Wr = (const R *)a.win + blockIdx.y * a.s_w + (size_t)b * T;
@@ -541,7 +547,7 @@ __global__ void __launch_bounds__(256) gamma_alpha_adj_kernel(const GammaAlphaAr
             wn[g] = (g < G && x < T) ? (double)__builtin_nontemporal_load(Wr + g * plane + x) : 0.0;
     };
     load_chunk(0);
-    double2 acc = zero2<double2>();
+    double2 acc1 = zero2<double2>(), acc2 = zero2<double2>();
     for (int a0 = 0; a0 < T; a0 += NT) {
         {
             double2 xv[NH];
@@ -567,21 +573,26 @@ __global__ void __launch_bounds__(256) gamma_alpha_adj_kernel(const GammaAlphaAr
             // sum_{x in [s0, s1)} X(x) rho^x = rho^s0 sum_j X(s0 + j) rho^j, by Horner's rule in rho
             const int s0 = a0 + h * len, s1 = min(min(s0 + len, a0 + NT), T);
             if (s0 < s1) {
-                double2 hs = zero2<double2>();
+                double2 h1 = zero2<double2>(), h2 = zero2<double2>();
                 for (int x = s1 - 1; x >= s0; --x) {
-                    const double2 xv = xs[k][x - a0];
-                    hs = mk<double2>(fma(hs.x, rho.x, fma(-hs.y, rho.y, xv.x)), fma(hs.x, rho.y, fma(hs.y, rho.x, xv.y)));
+                    const double2 y1 = xs[k1][x - a0], y2 = xs[k2][x - a0];
+                    h1 = mk<double2>(fma(h1.x, rho1.x, fma(-h1.y, rho1.y, y1.x)), fma(h1.x, rho1.y, fma(h1.y, rho1.x, y1.y)));
+                    h2 = mk<double2>(fma(h2.x, rho2.x, fma(-h2.y, rho2.y, y2.x)), fma(h2.x, rho2.y, fma(h2.y, rho2.x, y2.y)));
                 }
-                acc = cadd(acc, cmul(hs, cconj(eph[(int)(((long long)mm * s0) % T)])));
+                acc1 = cadd(acc1, cmul(h1, cconj(eph[(int)(((long long)mm1 * s0) % T)])));
+                acc2 = cadd(acc2, cmul(h2, cconj(eph[(int)(((long long)mm2 * s0) % T)])));
             }
         }
         __syncthreads();
     }
-    red[tid] = act ? acc : zero2<double2>();
+    red[0][tid] = act ? acc1 : zero2<double2>();
+    red[1][tid] = act ? acc2 : zero2<double2>();
     __syncthreads();
     if (tid < nouts) {
-        double2 tot = red[tid];
-        for (int hh = 1; hh < H; ++hh) tot = cadd(tot, red[hh * nouts + tid]);
+        const int side = tid < np ? 0 : 1, pp = tid - side * np;
+        double2 tot = red[side][pp];
+        for (int hh = 1; hh < H; ++hh) tot = cadd(tot, red[side][hh * np + pp]);
+        const int k = tid / nm, m = tid - k * nm - (Lj - 1);
         const C z = mk<C>((R)(tot.x * a.scale), (R)(tot.y * a.scale));
         const int ni = N / 2 + k, nj = N - 1 - ni;
         C *__restrict__ Gout = (C *)a.out + blockIdx.y * a.s_out + b;
