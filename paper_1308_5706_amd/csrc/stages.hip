@@ -731,8 +731,9 @@ __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int co
     const C *__restrict__ cpp = (const C *)a.cpp;
     C *__restrict__ Po = out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
     C *__restrict__ Qo = out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
-    C keep[kRM];  // V of column +n by storer slot (two columns), and its index q (or -1)
-    int kq[kRM];
+    // V of column +n by storer slot (two columns).  The storer of the last inverse pass
+    // gets element tid + s NT in slot s (span P/kRM = NT), so the slot gives the index back.
+    C keep[kRM];
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
         const C *__restrict__ Gc = in + ((size_t)ni * Lj + m) * L;
@@ -753,11 +754,7 @@ __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int co
         // first one waits in registers (each thread keeps the outputs of its storer slots)
         // while the second one uses the whole buffer; the second one goes to slots Nk + q.
         if (c == 0 && ncol > 1) {
-            auto st2 = [&](int i, C v, int slot) {
-                const int q = i - (T - 1);
-                kq[slot] = (q >= 0 && q < Nk) ? q : -1;
-                keep[slot] = v;
-            };
+            auto st2 = [&](int, C v, int slot) { keep[slot] = v; };
             fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, hh2, in2, st2, T);
         } else {
             const int sh = c * Nk;
@@ -770,8 +767,10 @@ __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int co
     }
     if (ncol > 1) {
 #pragma unroll
-        for (int r = 0; r < kRM; ++r)
-            if (kq[r] >= 0) buf[pad(kq[r])] = keep[r];
+        for (int r = 0; r < kRM; ++r) {
+            const int q = tid + r * NT - (T - 1);
+            if (q >= 0 && q < Nk) buf[pad(q)] = keep[r];
+        }
     }
     __syncthreads();
     fold_pq<C, NT>(buf, tid, Lj, m, n, ncol, odd, a.eta_imag ? 1 : 0, Po, Qo);
@@ -823,8 +822,8 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_dh_kernel(const S
     const real_t<C> *__restrict__ qw = (const real_t<C> *)a.qw;
     C *__restrict__ Po = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
     C *__restrict__ Qo = (C *)a.out + blockIdx.y * a.s_out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
-    C keep[kRM];  // V of column +n by storer slot (two columns), and its index q (or -1)
-    int kq[kRM];
+    // V of column +n by storer slot (two columns); slot s holds element tid + s NT
+    C keep[kRM];
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
         const C *__restrict__ Gc = (const C *)a.in + blockIdx.y * a.s_in + ((size_t)ni * Lj + m) * nb;
@@ -833,9 +832,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_dh_kernel(const S
         if (c == 0 && ncol > 1) {
             auto st = [&](int i, C v, int slot) {
                 const int q = i - (nb - 1);
-                const bool ok = q >= 0 && q < Nk;
-                kq[slot] = ok ? q : -1;
-                keep[slot] = ok ? cmulc(v, cpp[q - (Lj - 1)]) : v;
+                keep[slot] = (q >= 0 && q < Nk) ? cmulc(v, cpp[q - (Lj - 1)]) : v;
             };
             fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, nb);
         } else {
@@ -849,8 +846,10 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_dh_kernel(const S
     }
     if (ncol > 1) {
 #pragma unroll
-        for (int r = 0; r < kRM; ++r)
-            if (kq[r] >= 0) buf[pad(kq[r])] = keep[r];
+        for (int r = 0; r < kRM; ++r) {
+            const int q = tid + r * NT - (nb - 1);
+            if (q >= 0 && q < Nk) buf[pad(q)] = keep[r];
+        }
     }
     __syncthreads();
     fold_pq<C, NT>(buf, tid, Lj, m, n, ncol, odd, a.eta_imag ? 1 : 0, Po, Qo);
