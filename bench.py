@@ -162,32 +162,108 @@ def stage_units(kappa, L, N, T, fused=True, fused_adj=True):
 def roofline(stage, ps, units):
     """Achieved rate of a stage: its algorithmic work per step (all scales; several scales
     may share a launch) over its device time per step, i.e. the work of an average launch
-    over the average launch duration.  A stage with both byte and FLOP counts is placed
-    under the roof it comes closer to; the other one is given as ``other``."""
+    over the average launch duration.  The roof is fixed per stage: the Wigner stages
+    (Delta recursion + l-sum or m'-contraction) are FP64 vector arithmetic, priced by the
+    algorithmic FLOP of their terms; every separation-of-variables stage (the beta, alpha
+    and gamma sums of both directions) is priced by the HBM bytes it must move.  For the
+    four Fourier stages the FFT-FLOP count (5 n log2 n per length-n DFT) is added as a
+    secondary figure, ``flop_model``."""
     per_launch_s = ps["ms_per_launch"] * 1e-3
-    cands = []
-    for kind, per_step in units.get(stage, [("hbm", 0.0)]):
-        per_launch = per_step / ps["launches_per_step"]
-        if kind == "alu":
-            achieved = per_launch / per_launch_s / 1e12
-            r = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
-        else:
-            achieved = per_launch / per_launch_s / 1e9
-            r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-        r["frac"] = r["achieved"] / r["peak"]
-        r["algorithmic_per_launch"] = per_launch
-        cands.append(r)
-    cands.sort(key=lambda r: -r["frac"])
-    r = dict(cands[0])
+    entries = dict(units.get(stage, [("hbm", 0.0)]))
+    primary = "alu" if stage.startswith("wigner") else "hbm"
+    work = entries.get(primary, 0.0) / ps["launches_per_step"]
+    if primary == "alu":
+        r = {"bound": "alu", "achieved": work / per_launch_s / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        r = {"bound": "hbm", "achieved": work / per_launch_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["algorithmic_per_launch"] = work
     r["traffic"] = None
     r["kernel"] = stage
     r["launch_ms"] = ps["ms_per_launch"]
     r["launches_per_step"] = ps["launches_per_step"]
-    if len(cands) > 1:
-        o = cands[1]
-        r["other"] = {"bound": o["bound"], "achieved": o["achieved"], "peak": o["peak"], "unit": o["unit"],
-                      "frac": o["frac"]}
+    if primary == "hbm" and "alu" in entries:
+        fl = entries["alu"] / ps["launches_per_step"]
+        r["flop_model"] = {"what": "FFT-FLOP, 5 n log2 n per length-n DFT", "achieved": fl / per_launch_s / 1e12,
+                           "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                           "frac": fl / per_launch_s / 1e12 / PEAK_FP64_TFLOPS}
     return r
+
+
+def step_stats(ms):
+    """Median, mean, standard deviation, minimum and maximum of per-step device times."""
+    import numpy as np
+    a = np.asarray(ms, dtype=np.float64)
+    return {"median_ms": float(np.median(a)), "mean_ms": float(a.mean()), "std_ms": float(a.std()),
+            "min_ms": float(a.min()), "max_ms": float(a.max()), "steps": int(a.size)}
+
+
+def batched_leg(maps=256, replays=5, oracle_maps=4):
+    """The batched mixed-precision form (many maps of mixed (L, N) in one HIP graph): its
+    throughput against the plain FP64 path, each map's error against the FP64 GPU result,
+    and the checker: sampled maps (L <= 128) against the FP64 CPU oracle."""
+    import numpy as np
+    import oracle
+    from paper_1308_5706_amd import batch
+    out, data = batch.run(maps, replays)
+    errs = []
+    for (L, N), (idx, F, W, fr) in sorted(data.items()):
+        if L > 128:
+            continue
+        for k in range(min(F.shape[0], oracle_maps - len(errs))):
+            ref = oracle.analysis(F[k].cpu().numpy(), L, N, 2.0, 1)
+            got = W[k].double().cpu().numpy()
+            errs.append(max(float(np.max(np.abs(got[j] - ref[j])) / np.max(np.abs(ref[j])))
+                            for j in range(ref.shape[0])))
+        if len(errs) >= oracle_maps:
+            break
+    out["oracle_maps"] = len(errs)
+    out["max_rel_err_W_vs_oracle"] = max(errs) if errs else None
+    del data
+    return out
+
+
+def oracle_config1():
+    """The CPU oracle timed end to end (analysis with scaling, then synthesis) on the
+    medium configuration L = 256, N = 8, lambda = 2, J_min = 2, on every host core it uses."""
+    import numpy as np
+    import oracle
+    from oracle import tables
+    from paper_1308_5706_amd.inputs import random_flm
+    L, N, lam, J_min = 256, 8, 2.0, 2
+    f = random_flm(L, 0)
+    psi = tables.wavelets(L, N, lam, J_min)
+    phi = tables.phi_table(L, lam, J_min)
+    t0 = time.perf_counter()
+    W = oracle.analysis(f, L, N, lam, J_min, psi=psi)
+    wp = oracle.scaling(f, L, lam, J_min, phi=phi)
+    t1 = time.perf_counter()
+    fr = oracle.synthesis(W, wp, L, N, lam, J_min, psi=psi, phi=phi)
+    t2 = time.perf_counter()
+    coeffs = W.size
+    return {"workload": f"L={L}, N={N}, lambda={lam}, J_min={J_min}, one map, round trip", "seconds": t2 - t0,
+            "analysis_s": t1 - t0, "synthesis_s": t2 - t1, "coeffs_per_s": coeffs / (t2 - t0),
+            "cores": int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1)),
+            "round_trip_rel_err": float(np.max(np.abs(fr - f)) / np.max(np.abs(f)))}
+
+
+def gpu_config1(s2dw, torch, steps=20):
+    """The GPU round trip on the same medium configuration, for comparison with the oracle."""
+    from paper_1308_5706_amd.inputs import random_flm
+    L, N, lam, J_min = 256, 8, 2.0, 2
+    f = torch.as_tensor(random_flm(L, 0)).to("cuda")
+    for _ in range(3):
+        W, Wp = s2dw.analysis(f, L, N, lam, J_min)
+        fr = s2dw.synthesis(W, Wp, L, N, lam, J_min)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        W, Wp = s2dw.analysis(f, L, N, lam, J_min, out=W)
+        s2dw.synthesis(W, Wp, L, N, lam, J_min, out=fr)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"ms_per_round_trip": ms, "coeffs_per_s": W.numel() / (ms * 1e-3),
+            "round_trip_rel_err": float((fr - f).abs().max().item() / f.abs().max().item())}
 
 
 def extra_legs(args, s2dw, torch, dev, f, W, fr, L, N, lam, J_min, S, prec):
@@ -351,6 +427,8 @@ def main():
                     help="only run the analogue of the paper's accuracy and timing experiment (Fig. 3): "
                          "N = 3, all scales, ten uniform random signals per band-limit, both grids")
     ap.add_argument("--sweep-L", default="64,128,256,512,1024,2048", help="band-limits of --paper-sweep")
+    ap.add_argument("--batch-maps", type=int, default=256, help="maps of the batched leg")
+    ap.add_argument("--requests", type=int, default=10000, help="requests of the served leg")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -425,12 +503,16 @@ def main():
 
     s2dw.profile_stages([dom])
     s2dw.profile(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         step()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    spread = step_stats([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     live = per_launch(s2dw.profile_read())
     s2dw.profile(False)
     s2dw.profile_stages(None)
@@ -458,6 +540,19 @@ def main():
 
     extras = {} if args.no_extras else extra_legs(args, s2dw, torch, dev, f, W, fr, L, N, lam, J_min, S, prec)
     W = None
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        print("# batched leg: 256 maps of mixed (L, N), mixed precision, one graph", file=sys.stderr, flush=True)
+        extras["batched"] = batched_leg(args.batch_maps)
+        s2dw.release_caches()
+        torch.cuda.empty_cache()
+        print(f"# served leg: {args.requests} Poisson requests, mixed L", file=sys.stderr, flush=True)
+        from paper_1308_5706_amd import serve
+        served = serve.benchmark(args.requests, 0.7, ("fp64", "mixed"))
+        extras["served"] = {r["precision"]: r for r in served}
+        s2dw.release_caches()
+        torch.cuda.empty_cache()
+        extras["gpu_config1"] = gpu_config1(s2dw, torch)
 
     out = {"metric": "SO(3) wavelet coeffs/s (analysis+synthesis) at L=1024,N=8; p50/p99 mixed-L",
            "value": value, "unit": "SO(3) coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -469,13 +564,26 @@ def main():
                       "precision": prec, "round_trip_rel_err": rt_err,
                       "wigner_slots": tuned[0] if tuned else None},
            "roofline": roof,
+           "step_time": spread,
            "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in per_stage.items()},
-           "stages_roofline": {k: {"bound": v["bound"], "frac": round(v["frac"], 4)} for k, v in stage_roofs.items()},
+           "stages_roofline": {k: {"bound": v["bound"], "frac": round(v["frac"], 4),
+                                   "achieved": round(v["achieved"], 2), "unit": v["unit"]}
+                               for k, v in stage_roofs.items()},
            "wigner_terms_per_direction": T}
     out.update(extras)
+    if "served" in extras:
+        for prec_s, r in extras["served"].items():
+            sfx = "" if prec_s == "fp64" else "_mixed"
+            out["p50_ms" + sfx] = r["p50_ms"]
+            out["p99_ms" + sfx] = r["p99_ms"]
+    if "batched" in extras:
+        out["batched_coeffs_per_s"] = extras["batched"]["value"]
     if not args.no_cpu_baseline:
         print("# cpu baseline sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(L, N, lam, J_min)
+        if not args.no_extras:
+            print("# oracle round trip at L=256, N=8, J_min=2", file=sys.stderr, flush=True)
+            out["oracle_config1"] = oracle_config1()
     print(json.dumps(out), flush=True)
 
 

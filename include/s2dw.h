@@ -59,7 +59,14 @@
  *    builds the plan on the host and uploads it (it synchronises the
  *    stream once).  Workspaces are per stream: the first call on a stream
  *    (or a larger batch) allocates them, and calls on different streams may
- *    overlap.
+ *    overlap.  Calls on one stream from several host threads must be
+ *    serialised by the caller.
+ *  - Graph capture: after a first call with the same parameters and stream
+ *    (which builds the plan and allocates the stream's workspace), the
+ *    batched and single-map calls launch kernels only and can be captured.
+ *    A captured graph holds the workspace's addresses: it stays valid until a
+ *    later call on the same stream needs a larger workspace (more maps, or a
+ *    larger tile shape chosen by s2dw_autotune) or s2dw_release_caches runs.
  *
  * Errors: every function returns S2DW_OK (0) or a negative code.  Argument
  * errors are found before any device work and leave outputs untouched.
@@ -183,6 +190,9 @@ int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gam
  * the number of carried orders) and for batch chunks 1, 2, 4, ... up to min(count, what
  * fits 8 GiB of workspace), keeps the fastest per map in the plan of p, and reports them.
  * Synchronises the stream; allocates probe buffers.  slots and chunk may be NULL.
+ * Calls of the same plan on other streams may run meanwhile: each call uses the tile
+ * shape it found when it started, and no other stream's workspace is freed.  Results
+ * change only by rounding between tile shapes.
  */
 int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *slots, int32_t *chunk);
 

@@ -307,19 +307,27 @@ def alpha_gamma_rules_mw(W, L: int, N: int) -> np.ndarray:
     return out
 
 
-def beta_wigner_mw(Gt, L: int, N: int, m_range) -> np.ndarray:
+def beta_wigner_mw(Gt, L: int, N: int, m_range=None, cols=None) -> np.ndarray:
     """Second step of forward_wigner_mw: Gt [S][len(n_list)][L][2L-1] -> Wigner coefficients of
-    the columns m in m_range (complex [S][L][2L-1][len(n_list)], others zero)."""
+    the columns m in m_range = (lo, hi), or of the listed columns `cols` (complex
+    [S][L][2L-1][len(n_list)], others zero)."""
     Gt = _cplx(Gt)
     S = Gt.shape[0]
     nl = tables.n_list(N)
     nla = np.ascontiguousarray(np.array(nl, dtype=np.int32))
     xg, wg = beta_rule(L)
     out = np.zeros((S, L, 2 * L - 1, len(nl)), dtype=np.complex128)
-    rc = _load().orc_beta_wigner_mw(ctypes.c_int(L), ctypes.c_int(len(nl)), _ip(nla), ctypes.c_int(S),
-                                    _dp(Gt.view(np.float64)), ctypes.c_int(len(xg)), _dp(xg), _dp(wg),
-                                    ctypes.c_int(m_range[0]), ctypes.c_int(m_range[1]), _dp(out.view(np.float64)),
-                                    ctypes.c_int(_nthreads()))
+    if cols is not None:
+        ca = np.ascontiguousarray(np.array(cols, dtype=np.int32))
+        rc = _load().orc_beta_wigner_mw_cols(ctypes.c_int(L), ctypes.c_int(len(nl)), _ip(nla), ctypes.c_int(S),
+                                             _dp(Gt.view(np.float64)), ctypes.c_int(len(xg)), _dp(xg), _dp(wg),
+                                             ctypes.c_int(len(ca)), _ip(ca), _dp(out.view(np.float64)),
+                                             ctypes.c_int(_nthreads()))
+    else:
+        rc = _load().orc_beta_wigner_mw(ctypes.c_int(L), ctypes.c_int(len(nl)), _ip(nla), ctypes.c_int(S),
+                                        _dp(Gt.view(np.float64)), ctypes.c_int(len(xg)), _dp(xg), _dp(wg),
+                                        ctypes.c_int(m_range[0]), ctypes.c_int(m_range[1]),
+                                        _dp(out.view(np.float64)), ctypes.c_int(_nthreads()))
     if rc != 0:
         raise MemoryError("oracle beta/Wigner step failed")
     return out

@@ -356,10 +356,11 @@ int orc_alpha_gamma_rules_mw(int L, int nn, const int *nlist, int S, const doubl
 }
 
 /* Second step: the beta integral of the interpolant of Gt (all L rows) against
- * sin(beta) d^l_mn(beta), for the columns m in [m_lo, m_hi]. */
-int orc_beta_wigner_mw(int L, int nn, const int *nlist, int S, const double *Gt,
-                       int ngl, const double *xgl, const double *wgl,
-                       int m_lo, int m_hi, double *out, int nthreads)
+ * sin(beta) d^l_mn(beta), for the columns m in [m_lo, m_hi], or, when cols is not NULL,
+ * for the ncols columns listed in cols (each column is independent of the others). */
+static int beta_wigner_cols(int L, int nn, const int *nlist, int S, const double *Gt,
+                            int ngl, const double *xgl, const double *wgl,
+                            int m_lo, int m_hi, int ncols_list, const int *cols, double *out, int nthreads)
 {
     int M = 2 * L - 1;
     int T = 2 * L - 1; /* samples on the full circle after the extension */
@@ -384,11 +385,14 @@ int orc_beta_wigner_mw(int L, int nn, const int *nlist, int S, const double *Gt,
     }
     if (m_lo < -(L - 1)) m_lo = -(L - 1);
     if (m_hi > L - 1) m_hi = L - 1;
-    int ncols = m_hi - m_lo + 1;
+    int ncols = cols ? ncols_list : m_hi - m_lo + 1;
+    if (cols)
+        for (int ci = 0; ci < ncols; ++ci)
+            if (cols[ci] < -(L - 1) || cols[ci] > L - 1) { free(eb); free(ek); return -2; }
 #pragma omp parallel for collapse(2) schedule(dynamic, 1) num_threads(nthreads)
     for (int ni = 0; ni < nn; ++ni) {
         for (int ci = 0; ci < ncols; ++ci) {
-            int m = m_lo + ci;
+            int m = cols ? cols[ci] : m_lo + ci;
             int n = nlist[ni];
             int mi = m + L - 1;
             int par = ((m + n) % 2 == 0) ? 1 : -1;
@@ -472,6 +476,20 @@ int orc_beta_wigner_mw(int L, int nn, const int *nlist, int S, const double *Gt,
     }
     free(eb); free(ek);
     return err;
+}
+
+int orc_beta_wigner_mw(int L, int nn, const int *nlist, int S, const double *Gt,
+                       int ngl, const double *xgl, const double *wgl,
+                       int m_lo, int m_hi, double *out, int nthreads)
+{
+    return beta_wigner_cols(L, nn, nlist, S, Gt, ngl, xgl, wgl, m_lo, m_hi, 0, NULL, out, nthreads);
+}
+
+int orc_beta_wigner_mw_cols(int L, int nn, const int *nlist, int S, const double *Gt,
+                            int ngl, const double *xgl, const double *wgl,
+                            int ncols, const int *cols, double *out, int nthreads)
+{
+    return beta_wigner_cols(L, nn, nlist, S, Gt, ngl, xgl, wgl, -(L - 1), L - 1, ncols, cols, out, nthreads);
 }
 
 int orc_forward_wigner_mw(int L, int nn, const int *nlist, int S, const double *W,

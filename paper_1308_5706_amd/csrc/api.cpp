@@ -25,8 +25,21 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Wigner tile shape of a plan (R m' slots per wave, the tile lists of both directions and
+// the layout of the synthesis partial sums) and the maps per batched launch sequence.
+// s2dw_autotune replaces it; every call copies it under g_mu when it starts and uses its
+// copy throughout, so a call in flight on another stream keeps a consistent shape (tile
+// lists are kept until the plan is freed).
+struct Shape {
+    int R = 0, group = 0, nblk = 0;
+    const int2 *tiles_fwd = nullptr, *tiles_adj = nullptr;
+    int nfwd_plain = 0, nfwd_x = 0, nadj_plain = 0, nadj_x = 0;
+    size_t s_F = 0;                             // per-map partial-sum elements
+    int chunk = 1;                              // maps per batched launch sequence (tunable)
+};
+
 struct Plan {
-    int kind = 0, L = 0, N = 0, J_min = 0, S = 0, K = 0, Lp = 0, R = 0, group = 0, Lmax = 0;
+    int kind = 0, L = 0, N = 0, J_min = 0, S = 0, K = 0, Lp = 0, Lmax = 0;
     double lam = 2.0;
     HostTables ht;
     SegTab seg{};
@@ -68,8 +81,7 @@ struct Plan {
     double2 *tgf = nullptr, *tga = nullptr;     // gamma pass factors [2N-1][Nh]
     double *kb2 = nullptr, *seed = nullptr, *seedm = nullptr, *phi = nullptr, *fac = nullptr;
     int *seede = nullptr;
-    int2 *tiles_fwd = nullptr, *tiles_adj = nullptr;
-    int nfwd_plain = 0, nfwd_x = 0, nadj_plain = 0, nadj_x = 0;
+    Shape cur;                                  // current tile shape (guarded by g_mu)
     // tile lists per number R of m' slots per wave (the Wigner tile shape), built on demand
     struct TileSet {
         int2 *fwd = nullptr, *adj = nullptr;
@@ -94,10 +106,8 @@ struct Plan {
     float *kb2f = nullptr;
     size_t n_kb2 = 0, n_tg = 0;
     int Nh = 0;                                 // orders n >= 0 carried: ceil(N/2)
-    int nblk = 0;
-    int chunk = 1;                              // maps per batched launch sequence (tunable)
-    // per-map workspace sizes (complex elements)
-    size_t s_fpad = 0, s_U = 0, s_Ub = 0, s_Y = 0, s_F = 0;
+    // per-map workspace sizes (complex elements; the partial sums' size is part of the shape)
+    size_t s_fpad = 0, s_U = 0, s_Ub = 0, s_Y = 0;
     std::vector<void *> allocs;
     size_t dev_bytes = 0;
     // workspaces, one context per stream (calls on different streams may overlap)
@@ -105,9 +115,11 @@ struct Plan {
     ~Plan();
 };
 
-// Workspace of one stream: room for `cap` maps of a batch, map i at i * Plan::s_*.
+// Workspace of one stream: room for `cap` maps of a batch, map i at i * Plan::s_* (the
+// partial sums at i * Shape::s_F, room for cap * s_F elements).
 struct Work {
     int cap = 0;
+    size_t s_F = 0;
     double2 *fpad = nullptr, *U = nullptr, *Ub = nullptr, *Y = nullptr, *Fpart = nullptr;
     std::vector<void *> allocs;
     size_t bytes = 0;
@@ -303,9 +315,9 @@ void build_tiles(const Plan &pl, const std::vector<int> &seede, int Lp, int mgro
 }
 
 // Selects the Wigner tile shape: R m' slots per wave (the analysis workgroup covers 4R
-// m', the synthesis one kAdjWaves R).  Tile lists are built once per R.  The caller makes
-// sure that no call of the plan is in flight (workspaces are dropped: the partial-sum
-// buffer depends on R).
+// m', the synthesis one kAdjWaves R).  Tile lists are built once per R and kept.  Caller
+// holds g_mu.  Calls in flight keep the shape they copied; a stream whose workspace is too
+// small for the new partial-sum layout gets a larger one at its next call.
 int set_slots(Plan &P, int R) {
     auto it = P.tilesets.find(R);
     if (it == P.tilesets.end()) {
@@ -323,26 +335,29 @@ int set_slots(Plan &P, int R) {
         it = P.tilesets.emplace(R, ts).first;
     }
     const Plan::TileSet &ts = it->second;
-    P.R = R;
-    P.tiles_fwd = ts.fwd;
-    P.tiles_adj = ts.adj;
-    P.nfwd_plain = ts.nfwd_plain;
-    P.nfwd_x = ts.nfwd_x;
-    P.nadj_plain = ts.nadj_plain;
-    P.nadj_x = ts.nadj_x;
-    P.group = kAdjWaves * R;
-    P.nblk = (P.L + P.group - 1) / P.group;
-    const size_t s_F = (size_t)P.nblk * P.L * P.Lp;
-    if (s_F != P.s_F) {
-        P.work.clear();
-        P.s_F = s_F;
-    }
+    Shape &sh = P.cur;
+    sh.R = R;
+    sh.tiles_fwd = ts.fwd;
+    sh.tiles_adj = ts.adj;
+    sh.nfwd_plain = ts.nfwd_plain;
+    sh.nfwd_x = ts.nfwd_x;
+    sh.nadj_plain = ts.nadj_plain;
+    sh.nadj_x = ts.nadj_x;
+    sh.group = kAdjWaves * R;
+    sh.nblk = (P.L + sh.group - 1) / sh.group;
+    sh.s_F = (size_t)sh.nblk * P.L * P.Lp;
     return S2DW_OK;
+}
+
+// The plan's current shape (copied under g_mu).
+Shape shape_of(Plan &P) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return P.cur;
 }
 
 // Default maps per batched launch sequence: as many as fit 8 GiB of workspace, at most 64.
 int default_chunk(const Plan &P) {
-    const double per_map = 16.0 * (double)(P.s_fpad + P.s_U + P.s_Ub + P.s_Y + P.s_F);
+    const double per_map = 16.0 * (double)(P.s_fpad + P.s_U + P.s_Ub + P.s_Y + P.cur.s_F);
     return (int)std::max(1.0, std::min(64.0, std::floor(8.0 * (1ull << 30) / per_map)));
 }
 
@@ -696,7 +711,7 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
     P.s_U = (size_t)std::max<int64_t>(off, 1);
     P.s_Ub = (size_t)t.N * P.nb * std::max(maxLj, 1);
     P.s_Y = (size_t)P.Nh * P.nb * M;
-    P.chunk = default_chunk(P);
+    P.cur.chunk = default_chunk(P);
     out = pl.release();
     return S2DW_OK;
 }
@@ -788,12 +803,14 @@ bool walloc(Work &w, T *&p, size_t count) {
     return true;
 }
 
-// The workspace of `stream` for a batch of `maps` maps (grown on demand: the first call on a
-// stream, or a larger batch, allocates; the old buffers are freed after the stream drains).
-int get_work(Plan &P, hipStream_t stream, int maps, Work *&out) {
+// The workspace of `stream` for a batch of `maps` maps with per-map partial sums of s_F
+// elements (grown on demand: the first call on a stream, a larger batch or a larger
+// partial-sum layout allocates; the old buffers are freed after that stream drains, and only
+// calls on that stream use them).
+int get_work(Plan &P, hipStream_t stream, int maps, size_t s_F, Work *&out) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto &slot = P.work[(void *)stream];
-    if (slot && slot->cap >= maps) {
+    if (slot && slot->cap >= maps && slot->s_F >= s_F) {
         out = slot.get();
         return S2DW_OK;
     }
@@ -805,9 +822,10 @@ int get_work(Plan &P, hipStream_t stream, int maps, Work *&out) {
     if (!w) return S2DW_E_NOMEM;
     const size_t n = (size_t)maps;
     if (!walloc(*w, w->fpad, n * P.s_fpad) || !walloc(*w, w->U, n * P.s_U) || !walloc(*w, w->Ub, n * P.s_Ub) ||
-        !walloc(*w, w->Y, n * P.s_Y) || !walloc(*w, w->Fpart, n * P.s_F))
+        !walloc(*w, w->Y, n * P.s_Y) || !walloc(*w, w->Fpart, n * s_F))
         return S2DW_E_NOMEM;
     w->cap = maps;
+    w->s_F = s_F;
     slot = std::move(w);
     out = slot.get();
     return S2DW_OK;
@@ -875,7 +893,8 @@ bool direct_alpha_gamma(int Nh, int G, int Lj, bool cx) {
 // With cx (complex signals), flm holds maps / 2 complex signals, each run as the two real maps
 // 2z, 2z + 1 (real and imaginary part on the sphere), and W holds maps / 2 complex arrays
 // ((re, im) pairs, same per-map layout).
-int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32, hipStream_t st, bool cx = false) {
+int run_inverse(Plan &P, const Shape &sh, Work &w, int maps, const double2 *flm, void *W, int f32, hipStream_t st,
+                bool cx = false) {
     const int L = P.L;
     {
         Stage sg("pad", st);
@@ -902,9 +921,9 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
     a.sc = P.sc;
     {
         Stage sg("wigner_fwd", st);
-        a.tiles = P.tiles_fwd;
-        a.nplain = P.nfwd_plain;
-        S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, P.R, P.nfwd_plain + P.nfwd_x, maps, st));
+        a.tiles = sh.tiles_fwd;
+        a.nplain = sh.nfwd_plain;
+        S2DW_CHECK_HIP(launch_wig_fwd(a, P.K, sh.R, sh.nfwd_plain + sh.nfwd_x, maps, st));
     }
     const int N = P.ht.N;
     const size_t per_map = P.woff[P.S];  // elements of one W (complex ones with cx)
@@ -1004,8 +1023,8 @@ int run_inverse(Plan &P, Work &w, int maps, const double2 *flm, void *W, int f32
 // per-map layout as run_inverse; wphi of map i at wphi + i L^2, or null).
 // With cx, W holds maps / 2 complex arrays; real map 2z (2z + 1) is the real (imaginary) part
 // of complex array z, and f_lm of real map k goes to flm + k L^2.
-int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, double2 *flm, int f32,
-                hipStream_t st, bool cx = false) {
+int run_forward(Plan &P, const Shape &sh, Work &w, int maps, const void *W, const double2 *wphi, double2 *flm,
+                int f32, hipStream_t st, bool cx = false) {
     const int L = P.L, N = P.ht.N;
     const size_t per_map = P.woff[P.S];
     const size_t ew = (f32 ? 4 : 8) * (cx ? 2 : 1);
@@ -1146,22 +1165,22 @@ int run_forward(Plan &P, Work &w, int maps, const void *W, const double2 *wphi, 
     a.V = w.U;
     a.Fpart = w.Fpart;
     a.s_V = P.s_U;
-    a.s_F = P.s_F;
+    a.s_F = sh.s_F;
     a.L = L;
     a.Lp = P.Lp;
-    a.group = P.group;
+    a.group = sh.group;
     a.f32 = f32;
     a.seg = P.seg;
     a.sc = P.sc;
     {
         Stage sg("wigner_adj", st);
-        a.tiles = P.tiles_adj;
-        a.nplain = P.nadj_plain;
-        S2DW_CHECK_HIP(launch_wig_adj(a, P.K, P.R, P.nadj_plain + P.nadj_x, maps, st));
+        a.tiles = sh.tiles_adj;
+        a.nplain = sh.nadj_plain;
+        S2DW_CHECK_HIP(launch_wig_adj(a, P.K, sh.R, sh.nadj_plain + sh.nadj_x, maps, st));
     }
     {
         Stage sg("syn_final", st);
-        S2DW_CHECK_HIP(launch_syn_final(w.Fpart, P.s_F, f32, P.nblk, P.group, P.Lmax, P.fac, P.gsc, wphi, P.phi, flm,
+        S2DW_CHECK_HIP(launch_syn_final(w.Fpart, sh.s_F, f32, sh.nblk, sh.group, P.Lmax, P.fac, P.gsc, wphi, P.phi, flm,
                                         L, P.Lp, maps, st));
     }
     return S2DW_OK;
@@ -1248,15 +1267,16 @@ int s2dw_analysis_batched(const s2dw_params *p, int32_t count, const double *flm
     hipStream_t st = (hipStream_t)stream;
     const bool cx = p->reality == 0;
     const int per = cx ? 2 : 1;  // real maps per signal
-    const int chunk = std::max(1, std::min<int>(count, P->chunk / per));
+    const Shape sh = shape_of(*P);
+    const int chunk = std::max(1, std::min<int>(count, sh.chunk / per));
     Work *w = nullptr;
-    rc = get_work(*P, st, chunk * per, w);
+    rc = get_work(*P, st, chunk * per, sh.s_F, w);
     if (rc != S2DW_OK) return rc;
     const size_t L2 = (size_t)p->L * p->L;
     const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8) * per;
     for (int i0 = 0; i0 < count; i0 += chunk) {
         const int n = std::min(chunk, count - i0);
-        rc = run_inverse(*P, *w, n * per, (const double2 *)flm + L2 * i0, (char *)W + wmap * i0, f32, st, cx);
+        rc = run_inverse(*P, sh, *w, n * per, (const double2 *)flm + L2 * i0, (char *)W + wmap * i0, f32, st, cx);
         if (rc != S2DW_OK) return rc;
         if (Wphi_lm) {
             Stage sg("scaling", st);
@@ -1280,9 +1300,10 @@ int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, c
     hipStream_t st = (hipStream_t)stream;
     const bool cx = p->reality == 0;
     const int per = cx ? 2 : 1;
-    const int chunk = std::max(1, std::min<int>(count, P->chunk / per));
+    const Shape sh = shape_of(*P);
+    const int chunk = std::max(1, std::min<int>(count, sh.chunk / per));
     Work *w = nullptr;
-    rc = get_work(*P, st, chunk * per, w);
+    rc = get_work(*P, st, chunk * per, sh.s_F, w);
     if (rc != S2DW_OK) return rc;
     const size_t L2 = (size_t)p->L * p->L;
     const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8) * per;
@@ -1290,13 +1311,13 @@ int s2dw_synthesis_batched(const s2dw_params *p, int32_t count, const void *W, c
         const int n = std::min(chunk, count - i0);
         const double2 *wphi = Wphi_lm ? (const double2 *)Wphi_lm + L2 * i0 : nullptr;
         if (!cx) {
-            rc = run_forward(*P, *w, n, (const char *)W + wmap * i0, wphi, (double2 *)flm_out + L2 * i0, f32, st);
+            rc = run_forward(*P, sh, *w, n, (const char *)W + wmap * i0, wphi, (double2 *)flm_out + L2 * i0, f32, st);
             if (rc != S2DW_OK) return rc;
             continue;
         }
         // the real and imaginary parts' syntheses land in the (free) padded-input workspace,
         // map k at k L^2, and are combined with the scaling part
-        rc = run_forward(*P, *w, 2 * n, (const char *)W + wmap * i0, nullptr, w->fpad, f32, st, true);
+        rc = run_forward(*P, sh, *w, 2 * n, (const char *)W + wmap * i0, nullptr, w->fpad, f32, st, true);
         if (rc != S2DW_OK) return rc;
         Stage sg("syn_final", st);
         S2DW_CHECK_HIP(launch_merge_complex(w->fpad, L2, wphi, P->phi, (double2 *)flm_out + L2 * i0, p->L, n, st));
@@ -1314,7 +1335,11 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     if (hipStreamSynchronize(st) != hipSuccess) return S2DW_E_DEVICE;
-    int cmax = std::min<int>(count, std::max(default_chunk(*P), 1));
+    int cmax = 1;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        cmax = std::min<int>(count, std::max(default_chunk(*P), 1));
+    }
     // probe buffers (zero coefficients: the kernels have no data-dependent control flow)
     const size_t L2 = (size_t)p->L * p->L;
     const size_t wmap = P->woff[P->S] * (f32 ? 4 : 8) * (p->reality == 0 ? 2 : 1);
@@ -1336,7 +1361,7 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
             std::lock_guard<std::mutex> lk(g_mu);
             int r2 = set_slots(*P, R);
             if (r2 != S2DW_OK) return r2;
-            P->chunk = c;
+            P->cur.chunk = c;
         }
         for (int it = 0; it < 3; ++it) {
             if (it == 1) hipEventRecord(e0, st);
@@ -1353,7 +1378,7 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     };
     int Ropt[3];
     const int nR = wig_slot_options(P->K, Ropt);
-    int bestR = P->R, bestC = cmax;
+    int bestR = shape_of(*P).R, bestC = cmax;
     double best = 1e30;
     for (int i = 0; i < nR && rc == S2DW_OK; ++i) {
         double sec = 0;
@@ -1387,7 +1412,7 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     {
         std::lock_guard<std::mutex> lk(g_mu);
         rc = set_slots(*P, bestR);
-        P->chunk = bestC;
+        P->cur.chunk = bestC;
     }
     if (slots) *slots = bestR;
     if (chunk) *chunk = bestC;
@@ -1401,9 +1426,10 @@ int s2dw_workspace_bytes(const s2dw_params *p, int32_t count, uint64_t *bytes) {
     Plan *P = nullptr;
     rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, p->precision == S2DW_MIXED, p->grid);
     if (rc != S2DW_OK) return rc;
-    const uint64_t per_map = 16ull * (P->s_fpad + P->s_U + P->s_Ub + P->s_Y + P->s_F);
+    const Shape sh = shape_of(*P);
+    const uint64_t per_map = 16ull * (P->s_fpad + P->s_U + P->s_Ub + P->s_Y + sh.s_F);
     const int per = p->reality == 0 ? 2 : 1;  // real maps per signal
-    *bytes = per_map * per * (uint64_t)std::min<int>(count, std::max(P->chunk / per, 1));
+    *bytes = per_map * per * (uint64_t)std::min<int>(count, std::max(sh.chunk / per, 1));
     return S2DW_OK;
 }
 
@@ -1439,7 +1465,7 @@ int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, doubl
     if (rc != S2DW_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     Work *w = nullptr;
-    rc = get_work(*P, st, 1, w);
+    rc = get_work(*P, st, 1, shape_of(*P).s_F, w);
     if (rc != S2DW_OK) return rc;
     double2 *wphi = (double2 *)Wphi_lm;
     if (!wphi) wphi = w->fpad;  // scratch: L*Lp >= L*L complex
@@ -1449,9 +1475,10 @@ int s2dw_scaling(const s2dw_params *p, const double *flm, double *Wphi_lm, doubl
         rc = get_plan(kShtInverse, p->L, 1, 0.0, 0, Q);
         if (rc != S2DW_OK) return rc;
         Work *wq = nullptr;
-        rc = get_work(*Q, st, 1, wq);
+        const Shape shq = shape_of(*Q);
+        rc = get_work(*Q, st, 1, shq.s_F, wq);
         if (rc != S2DW_OK) return rc;
-        rc = run_inverse(*Q, *wq, 1, wphi, Wphi_map, 0, st);
+        rc = run_inverse(*Q, shq, *wq, 1, wphi, Wphi_map, 0, st);
     }
     return rc;
 }
@@ -1509,9 +1536,10 @@ int s2dw_sht_forward(const s2dw_params *p, const double *f_map, double *flm, voi
     int rc = get_plan(kShtForward, p->L, 1, 0.0, 0, Q);
     if (rc != S2DW_OK) return rc;
     Work *w = nullptr;
-    rc = get_work(*Q, (hipStream_t)stream, 1, w);
+    const Shape sh = shape_of(*Q);
+    rc = get_work(*Q, (hipStream_t)stream, 1, sh.s_F, w);
     if (rc != S2DW_OK) return rc;
-    return run_forward(*Q, *w, 1, f_map, nullptr, (double2 *)flm, 0, (hipStream_t)stream);
+    return run_forward(*Q, sh, *w, 1, f_map, nullptr, (double2 *)flm, 0, (hipStream_t)stream);
 }
 
 int s2dw_sht_inverse(const s2dw_params *p, const double *flm, double *f_map, void *stream) {
@@ -1521,9 +1549,10 @@ int s2dw_sht_inverse(const s2dw_params *p, const double *flm, double *f_map, voi
     int rc = get_plan(kShtInverse, p->L, 1, 0.0, 0, Q);
     if (rc != S2DW_OK) return rc;
     Work *w = nullptr;
-    rc = get_work(*Q, (hipStream_t)stream, 1, w);
+    const Shape sh = shape_of(*Q);
+    rc = get_work(*Q, (hipStream_t)stream, 1, sh.s_F, w);
     if (rc != S2DW_OK) return rc;
-    return run_inverse(*Q, *w, 1, (const double2 *)flm, f_map, 0, (hipStream_t)stream);
+    return run_inverse(*Q, sh, *w, 1, (const double2 *)flm, f_map, 0, (hipStream_t)stream);
 }
 
 int s2dw_wavelet_tables(const s2dw_params *p, double *kappa, double *phi, double *s_ln) {

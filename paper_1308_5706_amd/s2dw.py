@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libs2dw.so")
 FP64, MIXED = 0, 1
 GRID_MW, GRID_MW_MULTIRES, GRID_DH = 0, 1, 2
 GRIDS = {"mw": GRID_MW, "multires": GRID_MW_MULTIRES, "dh": GRID_DH}
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 
 _lib = None
 
@@ -100,8 +101,9 @@ def params(L: int, N: int, lam: float = 2.0, J_min: int = 0, precision: str = "f
     reality: real signal (real W) or complex signal (complex W)."""
     if grid not in GRIDS:
         raise ValueError(f"grid must be one of {sorted(GRIDS)}, not {grid!r}")
-    return Params(L, N, float(lam), J_min, GRIDS[grid], FP64 if precision == "fp64" else MIXED,
-                  1 if reality else 0)
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, not {precision!r}")
+    return Params(L, N, float(lam), J_min, GRIDS[grid], PRECISIONS[precision], 1 if reality else 0)
 
 
 def _check(rc: int, what: str):

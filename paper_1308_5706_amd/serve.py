@@ -209,21 +209,18 @@ def coeffs_of(L, N, lam, J_min):
     return s2dw.num_scales(L, lam, J_min) * (2 * N - 1) * L * (2 * L - 1)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--requests", type=int, default=10000)
-    ap.add_argument("--load", type=float, default=0.7, help="offered rate as a fraction of the saturated rate")
-    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
-    ap.add_argument("--streams", type=int, default=4)
-    ap.add_argument("--max-batch", type=int, default=16)
-    args = ap.parse_args()
-    lam, J_min = 2.0, 1
-    Ls, Ns, rng = draw_mix(args.requests)
+def benchmark(requests: int = 10000, load: float = 0.7, precisions=("fp64", "mixed"), streams: int = 4,
+              max_batch: int = 16, lam: float = 2.0, J_min: int = 1) -> list:
+    """The serving benchmark of the request mix: per precision, the plain path (each request
+    alone, one after the other), the saturated rate (every request queued at once) and a
+    Poisson stream at `load` times that rate with its p50/p99 latency.  Returns one dict per
+    precision."""
+    Ls, Ns, rng = draw_mix(requests)
     pool = {L: [torch.as_tensor(random_flm(L, 4_000_000 + 10 * L + k)).to("cuda") for k in range(4)]
             for L in L_CHOICES}
-    gaps = rng.exponential(1.0, size=args.requests)  # unit-rate Poisson gaps, scaled below
+    gaps = rng.exponential(1.0, size=requests)  # unit-rate Poisson gaps, scaled below
     total_coeffs = sum(coeffs_of(L, N, lam, J_min) for L, N in zip(Ls, Ns))
-    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    results = []
     for prec in precisions:
         # the plain GPU path at equal accuracy: each request alone, one after the other
         for (L, N) in sorted(set(zip(Ls, Ns))):
@@ -234,27 +231,44 @@ def main():
             W, Wp = s2dw.analysis(pool[L][i % len(pool[L])], L, N, lam, J_min, precision=prec)
             del W, Wp
         torch.cuda.synchronize()
-        plain = args.requests / (time.perf_counter() - t0)
+        plain = requests / (time.perf_counter() - t0)
         print(f"# {prec}: plain path {plain:.1f} requests/s", file=sys.stderr, flush=True)
-        srv = Server(lam=lam, J_min=J_min, precision=prec, streams=args.streams, max_batch=args.max_batch)
+        srv = Server(lam=lam, J_min=J_min, precision=prec, streams=streams, max_batch=max_batch)
         print(f"# {prec}: warming plans and stream workspaces", file=sys.stderr, flush=True)
         srv.warm(sorted(set(zip(Ls, Ns))))
-        done, T = run(srv, Ls, Ns, pool, np.zeros(args.requests))
-        r_max = args.requests / T
+        done, T = run(srv, Ls, Ns, pool, np.zeros(requests))
+        r_max = requests / T
         print(f"# {prec}: saturated {r_max:.1f} requests/s", file=sys.stderr, flush=True)
-        rate = args.load * r_max
+        rate = load * r_max
         arrivals = np.cumsum(gaps) / rate
         done, T = run(srv, Ls, Ns, pool, arrivals)
         lat = np.array([r.t_done - r.t_arrival for r in done]) * 1e3
-        out = {"metric": "SO(3) wavelet coeffs/s (analysis) served, mixed-L request stream",
-               "value": total_coeffs / T, "unit": "SO(3) coeffs/s", "precision": prec,
-               "requests": args.requests, "requests_per_s": args.requests / T,
-               "saturated_requests_per_s": r_max, "offered_requests_per_s": rate, "load": args.load,
-               "plain_path_requests_per_s": plain,
-               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-               "streams": args.streams, "max_batch": args.max_batch, "data": "synthetic",
-               "mix": {"L": dict(zip(map(str, L_CHOICES), L_WEIGHTS)), "N": N_CHOICES, "lambda": lam,
-                       "J_min": J_min}}
+        print(f"# {prec}: {requests} Poisson requests at {rate:.0f}/s: p50 {np.percentile(lat, 50):.2f} ms, "
+              f"p99 {np.percentile(lat, 99):.2f} ms", file=sys.stderr, flush=True)
+        results.append({"metric": "SO(3) wavelet coeffs/s (analysis) served, mixed-L request stream",
+                        "value": total_coeffs / T, "unit": "SO(3) coeffs/s", "precision": prec,
+                        "requests": requests, "requests_per_s": requests / T,
+                        "saturated_requests_per_s": r_max, "offered_requests_per_s": rate, "load": load,
+                        "plain_path_requests_per_s": plain,
+                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                        "mean_ms": float(np.mean(lat)),
+                        "streams": streams, "max_batch": max_batch, "data": "synthetic",
+                        "mix": {"L": dict(zip(map(str, L_CHOICES), L_WEIGHTS)), "N": N_CHOICES, "lambda": lam,
+                                "J_min": J_min}})
+        del srv
+    return results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--load", type=float, default=0.7, help="offered rate as a fraction of the saturated rate")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=16)
+    args = ap.parse_args()
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    for out in benchmark(args.requests, args.load, precisions, args.streams, args.max_batch):
         print(json.dumps(out), flush=True)
 
 

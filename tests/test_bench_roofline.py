@@ -1,6 +1,6 @@
 """Host checks of the roofline accounting in bench.py (no device work): the algorithmic work
-per stage follows the stated formulas, and a stage with both a byte and a FLOP count is
-placed under the roof it comes closer to."""
+per stage follows the stated formulas, and each stage is priced under its fixed roof (HBM
+bytes for the separation-of-variables stages, FP64 FLOP for the Wigner stages)."""
 import importlib.util
 import math
 import os
@@ -68,16 +68,27 @@ def test_stage_units_formulas(bench):
     assert u["wigner_fwd"] == [("alu", 5.0 * T)]
 
 
-def test_roofline_takes_the_nearer_roof(bench):
-    units = {"s": [("hbm", 8e9), ("alu", 1e10)]}   # per step
+def test_roofline_roof_is_fixed_per_stage(bench):
+    # separation-of-variables stages are priced by HBM bytes whatever their FLOP count, with the
+    # FFT-FLOP figure as a secondary field; the Wigner stages by their algorithmic FLOP
     ps = {"ms_per_launch": 1.0, "launches_per_step": 2.0}
-    r = bench.roofline("s", ps, units)
-    # per launch 4e9 B and 5e9 FLOP in 1 ms: 4000 GB/s (50 %) against 5 TFLOP/s (6.4 %)
-    assert r["bound"] == "hbm" and r["achieved"] == pytest.approx(4000.0) and r["frac"] == pytest.approx(0.5)
-    assert r["other"]["bound"] == "alu" and r["other"]["frac"] == pytest.approx(5.0 / bench.PEAK_FP64_TFLOPS)
-    units = {"s": [("hbm", 8e8), ("alu", 1e11)]}
-    r = bench.roofline("s", ps, units)
+    for units in ({"beta_adj": [("hbm", 8e9), ("alu", 1e10)]}, {"beta_adj": [("hbm", 8e8), ("alu", 1e11)]}):
+        r = bench.roofline("beta_adj", ps, units)
+        by, fl = dict(units["beta_adj"])["hbm"] / 2, dict(units["beta_adj"])["alu"] / 2
+        assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+        assert r["achieved"] == pytest.approx(by / 1e-3 / 1e9) and r["frac"] == pytest.approx(by / 1e-3 / 1e9 / 8000.0)
+        assert r["algorithmic_per_launch"] == pytest.approx(by)
+        assert r["flop_model"]["frac"] == pytest.approx(fl / 1e-3 / 1e12 / bench.PEAK_FP64_TFLOPS)
+    r = bench.roofline("gamma_fwd", ps, {"gamma_fwd": [("hbm", 4e9)]})
+    assert r["bound"] == "hbm" and "flop_model" not in r and r["achieved"] == pytest.approx(2000.0)
+    r = bench.roofline("wigner_adj", ps, {"wigner_adj": [("alu", 1e11)]})
     assert r["bound"] == "alu" and r["frac"] == pytest.approx(50.0 / bench.PEAK_FP64_TFLOPS)
+
+
+def test_step_stats(bench):
+    s = bench.step_stats([1.0, 3.0, 2.0, 10.0])
+    assert s["median_ms"] == 2.5 and s["mean_ms"] == 4.0 and s["min_ms"] == 1.0 and s["max_ms"] == 10.0
+    assert s["std_ms"] == pytest.approx(np.std([1.0, 3.0, 2.0, 10.0])) and s["steps"] == 4
 
 
 def test_profile_kernel_names_map_to_stages():

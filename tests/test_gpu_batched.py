@@ -81,3 +81,23 @@ def test_graph_capture_replays_match_eager():
         # eager work between replays
         s2dw.analysis(F[0], L, N, 2.0, J_min)
         torch.cuda.synchronize()
+
+
+def test_batched_mixed_maps_against_oracle():
+    # the batched mixed-precision form of the many-maps configuration (L from {64, 128}, N from
+    # {2, 4, 8}, J_min = 1), every map of each batch against the FP64 oracle at the mixed bar
+    print("batched mixed-precision maps vs oracle", flush=True)
+    lam, J_min = 2.0, 1
+    for (L, N) in [(64, 8), (128, 2), (128, 4)]:
+        F = torch.stack([dev(random_flm(L, 3_000_000 + 10 * L + N + i)) for i in range(3)])
+        W, Wp = s2dw.analysis_batched(F, L, N, lam, J_min, precision="mixed")
+        fr = s2dw.synthesis_batched(W, Wp, L, N, lam, J_min, precision="mixed")
+        torch.cuda.synchronize()
+        for k in range(F.shape[0]):
+            fk = F[k].cpu().numpy()
+            ref = oracle.analysis(fk, L, N, lam, J_min)
+            Wk = W[k].double().cpu().numpy()
+            e = max(rel(Wk[j], ref[j]) for j in range(ref.shape[0]))
+            print(f"  L={L} N={N} map {k}: W rel. error {e:.1e}", flush=True)
+            assert e < 1e-5, (L, N, k, e)
+            assert rel(fr[k].cpu().numpy(), fk) < 1e-5

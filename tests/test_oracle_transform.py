@@ -265,3 +265,18 @@ def test_beta_integral_of_interpolant_for_arbitrary_samples():
             val = mpmath.quad(lambda b: mpmath.sin(b) * G(b) * explicit_d(el, m, 0, b, dps=30), [0, mpmath.pi])
             ref = math.sqrt((2 * el + 1) / (4 * math.pi)) * complex(val)
             assert abs(got[el * el + el + m] - ref) < 1e-13, (el, m)
+
+
+def test_beta_wigner_column_list_equals_column_ranges():
+    # the column-list entry point schedules the same per-column arithmetic as the range one
+    from paper_1308_5706_amd.inputs import random_wavelet_samples
+    L, N = 12, 4
+    Wr = random_wavelet_samples(2, 2 * N - 1, L, 2 * L - 1, 3)
+    Gt = oracle.alpha_gamma_rules_mw(Wr, L, N)
+    cols = [-5, 0, 3, 11]
+    a = oracle.beta_wigner_mw(Gt, L, N, cols=cols)
+    for m in cols:
+        b = oracle.beta_wigner_mw(Gt, L, N, (m, m))
+        assert np.array_equal(a[:, :, m + L - 1, :], b[:, :, m + L - 1, :])
+    others = [i for i in range(2 * L - 1) if i - (L - 1) not in cols]
+    assert not np.any(a[:, :, others, :])
