@@ -73,6 +73,10 @@ struct Plan {
         double2 *csq = nullptr, *cpp = nullptr, *hD1 = nullptr, *eph = nullptr;
         float2 *csqf = nullptr, *cppf = nullptr, *hD1f = nullptr, *ephf = nullptr;
         int PD = 0;
+        // prime-factor transform tables of length T (when T is one of its lengths)
+        double2 *pcs = nullptr;
+        float2 *pcsf = nullptr;
+        int npcs = 0;
     };
     std::map<int, GridTab> gt;
     // device tables
@@ -255,7 +259,7 @@ bool build_segments(const HostTables &t, SegTab &seg) {
 // keeping a group on one XCD lets those rows come from that XCD's L2.  Groups go to the XCD
 // with the least work so far (heaviest group first), each as a run of its tiles, heaviest
 // first; positions whose XCD has no tile left take one from the fullest XCD.
-std::vector<int2> xcd_order(const std::vector<std::pair<long, int2>> &tiles, int phase) {
+std::vector<int2> xcd_order(const std::vector<std::pair<long, int2>> &tiles, int phase, bool mmajor = false) {
     std::map<int, std::vector<std::pair<long, int2>>> groups;  // by m'0
     for (const auto &e : tiles) groups[e.second.y].push_back(e);
     std::vector<std::pair<long, int>> gw;
@@ -275,6 +279,13 @@ std::vector<int2> xcd_order(const std::vector<std::pair<long, int2>> &tiles, int
         load[x] += g.first;
         for (const auto &e : groups[g.second]) bins[x].push_back(e.second);
     }
+    // mmajor: each XCD takes its tiles m-tile by m-tile (then m' group), so that the workgroups
+    // resident on it at one time share the per-lane columns (g f_lm and pt) of a few m-tiles
+    // rather than the table rows of a few m' groups
+    if (mmajor)
+        for (auto &b : bins)
+            std::stable_sort(b.begin(), b.end(),
+                             [](const int2 &u, const int2 &v) { return u.x < v.x || (u.x == v.x && u.y < v.y); });
     std::vector<int2> out;
     size_t pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     while (out.size() < tiles.size()) {
@@ -295,7 +306,7 @@ std::vector<int2> xcd_order(const std::vector<std::pair<long, int2>> &tiles, int
 // Tile lists for the Wigner kernels: (m0, m'0) pairs in XCD-aware order (above); tiles holding
 // a start value below 2^-1000 go to the extended-exponent list, launched after the others.
 void build_tiles(const Plan &pl, const std::vector<int> &seede, int Lp, int mgroup, std::vector<int2> &plain,
-                 std::vector<int2> &xn) {
+                 std::vector<int2> &xn, bool mmajor = false) {
     std::vector<std::pair<long, int2>> a, b;
     const int L = pl.L, Lmax = pl.Lmax;
     for (int m0 = 0; m0 < Lmax; m0 += 64)
@@ -310,8 +321,8 @@ void build_tiles(const Plan &pl, const std::vector<int> &seede, int Lp, int mgro
                     }
             (x ? b : a).push_back({work, make_int2(m0, p0)});
         }
-    plain = xcd_order(a, 0);
-    xn = xcd_order(b, (int)(a.size() % 8));
+    plain = xcd_order(a, 0, mmajor);
+    xn = xcd_order(b, (int)(a.size() % 8), mmajor);
 }
 
 // Selects the Wigner tile shape: R m' slots per wave (the analysis workgroup covers 4R
@@ -323,7 +334,10 @@ int set_slots(Plan &P, int R) {
     if (it == P.tilesets.end()) {
         Plan::TileSet ts;
         std::vector<int2> pl_a, x_a, pl_s, x_s;
-        build_tiles(P, P.seede_h, P.Lp, 4 * R, pl_a, x_a);
+        // the analysis reads per-lane columns at every step, the synthesis does not: at large L
+        // (32 m-tiles or more) its tiles go m-tile major (measured at L = 2048, N = 4: analysis
+        // 2.55 -> 2.30 ms; at L = 1024 and for the synthesis the m' group order is faster)
+        build_tiles(P, P.seede_h, P.Lp, 4 * R, pl_a, x_a, P.Lmax >= 1536);
         build_tiles(P, P.seede_h, P.Lp, kAdjWaves * R, pl_s, x_s);
         ts.nfwd_plain = (int)pl_a.size();
         ts.nfwd_x = (int)x_a.size();
@@ -419,6 +433,34 @@ std::pair<ld, ld> chirp_val(long long d, int T, int sign) {
     return {cosl(a), sinl(a)};
 }
 
+// Constant tables of the direct prime-factor transforms of length T (see pfa.h): cos and sin
+// of 2 pi j/q for each factor q, and for T = 2047 the per-wave constants of the length-89
+// stage.  Empty when T is not one of those lengths.
+std::vector<double2> pfa_tables(int T) {
+    auto cs = [](ld x) { return make_double2((double)cosl(x), (double)sinl(x)); };
+    std::vector<double2> t;
+    auto roots = [&](int q) {
+        for (int j = 0; j < q; ++j) t.push_back(cs(2.0L * kPiL * j / q));
+    };
+    if (T == 2047) {
+        roots(23);
+        roots(89);
+        const int NW = 4, KG = 11, H = 44;
+        for (int w = 0; w < NW; ++w)
+            for (int r = 1; r <= H; ++r)
+                for (int kk = 0; kk < KG; ++kk) {
+                    const int k = 1 + w * KG + kk;
+                    t.push_back(cs(2.0L * kPiL * ((r * k) % 89) / 89));
+                }
+    } else if (T == 4095) {
+        roots(5);
+        roots(7);
+        roots(9);
+        roots(13);
+    }
+    return t;
+}
+
 // Chirp tables of grid band-limit Lg (T = 2Lg - 1) and the spectrum of the first synthesis
 // beta convolution, shared by the scales sampled on that grid.
 int build_grid_tab(Plan &P, int Lg) {
@@ -443,6 +485,11 @@ int build_grid_tab(Plan &P, int Lg) {
     auto hd1 = spectrum(g.PD, 2 * M - 1, (ld)M, [&](int i) { return chirp_val((long long)i - Lg - M + 2, M, +1); });
     if (!upload(P, g.csq, csq) || !upload(P, g.cpp, cpp) || !upload(P, g.hD1, hd1) || !upload(P, g.eph, eph))
         return S2DW_E_NOMEM;
+    const std::vector<double2> pt = pfa_tables(M);
+    if (!pt.empty()) {
+        if (!upload(P, g.pcs, pt)) return S2DW_E_NOMEM;
+        g.npcs = (int)pt.size();
+    }
     P.gt[Lg] = g;
     return S2DW_OK;
 }
@@ -651,17 +698,20 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
                 if (!upload(P, P.hBb[j], hb) || !upload(P, P.hCb[j], hc)) return S2DW_E_NOMEM;
             }
         }
-        auto ha = spectrum(P.PA[j], 2 * Lj + nbj - 2, 1.0L,
+        // the kernel's support covers nbj outputs, or all T ring positions where the analysis
+        // beta stage transforms two columns at once (the two-column condition of run_inverse)
+        const int na_out = (!dh && pow2_at_least(2 * Lj + 2 * Lg - 3) <= P.PA[j]) ? T : nbj;
+        auto ha = spectrum(P.PA[j], 2 * Lj + na_out - 2, 1.0L,
                            [&](int i) { return chirp_val((long long)i - Lj + 1, Tbj, -1); });
         auto hb = spectrum(P.PB[j], 2 * Lj + T - 2, 1.0L,
                            [&](int i) { return chirp_val((long long)i - Lj + 1, T, -1); });
         auto hc = spectrum(P.PB[j], 2 * Lj + T - 2, 1.0L,
                            [&](int i) { return chirp_val((long long)i - Lj - T + 2, T, +1); });
-        // w(q) = int_0^pi sin(b) e^{i q b} db at q = Lj + Lg - 2 - i
+        // the even part of w(q) = int_0^pi sin(b) e^{i q b} db, 2/(1 - q^2) at even q (its odd
+        // part, +-i pi/2 at q = +-1, drops out of the folded sums of the paired columns, see
+        // stages.hip), at q = Lj + Lg - 2 - i
         auto hd2 = spectrum(PD, T + 2 * Lj - 2, 1.0L, [&](int i) {
             const long long q = (long long)Lj + Lg - 2 - i;
-            if (q == 1) return std::pair<ld, ld>(0.0L, kPiL / 2);
-            if (q == -1) return std::pair<ld, ld>(0.0L, -kPiL / 2);
             if (q % 2 == 0) return std::pair<ld, ld>(2.0L / (1.0L - (ld)q * (ld)q), 0.0L);
             return std::pair<ld, ld>(0.0L, 0.0L);
         });
@@ -669,12 +719,12 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
             return S2DW_E_NOMEM;
     }
     if (grid == S2DW_GRID_MW && kind == kWavelet) {
-        // coarse scales (at most 256 column pairs each) at the end of the scale list, as many
+        // coarse scales (at most 256 order-column pairs each) at the end of the scale list, as many
         // as the beta-stage workspace holds side by side (sum of their Lj <= the largest Lj)
         int maxL = 0;
         for (int j = 0; j < t.S; ++j) maxL = std::max(maxL, P.sc.Lj[j]);
         int j0 = t.S, sumL = 0;
-        while (j0 > 0 && P.K * P.sc.Lj[j0 - 1] <= 256 && sumL + P.sc.Lj[j0 - 1] <= maxL) sumL += P.sc.Lj[--j0];
+        while (j0 > 0 && P.K * ((P.sc.Lj[j0 - 1] + 1) / 2) <= 256 && sumL + P.sc.Lj[j0 - 1] <= maxL) sumL += P.sc.Lj[--j0];
         std::vector<BetaAdjScale> tab;
         size_t go = 0;
         int nwg = 0;
@@ -684,7 +734,7 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
             P.goff[j] = go;
             tab.push_back(BetaAdjScale{nwg, Lj, (long long)go, (long long)P.sc.off[j], (const void *)P.hD2[j]});
             go += (size_t)t.N * Lj * L;
-            nwg += P.K * Lj;
+            nwg += P.K * ((Lj + 1) / 2);  // one workgroup per order and pair of columns (m, m + 1)
         }
         if (tab.size() >= 2) {
             if (!upload(P, P.mtab, tab)) return S2DW_E_NOMEM;
@@ -736,6 +786,7 @@ int ensure_f32(Plan &P) {
         Plan::GridTab &g = kv.second;
         ok = f32_copy(P, g.csqf, g.csq, T) && f32_copy(P, g.cppf, g.cpp, T) && f32_copy(P, g.hD1f, g.hD1, g.PD) &&
              f32_copy(P, g.ephf, g.eph, T);
+        if (ok && g.pcs) ok = f32_copy(P, g.pcsf, g.pcs, g.npcs);
     }
     if (ok && P.grid == S2DW_GRID_DH)
         ok = f32_copy(P, P.dh_csqf, P.dh_csq, P.nb) && f32_copy(P, P.dh_cppf, P.dh_cpp, 2 * P.L - 1) &&
@@ -957,7 +1008,17 @@ int run_inverse(Plan &P, const Shape &sh, Work &w, int maps, const double2 *flm,
         b.Nh = P.Nh;
         {
             Stage sg("beta_fwd", st);
-            S2DW_CHECK_HIP(launch_beta_fwd_fft(b, P.PA[j], maps, st));
+            // two columns per transform: as a prime-factor transform of length T where T is one
+            // of its lengths, else as a chirp convolution where that needs no larger transform
+            // than one column's (equiangular grid)
+            if (!dh && gtab.pcs) {
+                b.eph = f32 ? (const void *)gtab.ephf : gtab.eph;
+                b.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
+                S2DW_CHECK_HIP(launch_beta_fwd_pfa(b, maps, st));
+            } else if (!dh && pow2_at_least(2 * Lj + 2 * Lg - 3) <= P.PA[j])
+                S2DW_CHECK_HIP(launch_beta_fwd_pair(b, P.PA[j], maps, st));
+            else
+                S2DW_CHECK_HIP(launch_beta_fwd_fft(b, P.PA[j], maps, st));
         }
         if (direct_alpha_gamma(P.Nh, P.ng, Lj, cx)) {
             AlphaGammaArgs d{};
@@ -995,6 +1056,10 @@ int run_inverse(Plan &P, const Shape &sh, Work &w, int maps, const double2 *flm,
             c.B = P.Bb[j];
             Stage sg("alpha_fwd", st);
             S2DW_CHECK_HIP(launch_alpha_fwd_blk(c, P.PBb[j], maps, st));
+        } else if (gtab.pcs) {
+            c.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
+            Stage sg("alpha_fwd", st);
+            S2DW_CHECK_HIP(launch_alpha_fwd_pfa(c, maps, st));
         } else {
             Stage sg("alpha_fwd", st);
             S2DW_CHECK_HIP(launch_alpha_fwd_fft(c, P.PB[j], maps, st));
@@ -1094,6 +1159,11 @@ int run_forward(Plan &P, const Shape &sh, Work &w, int maps, const void *W, cons
         c.scale = qscale;
         if (fused) {
             // the alpha quadrature ran in the fused pass above
+        } else if (P.nblkb[j] <= 1 && gtab.pcs) {
+            StageArgs cp = c;
+            cp.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
+            Stage sg("alpha_adj", st);
+            S2DW_CHECK_HIP(launch_alpha_adj_pfa(cp, maps, st));
         } else if (P.nblkb[j] > 1) {
             StageArgs cb = c;
             cb.hh = f32 ? (const void *)P.hCbf[j] : P.hCb[j];
@@ -1128,6 +1198,8 @@ int run_forward(Plan &P, const Shape &sh, Work &w, int maps, const void *W, cons
         } else {
             v.hh = f32 ? (const void *)gtab.hD1f : gtab.hD1;
             v.hh2 = f32 ? (const void *)P.hD2f[j] : P.hD2[j];
+            v.eph = f32 ? (const void *)gtab.ephf : gtab.eph;
+            v.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
             v.tw = f32 ? (const void *)P.twPf[gtab.PD] : P.twP[gtab.PD];
             Stage sg("beta_adj", st);
             S2DW_CHECK_HIP(launch_beta_adj_fft(v, gtab.PD, maps, st));
@@ -1145,6 +1217,8 @@ int run_forward(Plan &P, const Shape &sh, Work &w, int maps, const void *W, cons
         v.cpp = f32 ? (const void *)gtab.cppf : gtab.cpp;
         v.hh = f32 ? (const void *)gtab.hD1f : gtab.hD1;
         v.tw = f32 ? (const void *)P.twPf[gtab.PD] : P.twP[gtab.PD];
+        v.eph = f32 ? (const void *)gtab.ephf : gtab.eph;
+        v.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
         v.L = L;
         v.nb = L;
         v.N = N;

@@ -70,6 +70,7 @@ struct StageArgs {
     const void *cpp;       // e^{i pi p(p+1)/T} at p + L - 1, |p| < L (T as for csq)
     const void *qw;        // Driscoll-Healy quadrature weights q_t, t < nb (real; synthesis beta stage)
     const void *eph;       // e^{2 pi i r/T}, r < T (blocked alpha stages)
+    const void *pcs;       // constant tables of the prime-factor transforms of length T (pfa.h)
     int nblk, B;           // blocked alpha stages: nblk blocks of B samples
     size_t s_in, s_out;    // per-map strides (complex elements) of a batch; map = blockIdx.y
     int L, nb, Lj, N, Nh, K, eta_imag, f32;  // nb: beta rings (L, or 2L on the Driscoll-Healy grid)
@@ -78,9 +79,18 @@ struct StageArgs {
 };
 // Every launcher takes the number of maps of the batch (grid y).
 hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st);
+// Equiangular grid only: columns (n, m) and (n, m + 1) in one transform of size P >= 2Lj + 2L - 3.
+hipError_t launch_beta_fwd_pair(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_alpha_fwd_blk(const StageArgs &a, int P, int maps, hipStream_t st);
+// Direct prime-factor alpha transforms, T = 2L - 1 in {2047, 4095} (pcs: that length's tables).
+bool pfa_length(int T);
+hipError_t launch_alpha_fwd_pfa(const StageArgs &a, int maps, hipStream_t st);
+hipError_t launch_alpha_adj_pfa(const StageArgs &a, int maps, hipStream_t st);
+// Equiangular grid, T = 2L - 1 in {2047, 4095}: the two-column analysis beta transform as a
+// prime-factor transform (eph: e^{2 pi i r/T}; pcs as above).
+hipError_t launch_beta_fwd_pfa(const StageArgs &a, int maps, hipStream_t st);
 hipError_t launch_alpha_adj_blk(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t st);

@@ -19,6 +19,7 @@
 // analysis input U is FP64 in both).
 #include "fft.h"
 #include "kernels.h"
+#include "pfa.h"
 
 #ifndef S2DW_FFT_RADIX
 #define S2DW_FFT_RADIX 8
@@ -93,6 +94,107 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_fft_kernel(const 
         if (b >= 0 && b < nb) out[b] = cmul(v, csq[b]);
     };
     fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, Na);
+}
+
+// Two columns (n, m0) and (n, m0 + 1) of the equiangular grid in one transform.  With
+// s = (-1)^{m+n}, F(beta) = sum_{m'} U_{m m' n} e^{i m' beta} obeys F(2 pi - beta) = s F(beta), and
+// the two columns have opposite s.  The transform of their sum, evaluated at all T ring
+// positions beta_t = pi (2t+1)/T (t < T; beta_{T-1-b} = 2 pi - beta_b), is F_z = F_a + F_b, so
+//   F_a(beta_b) = (F_z(beta_b) + s_a F_z(beta_{T-1-b}))/2,  F_b(beta_b) = (F_z(beta_b) - s_a F_z(beta_{T-1-b}))/2.
+// Taken where the convolution of 2Lj - 1 inputs and T outputs needs no larger transform than
+// the single column's (the scales with Lj = L).  Workgroup col = ni ceil(Lj/2) + c takes
+// columns m0 = 2c and m0 + 1.
+template <class C, int P>
+__global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_pair_kernel(const StageArgs a) {
+    __shared__ C buf[fft::padded(P)];
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, L = a.L, T = 2 * L - 1;
+    const int Mp = (Lj + 1) >> 1;
+    const int ni = blockIdx.x / Mp, m0 = 2 * (blockIdx.x - ni * Mp);
+    const bool two = m0 + 1 < Lj;
+    const int n = 2 * ni - (a.N - 1);
+    const bool odd0 = ((m0 + n) & 1) != 0;  // s of column m0 is -1
+    const double2 *__restrict__ Ua = (const double2 *)a.in + blockIdx.y * a.s_in + ((size_t)ni * Lj + m0) * Lj;
+    const double2 *__restrict__ Ub = Ua + Lj;
+    const C *__restrict__ cpp = (const C *)a.cpp + (L - 1);
+    const C *__restrict__ csq = (const C *)a.csq;
+    const int Na = 2 * Lj - 1;
+    auto in = [&](int i, int = 0) {
+        if (i >= Na) return zero2<C>();
+        const int mp = i - (Lj - 1), am = mp < 0 ? -mp : mp;
+        C va = to_c<C>(Ua[am]);
+        C vb = two ? to_c<C>(Ub[am]) : zero2<C>();
+        if (mp < 0) {
+            if (odd0) va = mk<C>(-va.x, -va.y);
+            else vb = mk<C>(-vb.x, -vb.y);
+        }
+        return cmul(cadd(va, vb), cpp[mp]);
+    };
+    auto st = [&](int i, C v, int = 0) {
+        const int t = i - (Na - 1);
+        if (t >= 0 && t < T) buf[pad(t)] = cmul(v, csq[t]);
+    };
+    fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, Na);
+    C *__restrict__ oa = (C *)a.out + blockIdx.y * a.s_out + ((size_t)ni * Lj + m0) * L;
+    C *__restrict__ ob = oa + L;
+    const real_t<C> h = (real_t<C>)0.5;
+    for (int b = tid; b < L; b += P / kRM) {
+        const C x = buf[pad(b)], y = buf[pad(T - 1 - b)];
+        const C p = cscale(cadd(x, y), h), q = cscale(csub(x, y), h);
+        oa[b] = odd0 ? q : p;
+        if (two) ob[b] = odd0 ? p : q;
+    }
+}
+
+// The same two-column transform as a direct prime-factor transform of length T (pfa.h):
+//   F_z(beta_t) = sum_{m'} [z(m') e^{i pi m'/T}] e^{2 pi i m' t/T},  input index n = m' mod T,
+// for every scale of the equiangular grid when T is one of its lengths; LN::NC column pairs per
+// workgroup.  e^{i pi m'/T} = eph[m'/2 mod T] for even m', -eph[(m' + T)/2 mod T] for odd m'.
+template <class C, class LN>
+__global__ void __launch_bounds__(256) beta_fwd_pfa_kernel(const StageArgs a) {
+    __shared__ C buf[LN::lds];
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, L = a.L, T = LN::T, N = a.N;
+    const int Mp = (Lj + 1) >> 1, ncols = N * Mp, nwg = (ncols + LN::NC - 1) / LN::NC;
+    if ((int)blockIdx.x >= nwg) return;
+    const int u0 = blockIdx.x * LN::NC, ncol = min(LN::NC, ncols - u0);
+    const double2 *__restrict__ U = (const double2 *)a.in + blockIdx.y * a.s_in;
+    const C *__restrict__ eph = (const C *)a.eph;
+    auto in = [&](int c, int n) {
+        const int u = u0 + c, ni = u / Mp, m0 = 2 * (u - (u / Mp) * Mp);
+        const int mp = n < Lj ? n : (n > T - Lj ? n - T : T);
+        if (mp == T) return mk<C>(0, 0);
+        const bool two = m0 + 1 < Lj;
+        const bool odd0 = ((m0 + 2 * ni - (N - 1)) & 1) != 0;
+        const int am = mp < 0 ? -mp : mp;
+        const double2 *Ua = U + ((size_t)ni * Lj + m0) * Lj;
+        C va = to_c<C>(Ua[am]);
+        C vb = two ? to_c<C>(Ua[Lj + am]) : mk<C>(0, 0);
+        if (mp < 0) {
+            if (odd0) va = mk<C>(-va.x, -va.y);
+            else vb = mk<C>(-vb.x, -vb.y);
+        }
+        const bool oddm = (mp & 1) != 0;
+        int r = oddm ? (mp + T) / 2 : mp / 2;
+        r %= T;
+        if (r < 0) r += T;
+        C e = eph[r];
+        if (oddm) e = mk<C>(-e.x, -e.y);
+        return cmul(cadd(va, vb), e);
+    };
+    pfa::dft_lds<LN, +1>(buf, (const C *)a.pcs, tid, ncol, in);
+    const real_t<C> h = (real_t<C>)0.5;
+    for (int e = tid; e < ncol * L; e += LN::NTH) {
+        const int c = e / L, b = e - (e / L) * L;
+        const int u = u0 + c, ni = u / Mp, m0 = 2 * (u - (u / Mp) * Mp);
+        const bool two = m0 + 1 < Lj;
+        const bool odd0 = ((m0 + 2 * ni - (N - 1)) & 1) != 0;
+        const C x = buf[c * LN::CS + LN::pos_out(b)], y = buf[c * LN::CS + LN::pos_out(T - 1 - b)];
+        const C p = cscale(cadd(x, y), h), q = cscale(csub(x, y), h);
+        C *__restrict__ oa = (C *)a.out + blockIdx.y * a.s_out + ((size_t)ni * Lj + m0) * L;
+        oa[b] = odd0 ? q : p;
+        if (two) oa[L + b] = odd0 ? p : q;
+    }
 }
 
 // ------------------------------------------------------------------ alpha and gamma stages
@@ -184,6 +286,67 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const
         }
     };
     fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in, st, T);
+}
+
+// The same alpha sums as direct prime-factor transforms of length T (pfa.h) where T is one of
+// its lengths: LN::NC consecutive rings b of one order row per workgroup, no chirps.
+//   analysis:  Y(a) = sum_{|m|<Lj} C(m) e^{2 pi i m a/T}: input index n = m mod T (sign +1)
+//   synthesis: Gs(m) = wa wg sum_a X(a) e^{-2 pi i m a/T}: output index k = m mod T (sign -1)
+template <class C, class LN>
+__global__ void __launch_bounds__(256) alpha_fwd_pfa_kernel(const StageArgs a) {
+    __shared__ C buf[LN::lds];
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, T = LN::T, N = a.N, Nh = a.Nh, nb = a.nb;
+    const int ncols = Nh * nb, nwg = (ncols + LN::NC - 1) / LN::NC;
+    const int g = xcd_column(blockIdx.x, nwg);
+    if (g >= nwg) return;
+    const int t0 = g * LN::NC, ncol = min(LN::NC, ncols - t0);
+    const C *__restrict__ U = (const C *)a.in + blockIdx.y * a.s_in;
+    C *__restrict__ Y = (C *)a.out + blockIdx.y * a.s_out;
+    auto in = [&](int c, int n) {
+        const int t = t0 + c, np = t / nb, b = t - (t / nb) * nb;
+        const int ni = (N / 2) + np, nj = N - 1 - ni;
+        const int m = n < Lj ? n : (n > T - Lj ? n - T : T);
+        if (m == T) return mk<C>(0, 0);
+        const int am = m < 0 ? -m : m;
+        C v = U[((size_t)(m >= 0 ? ni : nj) * Lj + am) * nb + b];
+        if (m < 0) v = cconj(v);
+        if (m == 0 && ni == nj) v.y = 0;
+        return v;
+    };
+    auto out = [&](int c, int k, C v) {
+        const int t = t0 + c, np = t / nb, b = t - (t / nb) * nb;
+        Y[((size_t)np * nb + b) * T + k] = v;
+    };
+    pfa::dft<LN, +1>(buf, (const C *)a.pcs, tid, ncol, in, out);
+}
+
+template <class C, class LN>
+__global__ void __launch_bounds__(256) alpha_adj_pfa_kernel(const StageArgs a) {
+    __shared__ C buf[LN::lds];
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, T = LN::T, N = a.N, Nh = a.Nh, nb = a.nb;
+    const int ncols = Nh * nb, nwg = (ncols + LN::NC - 1) / LN::NC;
+    const int g = xcd_column(blockIdx.x, nwg);
+    if (g >= nwg) return;
+    const int t0 = g * LN::NC, ncol = min(LN::NC, ncols - t0);
+    const C *__restrict__ X = (const C *)a.in + blockIdx.y * a.s_in;
+    C *__restrict__ G = (C *)a.out + blockIdx.y * a.s_out;
+    const real_t<C> sc = (real_t<C>)a.scale;
+    auto in = [&](int c, int n) {
+        const int t = t0 + c, np = t / nb, b = t - (t / nb) * nb;
+        return X[((size_t)np * nb + b) * T + n];
+    };
+    auto out = [&](int c, int k, C v) {
+        const int m = k < Lj ? k : (k > T - Lj ? k - T : T);
+        if (m == T) return;
+        const int t = t0 + c, np = t / nb, b = t - (t / nb) * nb;
+        const int ni = (N / 2) + np, nj = N - 1 - ni;
+        const C z = cscale(v, sc);
+        if (m >= 0) G[((size_t)ni * Lj + m) * nb + b] = z;
+        if (m <= 0 && ni != nj) G[((size_t)nj * Lj - m) * nb + b] = cconj(z);
+    };
+    pfa::dft<LN, -1>(buf, (const C *)a.pcs, tid, ncol, in, out);
 }
 
 // Blocked alpha sums for scales with few coefficients (2Lj - 1 well below T): the T samples
@@ -704,53 +867,96 @@ __device__ __forceinline__ void fold_pq(C *buf, int tid, int Lj, int m, int n, i
 }
 
 // Equiangular grid.
-// Column pair (+n, -n), fixed m.  (1) Fourier coefficients of the samples extended to the
-// full circle (G(2 pi - beta) = (-1)^{m+n} G(beta)):
+// For one column (n, m): (1) Fourier coefficients of the samples extended to the full circle
+// (G(2 pi - beta) = s G(beta), s = (-1)^{m+n}):
 //   Gh(p) = (1/T) sum_{t<T} ext_t e^{-i p beta_t},  |p| < L,  beta_t = pi(2t+1)/T;
 // (2) V(m') = sum_p Gh(p) w(p - m'), |m'| < Lj, with w(q) = int_0^pi sin(b) e^{i q b} db
 // (2/(1-q^2) for even q, +-i pi/2 for q = +-1, else 0): the exact beta integral of the
-// interpolant against e^{-i m' beta}; (3) the fold over +-m' and the even/odd-l
-// combinations P, Q of the two n columns (see the synthesis Wigner kernel).
-// Column pair col = k Lj + m of a scale of band-limit Lj; in / out: the scale's G and V of
-// the map, hh2: the scale's w(q) spectrum.
-template <class C, int P>
+// interpolant against e^{-i m' beta}; (3) the fold U(m') = V(m') + s V(-m') over +-m' (m' > 0;
+// U(0) = V(0)) and the even/odd-l combinations P, Q of the two n columns (see the synthesis
+// Wigner kernel).
+//
+// Columns m and m + 1 have opposite s, and one convolution serves both.  Every sample but the
+// one at beta = pi (t = L - 1, its own mirror image) pairs with its mirror, so Gh is even in p
+// for s = +1 and odd for s = -1 once the beta = pi sample of the s = -1 column is set aside.
+// With w = we + wo split into its even part (the even q) and its odd part (q = +-1), the fold
+// of an even (odd) Gh only keeps 2 sum_p Gh(p) we(p - m'), and the we-convolution of an odd
+// (even) Gh is odd (even) in m'.  So the packed column Gh_m + Gh_{m+1}, convolved with we into
+// y(m'), |m'| < Lj, gives U_X(m') = y(m') + s_X y(-m') for both members X (m' > 0; at m' = 0 the
+// even member's U is y(0), and the odd member's term is multiplied by Delta^l_{0m} Delta^l_{0n}
+// = 0 in the contraction).  The set-aside beta = pi sample G_X(L-1) of the odd member adds
+// (1/T) G_X(L-1) (-1)^p to its Gh; through the fold that contributes 2 sum_p (1/T) G_X(L-1) (-1)^p
+// wo(p - m'), which vanishes except at m' = L - 1, where it is -(i pi/T) (-1)^L G_X(L-1).
+// hh2 is the spectrum of we.
+// Work item col = k Mp + c of a scale of band-limit Lj: order k, columns m0 = 2c and m0 + 1
+// (Mp = ceil(Lj/2)); in / out: the scale's G and V of the map.
+// DIRECT (P = 8192, T = 4095): step (1) as the prime-factor transform of length T (pfa.h).
+template <class C, int P, bool DIRECT = false>
 __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int col, int Lj, const C *in, C *out,
                                               const C *hh2) {
     constexpr int NT = P / kRM;
     const int tid = threadIdx.x;
     const int L = a.L, T = 2 * L - 1, N = a.N;
-    const int k = col / Lj, m = col - (col / Lj) * Lj;
+    const int Mp = (Lj + 1) >> 1;
+    const int k = col / Mp, m0 = 2 * (col - (col / Mp) * Mp);
+    const bool two = m0 + 1 < Lj;  // column m0 + 1 present
     int n = 0;  // a.nk[k] without a dynamically indexed copy of the argument block
 #pragma unroll
     for (int kk = 0; kk < kMaxK; ++kk)
         if (kk == k) n = a.nk[kk];
     const int ncol = n == 0 ? 1 : 2;
-    const bool odd = ((m + n) & 1) != 0;
+    const bool odd0 = ((m0 + n) & 1) != 0;  // column m0 is the odd member (s = -1), else m0 + 1
     const int Nk = 2 * Lj - 1;
     const C *__restrict__ csq = (const C *)a.csq;
     const C *__restrict__ cpp = (const C *)a.cpp;
-    C *__restrict__ Po = out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
-    C *__restrict__ Qo = out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
-    // V of column +n by storer slot (two columns).  The storer of the last inverse pass
-    // gets element tid + s NT in slot s (span P/kRM = NT), so the slot gives the index back.
+    // y of order +n by storer slot (two orders).  The storer of the last inverse pass gets
+    // element tid + s NT in slot s (span P/kRM = NT), so the slot gives the index back.
     C keep[kRM];
     for (int c = 0; c < ncol; ++c) {
         const int ni = ((c == 0 ? n : -n) + N - 1) >> 1;
-        const C *__restrict__ Gc = in + ((size_t)ni * Lj + m) * L;
-        auto in1 = [&](int i, int = 0) {
+        const C *__restrict__ Ga = in + ((size_t)ni * Lj + m0) * L;
+        const C *__restrict__ Gb = Ga + L;  // column m0 + 1
+        // the packed extended column at t < T
+        auto ext = [&](int i) {
+            const int b = i < L ? i : 2 * L - 2 - i;
+            C va = Ga[b];
+            C vb = two ? Gb[b] : zero2<C>();
+            C &vo = odd0 ? va : vb;  // the odd member
+            if (i == L - 1) vo = zero2<C>();
+            else if (i >= L) vo = mk<C>(-vo.x, -vo.y);
+            return cadd(va, vb);
+        };
+        if constexpr (DIRECT) {
+            // Gh(p) = (1/T) e^{-i pi p/T} X[p mod T], X = sum_t ext_t e^{-2 pi i p t/T}; X[k] sits at
+            // buf[pos_out(k)]; the first pass of the next convolution reads every input before it
+            // writes its outputs, so the transform's layout may share the buffer
+            static_assert(P == 8192, "the direct transform serves T = 4095");
+            pfa::dft_lds<pfa::Len4095T<NT>, -1>(buf, (const C *)a.pcs, tid, 1, [&](int, int t) { return ext(t); });
+        } else {
+            auto in1 = [&](int i, int = 0) { return i < T ? cmulc(ext(i), csq[i]) : zero2<C>(); };
+            // Gh(p), q = p + L - 1 < T, comes out at q + T - 1 (1/T is folded into the spectrum)
+            auto st1 = [&](int i, C v, int = 0) {
+                const int q = i - (T - 1);
+                if (q >= 0 && q < T) buf[pad(q)] = cmulc(v, cpp[q]);
+            };
+            fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in1, st1, T);
+        }
+        const C *__restrict__ eph = (const C *)a.eph;
+        const real_t<C> invT = (real_t<C>)(1.0 / T);
+        auto in2 = [&](int i, int = 0) {
             if (i >= T) return zero2<C>();
-            C v = i < L ? Gc[i] : Gc[2 * L - 2 - i];
-            if (i >= L && odd) v = mk<C>(-v.x, -v.y);
-            return cmulc(v, csq[i]);
+            if constexpr (!DIRECT) return buf[pad(i)];
+            // p = i - (L - 1); e^{i pi p/T} = eph[p/2 mod T] (p even), -eph[(p + T)/2 mod T] (p odd)
+            const int p = i - (L - 1);
+            const bool oddp = (p & 1) != 0;
+            int r = oddp ? (p + T) / 2 : p / 2;
+            r %= T;
+            if (r < 0) r += T;
+            C e = eph[r];
+            if (oddp) e = mk<C>(-e.x, -e.y);
+            return cscale(cmulc(buf[pfa::Len4095::pos_out(p < 0 ? p + T : p)], e), invT);
         };
-        // Gh(p), q = p + L - 1 < T, comes out at q + T - 1 (1/T is folded into the spectrum)
-        auto st1 = [&](int i, C v, int = 0) {
-            const int q = i - (T - 1);
-            if (q >= 0 && q < T) buf[pad(q)] = cmulc(v, cpp[q]);
-        };
-        fft::convolve_io<P, kRM>(buf, tid, (const C *)a.tw, (const C *)a.hh, in1, st1, T);
-        auto in2 = [&](int i, int = 0) { return i < T ? buf[pad(i)] : zero2<C>(); };
-        // V(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + T - 1.  With two columns the
+        // y(m'), q = m' + Lj - 1 < 2Lj - 1, comes out at q + T - 1.  With two orders the
         // first one waits in registers (each thread keeps the outputs of its storer slots)
         // while the second one uses the whole buffer; the second one goes to slots Nk + q.
         if (c == 0 && ncol > 1) {
@@ -773,19 +979,66 @@ __device__ __forceinline__ void beta_adj_body(const StageArgs &a, C *buf, int co
         }
     }
     __syncthreads();
-    fold_pq<C, NT>(buf, tid, Lj, m, n, ncol, odd, a.eta_imag ? 1 : 0, Po, Qo);
+    // the fold and the P, Q combinations of both members
+    using R = real_t<C>;
+    const int eta = a.eta_imag ? 1 : 0;
+    const R dsc = (R)((L & 1) ? M_PI / T : -M_PI / T);  // -(pi/T) (-1)^L: times i G(L-1)
+    for (int x = 0; x < (two ? 2 : 1); ++x) {
+        const int m = m0 + x;
+        const bool oddx = (x == 0) == odd0;  // this member has s = -1
+        C *__restrict__ Po = out + (((size_t)k * 2 + 0) * Lj + m) * Lj;
+        C *__restrict__ Qo = out + (((size_t)k * 2 + 1) * Lj + m) * Lj;
+        const C *Gx = in + m * (size_t)L;
+        for (int mp = tid; mp < Lj; mp += NT) {
+            C tp, tm;
+            if (mp == 0) {
+                tp = oddx ? zero2<C>() : buf[pad(Lj - 1)];
+                tm = (oddx || ncol == 1) ? zero2<C>() : buf[pad(Nk + Lj - 1)];
+            } else {
+                const C yp = buf[pad(mp + Lj - 1)], yn = buf[pad(-mp + Lj - 1)];
+                tp = oddx ? csub(yp, yn) : cadd(yp, yn);
+                if (ncol > 1) {
+                    const C zp = buf[pad(Nk + mp + Lj - 1)], zn = buf[pad(Nk - mp + Lj - 1)];
+                    tm = oddx ? csub(zp, zn) : cadd(zp, zn);
+                } else {
+                    tm = zero2<C>();
+                }
+                if (oddx && mp == L - 1) {
+                    // the set-aside beta = pi samples of orders +n and -n
+                    const C gp = Gx[((size_t)((n + N - 1) >> 1) * Lj) * L + (L - 1)];
+                    tp = cadd(tp, mk<C>(-dsc * gp.y, dsc * gp.x));
+                    if (ncol > 1) {
+                        const C gm = Gx[((size_t)((-n + N - 1) >> 1) * Lj) * L + (L - 1)];
+                        tm = cadd(tm, mk<C>(-dsc * gm.y, dsc * gm.x));
+                    }
+                }
+            }
+            C Pv, Qv;
+            if (n == 0) {
+                Pv = Qv = rot_i(tp, m + eta);
+            } else {
+                const C A = rot_i(tp, -n);
+                C B = rot_i(tm, n);
+                if (mp & 1) B = mk<C>(-B.x, -B.y);
+                Pv = rot_i(cadd(A, B), m + eta);
+                Qv = rot_i(csub(A, B), m + eta);
+            }
+            Po[mp] = Pv;
+            Qo[mp] = Qv;
+        }
+    }
 }
 
-template <class C, int P>
+template <class C, int P, bool DIRECT = false>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_fft_kernel(const StageArgs a) {
     __shared__ C buf[fft::padded(P)];
-    beta_adj_body<C, P>(a, buf, blockIdx.x, a.Lj, (const C *)a.in + blockIdx.y * a.s_in,
-                        (C *)a.out + blockIdx.y * a.s_out, (const C *)a.hh2);
+    beta_adj_body<C, P, DIRECT>(a, buf, blockIdx.x, a.Lj, (const C *)a.in + blockIdx.y * a.s_in,
+                                (C *)a.out + blockIdx.y * a.s_out, (const C *)a.hh2);
 }
 
 // The coarse scales of a map in one launch (each alone would fill only a few workgroups):
 // workgroups [tab[s].first, tab[s + 1].first) take scale s.
-template <class C, int P>
+template <class C, int P, bool DIRECT = false>
 __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_multi_kernel(const StageArgs a,
                                                                               const BetaAdjScale *tab, int ns) {
     __shared__ C buf[fft::padded(P)];
@@ -793,7 +1046,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_adj_multi_kernel(cons
     for (int i = 1; i < ns; ++i)
         if ((int)blockIdx.x >= tab[i].first) s = i;
     const BetaAdjScale e = tab[s];
-    beta_adj_body<C, P>(a, buf, blockIdx.x - e.first, e.Lj, (const C *)a.in + blockIdx.y * a.s_in + e.in_off,
+    beta_adj_body<C, P, DIRECT>(a, buf, blockIdx.x - e.first, e.Lj, (const C *)a.in + blockIdx.y * a.s_in + e.in_off,
                         (C *)a.out + blockIdx.y * a.s_out + e.out_off, (const C *)e.hh2);
 }
 
@@ -886,6 +1139,11 @@ hipError_t launch_beta_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t 
     return hipGetLastError();
 }
 
+hipError_t launch_beta_fwd_pair(const StageArgs &a, int P, int maps, hipStream_t st) {
+    S2DW_P_SWITCH(P, beta_fwd_pair_kernel, a.N * ((a.Lj + 1) / 2), a)
+    return hipGetLastError();
+}
+
 hipError_t launch_alpha_fwd_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
     S2DW_P_SWITCH(P, alpha_fwd_fft_kernel, 8 * ((a.Nh * a.nb + 7) / 8), a)
     return hipGetLastError();
@@ -895,6 +1153,45 @@ hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, int maps, hipStream_t
     S2DW_P_SWITCH(P, alpha_adj_fft_kernel, 8 * ((a.Nh * a.nb + 7) / 8), a)
     return hipGetLastError();
 }
+
+bool pfa_length(int T) { return T == 2047 || T == 4095; }
+
+// T = 2L - 1 in {2047, 4095}
+#define S2DW_PFA_LAUNCH(KER)                                                                         \
+    {                                                                                                \
+        const int T = 2 * a.L - 1;                                                                   \
+        if (T != 2047 && T != 4095) return hipErrorInvalidValue;                                     \
+        const int NC = T == 2047 ? pfa::Len2047::NC : pfa::Len4095::NC;                              \
+        const int nwg = (a.Nh * a.nb + NC - 1) / NC;                                                 \
+        const dim3 grid((unsigned)(8 * ((nwg + 7) / 8)), (unsigned)maps);                            \
+        if (T == 2047) {                                                                             \
+            if (a.f32) hipLaunchKernelGGL((KER<float2, pfa::Len2047>), grid, dim3(256), 0, st, a);   \
+            else hipLaunchKernelGGL((KER<double2, pfa::Len2047>), grid, dim3(256), 0, st, a);        \
+        } else {                                                                                     \
+            if (a.f32) hipLaunchKernelGGL((KER<float2, pfa::Len4095>), grid, dim3(256), 0, st, a);   \
+            else hipLaunchKernelGGL((KER<double2, pfa::Len4095>), grid, dim3(256), 0, st, a);        \
+        }                                                                                            \
+        return hipGetLastError();                                                                    \
+    }
+
+hipError_t launch_alpha_fwd_pfa(const StageArgs &a, int maps, hipStream_t st) S2DW_PFA_LAUNCH(alpha_fwd_pfa_kernel)
+
+hipError_t launch_beta_fwd_pfa(const StageArgs &a, int maps, hipStream_t st) {
+    const int T = 2 * a.L - 1;
+    if (T != 2047 && T != 4095) return hipErrorInvalidValue;
+    const int NC = T == 2047 ? pfa::Len2047::NC : pfa::Len4095::NC;
+    const dim3 grid((unsigned)((a.N * ((a.Lj + 1) / 2) + NC - 1) / NC), (unsigned)maps);
+    if (T == 2047) {
+        if (a.f32) hipLaunchKernelGGL((beta_fwd_pfa_kernel<float2, pfa::Len2047>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((beta_fwd_pfa_kernel<double2, pfa::Len2047>), grid, dim3(256), 0, st, a);
+    } else {
+        if (a.f32) hipLaunchKernelGGL((beta_fwd_pfa_kernel<float2, pfa::Len4095>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((beta_fwd_pfa_kernel<double2, pfa::Len4095>), grid, dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha_adj_pfa(const StageArgs &a, int maps, hipStream_t st) S2DW_PFA_LAUNCH(alpha_adj_pfa_kernel)
 
 hipError_t launch_alpha_fwd_blk(const StageArgs &a, int P, int maps, hipStream_t st) {
     S2DW_P_SWITCH(P, alpha_fwd_blk_kernel, 8 * ((a.Nh * a.nb + 7) / 8), a)
@@ -907,7 +1204,13 @@ hipError_t launch_alpha_adj_blk(const StageArgs &a, int P, int maps, hipStream_t
 }
 
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st) {
-    S2DW_P_SWITCH(P, beta_adj_fft_kernel, a.K * a.Lj, a)
+    if (P == 8192 && a.pcs) {  // T = 4095
+        const dim3 grid((unsigned)(a.K * ((a.Lj + 1) / 2)), (unsigned)maps);
+        if (a.f32) hipLaunchKernelGGL((beta_adj_fft_kernel<float2, 8192, true>), grid, dim3(8192 / kRM), 0, st, a);
+        else hipLaunchKernelGGL((beta_adj_fft_kernel<double2, 8192, true>), grid, dim3(8192 / kRM), 0, st, a);
+        return hipGetLastError();
+    }
+    S2DW_P_SWITCH(P, beta_adj_fft_kernel, a.K * ((a.Lj + 1) / 2), a)
     return hipGetLastError();
 }
 
@@ -924,7 +1227,14 @@ hipError_t launch_beta_adj_multi(const StageArgs &a, const BetaAdjScale *tab, in
         S2DW_MULTI_CASE(C, 2048) S2DW_MULTI_CASE(C, 4096) S2DW_MULTI_CASE(C, 8192)               \
         default: return hipErrorInvalidValue;                                                   \
     }
-    if (a.f32) {
+    if (P == 8192 && a.pcs) {  // T = 4095
+        if (a.f32)
+            hipLaunchKernelGGL((beta_adj_multi_kernel<float2, 8192, true>), dim3(nwg, maps), dim3(8192 / kRM), 0, st, a,
+                               tab, ns);
+        else
+            hipLaunchKernelGGL((beta_adj_multi_kernel<double2, 8192, true>), dim3(nwg, maps), dim3(8192 / kRM), 0, st,
+                               a, tab, ns);
+    } else if (a.f32) {
         S2DW_MULTI_SWITCH(float2)
     } else {
         S2DW_MULTI_SWITCH(double2)

@@ -35,11 +35,11 @@ STAGE_KERNELS = {  # first match wins: the fused passes before the gamma passes 
     "gamma_alpha_adj": ("gamma_alpha_adj_kernel",),
     "wigner_fwd": ("wig_fwd_kernel",),
     "wigner_adj": ("wig_adj_kernel",),
-    "beta_fwd": ("beta_fwd_fft_kernel",),
-    "alpha_fwd": ("alpha_fwd_fft_kernel", "alpha_fwd_blk_kernel"),
+    "beta_fwd": ("beta_fwd_fft_kernel", "beta_fwd_pair_kernel", "beta_fwd_pfa_kernel"),
+    "alpha_fwd": ("alpha_fwd_fft_kernel", "alpha_fwd_blk_kernel", "alpha_fwd_pfa_kernel"),
     "gamma_fwd": ("gamma_fwd_kernel",),
     "gamma_adj": ("gamma_adj_kernel",),
-    "alpha_adj": ("alpha_adj_fft_kernel", "alpha_adj_blk_kernel"),
+    "alpha_adj": ("alpha_adj_fft_kernel", "alpha_adj_blk_kernel", "alpha_adj_pfa_kernel"),
     "beta_adj": ("beta_adj_fft_kernel", "beta_adj_multi_kernel"),
     "syn_final": ("syn_final_kernel",),
     "pad": ("pad_flm_kernel",),
