@@ -139,6 +139,26 @@ int s2dw_scale_grid(const s2dw_params *p, int32_t j, int32_t shape[3], uint64_t 
 int s2dw_analysis(const s2dw_params *p, const double *flm, void *W, double *Wphi_lm, void *stream);
 
 /*
+ * Wavelet analysis that allocates nothing, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments and results as s2dw_analysis (bitwise), one map.  The stage workspaces
+ * live in a fixed device scratch of S2DW_NOALLOC_SCRATCH_BYTES that every GPU the library
+ * runs on holds until the process ends; the call makes no hipMalloc or hipFree, and
+ * records no stage-timing events.
+ *  - The plan of p must exist: build it first with any call that allocates (for example
+ *    s2dw_workspace_bytes, or s2dw_analysis, with the same parameters and precision);
+ *    otherwise S2DW_E_ARG.
+ *  - Parameters whose workspace exceeds the scratch return S2DW_E_UNSUPPORTED (about
+ *    L <= 256 at N = 8; s2dw_workspace_bytes, which also counts the synthesis's partial
+ *    sums, is an upper bound).
+ *  - All calls on one GPU share its scratch: calls that overlap in time on one GPU (on
+ *    different streams or from different host threads) race and give wrong results.  The
+ *    scratch keeps the last call's contents; every call writes what it reads first.
+ */
+#define S2DW_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int s2dw_analysis_noalloc(const s2dw_params *p, const double *flm, void *W, double *Wphi_lm, void *stream);
+
+/*
  * Wavelet synthesis (Eq. 4 through Eq. 32-41, with exact quadrature on the
  * equiangular grid).
  *   W        in : [S][2N-1][L][2L-1] real.

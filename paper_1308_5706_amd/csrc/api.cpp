@@ -162,13 +162,17 @@ hipEvent_t prof_event() {
     return g_prof.pool[g_prof.used++];
 }
 
+// Set while the calling thread runs the entry point that allocates nothing: its launches
+// record no timing events (creating one may allocate).
+thread_local bool t_no_events = false;
+
 // Records events around one launch when timing is on.
 struct Stage {
     hipStream_t st;
     hipEvent_t a = nullptr;
     const char *name;
     Stage(const char *n, hipStream_t s) : st(s), name(n) {
-        if (!g_prof.on) return;
+        if (!g_prof.on || t_no_events) return;
         std::lock_guard<std::mutex> lk(g_prof.mu);
         if (!g_prof.only.empty() && !g_prof.only.count(n)) return;
         a = prof_event();
@@ -826,6 +830,16 @@ int ensure_f32(Plan &P) {
     return S2DW_OK;
 }
 
+// The plan of these parameters if it was built before (and, with f32, its FP32 tables too),
+// else null; builds nothing.
+Plan *find_plan(int L, int N, double lam, int J_min, bool f32, int grid) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(PlanKey(kWavelet, L, N, lam, J_min, grid));
+    if (it == g_plans.end()) return nullptr;
+    if (f32 && !it->second->f32_ready) return nullptr;
+    return it->second.get();
+}
+
 int get_plan(int kind, int L, int N, double lam, int J_min, Plan *&out, bool f32 = false, int grid = S2DW_GRID_MW) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (kind != kWavelet) grid = S2DW_GRID_MW;
@@ -1263,6 +1277,41 @@ int run_forward(Plan &P, const Shape &sh, Work &w, int maps, const void *W, cons
 }  // namespace
 }  // namespace s2dw
 
+namespace s2dw {
+
+// Fixed device scratch of s2dw_analysis_noalloc (the stage workspaces of one call): one copy
+// per GPU, held until the process ends.  In host code the name is only a stand-in for the
+// device symbol; its device address comes from hipGetSymbolAddress (per device, below).
+// File-scope array with external linkage: a `static` one keeps a local binding in the
+// device code object, outside its dynamic symbol table, and the runtime cannot resolve
+// it by name.
+__device__ __align__(256) double2 scratch[S2DW_NOALLOC_SCRATCH_BYTES / sizeof(double2)];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, double2 *> g_scratch;  // device -> device address of that device's scratch
+
+// The scratch of the current device, looked up once per device (with that device current).
+int scratch_of_current_device(double2 *&out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return S2DW_E_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        out = it->second;
+        return S2DW_OK;
+    }
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return S2DW_E_DEVICE;
+    g_scratch[dev] = (double2 *)ptr;
+    out = (double2 *)ptr;
+    return S2DW_OK;
+}
+
+}  // namespace
+}  // namespace s2dw
+
 using namespace s2dw;
 
 extern "C" {
@@ -1522,6 +1571,37 @@ int s2dw_cache_bytes(uint64_t *bytes) {
 
 int s2dw_analysis(const s2dw_params *p, const double *flm, void *W, double *Wphi_lm, void *stream) {
     return s2dw_analysis_batched(p, 1, flm, W, Wphi_lm, stream);
+}
+
+int s2dw_analysis_noalloc(const s2dw_params *p, const double *flm, void *W, double *Wphi_lm, void *stream) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    if (!flm || !W || !aligned(flm) || !aligned(W) || (Wphi_lm && !aligned(Wphi_lm))) return S2DW_E_ARG;
+    const int f32 = p->precision == S2DW_MIXED ? 1 : 0;
+    Plan *P = find_plan(p->L, p->N, p->lambda, p->J_min, f32 != 0, p->grid);
+    if (!P) return S2DW_E_ARG;  // the plan must have been built by an allocating call
+    const bool cx = p->reality == 0;
+    const int per = cx ? 2 : 1;  // real maps of the signal
+    const size_t per_map = P->s_fpad + P->s_U + P->s_Ub + P->s_Y;  // complex elements
+    if ((size_t)per * per_map * sizeof(double2) > S2DW_NOALLOC_SCRATCH_BYTES) return S2DW_E_UNSUPPORTED;
+    double2 *base = nullptr;
+    rc = scratch_of_current_device(base);
+    if (rc != S2DW_OK) return rc;
+    Work w;  // views into the scratch (owns nothing)
+    w.cap = per;
+    w.fpad = base;
+    w.U = w.fpad + (size_t)per * P->s_fpad;
+    w.Ub = w.U + (size_t)per * P->s_U;
+    w.Y = w.Ub + (size_t)per * P->s_Ub;
+    const Shape sh = shape_of(*P);
+    hipStream_t st = (hipStream_t)stream;
+    t_no_events = true;
+    rc = run_inverse(*P, sh, w, per, (const double2 *)flm, W, f32, st, cx);
+    if (rc == S2DW_OK && Wphi_lm && launch_scaling((const double2 *)flm, P->phi, (double2 *)Wphi_lm, p->L, 1, st) !=
+                                        hipSuccess)
+        rc = S2DW_E_DEVICE;
+    t_no_events = false;
+    return rc;
 }
 
 int s2dw_synthesis(const s2dw_params *p, const void *W, const double *Wphi_lm, double *flm_out, void *stream) {

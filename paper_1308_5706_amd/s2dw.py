@@ -51,6 +51,7 @@ def lib():
                            ("s2dw_grid_shape", [cp, ctypes.POINTER(ctypes.c_int32)]),
                            ("s2dw_wavelet_bytes", [cp, ctypes.POINTER(ctypes.c_uint64)]),
                            ("s2dw_analysis", [cp, vp, vp, vp, vp]),
+                           ("s2dw_analysis_noalloc", [cp, vp, vp, vp, vp]),
                            ("s2dw_synthesis", [cp, vp, vp, vp, vp]),
                            ("s2dw_scaling", [cp, vp, vp, vp, vp]),
                            ("s2dw_sht_forward", [cp, vp, vp, vp]),
@@ -87,6 +88,7 @@ def lib():
 
 
 EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_scale_grid", "s2dw_analysis",
+            "s2dw_analysis_noalloc",
             "s2dw_synthesis", "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_workspace_bytes",
             "s2dw_cache_bytes",
             "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
@@ -211,6 +213,20 @@ def analysis(flm: torch.Tensor, L: int, N: int, lam: float = 2.0, J_min: int = 0
                                ctypes.c_void_p(Wp.data_ptr() if Wp is not None else None), _stream(stream)),
            "s2dw_analysis")
     return W, Wp
+
+
+def analysis_noalloc(flm: torch.Tensor, W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int,
+                     lam: float = 2.0, J_min: int = 0, *, stream=None, precision: str = "fp64", grid: str = "mw",
+                     reality: bool = True) -> None:
+    """s2dw_analysis into caller-given W (and W^Phi, or None) through the entry point that
+    allocates no device memory (the plan must exist, see include/s2dw.h)."""
+    p = params(L, N, lam, J_min, precision, grid, reality)
+    f = _as_complex(flm, L * L, "flm")
+    _check_w(W, _w_shape(L, N, lam, J_min, grid), _w_dtype(precision, reality), 1, "W")
+    wp = _as_complex(Wphi, L * L, "Wphi") if Wphi is not None else None
+    _check(lib().s2dw_analysis_noalloc(ctypes.byref(p), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(W.data_ptr()),
+                                       ctypes.c_void_p(wp.data_ptr() if wp is not None else None), _stream(stream)),
+           "s2dw_analysis_noalloc")
 
 
 def synthesis(W: torch.Tensor, Wphi: torch.Tensor | None, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,
