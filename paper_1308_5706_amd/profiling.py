@@ -170,6 +170,56 @@ def write_profiles(d: str, name: str, commands: str, copy_bytes: int, out_dir: s
     return stages
 
 
+def wigner_valu(d: str, name: str, L: int, N: int, lam: float, J_min: int, commands: str, out_dir: str | None = None):
+    """profiles/NAME_wigner_fp64.md from DIR/valu (rocprofv3 --pmc SQ_INSTS_VALU_{ADD,MUL,FMA,
+    TRANS}_F64 SQ_ACTIVE_INST_VALU SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE on the Wigner kernels)
+    and DIR/trace: per Wigner kernel the algorithmic GFLOP (5 per term of the l-sum or the
+    m'-contraction, the count the benchmark uses), the executed FP64 GFLOP (64 lanes per wave
+    instruction, 2 per FMA; full execution masks assumed, so an upper bound) and the share of
+    SIMD cycles with a VALU instruction issued (4 cycles per wave64 instruction over 1024 SIMDs
+    for the kernel's duration)."""
+    import importlib.util
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    spec = importlib.util.spec_from_file_location("bench_for_profiles", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    from . import s2dw
+    kappa, _, _ = s2dw.wavelet_tables(L, N, lam, J_min)
+    alg = 5.0 * bench.wigner_terms(kappa, N)
+    trace = {n: (int(c), float(a)) for n, c, t, a in
+             _q(_db(os.path.join(d, "trace")),
+                "select name, count(*), sum(end - start), avg(end - start) from kernels group by name")}
+    rows = _q(_db(os.path.join(d, "valu")),
+              "select kernel_name, counter_name, sum(value), count(*) from counters_collection "
+              "group by kernel_name, counter_name")
+    per = defaultdict(dict)
+    for k, c, v, n in rows:
+        per[k][c] = float(v) / n * 1.0  # per dispatch (counters summed over the device)
+        per[k]["_n"] = n
+    lines = [f"# FP64 VALU counters of the Wigner kernels: {name}", "", "Commands (run from the repository root):", "",
+             "```", commands.strip(), "```", "", f"Kernel sources sha256: `{kernel_sources_hash()}`", "",
+             "| kernel | avg us | algorithmic GFLOP | executed FP64 GFLOP | executed / algorithmic | "
+             "algorithmic TFLOP/s (% of 78.6) | executed TFLOP/s | VALU busy % | FP64 share of VALU instructions |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k, c in sorted(per.items()):
+        avg_ns = next((a for n, (cnt, a) in trace.items() if n == k), None)
+        if avg_ns is None:
+            continue
+        fma, mul, add, tr = (c.get(x, 0.0) for x in ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64",
+                                                     "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_TRANS_F64"))
+        exe = 64.0 * (2.0 * fma + mul + add + tr)
+        valu = c.get("SQ_INSTS_VALU", 0.0)
+        busy = 4.0 * valu / (1024.0 * avg_ns * 1e-9 * 2.4e9)
+        t = avg_ns * 1e-9
+        lines.append(f"| `{k[:60]}` | {avg_ns / 1e3:.1f} | {alg / 1e9:.2f} | {exe / 1e9:.2f} | {exe / alg:.2f} | "
+                     f"{alg / t / 1e12:.1f} ({100 * alg / t / 78.6e12:.1f} %) | {exe / t / 1e12:.1f} | "
+                     f"{100 * busy:.1f} | {100 * (fma + mul + add + tr) / max(valu, 1):.0f} % |")
+    lines += ["", "Counters per dispatch: the value rocprofv3 reports summed over the device, averaged over the "
+              "profiled dispatches; VALU busy assumes 2.4 GHz.", ""]
+    with open(os.path.join(out_dir, f"{name}_wigner_fp64.md"), "w") as f:
+        f.write("\n".join(lines))
+
+
 def read_stage_traffic(name: str, out_dir: str | None = None):
     """HBM bytes per dispatch for each stage from a committed summary, or None when the
     summary is missing or the kernel sources changed since it was taken."""
@@ -185,6 +235,11 @@ def read_stage_traffic(name: str, out_dir: str | None = None):
 
 
 if __name__ == "__main__":
+    if len(sys.argv) >= 2 and sys.argv[1] == "--wigner":
+        # python -m paper_1308_5706_amd.profiling --wigner DIR NAME L N LAMBDA J_MIN "COMMANDS"
+        a = sys.argv[2:]
+        wigner_valu(a[0], a[1], int(a[2]), int(a[3]), float(a[4]), int(a[5]), a[6])
+        sys.exit(0)
     if len(sys.argv) < 4:
         print(__doc__)
         sys.exit(2)

@@ -51,15 +51,59 @@ class Request:
     t_done: float = 0.0
     W: torch.Tensor | None = None      # [S][2N-1][L][2L-1] once done
     Wphi: torch.Tensor | None = None
+    error: Exception | None = None     # set when its batch failed to launch
+    cancelled: bool = False            # set by Server.cancel; no results are kept
 
 
 @dataclass
 class _Batch:
     reqs: list
-    event: torch.cuda.Event
+    event: object                      # completion marker with .query()
     bytes: int
     W: torch.Tensor = None
     Wp: torch.Tensor = None
+
+
+class CudaBackend:
+    """The device side of the server: HIP streams, memory queries and the batched C entry
+    point.  The scheduler only uses these methods, so that its logic runs with any backend."""
+
+    def __init__(self, device: str, streams: int):
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+
+    def total_memory(self) -> int:
+        return torch.cuda.get_device_properties(self.device).total_memory
+
+    def held_bytes(self) -> int:
+        """The library's plans and workspaces plus torch's live tensors (results in flight or
+        kept by the caller)."""
+        return s2dw.cache_bytes() + torch.cuda.memory_allocated(self.device)
+
+    def cache_bytes(self) -> int:
+        return s2dw.cache_bytes()
+
+    def workspace_bytes(self, L, N, lam, J_min, n, precision) -> int:
+        return s2dw.workspace_bytes(L, N, lam, J_min, count=n, precision=precision)
+
+    def warm(self, L, N, lam, J_min, n, precision):
+        f = torch.zeros((n, L * L), dtype=torch.complex128, device=self.device)
+        for st in self.streams:
+            with torch.cuda.stream(st):
+                s2dw.analysis_batched(f, L, N, lam, J_min, precision=precision)
+            torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+    def launch(self, i, reqs, L, N, lam, J_min, precision):
+        """Analysis of the batch on stream i: (W, W^Phi, completion event)."""
+        st = self.streams[i]
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            F = torch.stack([r.flm for r in reqs])
+            W, Wp = s2dw.analysis_batched(F, L, N, lam, J_min, precision=precision)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return W, Wp, ev
 
 
 @dataclass
@@ -72,15 +116,19 @@ class Server:
     max_batch_bytes: int = 2 << 30     # cap on the W + W^Phi bytes of one batch
     max_bytes: int | None = None
     device: str = "cuda:0"
+    backend: object = None             # CudaBackend(device, streams) unless given
+    on_launch: object = None           # called with a batch's requests before it launches; an
+                                       # exception it raises fails that batch only
     _pending: deque = field(default_factory=deque)
     _busy: list = field(default_factory=list)
     _inflight_bytes: int = 0
+    _finished: list = field(default_factory=list)
 
     def __post_init__(self):
-        dev = torch.device(self.device)
+        if self.backend is None:
+            self.backend = CudaBackend(self.device, self.streams)
         if self.max_bytes is None:
-            self.max_bytes = int(0.7 * torch.cuda.get_device_properties(dev).total_memory)
-        self._streams = [torch.cuda.Stream(device=dev) for _ in range(self.streams)]
+            self.max_bytes = int(0.7 * self.backend.total_memory())
         self._busy = [None] * self.streams
         self._wel = 4 if self.precision == "mixed" else 8
 
@@ -93,41 +141,55 @@ class Server:
         return max(1, min(self.max_batch, self.max_batch_bytes // self._w_bytes(L, N)))
 
     def _footprint(self, L, N, n):
-        return n * self._w_bytes(L, N) + s2dw.workspace_bytes(L, N, self.lam, self.J_min, count=n,
-                                                              precision=self.precision)
+        return n * self._w_bytes(L, N) + self.backend.workspace_bytes(L, N, self.lam, self.J_min, n, self.precision)
 
     def submit(self, req: Request):
-        if s2dw.cache_bytes() + self._footprint(req.L, req.N, 1) > self.max_bytes:
+        if self.backend.cache_bytes() + self._footprint(req.L, req.N, 1) > self.max_bytes:
             raise MemoryError(f"a request with L={req.L}, N={req.N} does not fit the HBM budget "
                               f"({self.max_bytes} bytes)")
         self._pending.append(req)
 
+    def cancel(self, rid: int) -> bool:
+        """Cancels a request: a pending one leaves the queue, one in flight keeps running but
+        its results are dropped.  Either way it is returned by the next step() with
+        cancelled set.  Returns False if the server does not hold the request."""
+        for r in self._pending:
+            if r.rid == rid:
+                self._pending.remove(r)
+                r.cancelled = True
+                self._finished.append(r)
+                return True
+        for b in self._busy:
+            if b is not None:
+                for r in b.reqs:
+                    if r.rid == rid:
+                        r.cancelled = True
+                        return True
+        return False
+
     def idle(self) -> bool:
-        return not self._pending and all(b is None for b in self._busy)
+        return not self._pending and not self._finished and all(b is None for b in self._busy)
 
     def warm(self, shapes, per_stream=True):
         """Builds the plans of the (L, N) shapes and, per stream, their workspaces (the first
         call on a stream allocates), so that serving itself allocates only result buffers."""
         for (L, N) in shapes:
-            f = torch.zeros((self._batch_cap(L, N), L * L), dtype=torch.complex128, device=self.device)
-            for st in (self._streams if per_stream else self._streams[:1]):
-                with torch.cuda.stream(st):
-                    s2dw.analysis_batched(f, L, N, self.lam, self.J_min, precision=self.precision)
-                torch.cuda.synchronize()
-        torch.cuda.empty_cache()
+            self.backend.warm(L, N, self.lam, self.J_min, self._batch_cap(L, N), self.precision)
 
     def step(self) -> list:
         """Collects finished batches, then launches new ones on free streams.  Returns the
-        requests completed since the last call."""
-        done = []
+        requests completed since the last call: with results, or with error or cancelled set."""
+        done = self._finished
+        self._finished = []
         now = None
         for i, b in enumerate(self._busy):
             if b is not None and b.event.query():
                 now = now or time.perf_counter()
                 for k, r in enumerate(b.reqs):
                     r.t_done = now
-                    r.W = b.W[k]
-                    r.Wphi = b.Wp[k]
+                    if not r.cancelled:
+                        r.W = b.W[k]
+                        r.Wphi = b.Wp[k]
                     done.append(r)
                 self._inflight_bytes -= b.bytes
                 self._busy[i] = None
@@ -135,15 +197,15 @@ class Server:
             if self._busy[i] is None and self._pending:
                 if not self._launch(i):
                     break
+        done.extend(self._finished)
+        self._finished = []
         return done
 
     def _launch(self, i) -> bool:
         head = self._pending[0]
         key = (head.L, head.N)
         picked = [r for r in self._pending if (r.L, r.N) == key][: self._batch_cap(*key)]
-        # held now: the library's plans and workspaces plus torch's live tensors (results in
-        # flight or kept by the caller)
-        held = s2dw.cache_bytes() + torch.cuda.memory_allocated(self.device)
+        held = self.backend.held_bytes()
         while picked:
             need = self._footprint(key[0], key[1], len(picked))
             if held + need <= self.max_bytes:
@@ -154,14 +216,17 @@ class Server:
         ids = {id(r) for r in picked}
         self._pending = deque(r for r in self._pending if id(r) not in ids)
         L, N = key
-        st = self._streams[i]
         t = time.perf_counter()
-        st.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(st):
-            F = torch.stack([r.flm for r in picked])
-            W, Wp = s2dw.analysis_batched(F, L, N, self.lam, self.J_min, precision=self.precision)
-            ev = torch.cuda.Event()
-            ev.record(st)
+        try:
+            if self.on_launch is not None:
+                self.on_launch(picked)
+            W, Wp, ev = self.backend.launch(i, picked, L, N, self.lam, self.J_min, self.precision)
+        except Exception as e:  # this batch fails; the others go on
+            for r in picked:
+                r.error = e
+                r.t_done = time.perf_counter()
+                self._finished.append(r)
+            return True
         for r in picked:
             r.t_launch = t
         self._busy[i] = _Batch(picked, ev, need, W, Wp)
