@@ -89,7 +89,44 @@ def direct_alpha_gamma(N, Lj):
     return Nh * (2 * Lj - 1) <= min(9 * (2 * N - 1), 256) and 2 * Nh * Lj <= 1024
 
 
-def stage_units(kappa, L, N, T, fused=True, fused_adj=True):
+def pfa_fused(L, N):
+    """Whether the fused prime-factor alpha and gamma kernels serve a real-signal transform
+    at band-limit L (T = 2L - 1 of 2047 or 4095, at most 16 complex values per thread waiting
+    in registers: the library's rule)."""
+    Nh, T = N - N // 2, 2 * L - 1
+    return (T == 2047 and Nh <= 4) or (T == 4095 and Nh <= 2)
+
+
+def blocked_alpha(L, Lj):
+    """Whether the library takes the blocked alpha transforms for a scale of band-limit Lj
+    (its cost model: nblk convolutions of size Q in {512, 1024, 2048} against one of size
+    PB >= T + 2Lj - 2, taken when they cost under 0.7 of it)."""
+    T = 2 * L - 1
+    cost = lambda q: q * math.log2(q)
+    PB = 1 << math.ceil(math.log2(2 * Lj + T - 2))
+    best, blk = 0.7 * cost(PB), False
+    for Q in (512, 1024, 2048):
+        B = Q - 2 * Lj + 2
+        if B < 64:
+            continue
+        nbk = -(-T // B)
+        if nbk >= 2 and nbk * cost(Q) < best:
+            best, blk = nbk * cost(Q), True
+    return blk
+
+
+def fused_scales(L, N, Ljs, mixed=False):
+    """The scales (by band-limit) that take the fused prime-factor kernels by the library's
+    default rule: (analysis, synthesis)."""
+    if not pfa_fused(L, N):
+        return [], []
+    T, Nh = 2 * L - 1, N - N // 2
+    fwd = [Lj for Lj in Ljs if T == 4095 or not blocked_alpha(L, Lj)]
+    adj = list(Ljs) if (T == 4095 or mixed or Nh <= 2) else []
+    return fwd, adj
+
+
+def stage_units(kappa, L, N, T, fused=True, fused_adj=True, pfa=None, mixed=False):
     """Algorithmic work of each stage per step (one map), summed over the scales.
 
     Wigner stages (one launch per direction): 5 FLOP per term of the l-sum / m'-contraction
@@ -107,6 +144,9 @@ def stage_units(kappa, L, N, T, fused=True, fused_adj=True):
                 alpha_fwd and gamma_fwd)  Ub 16 N Lj L in,  W 8 G L T out
       gamma_alpha_adj (the same scales of an FP64 synthesis, fused_adj = True; they leave
                 gamma_adj and alpha_adj)  W 8 G L T in,  G 16 N Lj L out
+    With pfa (default: pfa_fused(L, N)) the scales that fused_scales names take the fused
+    prime-factor kernels, also counted as alpha_gamma_fwd and gamma_alpha_adj, with the same
+    bytes and, as FLOP, the alpha DFTs of its rings.
     and, for the four Fourier stages, FLOP with a length-n complex DFT counted as an FFT,
     5 n log2 n, whatever way it is computed:
       beta_fwd  N Lj columns, one length-T DFT each
@@ -124,10 +164,16 @@ def stage_units(kappa, L, N, T, fused=True, fused_adj=True):
         nz = [l for l in range(L) if kappa[j, l] > 0.0]
         if nz:
             Ljs.append(max(nz) + 1)
-    two = [Lj for Lj in Ljs if not (fused and direct_alpha_gamma(N, Lj))]
-    one = [Lj for Lj in Ljs if fused and direct_alpha_gamma(N, Lj)]
-    two_adj = [Lj for Lj in Ljs if not (fused_adj and direct_alpha_gamma(N, Lj))]
-    one_adj = [Lj for Lj in Ljs if fused_adj and direct_alpha_gamma(N, Lj)]
+    if pfa is None:
+        pfa = pfa_fused(L, N)
+    fw, ad = fused_scales(L, N, Ljs, mixed) if pfa else ([], [])
+    direct = [Lj for Lj in Ljs if fused and direct_alpha_gamma(N, Lj)]
+    direct_adj = [Lj for Lj in Ljs if fused_adj and direct_alpha_gamma(N, Lj)]
+    pf = [Lj for Lj in Ljs if Lj in fw and Lj not in direct]
+    pf_adj = [Lj for Lj in Ljs if Lj in ad and Lj not in direct_adj]
+    one, one_adj = direct + pf, direct_adj + pf_adj
+    two = [Lj for Lj in Ljs if Lj not in one]
+    two_adj = [Lj for Lj in Ljs if Lj not in one_adj]
     per = {
         "beta_fwd": [16 * N * Lj * Lj + 16 * N * Lj * L for Lj in Ljs],
         "alpha_fwd": [16 * N * Lj * L + 16 * Nh * L * Tg for Lj in two],
@@ -148,11 +194,13 @@ def stage_units(kappa, L, N, T, fused=True, fused_adj=True):
         "beta_fwd": sum(N * Lj * dft for Lj in Ljs),
         "alpha_fwd": len(two) * Nh * L * dft,
         "alpha_adj": len(two_adj) * Nh * L * dft,
+        "alpha_gamma_fwd": len(pf) * Nh * L * dft,
+        "gamma_alpha_adj": len(pf_adj) * Nh * L * dft,
         "beta_adj": sum(N * Lj * (dft + conv(Lj)) for Lj in Ljs),
     }
     units = {k: [("hbm", float(sum(v)))] for k, v in per.items() if v}
     for k, v in flops.items():
-        if k in units:
+        if k in units and v > 0:
             units[k].append(("alu", float(v)))
     units["wigner_fwd"] = [("alu", 5.0 * T)]
     units["wigner_adj"] = [("alu", 5.0 * T)]
@@ -525,7 +573,7 @@ def main():
     # roofline of that kernel, timed with HIP events during the timed steps
     kappa, _, _ = s2dw.wavelet_tables(L, N, lam, J_min)
     T = wigner_terms(kappa, N)
-    units = stage_units(kappa, L, N, T, fused_adj=prec == "fp64")
+    units = stage_units(kappa, L, N, T, fused_adj=prec == "fp64", mixed=prec != "fp64")
     roof = roofline(dom, live[dom], units)
     traffic = None
     try:

@@ -207,14 +207,30 @@ int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gam
 /*
  * Autotuner: times round trips (analysis + synthesis) of zero-filled probe maps on
  * `stream` for each compiled Wigner tile shape (m' slots per wave, 1, 2 or 4 depending on
- * the number of carried orders) and for batch chunks 1, 2, 4, ... up to min(count, what
- * fits 8 GiB of workspace), keeps the fastest per map in the plan of p, and reports them.
+ * the number of carried orders), for the alpha and gamma forms where the prime-factor
+ * kernels apply (see s2dw_set_tuning), and for batch chunks 1, 2, 4, ... up to min(count,
+ * what fits 8 GiB of workspace), keeps the fastest per map in the plan of p, and reports the
+ * tile shape and chunk (s2dw_get_tuning reports all three).
  * Synchronises the stream; allocates probe buffers.  slots and chunk may be NULL.
  * Calls of the same plan on other streams may run meanwhile: each call uses the tile
  * shape it found when it started, and no other stream's workspace is freed.  Results
  * change only by rounding between tile shapes.
  */
 int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *slots, int32_t *chunk);
+
+/*
+ * The tuning of the plan of p (built on first use): the Wigner tile shape (m' slots per
+ * wave), the maps per batched launch sequence, and the form of the alpha and gamma passes
+ * at the prime-factor lengths T = 2L - 1 of 2047 and 4095 (real signals): 0 two passes
+ * (alpha transform, then gamma sum), 2 one fused kernel per scale wherever it applies, 1 the
+ * default, fused where it was measured faster.  s2dw_autotune also times forms 0 and 2.
+ * s2dw_set_tuning applies stored results (e.g. an earlier s2dw_autotune's) without timing:
+ * S2DW_E_ARG for a slot count that is not compiled for the plan's carried orders, chunk < 1
+ * or fuse outside 0..2.  Calls already running keep the tuning they started with; results
+ * change only by rounding between tunings.  Outputs may be NULL.
+ */
+int s2dw_get_tuning(const s2dw_params *p, int32_t *slots, int32_t *chunk, int32_t *fuse);
+int s2dw_set_tuning(const s2dw_params *p, int32_t slots, int32_t chunk, int32_t fuse);
 
 /*
  * Device memory queries for admission control (serving):

@@ -36,6 +36,10 @@ struct Shape {
     int nfwd_plain = 0, nfwd_x = 0, nadj_plain = 0, nadj_x = 0;
     size_t s_F = 0;                             // per-map partial-sum elements
     int chunk = 1;                              // maps per batched launch sequence (tunable)
+    // the fused alpha and gamma kernels of the prime-factor lengths (tunable): 0 never,
+    // 1 where they were measured faster than the two-pass form (fuse_fwd, fuse_adj),
+    // 2 wherever they apply
+    int fuse = 1;
 };
 
 struct Plan {
@@ -948,6 +952,22 @@ int grid_limits(const s2dw_params *p, std::vector<int> &Lg) {
 // then cost little more than their W traffic, against a blocked alpha transform plus a
 // gamma pass that also writes and reads Y or X (at L = 1024, N = 8, for Lj = 4, 8, 16:
 // analysis 65-73 us per scale, synthesis 57-113 us, against about 130 us each).
+// Whether scale j of the analysis (synthesis) takes the fused prime-factor alpha and gamma
+// kernel; the caller has checked that it applies (pfa_fused, real signals).  The default
+// follows measurements at L = 1024, N = 8 and L = 2048, N = 4: the fused analysis kernel
+// costs the same at every L_j and beats the two-pass form except on the scales with the
+// blocked alpha transforms at T = 2047; the fused synthesis kernel wins at T = 4095, and at
+// T = 2047 where it holds every order's gamma sums in registers (below 128 for them: not
+// FP64 with more than two orders), else its second sweep over W costs more than it saves.
+bool fuse_fwd(const Plan &P, const Shape &sh, int j, int T) {
+    if (sh.fuse != 1) return sh.fuse == 2;
+    return T == 4095 || P.nblkb[j] <= 1;
+}
+bool fuse_adj(const Plan &P, const Shape &sh, int f32, int T) {
+    if (sh.fuse != 1) return sh.fuse == 2;
+    return T == 4095 || f32 || P.Nh <= 2;
+}
+
 bool direct_alpha_gamma(int Nh, int G, int Lj, bool cx) {
     const int terms = Nh * (2 * Lj - 1);
     return !cx && terms <= 9 * G && terms <= 256 && 2 * Nh * Lj <= kAlphaGammaCoeffs;
@@ -1053,6 +1073,20 @@ int run_inverse(Plan &P, const Shape &sh, Work &w, int maps, const double2 *flm,
             S2DW_CHECK_HIP(launch_alpha_gamma_fwd(d, maps, st));
             continue;
         }
+        if (gtab.pcs && !cx && pfa_fused(2 * Lg - 1, P.Nh) && fuse_fwd(P, sh, j, 2 * Lg - 1)) {
+            // the alpha and gamma passes in one prime-factor kernel, one beta ring per workgroup
+            StageArgs d = b;
+            d.in = w.Ub;
+            d.s_in = P.s_Ub;
+            d.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
+            d.wout = Wj;
+            d.s_w = per_map;
+            d.tg = f32 ? (const void *)P.tgff : P.tgf;
+            d.G = P.ng;
+            Stage sg("alpha_gamma_fwd", st);
+            S2DW_CHECK_HIP(launch_alpha_gamma_fwd_pfa(d, maps, st));
+            continue;
+        }
         StageArgs c = b;
         c.in = w.Ub;
         c.out = w.Y;
@@ -1131,7 +1165,26 @@ int run_forward(Plan &P, const Shape &sh, Work &w, int maps, const void *W, cons
         // FP64 only: the fused pass computes in FP64 and is bound by its arithmetic at the
         // larger Lj, where the FP32 passes of the mixed path are cheaper
         const bool fused = direct_alpha_gamma(P.Nh, P.ng, Lj, cx) && !f32;
-        if (fused) {
+        const bool fused_pfa = !fused && gtab.pcs && !cx && pfa_fused(M, P.Nh) && fuse_adj(P, sh, f32, M);
+        if (fused_pfa) {
+            StageArgs d{};
+            d.f32 = f32;
+            d.win = Wj;
+            d.s_w = per_map;
+            d.tg = f32 ? (const void *)P.tgaf : P.tga;
+            d.G = P.ng;
+            d.out = gout;
+            d.s_out = P.s_Ub;
+            d.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
+            d.L = Lg;
+            d.nb = g.L;
+            d.Lj = Lj;
+            d.N = N;
+            d.Nh = P.Nh;
+            d.scale = qscale;
+            Stage sg("gamma_alpha_adj", st);
+            S2DW_CHECK_HIP(launch_gamma_alpha_adj_pfa(d, maps, st));
+        } else if (fused) {
             GammaAlphaArgs d{};
             d.win = Wj;
             d.out = gout;
@@ -1171,7 +1224,7 @@ int run_forward(Plan &P, const Shape &sh, Work &w, int maps, const void *W, cons
         c.Nh = P.Nh;
         c.K = P.K;
         c.scale = qscale;
-        if (fused) {
+        if (fused || fused_pfa) {
             // the alpha quadrature ran in the fused pass above
         } else if (P.nblkb[j] <= 1 && gtab.pcs) {
             StageArgs cp = c;
@@ -1478,13 +1531,14 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     s2dw_params q = *p;
-    // seconds per map of a round trip with tile shape R and batch chunk c
-    auto trial = [&](int R, int c, double &sec) -> int {
+    // seconds per map of a round trip with tile shape R, batch chunk c and fusion form fu
+    auto trial = [&](int R, int c, int fu, double &sec) -> int {
         {
             std::lock_guard<std::mutex> lk(g_mu);
             int r2 = set_slots(*P, R);
             if (r2 != S2DW_OK) return r2;
             P->cur.chunk = c;
+            P->cur.fuse = fu;
         }
         for (int it = 0; it < 3; ++it) {
             if (it == 1) hipEventRecord(e0, st);
@@ -1501,20 +1555,32 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     };
     int Ropt[3];
     const int nR = wig_slot_options(P->K, Ropt);
-    int bestR = shape_of(*P).R, bestC = cmax;
+    int bestR = shape_of(*P).R, bestC = cmax, bestF = 1;
     double best = 1e30;
     for (int i = 0; i < nR && rc == S2DW_OK; ++i) {
         double sec = 0;
-        rc = trial(Ropt[i], cmax, sec);
+        rc = trial(Ropt[i], cmax, 1, sec);
         if (rc == S2DW_OK && sec < best) {
             best = sec;
             bestR = Ropt[i];
         }
     }
+    // the alpha and gamma forms, where the fused prime-factor kernels apply (T = 2047, 4095)
+    const auto gfull = P->gt.find(P->L);
+    if (gfull != P->gt.end() && gfull->second.pcs && p->reality != 0 && pfa_fused(2 * P->L - 1, P->Nh)) {
+        for (int fu = 0; fu <= 2 && rc == S2DW_OK; fu += 2) {
+            double sec = 0;
+            rc = trial(bestR, cmax, fu, sec);
+            if (rc == S2DW_OK && sec < best) {
+                best = sec;
+                bestF = fu;
+            }
+        }
+    }
     best = 1e30;
     for (int c = 1; c <= cmax && rc == S2DW_OK; c *= 2) {
         double sec = 0;
-        rc = trial(bestR, c, sec);
+        rc = trial(bestR, c, bestF, sec);
         if (rc == S2DW_OK && sec < best * 0.97) {  // a larger batch must win by 3%
             best = sec;
             bestC = c;
@@ -1522,7 +1588,7 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     }
     if (rc == S2DW_OK && cmax & (cmax - 1)) {  // the largest chunk when it is not a power of two
         double sec = 0;
-        rc = trial(bestR, cmax, sec);
+        rc = trial(bestR, cmax, bestF, sec);
         if (rc == S2DW_OK && sec < best * 0.97) bestC = cmax;
     }
     hipStreamSynchronize(st);
@@ -1536,10 +1602,42 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
         std::lock_guard<std::mutex> lk(g_mu);
         rc = set_slots(*P, bestR);
         P->cur.chunk = bestC;
+        P->cur.fuse = bestF;
     }
     if (slots) *slots = bestR;
     if (chunk) *chunk = bestC;
     return rc;
+}
+
+int s2dw_get_tuning(const s2dw_params *p, int32_t *slots, int32_t *chunk, int32_t *fuse) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    Plan *P = nullptr;
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, p->precision == S2DW_MIXED, p->grid);
+    if (rc != S2DW_OK) return rc;
+    const Shape sh = shape_of(*P);
+    if (slots) *slots = sh.R;
+    if (chunk) *chunk = sh.chunk;
+    if (fuse) *fuse = sh.fuse;
+    return S2DW_OK;
+}
+
+int s2dw_set_tuning(const s2dw_params *p, int32_t slots, int32_t chunk, int32_t fuse) {
+    int rc = check_params(p);
+    if (rc != S2DW_OK) return rc;
+    if (chunk < 1 || fuse < 0 || fuse > 2) return S2DW_E_ARG;
+    Plan *P = nullptr;
+    rc = get_plan(kWavelet, p->L, p->N, p->lambda, p->J_min, P, p->precision == S2DW_MIXED, p->grid);
+    if (rc != S2DW_OK) return rc;
+    int Ropt[3];
+    const int nR = wig_slot_options(P->K, Ropt);
+    if (std::find(Ropt, Ropt + nR, (int)slots) == Ropt + nR) return S2DW_E_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    rc = set_slots(*P, slots);
+    if (rc != S2DW_OK) return rc;
+    P->cur.chunk = chunk;
+    P->cur.fuse = fuse;
+    return S2DW_OK;
 }
 
 int s2dw_workspace_bytes(const s2dw_params *p, int32_t count, uint64_t *bytes) {

@@ -71,6 +71,14 @@ struct StageArgs {
     const void *qw;        // Driscoll-Healy quadrature weights q_t, t < nb (real; synthesis beta stage)
     const void *eph;       // e^{2 pi i r/T}, r < T (blocked alpha stages)
     const void *pcs;       // constant tables of the prime-factor transforms of length T (pfa.h)
+    // fused alpha and gamma passes (prime-factor transforms): W written (analysis) or read
+    // (synthesis), [G][nb][T] per scale with per-map stride s_w real elements, and the gamma
+    // factors tg [G][Nh] ((1 or 2) e^{i n gamma_g} for the analysis, e^{-i n gamma_g} for the synthesis)
+    void *wout;
+    const void *win;
+    const void *tg;
+    size_t s_w;
+    int G;
     int nblk, B;           // blocked alpha stages: nblk blocks of B samples
     size_t s_in, s_out;    // per-map strides (complex elements) of a batch; map = blockIdx.y
     int L, nb, Lj, N, Nh, K, eta_imag, f32;  // nb: beta rings (L, or 2L on the Driscoll-Healy grid)
@@ -91,6 +99,12 @@ hipError_t launch_alpha_adj_pfa(const StageArgs &a, int maps, hipStream_t st);
 // Equiangular grid, T = 2L - 1 in {2047, 4095}: the two-column analysis beta transform as a
 // prime-factor transform (eph: e^{2 pi i r/T}; pcs as above).
 hipError_t launch_beta_fwd_pfa(const StageArgs &a, int maps, hipStream_t st);
+// The alpha and gamma passes of a scale in one kernel with the prime-factor transforms (real
+// signals): analysis Ub -> W, synthesis W -> G (scaled by a.scale); one beta ring per
+// workgroup.  pfa_fused(T, Nh): whether the fused kernel serves length T with Nh orders n >= 0.
+bool pfa_fused(int T, int Nh);
+hipError_t launch_alpha_gamma_fwd_pfa(const StageArgs &a, int maps, hipStream_t st);
+hipError_t launch_gamma_alpha_adj_pfa(const StageArgs &a, int maps, hipStream_t st);
 hipError_t launch_alpha_adj_blk(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t st);

@@ -158,6 +158,16 @@ struct Len2047 {
     __device__ static __forceinline__ int pos_out(int k) { return (k % 23) * 89 + (k % 89); }
 };
 
+// The stages alone, on inputs already placed at buf[c * CS + pos_in(n)] (after a barrier);
+// output k of column c ends at buf[c * CS + pos_out(k)] (after a barrier).
+template <int S, class C>
+__device__ __forceinline__ void dft2047_stages(C *buf, const C *__restrict__ tab, int tid, int ncol) {
+    using L = Len2047;
+    stage_small<23, 89, L::T, L::NTH, S>(buf, L::CS, ncol, tab + Tab2047::c23, tid);
+    __syncthreads();
+    stage89<L::T, Tab2047::NW, Tab2047::KG, S>(buf, L::CS, ncol, tab + Tab2047::g89, tid);
+}
+
 // in(c, n) gives element n < T of column c; on return output k of column c sits at
 // buf[c * CS + pos_out(k)] (after a barrier).
 template <int S, class C, class In>
@@ -168,9 +178,7 @@ __device__ __forceinline__ void dft2047_lds(C *buf, const C *__restrict__ tab, i
         buf[c * L::CS + L::pos_in(n)] = in(c, n);
     }
     __syncthreads();
-    stage_small<23, 89, L::T, L::NTH, S>(buf, L::CS, ncol, tab + Tab2047::c23, tid);
-    __syncthreads();
-    stage89<L::T, Tab2047::NW, Tab2047::KG, S>(buf, L::CS, ncol, tab + Tab2047::g89, tid);
+    dft2047_stages<S>(buf, tab, tid, ncol);
 }
 
 // ------------------------------------------------------------------ T = 4095 = 5 x 7 x 9 x 13
@@ -191,14 +199,9 @@ struct Len4095T : Len4095 {
     static constexpr int NTH = NTH_;
 };
 
-template <int S, int NTH, class C, class In>
-__device__ __forceinline__ void dft4095_lds(C *buf, const C *__restrict__ tab, int tid, int ncol, In in) {
+template <int S, int NTH, class C>
+__device__ __forceinline__ void dft4095_stages(C *buf, const C *__restrict__ tab, int tid, int ncol) {
     using L = Len4095;
-    for (int e = tid; e < ncol * L::T; e += NTH) {
-        const int c = e / L::T, n = e - (e / L::T) * L::T;
-        buf[c * L::CS + L::pos_in(n)] = in(c, n);
-    }
-    __syncthreads();
     stage_small<13, 1, L::T, NTH, S>(buf, L::CS, ncol, tab + Tab4095::c13, tid);
     __syncthreads();
     stage_small<9, 13, L::T, NTH, S>(buf, L::CS, ncol, tab + Tab4095::c9, tid);
@@ -207,6 +210,17 @@ __device__ __forceinline__ void dft4095_lds(C *buf, const C *__restrict__ tab, i
     __syncthreads();
     stage_small<5, 819, L::T, NTH, S>(buf, L::CS, ncol, tab + Tab4095::c5, tid);
     __syncthreads();
+}
+
+template <int S, int NTH, class C, class In>
+__device__ __forceinline__ void dft4095_lds(C *buf, const C *__restrict__ tab, int tid, int ncol, In in) {
+    using L = Len4095;
+    for (int e = tid; e < ncol * L::T; e += NTH) {
+        const int c = e / L::T, n = e - (e / L::T) * L::T;
+        buf[c * L::CS + L::pos_in(n)] = in(c, n);
+    }
+    __syncthreads();
+    dft4095_stages<S, NTH>(buf, tab, tid, ncol);
 }
 
 // The transform of length LN::T of ncol columns: in(c, n) gives element n of column c,
@@ -219,6 +233,14 @@ __device__ __forceinline__ void dft(C *buf, const C *__restrict__ tab, int tid, 
         const int c = e / LN::T, k = e - (e / LN::T) * LN::T;
         out(c, k, buf[c * LN::CS + LN::pos_out(k)]);
     }
+}
+
+// The stages of LN on inputs already placed at buf[c * CS + pos_in(n)] (after a barrier);
+// output k of column c ends at buf[c * CS + pos_out(k)] (after a barrier).
+template <class LN, int S, class C>
+__device__ __forceinline__ void dft_stages(C *buf, const C *__restrict__ tab, int tid, int ncol) {
+    if constexpr (LN::T == 2047) dft2047_stages<S>(buf, tab, tid, ncol);
+    else dft4095_stages<S, LN::NTH>(buf, tab, tid, ncol);
 }
 
 // As dft, leaving output k of column c at buf[c * CS + pos_out(k)].

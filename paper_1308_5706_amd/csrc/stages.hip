@@ -349,6 +349,167 @@ __global__ void __launch_bounds__(256) alpha_adj_pfa_kernel(const StageArgs a) {
     pfa::dft<LN, -1>(buf, (const C *)a.pcs, tid, ncol, in, out);
 }
 
+// The alpha and gamma passes of one scale fused, one beta ring per workgroup, with the
+// prime-factor transforms (real signals).  Each thread owns the samples a = tid + k NTH
+// (k < KS).  Analysis: the NH orders n >= 0 of the ring pass through the transform LN::NC at
+// a time; the owned outputs of the earlier passes wait in registers, and the gamma sum
+//   W(g, b, a) = sum_{n'} Re(Y_{n'}(a) tg[g][n'])
+// of the last pass writes W.  Synthesis: one sweep over the ring's W forms the gamma sums
+//   X_{n'}(a) = sum_g W(g, b, a) tg[g][n'],
+// of every order at the owned samples, and the orders pass through the transform NC at a
+// time (the later ones waiting in registers).  The Y and X arrays of the two-pass form never
+// go to HBM.  Register budget: the orders waiting in registers hold at most 16 complex values
+// per thread (pfa_fused).
+template <class LN>
+constexpr int pfa_ks() { return (LN::T + LN::NTH - 1) / LN::NTH; }
+
+template <class C, class LN, int NH>
+__global__ void __launch_bounds__(256) alpha_gamma_fwd_pfa_kernel(const StageArgs a) {
+    using R = real_t<C>;
+    constexpr int T = LN::T, NC = LN::NC, NTH = LN::NTH, KS = pfa_ks<LN>();
+    constexpr int NP = (NH + NC - 1) / NC, NHOLD = (NP - 1) * NC, NLAST = NH - NHOLD;
+    __shared__ C buf[LN::lds];
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, N = a.N, nb = a.nb, G = a.G;
+    const int b = xcd_column(blockIdx.x, nb);
+    if (b >= nb) return;
+    const C *__restrict__ U = (const C *)a.in + blockIdx.y * a.s_in;
+    const C *__restrict__ tab = (const C *)a.pcs;
+    C held[NHOLD > 0 ? NHOLD : 1][KS];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int nrow = p < NP - 1 ? NC : NLAST;
+        auto in = [&](int c, int n) {
+            const int np = p * NC + c;
+            const int ni = (N / 2) + np, nj = N - 1 - ni;
+            const int m = n < Lj ? n : (n > T - Lj ? n - T : T);
+            if (m == T) return mk<C>(0, 0);
+            const int am = m < 0 ? -m : m;
+            C v = U[((size_t)(m >= 0 ? ni : nj) * Lj + am) * nb + b];
+            if (m < 0) v = cconj(v);
+            if (m == 0 && ni == nj) v.y = 0;
+            return v;
+        };
+        pfa::dft_lds<LN, +1>(buf, tab, tid, nrow, in);
+        if (p < NP - 1) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const int x = tid + k * NTH;
+                    if (x < T) held[p * NC + c][k] = buf[c * LN::CS + LN::pos_out(x)];
+                }
+            __syncthreads();
+        }
+    }
+    R *__restrict__ W = (R *)a.wout + blockIdx.y * a.s_w + (size_t)b * T;
+    const C *__restrict__ tg = (const C *)a.tg;
+    const size_t plane = (size_t)nb * T;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int x = tid + k * NTH;
+        if (x >= T) continue;
+        C y[NH];
+#pragma unroll
+        for (int r = 0; r < NHOLD; ++r) y[r] = held[r][k];
+#pragma unroll
+        for (int c = 0; c < NLAST; ++c) y[NHOLD + c] = buf[c * LN::CS + LN::pos_out(x)];
+        for (int g = 0; g < G; ++g) {
+            R acc = 0;
+#pragma unroll
+            for (int r = 0; r < NH; ++r) {
+                const C w = tg[g * NH + r];
+                acc = fma(y[r].x, w.x, fma(-y[r].y, w.y, acc));
+            }
+            __builtin_nontemporal_store(acc, W + g * plane + x);  // written once, read by the synthesis
+        }
+    }
+}
+
+template <class C, class LN, int NH>
+__global__ void __launch_bounds__(256) gamma_alpha_adj_pfa_kernel(const StageArgs a) {
+    using R = real_t<C>;
+    constexpr int T = LN::T, NC = LN::NC, NTH = LN::NTH, KS = pfa_ks<LN>();
+    constexpr int NP = (NH + NC - 1) / NC;
+    __shared__ C buf[LN::lds];
+    const int tid = threadIdx.x;
+    const int Lj = a.Lj, N = a.N, nb = a.nb, G = a.G;
+    const int b = xcd_column(blockIdx.x, nb);
+    if (b >= nb) return;
+    const R *__restrict__ W = (const R *)a.win + blockIdx.y * a.s_w + (size_t)b * T;
+    const C *__restrict__ tg = (const C *)a.tg;
+    const size_t plane = (size_t)nb * T;
+    // the gamma sums of rows r0 .. r0 + NR - 1 into x[0 .. NR - 1]: plane by plane, the
+    // thread's KS samples of a plane loaded together
+    const int klast = (T - 1 - tid) / NTH;  // the thread's last sample: tid + klast NTH < T
+    auto gamma_sums = [&](auto nr_c, int r0, C (*x)[KS]) {
+        constexpr int NR = decltype(nr_c)::value;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int k = 0; k < KS; ++k) x[r][k] = mk<C>(0, 0);
+        for (int g = 0; g < G; ++g) {
+            R w[KS];
+#pragma unroll
+            for (int k = 0; k < KS; ++k)
+                w[k] = __builtin_nontemporal_load(W + g * plane + tid + min(k, klast) * NTH);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const C t = r0 + r < NH ? tg[g * NH + r0 + r] : mk<C>(0, 0);
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    x[r][k].x = fma(w[k], t.x, x[r][k].x);
+                    x[r][k].y = fma(w[k], t.y, x[r][k].y);
+                }
+            }
+        }
+    };
+    // HOLD: every order's sums from one sweep over W, the later passes' waiting in registers;
+    // else (FP64 at T = 2047 with more than two orders, which would take more than 128
+    // registers for them next to the length-89 stage's) each pass sweeps W for its own rows
+    constexpr bool HOLD = !(T == 2047 && sizeof(C) == 16 && NH > NC);
+    C x[HOLD ? NH : NC][KS];
+    C *__restrict__ Gout = (C *)a.out + blockIdx.y * a.s_out;
+    const C *__restrict__ tab = (const C *)a.pcs;
+    const real_t<C> sc = (real_t<C>)a.scale;
+    // pass p: rows p NC .. of the transform, their sums at x[x0 ..]
+    auto pass = [&](int p, int x0) {
+        const int nrow = min(NC, NH - p * NC);
+        if (p > 0) __syncthreads();  // the previous pass's outputs are read
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < nrow) {
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const int s = tid + k * NTH;
+                    if (s < T) buf[c * LN::CS + LN::pos_in(s)] = x[x0 + c][k];
+                }
+            }
+        __syncthreads();
+        pfa::dft_stages<LN, -1>(buf, tab, tid, nrow);
+        for (int e = tid; e < nrow * T; e += NTH) {
+            const int c = e / T, k = e - (e / T) * T;
+            const int m = k < Lj ? k : (k > T - Lj ? k - T : T);
+            if (m == T) continue;
+            const int np = p * NC + c, ni = (N / 2) + np, nj = N - 1 - ni;
+            const C z = cscale(buf[c * LN::CS + LN::pos_out(k)], sc);
+            if (m >= 0) Gout[((size_t)ni * Lj + m) * nb + b] = z;
+            if (m <= 0 && ni != nj) Gout[((size_t)nj * Lj - m) * nb + b] = cconj(z);
+        }
+    };
+    if constexpr (HOLD) {
+        gamma_sums(std::integral_constant<int, NH>(), 0, x);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) pass(p, p * NC);
+    } else {
+#pragma unroll 1
+        for (int p = 0; p < NP; ++p) {
+            gamma_sums(std::integral_constant<int, NC>(), p * NC, x);
+            pass(p, 0);
+        }
+    }
+}
+
 // Blocked alpha sums for scales with few coefficients (2Lj - 1 well below T): the T samples
 // are taken in nblk blocks of B consecutive ones, each through a short chirp convolution of
 // size P >= B + 2Lj - 2 instead of one of size >= T + 2Lj - 2.  With a = a0 + a' (a0 = k B),
@@ -1192,6 +1353,46 @@ hipError_t launch_beta_fwd_pfa(const StageArgs &a, int maps, hipStream_t st) {
 }
 
 hipError_t launch_alpha_adj_pfa(const StageArgs &a, int maps, hipStream_t st) S2DW_PFA_LAUNCH(alpha_adj_pfa_kernel)
+
+// Orders n >= 0 whose transforms can wait in registers: at most 16 complex values per thread.
+bool pfa_fused(int T, int Nh) {
+    if (T == 2047) return Nh >= 1 && Nh <= 4;  // two orders per pass, 8 samples per thread
+    if (T == 4095) return Nh >= 1 && Nh <= 2;  // one order per pass, 16 samples per thread
+    return false;
+}
+
+#define S2DW_FUSED_CASE(KER, LN, NH)                                                                     \
+    case NH:                                                                                             \
+        if (a.f32) hipLaunchKernelGGL((KER<float2, LN, NH>), grid, dim3(256), 0, st, a);                 \
+        else hipLaunchKernelGGL((KER<double2, LN, NH>), grid, dim3(256), 0, st, a);                      \
+        break;
+
+#define S2DW_FUSED_LAUNCH(KER)                                                                           \
+    {                                                                                                    \
+        const int T = 2 * a.L - 1;                                                                       \
+        if (!pfa_fused(T, a.Nh) || a.G < 1 || a.nb < 1) return hipErrorInvalidValue;                     \
+        const dim3 grid((unsigned)(8 * ((a.nb + 7) / 8)), (unsigned)maps);                               \
+        if (T == 2047) {                                                                                 \
+            switch (a.Nh) {                                                                              \
+                S2DW_FUSED_CASE(KER, pfa::Len2047, 1)                                                    \
+                S2DW_FUSED_CASE(KER, pfa::Len2047, 2)                                                    \
+                S2DW_FUSED_CASE(KER, pfa::Len2047, 3)                                                    \
+                S2DW_FUSED_CASE(KER, pfa::Len2047, 4)                                                    \
+                default: return hipErrorInvalidValue;                                                    \
+            }                                                                                            \
+        } else {                                                                                         \
+            switch (a.Nh) {                                                                              \
+                S2DW_FUSED_CASE(KER, pfa::Len4095, 1)                                                    \
+                S2DW_FUSED_CASE(KER, pfa::Len4095, 2)                                                    \
+                default: return hipErrorInvalidValue;                                                    \
+            }                                                                                            \
+        }                                                                                                \
+        return hipGetLastError();                                                                        \
+    }
+
+hipError_t launch_alpha_gamma_fwd_pfa(const StageArgs &a, int maps, hipStream_t st) S2DW_FUSED_LAUNCH(alpha_gamma_fwd_pfa_kernel)
+
+hipError_t launch_gamma_alpha_adj_pfa(const StageArgs &a, int maps, hipStream_t st) S2DW_FUSED_LAUNCH(gamma_alpha_adj_pfa_kernel)
 
 hipError_t launch_alpha_fwd_blk(const StageArgs &a, int P, int maps, hipStream_t st) {
     S2DW_P_SWITCH(P, alpha_fwd_blk_kernel, 8 * ((a.Nh * a.nb + 7) / 8), a)

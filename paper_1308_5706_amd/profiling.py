@@ -31,8 +31,8 @@ ROOT = os.path.dirname(HERE)
 
 # library stage name -> substring of the kernel symbol (demangled) that implements it
 STAGE_KERNELS = {  # first match wins: the fused passes before the gamma passes they contain
-    "alpha_gamma_fwd": ("alpha_gamma_fwd_kernel",),
-    "gamma_alpha_adj": ("gamma_alpha_adj_kernel",),
+    "alpha_gamma_fwd": ("alpha_gamma_fwd_kernel", "alpha_gamma_fwd_pfa_kernel"),
+    "gamma_alpha_adj": ("gamma_alpha_adj_kernel", "gamma_alpha_adj_pfa_kernel"),
     "wigner_fwd": ("wig_fwd_kernel",),
     "wigner_adj": ("wig_adj_kernel",),
     "beta_fwd": ("beta_fwd_fft_kernel", "beta_fwd_pair_kernel", "beta_fwd_pfa_kernel"),

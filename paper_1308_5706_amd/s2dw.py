@@ -73,6 +73,11 @@ def lib():
         L.s2dw_scale_grid.restype = ctypes.c_int
         L.s2dw_wavelet_tables.argtypes = [cp, vp, vp, vp]
         L.s2dw_wavelet_tables.restype = ctypes.c_int
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.s2dw_get_tuning.argtypes = [cp, i32p, i32p, i32p]
+        L.s2dw_get_tuning.restype = ctypes.c_int
+        L.s2dw_set_tuning.argtypes = [cp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.s2dw_set_tuning.restype = ctypes.c_int
         L.s2dw_workspace_bytes.argtypes = [cp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
         L.s2dw_workspace_bytes.restype = ctypes.c_int
         L.s2dw_cache_bytes.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
@@ -89,7 +94,7 @@ def lib():
 
 EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_scale_grid", "s2dw_analysis",
             "s2dw_analysis_noalloc",
-            "s2dw_synthesis", "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_workspace_bytes",
+            "s2dw_synthesis", "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_get_tuning", "s2dw_set_tuning", "s2dw_workspace_bytes",
             "s2dw_cache_bytes",
             "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
             "s2dw_profile_read", "s2dw_profile_stages",
@@ -292,6 +297,26 @@ def autotune(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1
     _check(lib().s2dw_autotune(ctypes.byref(params(L, N, lam, J_min, precision, grid, reality)), count, _stream(stream),
                                ctypes.byref(sl), ctypes.byref(ch)), "s2dw_autotune")
     return sl.value, ch.value
+
+
+FUSE_FORMS = {"two-pass": 0, "default": 1, "fused": 2}
+
+
+def get_tuning(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, precision: str = "fp64", grid: str = "mw",
+               reality: bool = True):
+    """The plan's tuning: (m' slots per wave, maps per chunk, alpha/gamma form 0..2)."""
+    sl, ch, fu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().s2dw_get_tuning(ctypes.byref(params(L, N, lam, J_min, precision, grid, reality)), ctypes.byref(sl),
+                                 ctypes.byref(ch), ctypes.byref(fu)), "s2dw_get_tuning")
+    return sl.value, ch.value, fu.value
+
+
+def set_tuning(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, slots: int, chunk: int, fuse,
+               precision: str = "fp64", grid: str = "mw", reality: bool = True) -> None:
+    """Applies a tuning (e.g. one autotune found before); fuse is 0..2 or a FUSE_FORMS name."""
+    fu = FUSE_FORMS[fuse] if isinstance(fuse, str) else int(fuse)
+    _check(lib().s2dw_set_tuning(ctypes.byref(params(L, N, lam, J_min, precision, grid, reality)), slots, chunk, fu),
+           "s2dw_set_tuning")
 
 
 def steer(W: torch.Tensor, gammas, L: int, N: int, lam: float = 2.0, J_min: int = 0, *,

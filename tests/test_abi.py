@@ -112,6 +112,10 @@ def test_batched_and_autotune_argument_errors():
     assert lib.s2dw_synthesis_batched(ctypes.byref(p), -2, fake, None, fake, None) == -1
     assert lib.s2dw_analysis_batched(ctypes.byref(p), 2, None, fake, None, None) == -1
     assert lib.s2dw_autotune(ctypes.byref(p), 0, None, None, None) == -1
+    # tuning values outside their ranges are refused before any plan is built
+    assert lib.s2dw_set_tuning(ctypes.byref(p), 2, 0, 1) == -1
+    assert lib.s2dw_set_tuning(ctypes.byref(p), 2, 1, 3) == -1
+    assert lib.s2dw_set_tuning(ctypes.byref(p), 2, 1, -1) == -1
     bad = s2dw.Params(64, 4, 2.0, 0, 0, 7, 1)  # unknown precision
     assert lib.s2dw_analysis_batched(ctypes.byref(bad), 1, fake, fake, None, None) == -1
 

@@ -68,6 +68,38 @@ def test_stage_units_formulas(bench):
     assert u["wigner_fwd"] == [("alu", 5.0 * T)]
 
 
+def test_stage_units_prime_factor_lengths(bench):
+    # T = 2047, N = 8: the analysis scales with the blocked alpha transforms keep the two-pass
+    # form, the others take the fused kernel; the FP64 synthesis (four orders) keeps the
+    # two-pass form, the mixed one is fused.  T = 4095, N = 4: every scale fused both ways
+    L, N, lam, J_min = 1024, 8, 2.0, 1
+    assert bench.pfa_fused(L, N) and bench.pfa_fused(2048, 4)
+    assert not bench.pfa_fused(1024, 10) and not bench.pfa_fused(2048, 8) and not bench.pfa_fused(512, 4)
+    kappa = tables.kappa_table(L, lam, J_min)
+    T = bench.wigner_terms(kappa, N)
+    Ljs = [max(np.nonzero(kappa[j] > 0)[0]) + 1 for j in range(kappa.shape[0]) if np.any(kappa[j] > 0)]
+    Tg, G, Nh = 2 * L - 1, 2 * N - 1, N - N // 2
+    blk = [Lj for Lj in Ljs if bench.blocked_alpha(L, Lj)]
+    assert blk and all(Lj < 256 for Lj in blk) and not bench.blocked_alpha(L, 1024)
+    direct = [Lj for Lj in Ljs if bench.direct_alpha_gamma(N, Lj)]
+    u = bench.stage_units(kappa, L, N, T)
+    fw = [Lj for Lj in Ljs if Lj not in blk or Lj in direct]
+    assert dict(u["alpha_gamma_fwd"])["hbm"] == float(sum(16 * N * Lj * L + 8 * G * L * Tg for Lj in fw))
+    two = [Lj for Lj in Ljs if Lj not in fw]
+    assert two and dict(u["gamma_fwd"])["hbm"] == float(len(two) * (16 * Nh * L * Tg + 8 * G * L * Tg))
+    npf = sum(1 for Lj in fw if Lj not in direct)
+    assert dict(u["alpha_gamma_fwd"])["alu"] == pytest.approx(npf * Nh * L * 5.0 * Tg * math.log2(Tg))
+    assert dict(u["gamma_alpha_adj"])["hbm"] == float(sum(8 * G * L * Tg + 16 * N * Lj * L for Lj in direct))
+    u3 = bench.stage_units(kappa, L, N, T, fused_adj=False, mixed=True)
+    assert dict(u3["gamma_alpha_adj"])["hbm"] == float(sum(8 * G * L * Tg + 16 * N * Lj * L for Lj in Ljs))
+    assert "gamma_adj" not in u3 and "alpha_adj" not in u3
+    L2, N2 = 2048, 4
+    kappa2 = tables.kappa_table(L2, lam, 4)
+    u4 = bench.stage_units(kappa2, L2, N2, bench.wigner_terms(kappa2, N2))
+    for st in ("alpha_fwd", "gamma_fwd", "alpha_adj", "gamma_adj"):
+        assert st not in u4
+
+
 def test_roofline_roof_is_fixed_per_stage(bench):
     # separation-of-variables stages are priced by HBM bytes whatever their FLOP count, with the
     # FFT-FLOP figure as a secondary field; the Wigner stages by their algorithmic FLOP
