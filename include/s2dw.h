@@ -219,6 +219,51 @@ int s2dw_steer(const s2dw_params *p, int32_t count, const void *W, int32_t n_gam
 int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *slots, int32_t *chunk);
 
 /*
+ * Persistent batched form (many maps, several parameter sets, all scales): the analysis or
+ * the synthesis of every group's batch as two launches of a persistent executor -- one for
+ * the Wigner stages (Sec. 3.2-3.3, Eq. 27 and 34; with the input padding of the analysis and
+ * the final sum of Eq. 32/41 of the synthesis), one for the beta, alpha and gamma stages
+ * (Eq. 29-31 and 35-40; with the scaling coefficients of Eq. 31).  The stages of every map run
+ * as work items of CU-resident workgroups that take them from a device work list in
+ * dependency order, so that maps of all groups move through the stages together and no
+ * per-stage launch is left.  Results equal those of s2dw_analysis_batched /
+ * s2dw_synthesis_batched of each group up to rounding (the executor's Wigner tiles have their
+ * own shape).
+ *   groups[g].params: L, N, lambda, J_min, precision of group g; every group must have the
+ *                     same precision, reality = 1, grid = S2DW_GRID_MW and N <= 8, and every
+ *                     transform of its stages must be of size 2048 or less (L <= 512);
+ *                     otherwise S2DW_E_UNSUPPORTED (other groups: s2dw_*_batched)
+ *   groups[g].count:  maps of the group (>= 1)
+ *   groups[g].flm:    [count][L^2] complex f_lm: input of the analysis, output of the synthesis
+ *   groups[g].W:      [count][S][2N-1][L][2L-1] wavelet coefficients (doubles, or floats with
+ *                     S2DW_MIXED): output of the analysis, input of the synthesis
+ *   groups[g].Wphi_lm: [count][L^2] complex scaling coefficients (analysis output, synthesis
+ *                     input), or NULL (analysis: not computed; synthesis: taken as zero)
+ *   status:           device int32 (may be NULL): after the call's work, 0, or 1 if a wait of
+ *                     the executor for a dependency ran past its bound (then the results are
+ *                     not valid; the executor still finishes and clears its state)
+ * All pointers are device memory, 8-byte aligned; arrays of different groups must not
+ * overlap.  The first call with a given list (groups, buffers, stream) records its work list,
+ * allocates its workspaces and uploads them (synchronously); later calls with the same list
+ * only launch, so they can be captured in a graph.  The program is held until
+ * s2dw_release_caches.  Calls of one program must not overlap (same stream: they don't).
+ */
+typedef struct s2dw_group {
+    s2dw_params params;
+    int32_t count;
+    void *flm;
+    void *W;
+    void *Wphi_lm;
+} s2dw_group;
+int s2dw_analysis_persistent(const s2dw_group *groups, int32_t ngroups, int32_t *status, void *stream);
+int s2dw_synthesis_persistent(const s2dw_group *groups, int32_t ngroups, int32_t *status, void *stream);
+/* The bound of the executor's dependency waits, in polls of about 0.2 us (0: the default,
+ * about three seconds), and, for tests of the bounded-wait path only, never_satisfied = 1:
+ * every wait then runs out (status 1, results not valid) while the launches still finish.
+ * S2DW_E_ARG if polls < 0 or never_satisfied is not 0 or 1. */
+int s2dw_persistent_wait_bound(int32_t polls, int32_t never_satisfied);
+
+/*
  * The tuning of the plan of p (built on first use): the Wigner tile shape (m' slots per
  * wave), the maps per batched launch sequence, and the form of the alpha and gamma passes
  * at the prime-factor lengths T = 2L - 1 of 2047 and 4095 (real signals): 0 two passes

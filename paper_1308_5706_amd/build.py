@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libs2dw.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "tables.cpp", "wigner.hip", "stages.hip", "misc.hip"]
+SOURCES = ["persist.hip", "api.cpp", "tables.cpp", "wigner.hip", "stages.hip", "misc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("S2DW_ARCH", "gfx950")
@@ -33,7 +33,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    with ThreadPoolExecutor(max_workers=6) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

@@ -169,6 +169,9 @@ hipEvent_t prof_event() {
 // Set while the calling thread runs the entry point that allocates nothing: its launches
 // record no timing events (creating one may allocate).
 thread_local bool t_no_events = false;
+}  // namespace
+thread_local Recorder *t_rec = nullptr;  // work-list recording (persistent executor), kernels.h
+namespace {
 
 // Records events around one launch when timing is on.
 struct Stage {
@@ -944,14 +947,6 @@ int grid_limits(const s2dw_params *p, std::vector<int> &Lg) {
         if ((x) != hipSuccess) return S2DW_E_DEVICE;    \
     } while (0)
 
-// Coarse scales of real signals take the fused alpha and gamma passes (the analysis one
-// in both precisions: it computes in FP64 and reads and writes Ub and W in the plan's
-// precision; the synthesis one in FP64) while Nh (2Lj - 1) stays within 9 G and 256 (the
-// outputs of a ring in the synthesis pass, at most one per thread).  Nh (2Lj - 1) is the number of complex
-// multiply-adds per sample, G the number of W values a sample writes or reads: the passes
-// then cost little more than their W traffic, against a blocked alpha transform plus a
-// gamma pass that also writes and reads Y or X (at L = 1024, N = 8, for Lj = 4, 8, 16:
-// analysis 65-73 us per scale, synthesis 57-113 us, against about 130 us each).
 // Whether scale j of the analysis (synthesis) takes the fused prime-factor alpha and gamma
 // kernel; the caller has checked that it applies (pfa_fused, real signals).  The default
 // follows measurements at L = 1024, N = 8 and L = 2048, N = 4: the fused analysis kernel
@@ -968,6 +963,14 @@ bool fuse_adj(const Plan &P, const Shape &sh, int f32, int T) {
     return T == 4095 || f32 || P.Nh <= 2;
 }
 
+// Coarse scales of real signals take the fused alpha and gamma passes (the analysis one
+// in both precisions: it computes in FP64 and reads and writes Ub and W in the plan's
+// precision; the synthesis one in FP64) while Nh (2Lj - 1) stays within 9 G and 256 (the
+// outputs of a ring in the synthesis pass, at most one per thread).  Nh (2Lj - 1) is the number of complex
+// multiply-adds per sample, G the number of W values a sample writes or reads: the passes
+// then cost little more than their W traffic, against a blocked alpha transform plus a
+// gamma pass that also writes and reads Y or X (at L = 1024, N = 8, for Lj = 4, 8, 16:
+// analysis 65-73 us per scale, synthesis 57-113 us, against about 130 us each).
 bool direct_alpha_gamma(int Nh, int G, int Lj, bool cx) {
     const int terms = Nh * (2 * Lj - 1);
     return !cx && terms <= 9 * G && terms <= 256 && 2 * Nh * Lj <= kAlphaGammaCoeffs;
@@ -1327,6 +1330,257 @@ int run_forward(Plan &P, const Shape &sh, Work &w, int maps, const void *W, cons
     return S2DW_OK;
 }
 
+// ------------------------------------------------------------------ persistent executor
+// The work list of a persistent batch is recorded from run_inverse / run_forward (kernels.h),
+// one parameter set ("group") at a time, with a shape of its own: Wigner tiles of
+// persist_slots(K) m' slots and four-wave synthesis workgroups (m' groups of 4R).  Each group
+// has its own workspaces (count maps), held by the program.
+
+struct PGroup {
+    Plan *P = nullptr;
+    int count = 0;
+    const void *flm = nullptr;
+    void *W = nullptr, *wphi = nullptr;
+};
+
+struct PProgram {
+    struct Part {
+        PJob *jobs = nullptr;
+        unsigned char *args = nullptr;
+        int *ctr = nullptr;
+        PState *state = nullptr;
+        int njobs = 0, nitems = 0, nctr = 0, workers = 0;
+    };
+    int dir = 0, f32 = 0;
+    Part part[2];
+    std::vector<std::unique_ptr<Work>> works;
+    std::vector<void *> allocs;
+    ~PProgram() {
+        for (void *q : allocs) hipFree(q);
+    }
+    template <class T>
+    bool alloc(T *&p, size_t count) {
+        void *q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return false;
+        allocs.push_back(q);
+        p = (T *)q;
+        return true;
+    }
+};
+
+std::map<std::string, std::unique_ptr<PProgram>> g_programs;  // under g_mu
+int g_spin_limit = 0;                                           // 0: the default bound
+int g_wait_extra = 0;                                           // 1: waits never satisfied (tests)
+
+constexpr int kDefaultSpinLimit = 1 << 24;  // polls of about 0.2 us: a few seconds
+
+// The persistent shape of a plan (caller holds g_mu): tiles built once and kept.
+int persist_shape(Plan &P, Shape &sh) {
+    const int R = persist_slots(P.K);
+    const int key = -R;  // tile sets of the persistent shape, beside the ordinary ones
+    auto it = P.tilesets.find(key);
+    if (it == P.tilesets.end()) {
+        Plan::TileSet ts;
+        std::vector<int2> pl_a, x_a, pl_s, x_s;
+        build_tiles(P, P.seede_h, P.Lp, 4 * R, pl_a, x_a);
+        build_tiles(P, P.seede_h, P.Lp, 4 * R, pl_s, x_s);
+        ts.nfwd_plain = (int)pl_a.size();
+        ts.nfwd_x = (int)x_a.size();
+        ts.nadj_plain = (int)pl_s.size();
+        ts.nadj_x = (int)x_s.size();
+        pl_a.insert(pl_a.end(), x_a.begin(), x_a.end());
+        pl_s.insert(pl_s.end(), x_s.begin(), x_s.end());
+        if (!upload(P, ts.fwd, pl_a) || !upload(P, ts.adj, pl_s)) return S2DW_E_NOMEM;
+        it = P.tilesets.emplace(key, ts).first;
+    }
+    const Plan::TileSet &ts = it->second;
+    sh = P.cur;
+    sh.R = R;
+    sh.tiles_fwd = ts.fwd;
+    sh.tiles_adj = ts.adj;
+    sh.nfwd_plain = ts.nfwd_plain;
+    sh.nfwd_x = ts.nfwd_x;
+    sh.nadj_plain = ts.nadj_plain;
+    sh.nadj_x = ts.nadj_x;
+    sh.group = 4 * R;
+    sh.nblk = (P.L + sh.group - 1) / sh.group;
+    sh.s_F = (size_t)sh.nblk * P.L * P.Lp;
+    sh.fuse = 0;
+    return S2DW_OK;
+}
+
+// Records the launch sequence of every group and lays out the program's two parts.
+int build_program(PProgram &pr, int dir, int f32, const std::vector<PGroup> &gs, hipStream_t st) {
+    pr.dir = dir;
+    pr.f32 = f32;
+    std::vector<std::vector<RecJob>> rec(gs.size());
+    for (size_t g = 0; g < gs.size(); ++g) {
+        Plan &P = *gs[g].P;
+        Shape sh;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            int rc = persist_shape(P, sh);
+            if (rc != S2DW_OK) return rc;
+        }
+        std::unique_ptr<Work> w(new (std::nothrow) Work());
+        if (!w) return S2DW_E_NOMEM;
+        const size_t n = (size_t)gs[g].count;
+        if (!walloc(*w, w->fpad, n * P.s_fpad) || !walloc(*w, w->U, n * P.s_U) || !walloc(*w, w->Ub, n * P.s_Ub) ||
+            !walloc(*w, w->Y, n * P.s_Y) || !walloc(*w, w->Fpart, n * sh.s_F))
+            return S2DW_E_NOMEM;
+        w->cap = gs[g].count;
+        w->s_F = sh.s_F;
+        Recorder R;
+        t_rec = &R;
+        t_no_events = true;
+        int rc;
+        if (dir == 0) {
+            rc = run_inverse(P, sh, *w, gs[g].count, (const double2 *)gs[g].flm, gs[g].W, f32, st);
+            if (rc == S2DW_OK && gs[g].wphi &&
+                launch_scaling((const double2 *)gs[g].flm, P.phi, (double2 *)gs[g].wphi, P.L, gs[g].count, st) !=
+                    hipSuccess)
+                rc = S2DW_E_DEVICE;
+        } else {
+            rc = run_forward(P, sh, *w, gs[g].count, gs[g].W, (const double2 *)gs[g].wphi, (double2 *)gs[g].flm, f32,
+                             st);
+        }
+        t_rec = nullptr;
+        t_no_events = false;
+        // while recording, a failed launch is a stage the executor does not run
+        if (rc != S2DW_OK) return rc == S2DW_E_DEVICE ? S2DW_E_UNSUPPORTED : rc;
+        rec[g] = std::move(R.jobs);
+        pr.works.push_back(std::move(w));
+    }
+    for (int part = 0; part < 2; ++part) {
+        // the part's jobs of every group, with their position in the group's sequence; each job
+        // of a full batch (maps = count) depends on the group's previous such job in the part,
+        // the others (per-map clears of empty scales) on nothing
+        struct E {
+            int g, pos, prev;  // prev: index into `order` (filled below)
+            const RecJob *j;
+        };
+        std::vector<E> es;
+        for (size_t g = 0; g < gs.size(); ++g) {
+            int pos = 0;
+            for (const RecJob &j : rec[g])
+                if (persist_part(j.kind) == part) es.push_back({(int)g, pos++, -1, &j});
+        }
+        std::stable_sort(es.begin(), es.end(), [](const E &a, const E &b) { return a.pos < b.pos; });
+        std::vector<int> last(gs.size(), -1);
+        std::vector<PJob> jobs(es.size());
+        std::vector<unsigned char> args;
+        long long item0 = 0;
+        int ctr0 = 0;
+        for (size_t i = 0; i < es.size(); ++i) {
+            const RecJob &r = *es[i].j;
+            const int g = es[i].g;
+            PJob &J = jobs[i];
+            const bool main = r.maps == gs[g].count;
+            J.kind = r.kind;
+            if (r.gx < 1 || r.gx > (1 << 30) || r.nt < 1 || r.nt > 256 || 256 % r.nt) return S2DW_E_UNSUPPORTED;
+            J.gx = (int)r.gx;
+            J.nt = r.nt;
+            const int per = 256 / r.nt;
+            const int wg = (J.gx + per - 1) / per;  // worker rounds per map
+            J.rounds = (wg + 255) / 256;            // at most 256 work items per map and job
+            J.nx = (wg + J.rounds - 1) / J.rounds;
+            J.maps = r.maps;
+            J.item0 = (int)item0;
+            J.prev = main ? last[g] : -1;
+            if (main) last[g] = (int)i;
+            J.ctr0 = ctr0;
+            while (args.size() % 16) args.push_back(0);
+            J.arg = args.size();
+            args.insert(args.end(), r.args.begin(), r.args.end());
+            item0 += (long long)J.nx * J.maps;
+            ctr0 += J.maps;
+            if (item0 > (1 << 30)) return S2DW_E_UNSUPPORTED;
+        }
+        PProgram::Part &pt = pr.part[part];
+        pt.njobs = (int)jobs.size();
+        pt.nitems = (int)item0;
+        pt.nctr = ctr0;
+        if (pt.njobs == 0) continue;
+        pt.workers = std::min(persist_workers(dir, part, f32), pt.nitems);
+        if (pt.workers < 1) return S2DW_E_DEVICE;
+        if (!pr.alloc(pt.jobs, jobs.size()) || !pr.alloc(pt.args, args.size()) || !pr.alloc(pt.ctr, pt.nctr) ||
+            !pr.alloc(pt.state, 1))
+            return S2DW_E_NOMEM;
+        if (hipMemcpy(pt.jobs, jobs.data(), jobs.size() * sizeof(PJob), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pt.args, args.data(), args.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(pt.ctr, 0, (size_t)pt.nctr * sizeof(int)) != hipSuccess ||
+            hipMemset(pt.state, 0, sizeof(PState)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            return S2DW_E_DEVICE;
+    }
+    return S2DW_OK;
+}
+
+// One persistent batch: checks the groups, finds or builds its program, launches the parts.
+int run_persistent(int dir, const s2dw_group *groups, int32_t ngroups, int32_t *status, hipStream_t st) {
+    if (!groups || ngroups < 1) return S2DW_E_ARG;
+    const int f32 = groups[0].params.precision == S2DW_MIXED ? 1 : 0;
+    std::vector<PGroup> gs;
+    std::string key((const char *)&dir, sizeof dir);
+    key.append((const char *)&st, sizeof st);
+    for (int32_t g = 0; g < ngroups; ++g) {  // every group checked before any device work
+        const s2dw_group &e = groups[g];
+        int rc = check_params(&e.params);
+        if (rc != S2DW_OK) return rc;
+        if (e.count < 1 || !e.flm || !e.W || !aligned(e.flm) || !aligned(e.W) || (e.Wphi_lm && !aligned(e.Wphi_lm)))
+            return S2DW_E_ARG;
+        if ((e.params.precision == S2DW_MIXED ? 1 : 0) != f32) return S2DW_E_ARG;
+    }
+    for (int32_t g = 0; g < ngroups; ++g)
+        if (groups[g].params.reality != 1 || groups[g].params.grid != S2DW_GRID_MW || groups[g].params.N > 8)
+            return S2DW_E_UNSUPPORTED;
+    for (int32_t g = 0; g < ngroups; ++g) {
+        const s2dw_group &e = groups[g];
+        PGroup pg;
+        int rc = get_plan(kWavelet, e.params.L, e.params.N, e.params.lambda, e.params.J_min, pg.P, f32 != 0, e.params.grid);
+        if (rc != S2DW_OK) return rc;
+        pg.count = e.count;
+        pg.flm = e.flm;
+        pg.W = e.W;
+        pg.wphi = e.Wphi_lm;
+        gs.push_back(pg);
+        const uintptr_t kv[5] = {(uintptr_t)pg.P, (uintptr_t)pg.count, (uintptr_t)pg.flm, (uintptr_t)pg.W,
+                                 (uintptr_t)pg.wphi};
+        key.append((const char *)kv, sizeof kv);
+    }
+    PProgram *pr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_programs.find(key);
+        if (it != g_programs.end()) pr = it->second.get();
+    }
+    if (!pr) {
+        std::unique_ptr<PProgram> np(new (std::nothrow) PProgram());
+        if (!np) return S2DW_E_NOMEM;
+        int rc = build_program(*np, dir, f32, gs, st);
+        if (rc != S2DW_OK) return rc;
+        std::lock_guard<std::mutex> lk(g_mu);
+        pr = (g_programs[key] = std::move(np)).get();
+    }
+    int spin, extra;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        spin = g_spin_limit > 0 ? g_spin_limit : kDefaultSpinLimit;
+        extra = g_wait_extra;
+    }
+    // analysis: Wigner part, then the separation-of-variables part; synthesis the reverse
+    const int order[2] = {dir == 0 ? 0 : 1, dir == 0 ? 1 : 0};
+    int launched = 0;
+    for (int k = 0; k < 2; ++k) {
+        const PProgram::Part &pt = pr->part[order[k]];
+        if (pt.njobs == 0) continue;
+        Stage sg(order[k] == 0 ? "persist_wigner" : "persist_sov", st);
+        S2DW_CHECK_HIP(launch_persist(dir, order[k], f32, pt.workers, pt.jobs, pt.njobs, pt.nitems, pt.args, pt.ctr,
+                                      pt.nctr, pt.state, status, spin, launched > 0 ? 1 : 0, extra, st));
+        ++launched;
+    }
+    return S2DW_OK;
+}
+
 }  // namespace
 }  // namespace s2dw
 
@@ -1609,6 +1863,22 @@ int s2dw_autotune(const s2dw_params *p, int32_t count, void *stream, int32_t *sl
     return rc;
 }
 
+int s2dw_analysis_persistent(const s2dw_group *groups, int32_t ngroups, int32_t *status, void *stream) {
+    return run_persistent(0, groups, ngroups, status, (hipStream_t)stream);
+}
+
+int s2dw_synthesis_persistent(const s2dw_group *groups, int32_t ngroups, int32_t *status, void *stream) {
+    return run_persistent(1, groups, ngroups, status, (hipStream_t)stream);
+}
+
+int s2dw_persistent_wait_bound(int32_t polls, int32_t never_satisfied) {
+    if (polls < 0 || (never_satisfied != 0 && never_satisfied != 1)) return S2DW_E_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_spin_limit = polls;
+    g_wait_extra = never_satisfied;
+    return S2DW_OK;
+}
+
 int s2dw_get_tuning(const s2dw_params *p, int32_t *slots, int32_t *chunk, int32_t *fuse) {
     int rc = check_params(p);
     if (rc != S2DW_OK) return rc;
@@ -1842,7 +2112,7 @@ int s2dw_profile_stages(const char *names) {
     static const char *const known[] = {"pad",       "wigner_fwd",      "beta_fwd",  "alpha_fwd",
                                         "gamma_fwd", "alpha_gamma_fwd", "gamma_adj", "gamma_alpha_adj",
                                         "alpha_adj", "beta_adj",        "wigner_adj", "syn_final",
-                                        "scaling",   "steer"};
+                                        "scaling",   "steer",           "persist_wigner", "persist_sov"};
     std::set<std::string> sel;
     if (names) {
         const std::string all(names);
@@ -1897,7 +2167,8 @@ const char *s2dw_strerror(int code) {
 
 void s2dw_release_caches(void) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_plans.empty()) hipDeviceSynchronize();
+    if (!g_plans.empty() || !g_programs.empty()) hipDeviceSynchronize();
+    g_programs.clear();  // they point into the plans' tables
     g_plans.clear();
 }
 

@@ -3,6 +3,8 @@
 
 #include "s2dw_internal.h"
 
+#include <cstring>
+
 namespace s2dw {
 
 constexpr int kAdjWaves = 8;                 // waves per synthesis Wigner workgroup
@@ -188,5 +190,120 @@ hipError_t launch_to_f32(const double *src, float *dst, size_t n, hipStream_t st
 // floats if f32; G <= 31, maps <= 65535.
 hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int G, double step, int Q,
                         int S, size_t P, size_t s_in, size_t s_out, int maps, hipStream_t st);
+
+// ------------------------------------------------------------ work-list recording
+// The persistent executor (persist.hip) runs whole analyses or syntheses of many maps as one
+// launch per direction.  Its work list is recorded from the ordinary launch sequence: while a
+// Recorder is set on the calling thread (t_rec), each launcher of a stage the executor runs
+// appends a job -- body kind, work items per map, threads per item, argument block --
+// instead of launching, and every other launcher returns hipErrorNotSupported.
+
+enum PStage : int {
+    PS_PAD = 1, PS_SCALING, PS_ZERO, PS_WIGF, PS_BETAF_FFT, PS_BETAF_PAIR, PS_ALPHAF_FFT, PS_ALPHAF_BLK, PS_AGF,
+    PS_GAMMAF, PS_GAMMAA, PS_GAA, PS_ALPHAA_FFT, PS_ALPHAA_BLK, PS_BETAA_FFT, PS_BETAA_MULTI, PS_WIGA, PS_SYNF,
+};
+// Body kind: stage, precision (1: FP32 stages), and two template parameters (log2 of the
+// transform size, K and R of the Wigner stages, NH and the pairing of the direct passes).
+constexpr int pkind(int stage, int f32, int a = 0, int b = 0) { return (stage << 20) | (f32 << 19) | (a << 8) | b; }
+constexpr int pkind_stage(int k) { return k >> 20; }
+constexpr int pkind_f32(int k) { return (k >> 19) & 1; }
+constexpr int pkind_a(int k) { return (k >> 8) & 0x7ff; }
+constexpr int pkind_b(int k) { return k & 0xff; }
+constexpr int kPersistMaxP = 2048;  // largest transform of the executor (P / 8 <= 256 threads)
+
+struct PadArgs {
+    const double2 *flm;
+    const double *g;
+    double2 *fpad;
+    int L, Lp;
+    size_t s_fpad;
+};
+struct ScalingArgs {
+    const double2 *flm;
+    const double *phi;
+    double2 *wphi;
+    int L;
+};
+struct SynFinalArgs {
+    const void *Fpart;
+    size_t s_F;
+    int nblk, group, Lmax, L, Lp;
+    const double *fac, *g, *phi;
+    const double2 *wphi;
+    double2 *flm;
+};
+struct ZeroArgs {
+    uint32_t *p;
+    size_t n;
+};
+struct BetaMultiArgs {
+    StageArgs a;
+    const BetaAdjScale *tab;
+    int ns;
+};
+
+struct RecJob {
+    int kind = 0;
+    long long gx = 0;  // work items (workgroups of the ordinary launch) per map
+    int maps = 0;
+    int nt = 256;      // threads per work item
+    std::vector<unsigned char> args;
+};
+struct Recorder {
+    std::vector<RecJob> jobs;
+};
+extern thread_local Recorder *t_rec;
+
+template <class A>
+hipError_t rec_job(int kind, long long gx, int maps, int nt, const A &a) {
+    RecJob j;
+    j.kind = kind;
+    j.gx = gx;
+    j.maps = maps;
+    j.nt = nt;
+    j.args.resize(sizeof(A));
+    std::memcpy(j.args.data(), &a, sizeof(A));
+    t_rec->jobs.push_back(std::move(j));
+    return hipSuccess;
+}
+// The executor's job table (device): job j takes tickets [item0, item0 + maps nx); ticket
+// item0 + z nx + i is work item i of map z, covering (256 / nt) rounds consecutive workgroups
+// of the ordinary launch (gx per map).  A job waits, per map, until every item of job prev
+// (-1: none) has signalled counter ctr0 + z of that job.
+struct PJob {
+    int kind, gx, nt, rounds, nx, maps, item0, prev, ctr0;
+    int pad_;
+    unsigned long long arg;  // byte offset of the argument block
+};
+struct PState {
+    int ticket, exited, error, pad_;
+};
+// The executor's two parts: 0 the Wigner stages (with the input padding and the final
+// synthesis reduction), 1 the separation-of-variables stages; part of a body kind.
+int persist_part(int kind);
+// m' slots per wave of the executor's Wigner tiles for K carried orders.
+int persist_slots(int K);
+// Workers one launch may keep resident (occupancy x compute units) for direction dir (0
+// analysis, 1 synthesis), part and precision f32; 0 when the query fails.
+int persist_workers(int dir, int part, int f32);
+// status (device, may be null): the launch's error word (1: a dependency wait ran out of
+// polls); with status_or only a nonzero value is written.  wait_extra = 1 (tests only) makes
+// every dependency wait unsatisfiable, so that each runs out after spin_limit polls.
+hipError_t launch_persist(int dir, int part, int f32, int workers, const PJob *jobs, int njobs, int nitems,
+                          const unsigned char *args, int *ctr, int nctr, PState *state, int *status, int spin_limit,
+                          int status_or, int wait_extra, hipStream_t st);
+
+inline int log2_exact(int P) {
+    int k = 0;
+    while ((1 << k) < P) ++k;
+    return (1 << k) == P ? k : -1;
+}
+// An FFT stage of size P: one work item per column, P / 8 threads.
+template <class A>
+hipError_t rec_fft(int stage, const A &a, int f32, int P, long long gx, int maps) {
+    const int lg = log2_exact(P);
+    if (lg < 5 || P > kPersistMaxP) return hipErrorNotSupported;
+    return rec_job(pkind(stage, f32, lg), gx, maps, P / 8, a);
+}
 
 }  // namespace s2dw

@@ -1,6 +1,6 @@
 // Small kernels of the wavelet library: input padding, scaling coefficients, and the
 // final reduction of the synthesis.
-#include "kernels.h"
+#include "misc_k.h"
 
 namespace s2dw {
 
@@ -9,22 +9,12 @@ namespace s2dw {
 // Batched small kernels: map = blockIdx.z; f_lm and W^Phi_lm of map i start at i L^2.
 // fpad = g_l(m) f_lm, m <= l: the Wigner stage's rescaled recurrence takes the factor g here.
 __global__ void pad_flm_kernel(const double2 *flm, const double *g, double2 *fpad, int L, int Lp, size_t s_fpad) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int l = blockIdx.y;
-    if (m >= Lp) return;
-    flm += (size_t)blockIdx.z * L * L;
-    fpad += (size_t)blockIdx.z * s_fpad;
-    double2 v = make_double2(0.0, 0.0);
-    if (m <= l) {
-        const double2 f = flm[(size_t)l * l + l + m];
-        const double c = g[(size_t)l * Lp + m];
-        v = make_double2(c * f.x, c * f.y);
-    }
-    fpad[(size_t)l * Lp + m] = v;
+    pad_flm_elem(flm, g, fpad, L, Lp, s_fpad, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, blockIdx.z);
 }
 
 hipError_t launch_pad_flm(const double2 *flm, const double *g, double2 *fpad, int L, int Lp, size_t s_fpad, int maps,
                           hipStream_t st) {
+    if (t_rec) return rec_job(pkind(PS_PAD, 0), (long long)((Lp + 255) / 256) * L, maps, 256, PadArgs{flm, g, fpad, L, Lp, s_fpad});
     hipLaunchKernelGGL(pad_flm_kernel, dim3((Lp + 255) / 256, L, maps), dim3(256), 0, st, flm, g, fpad, L, Lp,
                        s_fpad);
     return hipGetLastError();
@@ -57,6 +47,7 @@ __global__ void pad_flm_complex_kernel(const double2 *flm, const double *g, doub
 
 hipError_t launch_pad_flm_complex(const double2 *flm, const double *g, double2 *fpad, int L, int Lp, size_t s_fpad,
                                   int cmaps, hipStream_t st) {
+    if (t_rec) return hipErrorNotSupported;
     hipLaunchKernelGGL(pad_flm_complex_kernel, dim3((Lp + 255) / 256, L, cmaps), dim3(256), 0, st, flm, g, fpad, L,
                        Lp, s_fpad);
     return hipGetLastError();
@@ -84,6 +75,7 @@ __global__ void merge_complex_kernel(const double2 *fab, size_t s_fab, const dou
 
 hipError_t launch_merge_complex(const double2 *fab, size_t s_fab, const double2 *wphi, const double *phi,
                                 double2 *flm, int L, int cmaps, hipStream_t st) {
+    if (t_rec) return hipErrorNotSupported;
     hipLaunchKernelGGL(merge_complex_kernel, dim3((2 * L - 1 + 255) / 256, L, cmaps), dim3(256), 0, st, fab, s_fab,
                        wphi, phi, flm, L);
     return hipGetLastError();
@@ -91,16 +83,11 @@ hipError_t launch_merge_complex(const double2 *fab, size_t s_fab, const double2 
 
 // W^Phi_lm = sqrt(4 pi/(2l+1)) f_lm Phi_l0 (Eq. 31); Phi is real.
 __global__ void scaling_kernel(const double2 *flm, const double *phi, double2 *wphi, int L) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int l = blockIdx.y;
-    if (m > 2 * l) return;
-    const size_t i = (size_t)blockIdx.z * L * L + (size_t)l * l + m;
-    const double c = sqrt(4.0 * 3.14159265358979323846 / (2.0 * l + 1.0)) * phi[l];
-    const double2 f = flm[i];
-    wphi[i] = make_double2(c * f.x, c * f.y);
+    scaling_elem(flm, phi, wphi, L, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, blockIdx.z);
 }
 
 hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, int L, int maps, hipStream_t st) {
+    if (t_rec) return rec_job(pkind(PS_SCALING, 0), (long long)((2 * L - 1 + 255) / 256) * L, maps, 256, ScalingArgs{flm, phi, wphi, L});
     hipLaunchKernelGGL(scaling_kernel, dim3((2 * L - 1 + 255) / 256, L, maps), dim3(256), 0, st, flm, phi, wphi, L);
     return hipGetLastError();
 }
@@ -114,39 +101,16 @@ template <class VC>
 __global__ void syn_final_kernel(const VC *Fpart, size_t s_F, int nblk, int group, int Lmax, const double *fac,
                                  const double *gsc, const double2 *wphi, const double *phi, double2 *flm, int L,
                                  int Lp) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int l = blockIdx.y;
-    if (m > l) return;
-    Fpart += (size_t)blockIdx.z * s_F;
-    flm += (size_t)blockIdx.z * L * L;
-    if (wphi) wphi += (size_t)blockIdx.z * L * L;
-    double fr = 0.0, fi = 0.0;
-    // no wavelet coefficient reaches l >= Lmax; blocks starting above l hold no term of row l
-    const int gmax = (l < Lmax && m < Lmax) ? min(nblk - 1, l / group) : -1;
-    for (int g = 0; g <= gmax; ++g) {
-        const VC v = Fpart[((size_t)g * L + l) * Lp + m];
-        fr += (double)v.x;
-        fi += (double)v.y;
-    }
-    const double cg = fac[l] * gsc[(size_t)l * Lp + m];
-    fr *= cg;
-    fi *= cg;
-    if (wphi) {
-        const double c = sqrt((2.0 * l + 1.0) / (4.0 * 3.14159265358979323846)) * phi[l];
-        const double2 w = wphi[(size_t)l * l + l + m];
-        fr += c * w.x;
-        fi += c * w.y;
-    }
-    flm[(size_t)l * l + l + m] = make_double2(fr, fi);
-    if (m > 0) {
-        const double sg = (m & 1) ? -1.0 : 1.0;
-        flm[(size_t)l * l + l - m] = make_double2(sg * fr, -sg * fi);
-    }
+    syn_final_elem(Fpart, s_F, nblk, group, Lmax, fac, gsc, wphi, phi, flm, L, Lp, blockIdx.x * blockDim.x + threadIdx.x,
+                   blockIdx.y, blockIdx.z);
 }
 
 hipError_t launch_syn_final(const void *Fpart, size_t s_F, int f32, int nblk, int group, int Lmax, const double *fac,
                             const double *g, const double2 *wphi, const double *phi, double2 *flm, int L, int Lp,
                             int maps, hipStream_t st) {
+    if (t_rec)
+        return rec_job(pkind(PS_SYNF, f32), (long long)((L + 255) / 256) * L, maps, 256,
+                       SynFinalArgs{Fpart, s_F, nblk, group, Lmax, L, Lp, fac, g, phi, wphi, flm});
     const dim3 grid((L + 255) / 256, L, maps);
     if (f32)
         hipLaunchKernelGGL(syn_final_kernel<float2>, grid, dim3(256), 0, st, (const float2 *)Fpart, s_F, nblk, group,
@@ -167,6 +131,7 @@ hipError_t launch_zero_words(void *p, size_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
+    if (t_rec) return rec_job(pkind(PS_ZERO, 0), (long long)blocks, 1, 256, ZeroArgs{(uint32_t *)p, n});
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, n);
     return hipGetLastError();
 }
@@ -251,6 +216,7 @@ void steer_launch(const void *W, const double *gam, void *out, int N, int G, dou
 
 hipError_t launch_steer(const void *W, const double *gam, void *out, int f32, int N, int G, double step, int Q,
                         int S, size_t P, size_t s_in, size_t s_out, int maps, hipStream_t st) {
+    if (t_rec) return hipErrorNotSupported;
     // vector width: the plane size, the map strides and both base addresses are multiples of it
     const size_t es = f32 ? 4 : 8;
     auto fits = [&](int V) {

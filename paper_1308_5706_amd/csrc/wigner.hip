@@ -1,511 +1,7 @@
-// Wigner stage of the directional scale-discretized wavelet transform on gfx950.
-//
-// Analysis (Sec. 3.2, Eq. 27) for every scale j, m >= 0, m' >= 0 and carried n:
-//   U^j_{m m' n} = i^{n-m} sum_l Delta^l_{m'm} Delta^l_{m'n} f_lm conj(Psi^j_ln)
-// with Delta = d(pi/2) generated by the three-term recurrence in l on the fly.
-// Synthesis (Sec. 3.3, Eq. 34 and Eq. 32 fused) for every l, m >= 0:
-//   F_lm = sum_{m' >= 0} Delta^l_{m'm} sum_j kappa^j(l) sum_n sigma_ln Delta^l_{m'n} P^j_{m m' n}(l)
-// where P carries the folded quadrature values V of Eq. 35 (computed in stages.hip).
-//
-// Mapping: a wave owns R consecutive m' ("slots"); its 64 lanes own 64 consecutive
-// m.  Each lane runs the l-recurrence of Delta^l_{m'm} for its R pairs, on the rescaled
-// values D_l = Delta^l_{m'm} / (g_l(m) h_l(m')) whose Delta^{l-1} coefficient is 1:
-//   D_{l+1} = -(ut_l(m') pt_l(m)) D_l - D_{l-1}      (a multiply and an FMA per pair),
-// with g_l(m) carried by f_lm (analysis) or applied to the sums (synthesis) and h_l(m') by
-// the kappa sigma Delta table.  Values that depend on (l, m') only -- ut_l(m') and the table
-// kappa^j(l) sigma_{l,n} Delta^l_{m'n} h_l(m') -- are wave-uniform: both directions read them
-// with scalar loads one step ahead, their addresses advancing by one record per step (SGPR
-// operands cost no VGPRs, which keeps the occupancy up); values that depend on (l, m) --
-// g_l(m) f_lm and pt_l(m) -- are per-lane coalesced loads shared by the R slots.
-//
-// Symmetries used (exact identities of Delta): Delta^l_{m',-n} = (-1)^{l+m'}
-// Delta^l_{m'n} lets the l-sum run only over n >= 0 with separate even-l and odd-l
-// accumulators; Delta^l_{-m',m} = (-1)^{l+m} Delta^l_{m'm} gives U for m' < 0 from
-// m' > 0 (Eq. 29 is then a cosine or sine series).
-//
-// Extended exponent: the start value Delta^{l0}_{l0,l0} = 2^-l0 is below the double
-// range for l0 > 1022, yet the recurrence grows it back to O(1e-2) by l ~ sqrt(2) l0.
-// Tiles that hold such start values run the XN variant, which carries each D as
-// mantissa * 2^e with e <= 0 and renormalises the mantissa every 8 steps.
-#include "s2dw_internal.h"
-#include "kernels.h"
-
-#include <type_traits>
+// Launchers of the Wigner-stage kernels (wigner_k.h) and the tile-shape options.
+#include "wigner_k.h"
 
 namespace s2dw {
-
-namespace {
-
-// z * i^e
-__device__ __forceinline__ double2 rot_i(double2 z, int e) {
-    e &= 3;
-    if (e == 0) return z;
-    if (e == 1) return make_double2(-z.y, z.x);
-    if (e == 2) return make_double2(-z.x, -z.y);
-    return make_double2(z.y, -z.x);
-}
-
-constexpr double kBig = 0x1p400;
-constexpr double kBigInv = 0x1p-400;
-
-__device__ __forceinline__ double scale_of(int e) { return e < -1074 ? 0.0 : ldexp(1.0, e); }
-
-typedef const __attribute__((address_space(4))) double *cdptr;
-
-__device__ __forceinline__ cdptr as_const(const double *p) { return (cdptr)(p); }
-
-// l-window of the synthesis contraction's cross-wave reduction: 16 steps where the kernel's
-// registers allow one workgroup per CU anyway (FP64 with K R >= 6 or R = 4: more than 128
-// VGPRs), else 8 so that two workgroups fit in LDS.
-template <int K, int R, typename VT>
-constexpr int adj_win() {
-    return (sizeof(VT) == 8 && (K * R >= 6 || R >= 4)) ? 16 : 8;
-}
-
-}  // namespace
-
-// ------------------------------------------------------------------------------- analysis
-
-template <int K, int R, bool XN>
-__device__ __forceinline__ void wig_fwd_body(const WigFwdArgs &a) {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const int2 t = a.tiles[blockIdx.x];
-    const int L = a.L, Lp = a.Lp;
-    const int m = t.x + lane;
-    const int mpb = t.y + wave * R;
-    if (mpb >= L) return;
-    const int lstart = max(t.x, mpb);
-
-    int mp[R], l0[R];
-    double sv[R], D0[R], D1[R];
-    int ex[R], se[R];
-    double scl[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int mpv = mpb + r;
-        mp[r] = mpv < L ? mpv : L - 1;
-        l0[r] = max(m, mpv);
-        const bool ok = mpv < L && m < L;
-        const size_t si = (size_t)mp[r] * Lp + (m < Lp ? m : Lp - 1);
-        if (XN) {
-            sv[r] = ok ? a.seedm[si] : 0.0;
-            se[r] = ok ? a.seede[si] : 0;
-        } else {
-            sv[r] = ok ? a.seed[si] : 0.0;
-            se[r] = 0;
-        }
-        D0[r] = 0.0;
-        D1[r] = 0.0;
-        ex[r] = 0;
-        scl[r] = 1.0;
-    }
-    // acc[r][slot][l parity][k][re, im]
-    double acc[R][2][2][K][2];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int k = 0; k < K; ++k) acc[r][s][p][k][0] = acc[r][s][p][k][1] = 0.0;
-
-    const int lhead = min(L - 1, max(t.x + 63, mpb + R - 1));
-    const double2 *__restrict__ fpad = a.fpad + blockIdx.y * a.s_fpad + m;
-    const double *__restrict__ pqt = a.pq + m;
-
-    // One l-step for the wave's R slots.  Both scale slots are always accumulated: the
-    // table holds zeros for a slot whose scale does not contain l, so the step has no
-    // branches and its scalar table loads issue together.  f and pt of the step are
-    // passed in, loaded one step ahead by the caller.
-    // the wave-uniform table entries of a step, loaded (scalar) one step ahead
-    struct Tab {
-        double kb[R][2 * K], u[R];
-    };
-    auto load_tab = [&](int l, Tab &tb) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            cdptr kb = as_const(a.kb2 + ((size_t)mp[r] * L + l) * (2 * K));
-            cdptr u = as_const(a.uv) + ((size_t)mp[r] * L + l);
-#pragma unroll
-            for (int i = 0; i < 2 * K; ++i) tb.kb[r][i] = kb[i];
-            tb.u[r] = u[0];
-        }
-    };
-    auto step = [&](int l, auto par_c, auto head_c, const double2 f, const double p, const Tab &tb) {
-        constexpr int PAR = decltype(par_c)::value;
-        constexpr bool HEAD = decltype(head_c)::value;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (HEAD && l == l0[r]) {
-                D1[r] = sv[r];
-                if (XN) {
-                    ex[r] = se[r];
-                    scl[r] = scale_of(se[r]);
-                }
-            }
-            const double x = XN ? D1[r] * scl[r] : D1[r];
-            const double gr = x * f.x, gi = x * f.y;
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const double w = tb.kb[r][s * K + k];
-                    acc[r][s][PAR][k][0] = fma(gr, w, acc[r][s][PAR][k][0]);
-                    acc[r][s][PAR][k][1] = fma(gi, w, acc[r][s][PAR][k][1]);
-                }
-            const double dn = -(tb.u[r] * p) * D1[r] - D0[r];
-            D0[r] = D1[r];
-            D1[r] = dn;
-        }
-        if (XN && (l & 7) == 7) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (fabs(D1[r]) > kBig) {
-                    D1[r] *= kBigInv;
-                    D0[r] *= kBigInv;
-                    ex[r] += 400;
-                    scl[r] = scale_of(ex[r]);
-                }
-            }
-        }
-    };
-
-    // steps lb <= l < le, with the loads of step l + 1 issued before step l runs; the table
-    // addresses advance by one record per step (the tables carry one record of padding, read
-    // after the last step)
-    auto run = [&](int lb, int le, auto head_c) {
-        if (lb >= le) return;
-        double2 f = fpad[(size_t)lb * Lp];
-        double pq = pqt[(size_t)lb * Lp];
-        Tab tb;
-        load_tab(lb, tb);
-        cdptr kbn[R], un[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            kbn[r] = as_const(a.kb2 + ((size_t)mp[r] * L + lb + 1) * (2 * K));
-            un[r] = as_const(a.uv) + ((size_t)mp[r] * L + lb + 1);
-        }
-        int l = lb;
-        auto one = [&](auto par_c) {
-            const int ln = l + 1 < L ? l + 1 : l;
-            const double2 fn = fpad[(size_t)ln * Lp];
-            const double pqn = pqt[(size_t)ln * Lp];
-            Tab tn;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-#pragma unroll
-                for (int i = 0; i < 2 * K; ++i) tn.kb[r][i] = kbn[r][i];
-                tn.u[r] = un[r][0];
-                kbn[r] += 2 * K;
-                un[r] += 1;
-            }
-            step(l, par_c, head_c, f, pq, tb);
-            f = fn;
-            pq = pqn;
-            tb = tn;
-            ++l;
-        };
-        if (l & 1) one(std::integral_constant<int, 1>());
-        for (; l + 1 < le;) {
-            one(std::integral_constant<int, 0>());
-            one(std::integral_constant<int, 1>());
-        }
-        if (l < le) one(std::integral_constant<int, 0>());
-    };
-
-    auto flush = [&](int slot, int j) {
-        const int Lj = a.sc.Lj[j];
-        double2 *__restrict__ U = a.U + blockIdx.y * a.s_U + a.sc.off[j];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int mpv = mpb + r;
-            if (m < Lj && mpv < Lj) {
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int n = a.nk[k];
-                    const double Er = acc[r][slot][0][k][0], Ei = acc[r][slot][0][k][1];
-                    const double Or = acc[r][slot][1][k][0], Oi = acc[r][slot][1][k][1];
-                    const int nip = (n + a.N - 1) >> 1;
-                    U[((size_t)nip * Lj + m) * Lj + mpv] = rot_i(make_double2(Er + Or, Ei + Oi), n - m + a.eoff);
-                    if (n != 0) {
-                        const int nim = (-n + a.N - 1) >> 1;
-                        double2 dd = make_double2(Er - Or, Ei - Oi);
-                        if (mpv & 1) dd = make_double2(-dd.x, -dd.y);
-                        U[((size_t)nim * Lj + m) * Lj + mpv] = rot_i(dd, -n - m + a.eoff);
-                    }
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int k = 0; k < K; ++k) acc[r][slot][p][k][0] = acc[r][slot][p][k][1] = 0.0;
-        }
-    };
-
-    for (int si = 0; si < a.seg.n; ++si) {
-        const int s1 = a.seg.s1[si];
-        if (s1 <= lstart) continue;
-        const int s0 = max(a.seg.s0[si], lstart);
-        const int je = a.seg.je[si], jo = a.seg.jo[si];
-        const bool ae = je >= 0, ao = jo >= 0;
-        const int hb = min(s1, lhead + 1);
-        if (s0 < hb) run(s0, hb, std::true_type());
-        if (max(s0, hb) < s1) run(max(s0, hb), s1, std::false_type());
-        const int jen = si + 1 < a.seg.n ? a.seg.je[si + 1] : -1;
-        const int jon = si + 1 < a.seg.n ? a.seg.jo[si + 1] : -1;
-        if (ae && je != jen) flush(0, je);
-        if (ao && jo != jon) flush(1, jo);
-    }
-}
-
-// ------------------------------------------------------------------------------ synthesis
-
-template <int K, int R, bool XN, typename VT>
-__device__ __forceinline__ void wig_adj_body(const WigAdjArgs &a, VT *win) {
-    // VT = double (FP64 path) or float (mixed precision: the m'-sum, its products and its
-    // accumulation in FP32; the Delta recursion stays FP64)
-    using VC = typename std::conditional<sizeof(VT) == 8, double2, float2>::type;
-    typedef const __attribute__((address_space(4))) VT *ckptr;
-    constexpr int WIN = adj_win<K, R, VT>();
-    // per-wave partial sums of the current l-window: win[wave][l - wb][lane][re, im]
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const int2 t = a.tiles[blockIdx.x];
-    const int L = a.L, Lp = a.Lp;
-    const int m = t.x + lane;
-    const int mpb = t.y + wave * R;
-    const int wg_start = max(t.x, t.y);                 // smallest l with a non-zero term in the group
-    const int wbase0 = wg_start / WIN * WIN;
-    const bool active = mpb < L;
-    const int lstart = active ? max(t.x, mpb) : L;
-
-    VT *mywin = win + (size_t)wave * WIN * 64 * 2;
-
-    int mp[R], l0[R];
-    double sv[R], D0[R], D1[R], scl[R];
-    int ex[R], se[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int mpv = mpb + r;
-        mp[r] = mpv < L ? mpv : L - 1;
-        l0[r] = max(m, mpv);
-        const bool ok = mpv < L && m < L;
-        const size_t si = (size_t)mp[r] * Lp + (m < Lp ? m : Lp - 1);
-        if (XN) {
-            sv[r] = ok ? a.seedm[si] : 0.0;
-            se[r] = ok ? a.seede[si] : 0;
-        } else {
-            sv[r] = ok ? a.seed[si] : 0.0;
-            se[r] = 0;
-        }
-        D0[r] = D1[r] = 0.0;
-        ex[r] = 0;
-        scl[r] = 1.0;
-    }
-    // folded quadrature values of the two active scales: pv[r][slot][P or Q][k][re, im]
-    VT pv[R][2][2][K][2];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int k = 0; k < K; ++k) pv[r][s][p][k][0] = pv[r][s][p][k][1] = 0;
-
-    auto load_slot = [&](int slot, int j) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int mpv = mpb + r;
-            const int Lj = j >= 0 ? a.sc.Lj[j] : 0;
-            const bool ok = j >= 0 && m < Lj && mpv < Lj;
-            const VC *V = (const VC *)a.V + blockIdx.y * a.s_V + (j >= 0 ? a.sc.off[j] : 0);
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    VC v;
-                    v.x = v.y = 0;
-                    if (ok) v = V[(((size_t)k * 2 + p) * Lj + m) * Lj + mpv];
-                    pv[r][slot][p][k][0] = v.x;
-                    pv[r][slot][p][k][1] = v.y;
-                }
-        }
-    };
-
-    const int lhead = min(L - 1, max(t.x + 63, mpb + R - 1));
-    const double *__restrict__ pqt = a.pq + (m < Lp ? m : Lp - 1);
-    int seg = 0;
-    int cur_je = -2, cur_jo = -2;
-
-    // The wave-uniform table entries of a step (scalar loads into SGPRs, as in the analysis).
-    struct Tab {
-        VT kb[R][2 * K];
-        double u[R];
-    };
-    // One l-step of the wave's R slots.
-    auto step = [&](int l, auto par_c, auto head_c, const double p, const Tab &tb, VT &fr, VT &fi) {
-        constexpr int PAR = decltype(par_c)::value;
-        constexpr bool HEAD = decltype(head_c)::value;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (HEAD && l == l0[r]) {
-                D1[r] = sv[r];
-                if (XN) {
-                    ex[r] = se[r];
-                    scl[r] = scale_of(se[r]);
-                }
-            }
-            const VT x = (VT)(XN ? D1[r] * scl[r] : D1[r]);
-            VT yr = 0, yi = 0;
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const VT w = tb.kb[r][s * K + k];
-                    yr = fma(w, pv[r][s][PAR][k][0], yr);
-                    yi = fma(w, pv[r][s][PAR][k][1], yi);
-                }
-            fr = fma(x, yr, fr);
-            fi = fma(x, yi, fi);
-            const double dn = -(tb.u[r] * p) * D1[r] - D0[r];
-            D0[r] = D1[r];
-            D1[r] = dn;
-        }
-        if (XN && (l & 7) == 7) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (fabs(D1[r]) > kBig) {
-                    D1[r] *= kBigInv;
-                    D0[r] *= kBigInv;
-                    ex[r] += 400;
-                    scl[r] = scale_of(ex[r]);
-                }
-            }
-        }
-    };
-
-    __syncthreads();
-    VC *__restrict__ out = (VC *)a.Fpart + blockIdx.y * a.s_F + (size_t)(t.y / a.group) * L * Lp;
-
-    // The values of the next step, loaded one step ahead and carried across windows: the
-    // table entries (their addresses advance by one record per step; the tables carry one
-    // record of padding, read after the last step) and pt.
-    Tab tb;
-    ckptr kbn[R];
-    cdptr un[R];
-    const int lfirst = lstart < L ? lstart : L - 1;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const ckptr kb = (ckptr)((const VT *)a.kb2 + ((size_t)mp[r] * L + lfirst) * (2 * K));
-        const cdptr u = as_const(a.uv) + ((size_t)mp[r] * L + lfirst);
-#pragma unroll
-        for (int i = 0; i < 2 * K; ++i) tb.kb[r][i] = kb[i];
-        tb.u[r] = u[0];
-        kbn[r] = kb + 2 * K;
-        un[r] = u + 1;
-    }
-    double pn = pqt[(size_t)lfirst * Lp];
-
-    // steps lb <= l < le of one segment (fixed active scales), results into the window slice
-    auto run = [&](int lb, int le, int wb, auto head_c) {
-        int l = lb;
-        auto one = [&](auto par_c) {
-            VT fr = 0, fi = 0;
-            const double p = pn;
-            pn = pqt[(size_t)(l + 1 < L ? l + 1 : l) * Lp];
-            Tab tn;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-#pragma unroll
-                for (int i = 0; i < 2 * K; ++i) tn.kb[r][i] = kbn[r][i];
-                tn.u[r] = un[r][0];
-                kbn[r] += 2 * K;
-                un[r] += 1;
-            }
-            step(l, par_c, head_c, p, tb, fr, fi);
-            tb = tn;
-            mywin[((l - wb) * 64 + lane) * 2 + 0] = fr;
-            mywin[((l - wb) * 64 + lane) * 2 + 1] = fi;
-            ++l;
-        };
-        if (l < le && (l & 1)) one(std::integral_constant<int, 1>());
-        for (; l + 1 < le;) {
-            one(std::integral_constant<int, 0>());
-            one(std::integral_constant<int, 1>());
-        }
-        if (l < le) one(std::integral_constant<int, 0>());
-    };
-
-    for (int wb = wbase0; wb < L; wb += WIN) {
-        const int we = min(L, wb + WIN);
-        if (active) {
-            int l = max(wb, lstart);
-            while (l < we) {
-                while (a.seg.s1[seg] <= l) ++seg;
-                const int je = a.seg.je[seg], jo = a.seg.jo[seg];
-                if (je != cur_je) {
-                    load_slot(0, je);
-                    cur_je = je;
-                }
-                if (jo != cur_jo) {
-                    load_slot(1, jo);
-                    cur_jo = jo;
-                }
-                const int le = min(we, a.seg.s1[seg]);
-                const int hb = min(le, lhead + 1);
-                if (l < hb) run(l, hb, wb, std::true_type());
-                if (max(l, hb) < le) run(max(l, hb), le, wb, std::false_type());
-                l = le;
-            }
-        }
-        __syncthreads();
-        // sum the waves' slices in a fixed order: the result does not depend on timing.  Wave
-        // w wrote every l of the window from its first active l on (max(t.x, its first m')),
-        // and nothing before it or when all its m' lie beyond L: those entries are skipped.
-        for (int i = threadIdx.x; i < (we - wb) * 64; i += blockDim.x) {
-            const int li = i >> 6, ln = i & 63;
-            const int mm = t.x + ln;
-            VT sr = 0, si = 0;
-#pragma unroll
-            for (int w = 0; w < kAdjWaves; ++w) {
-                const int mpw = t.y + w * R;
-                if (mpw < L && wb + li >= max(t.x, mpw)) {
-                    const VT *q = win + ((size_t)w * WIN * 64 + i) * 2;
-                    sr += q[0];
-                    si += q[1];
-                }
-            }
-            if (mm < Lp) {
-                // streamed out (read back only by the final reduction): non-temporal, so that
-                // the partial sums do not push the tables and V out of L2
-                typedef VT vc2 __attribute__((ext_vector_type(2)));
-                vc2 o;
-                o.x = sr;
-                o.y = si;
-                __builtin_nontemporal_store(o, (vc2 *)(out + (size_t)(wb + li) * Lp + mm));
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// One launch per direction: the first nplain workgroups take tiles whose start values
-// are normal doubles, the rest take the extended-exponent tiles.
-template <int K, int R>
-__global__ void __launch_bounds__(256, (K * R <= 4 && R <= 2 ? 4 : 1)) wig_fwd_kernel(const WigFwdArgs a) {
-    if ((int)blockIdx.x < a.nplain) wig_fwd_body<K, R, false>(a);
-    else wig_fwd_body<K, R, true>(a);
-}
-
-template <int K, int R, typename VT>
-__global__ void __launch_bounds__(kAdjThreads, (adj_win<K, R, VT>() == 8 ? 4 : 2)) wig_adj_kernel(const WigAdjArgs a) {
-    __shared__ VT win[kAdjWaves * adj_win<K, R, VT>() * 64 * 2];
-    if ((int)blockIdx.x < a.nplain) wig_adj_body<K, R, false, VT>(a, win);
-    else wig_adj_body<K, R, true, VT>(a, win);
-}
 
 // ------------------------------------------------------------------------------ launchers
 
@@ -560,10 +56,12 @@ int wig_slot_options(int K, int *R) {
     }
 
 hipError_t launch_wig_fwd(const WigFwdArgs &a, int K, int R, int ntiles, int maps, hipStream_t st) {
+    if (t_rec) return K <= 4 ? rec_job(pkind(PS_WIGF, 0, K, R), ntiles, maps, 256, a) : hipErrorNotSupported;
     S2DW_WIG_SWITCH(launch_fwd_k)
 }
 
 hipError_t launch_wig_adj(const WigAdjArgs &a, int K, int R, int ntiles, int maps, hipStream_t st) {
+    if (t_rec) return K <= 4 ? rec_job(pkind(PS_WIGA, a.f32, K, R), ntiles, maps, 256, a) : hipErrorNotSupported;
     S2DW_WIG_SWITCH(launch_adj_k)
 }
 

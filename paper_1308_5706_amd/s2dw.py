@@ -29,6 +29,11 @@ class Params(ctypes.Structure):
                 ("reality", ctypes.c_int32)]
 
 
+class Group(ctypes.Structure):
+    _fields_ = [("params", Params), ("count", ctypes.c_int32), ("flm", ctypes.c_void_p), ("W", ctypes.c_void_p),
+                ("Wphi_lm", ctypes.c_void_p)]
+
+
 class StageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_double), ("count", ctypes.c_int64)]
 
@@ -78,6 +83,13 @@ def lib():
         L.s2dw_get_tuning.restype = ctypes.c_int
         L.s2dw_set_tuning.argtypes = [cp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.s2dw_set_tuning.restype = ctypes.c_int
+        gp = ctypes.POINTER(Group)
+        L.s2dw_analysis_persistent.argtypes = [gp, ctypes.c_int32, vp, vp]
+        L.s2dw_analysis_persistent.restype = ctypes.c_int
+        L.s2dw_synthesis_persistent.argtypes = [gp, ctypes.c_int32, vp, vp]
+        L.s2dw_synthesis_persistent.restype = ctypes.c_int
+        L.s2dw_persistent_wait_bound.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.s2dw_persistent_wait_bound.restype = ctypes.c_int
         L.s2dw_workspace_bytes.argtypes = [cp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
         L.s2dw_workspace_bytes.restype = ctypes.c_int
         L.s2dw_cache_bytes.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
@@ -94,7 +106,8 @@ def lib():
 
 EXPORTED = ["s2dw_num_scales", "s2dw_grid_shape", "s2dw_wavelet_bytes", "s2dw_scale_grid", "s2dw_analysis",
             "s2dw_analysis_noalloc",
-            "s2dw_synthesis", "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_get_tuning", "s2dw_set_tuning", "s2dw_workspace_bytes",
+            "s2dw_synthesis", "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_steer", "s2dw_autotune", "s2dw_get_tuning", "s2dw_set_tuning",
+            "s2dw_analysis_persistent", "s2dw_synthesis_persistent", "s2dw_persistent_wait_bound", "s2dw_workspace_bytes",
             "s2dw_cache_bytes",
             "s2dw_scaling", "s2dw_sht_forward", "s2dw_sht_inverse", "s2dw_wavelet_tables", "s2dw_profile",
             "s2dw_profile_read", "s2dw_profile_stages",
@@ -299,6 +312,72 @@ def autotune(L: int, N: int, lam: float = 2.0, J_min: int = 0, *, count: int = 1
     return sl.value, ch.value
 
 
+def _groups(items, precision):
+    arr = (Group * len(items))()
+    for i, (L, N, lam, J_min, f, W, Wp) in enumerate(items):
+        arr[i].params = params(L, N, lam, J_min, precision, "mw", True)
+        arr[i].count = f.shape[0]
+        arr[i].flm = f.data_ptr()
+        arr[i].W = W.data_ptr()
+        arr[i].Wphi_lm = Wp.data_ptr() if Wp is not None else None
+    return arr
+
+
+def analysis_persistent(groups, *, precision: str = "fp64", stream=None, status: torch.Tensor | None = None,
+                        scaling: bool = True):
+    """Analyses of several batches, one per parameter set, through the persistent executor (two
+    launches).  groups: list of (L, N, lam, J_min, flm complex128 [B][L*L]); returns a list of
+    (W [B][S][2N-1][L][2L-1], W^Phi [B][L*L] or None).  The output buffers are allocated on the
+    first call with a given list of inputs and reused (the same tensors) on later calls, so
+    that the call can be replayed in a graph.  status: optional int32 device tensor of one
+    element, set to 0 (or 1: a dependency wait ran out; the results are not valid)."""
+    key = ("a", precision, tuple((L, N, lam, J, f.data_ptr(), f.shape[0]) for L, N, lam, J, f in groups))
+    outs = _persist_outs.get(key)
+    if outs is None:
+        outs = []
+        for L, N, lam, J_min, f in groups:
+            if f.dim() != 2 or f.shape[1] != L * L or f.dtype != torch.complex128 or not f.is_contiguous():
+                raise ValueError("flm: expected contiguous [B][L*L] complex128")
+            W = torch.empty((f.shape[0],) + _w_shape(L, N, lam, J_min, "mw"), dtype=_w_dtype(precision, True),
+                            device=f.device)
+            Wp = torch.empty((f.shape[0], L * L), dtype=torch.complex128, device=f.device) if scaling else None
+            outs.append((W, Wp))
+        _persist_outs[key] = outs
+    arr = _groups([(L, N, lam, J, f, W, Wp) for (L, N, lam, J, f), (W, Wp) in zip(groups, outs)], precision)
+    _check(lib().s2dw_analysis_persistent(arr, len(groups), ctypes.c_void_p(status.data_ptr() if status is not None
+                                                                              else None), _stream(stream)),
+           "s2dw_analysis_persistent")
+    return outs
+
+
+def synthesis_persistent(groups, *, precision: str = "fp64", stream=None, status: torch.Tensor | None = None):
+    """Syntheses of several batches through the persistent executor.  groups: list of
+    (L, N, lam, J_min, W [B][S][2N-1][L][2L-1], W^Phi [B][L*L] or None); returns the list of
+    f_lm complex128 [B][L*L] (allocated on the first call with these inputs, then reused)."""
+    key = ("s", precision, tuple((L, N, lam, J, W.data_ptr(), Wp.data_ptr() if Wp is not None else 0, W.shape[0])
+                                 for L, N, lam, J, W, Wp in groups))
+    outs = _persist_outs.get(key)
+    if outs is None:
+        outs = []
+        for L, N, lam, J_min, W, Wp in groups:
+            _check_w(W, _w_shape(L, N, lam, J_min, "mw"), _w_dtype(precision, True), W.shape[0], "W")
+            outs.append(torch.empty((W.shape[0], L * L), dtype=torch.complex128, device=W.device))
+        _persist_outs[key] = outs
+    arr = _groups([(L, N, lam, J, f, W, Wp) for (L, N, lam, J, W, Wp), f in zip(groups, outs)], precision)
+    _check(lib().s2dw_synthesis_persistent(arr, len(groups), ctypes.c_void_p(status.data_ptr() if status is not None
+                                                                               else None), _stream(stream)),
+           "s2dw_synthesis_persistent")
+    return outs
+
+
+def persistent_wait_bound(polls: int = 0, never_satisfied: bool = False) -> None:
+    """Bound of the persistent executor's dependency waits (polls of ~0.2 us; 0: default);
+    never_satisfied (tests only): every wait runs out."""
+    _check(lib().s2dw_persistent_wait_bound(polls, 1 if never_satisfied else 0), "s2dw_persistent_wait_bound")
+
+
+_persist_outs: dict = {}
+
 FUSE_FORMS = {"two-pass": 0, "default": 1, "fused": 2}
 
 
@@ -424,4 +503,5 @@ def profile_read() -> dict:
 
 
 def release_caches():
+    _persist_outs.clear()
     lib().s2dw_release_caches()

@@ -14,6 +14,11 @@ class Params(ctypes.Structure):
                 ("reality", ctypes.c_int32)]
 
 
+class Group(ctypes.Structure):
+    _fields_ = [("params", Params), ("count", ctypes.c_int32), ("flm", ctypes.c_void_p), ("W", ctypes.c_void_p),
+                ("Wphi_lm", ctypes.c_void_p)]
+
+
 def main():
     lib = ctypes.CDLL(sys.argv[1])
     for f in ("s2dw_analysis", "s2dw_synthesis", "s2dw_analysis_batched", "s2dw_synthesis_batched", "s2dw_scaling",
@@ -67,6 +72,25 @@ def main():
             fails += 1
         if lib.s2dw_sht_inverse(ctypes.byref(p), vp(0x1000), vp(0x1000), None) == 0:
             fails += 1
+    # persistent batches refused before any device work (bad groups, mixed precisions, what
+    # the executor does not run), and the wait-bound setting
+    for f in ("s2dw_analysis_persistent", "s2dw_synthesis_persistent"):
+        fn = getattr(lib, f)
+        fn.restype = ctypes.c_int
+        for gl in ([], [(0, 1, 0, 0x1000)], [(1, 1, 0, 0x1004)], [(1, 1, 0, 0x1000), (1, 1, 1, 0x1000)],
+                   [(1, 0, 0, 0x1000)], [(1, 1, 0, 0x1000), (0, 1, 0, 0x1000)]):
+            arr = (Group * max(len(gl), 1))()
+            for i, (count, reality, precision, ptr) in enumerate(gl):
+                arr[i].params = Params(32, 4, 2.0, 0, 0, precision, reality)
+                arr[i].count, arr[i].flm, arr[i].W = count, ptr, ptr
+            if fn(arr, len(gl), None, None) == 0:
+                fails += 1
+        if fn(None, 1, None, None) == 0:
+            fails += 1
+    if lib.s2dw_persistent_wait_bound(-1, 0) == 0 or lib.s2dw_persistent_wait_bound(1, 3) == 0:
+        fails += 1
+    if lib.s2dw_persistent_wait_bound(0, 0) != 0:
+        fails += 1
     # wavelet tables into host buffers
     for (L, N) in ((8, 1), (33, 4), (64, 16)):
         p = Params(L, N, 2.0, 0, 0, 0, 1)

@@ -120,6 +120,36 @@ def test_batched_and_autotune_argument_errors():
     assert lib.s2dw_analysis_batched(ctypes.byref(bad), 1, fake, fake, None, None) == -1
 
 
+def test_persistent_argument_errors():
+    # refused before any plan or device work: no groups, bad counts or pointers, mixed
+    # precisions, and what the executor does not run (complex signals, other grids, N > 8)
+    lib = s2dw.lib()
+    fake = 0x1000
+
+    def grp(L=32, N=4, precision=0, reality=1, grid=0, count=1, flm=fake, W=fake):
+        g = s2dw.Group()
+        g.params = s2dw.Params(L, N, 2.0, 0, grid, precision, reality)
+        g.count, g.flm, g.W, g.Wphi_lm = count, flm, W, None
+        return g
+
+    def call(*gs):
+        arr = (s2dw.Group * max(len(gs), 1))(*gs)
+        return lib.s2dw_analysis_persistent(arr, len(gs), None, None)
+
+    assert lib.s2dw_analysis_persistent(None, 1, None, None) == -1
+    assert call() == -1
+    assert call(grp(count=0)) == -1
+    assert call(grp(flm=None)) == -1
+    assert call(grp(W=0x1004)) == -1
+    assert call(grp(), grp(precision=1)) == -1
+    assert call(grp(reality=0)) == -4
+    assert call(grp(grid=2)) == -4
+    assert call(grp(N=10)) == -4
+    assert lib.s2dw_persistent_wait_bound(-1, 0) == -1
+    assert lib.s2dw_persistent_wait_bound(10, 2) == -1
+    assert lib.s2dw_persistent_wait_bound(0, 0) == 0
+
+
 def test_steer_argument_errors():
     lib = s2dw.lib()
     p = s2dw.params(64, 4, 2.0, 0)

@@ -59,7 +59,7 @@ def test_library_host_code_under_sanitizers(tmp_path):
     from paper_1308_5706_amd import build as B
     hipcc = B.HIPCC
     rt = _asan_runtime()
-    objs = [os.path.join(B.BUILD, n) for n in ("wigner.o", "stages.o", "misc.o")]
+    objs = [os.path.join(B.BUILD, n) for n in ("wigner.o", "stages.o", "misc.o", "persist.o")]
     if not os.path.exists(hipcc) or rt is None:
         pytest.skip("needs hipcc and the clang sanitizer runtime")
     if not all(os.path.exists(o) for o in objs):
