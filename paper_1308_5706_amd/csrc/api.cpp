@@ -1346,10 +1346,12 @@ struct PGroup {
 struct PProgram {
     struct Part {
         PJob *jobs = nullptr;
+        PEnt *ents = nullptr;
+        int *qoff = nullptr, *qn = nullptr;
         unsigned char *args = nullptr;
         int *ctr = nullptr;
         PState *state = nullptr;
-        int njobs = 0, nitems = 0, nctr = 0, workers = 0;
+        int njobs = 0, nitems = 0, nctr = 0, workers = 0, chunk = 1;
     };
     int dir = 0, f32 = 0;
     Part part[2];
@@ -1456,21 +1458,22 @@ int build_program(PProgram &pr, int dir, int f32, const std::vector<PGroup> &gs,
         // of a full batch (maps = count) depends on the group's previous such job in the part,
         // the others (per-map clears of empty scales) on nothing
         struct E {
-            int g, pos, prev;  // prev: index into `order` (filled below)
+            int g, pos;
             const RecJob *j;
         };
         std::vector<E> es;
         for (size_t g = 0; g < gs.size(); ++g) {
             int pos = 0;
             for (const RecJob &j : rec[g])
-                if (persist_part(j.kind) == part) es.push_back({(int)g, pos++, -1, &j});
+                if (persist_part(j.kind) == part) es.push_back({(int)g, pos++, &j});
         }
         std::stable_sort(es.begin(), es.end(), [](const E &a, const E &b) { return a.pos < b.pos; });
         std::vector<int> last(gs.size(), -1);
         std::vector<PJob> jobs(es.size());
         std::vector<unsigned char> args;
-        long long item0 = 0;
+        std::vector<double> work(gs.size(), 0.0);  // per map of each group: threads x workgroups
         int ctr0 = 0;
+        long long nitems = 0;
         for (size_t i = 0; i < es.size(); ++i) {
             const RecJob &r = *es[i].j;
             const int g = es[i].g;
@@ -1482,31 +1485,75 @@ int build_program(PProgram &pr, int dir, int f32, const std::vector<PGroup> &gs,
             J.nt = r.nt;
             const int per = 256 / r.nt;
             const int wg = (J.gx + per - 1) / per;  // worker rounds per map
-            J.rounds = (wg + 255) / 256;            // at most 256 work items per map and job
+            // at least four worker rounds per item (the fixed costs of an item: its ticket, its
+            // entry, the wait and the signal of its run), at most 256 items per map and job
+            J.rounds = std::max((wg + 255) / 256, std::min(wg, 4));
             J.nx = (wg + J.rounds - 1) / J.rounds;
             J.maps = r.maps;
-            J.item0 = (int)item0;
             J.prev = main ? last[g] : -1;
             if (main) last[g] = (int)i;
             J.ctr0 = ctr0;
             while (args.size() % 16) args.push_back(0);
             J.arg = args.size();
             args.insert(args.end(), r.args.begin(), r.args.end());
-            item0 += (long long)J.nx * J.maps;
             ctr0 += J.maps;
-            if (item0 > (1 << 30)) return S2DW_E_UNSUPPORTED;
+            nitems += (long long)J.nx * J.maps;
+            if (main) work[g] += (double)r.gx * r.nt;
         }
+        if (nitems > (1 << 30)) return S2DW_E_UNSUPPORTED;
+        // maps to queues, heaviest first to the least loaded (every map's jobs in one queue)
+        std::vector<std::vector<int>> qof(gs.size());
+        {
+            std::vector<std::pair<double, std::pair<int, int>>> ms;
+            for (size_t g = 0; g < gs.size(); ++g) {
+                qof[g].assign(gs[g].count, 0);
+                for (int z = 0; z < gs[g].count; ++z) ms.push_back({work[g], {(int)g, z}});
+            }
+            std::stable_sort(ms.begin(), ms.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+            double load[kPersistQueues] = {};
+            for (const auto &m : ms) {
+                const int q = (int)(std::min_element(load, load + kPersistQueues) - load);
+                load[q] += m.first;
+                qof[m.second.first][m.second.second] = q;
+            }
+        }
+        // entries of each queue in job order (jobs with one map but a larger batch, the
+        // per-map clears of empty scales, go to queue 0)
+        std::vector<std::vector<PEnt>> qe(kPersistQueues);
+        std::vector<int> qitems(kPersistQueues, 0);
+        for (size_t i = 0; i < es.size(); ++i) {
+            const int g = es[i].g;
+            const PJob &J = jobs[i];
+            for (int z = 0; z < J.maps; ++z) {
+                const int q = J.maps == gs[g].count ? qof[g][z] : 0;
+                qe[q].push_back(PEnt{(int)i, z, qitems[q], 0});
+                qitems[q] += J.nx;
+            }
+        }
+        std::vector<PEnt> ents;
+        std::vector<int> qoff(kPersistQueues + 1, 0);
+        for (int q = 0; q < kPersistQueues; ++q) {
+            qoff[q] = (int)ents.size();
+            ents.insert(ents.end(), qe[q].begin(), qe[q].end());
+        }
+        qoff[kPersistQueues] = (int)ents.size();
         PProgram::Part &pt = pr.part[part];
         pt.njobs = (int)jobs.size();
-        pt.nitems = (int)item0;
+        pt.nitems = (int)nitems;
         pt.nctr = ctr0;
         if (pt.njobs == 0) continue;
         pt.workers = std::min(persist_workers(dir, part, f32), pt.nitems);
         if (pt.workers < 1) return S2DW_E_DEVICE;
-        if (!pr.alloc(pt.jobs, jobs.size()) || !pr.alloc(pt.args, args.size()) || !pr.alloc(pt.ctr, pt.nctr) ||
-            !pr.alloc(pt.state, 1))
+        // tickets per fetch: small, so that a map's runs spread over many workers
+        pt.chunk = std::max(1, std::min(4, pt.nitems / (128 * pt.workers)));
+        if (!pr.alloc(pt.jobs, jobs.size()) || !pr.alloc(pt.ents, ents.size()) ||
+            !pr.alloc(pt.qoff, kPersistQueues + 1) || !pr.alloc(pt.qn, kPersistQueues) ||
+            !pr.alloc(pt.args, args.size()) || !pr.alloc(pt.ctr, pt.nctr) || !pr.alloc(pt.state, 1))
             return S2DW_E_NOMEM;
         if (hipMemcpy(pt.jobs, jobs.data(), jobs.size() * sizeof(PJob), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pt.ents, ents.data(), ents.size() * sizeof(PEnt), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pt.qoff, qoff.data(), qoff.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pt.qn, qitems.data(), qitems.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(pt.args, args.data(), args.size(), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemset(pt.ctr, 0, (size_t)pt.nctr * sizeof(int)) != hipSuccess ||
             hipMemset(pt.state, 0, sizeof(PState)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
@@ -1574,8 +1621,9 @@ int run_persistent(int dir, const s2dw_group *groups, int32_t ngroups, int32_t *
         const PProgram::Part &pt = pr->part[order[k]];
         if (pt.njobs == 0) continue;
         Stage sg(order[k] == 0 ? "persist_wigner" : "persist_sov", st);
-        S2DW_CHECK_HIP(launch_persist(dir, order[k], f32, pt.workers, pt.jobs, pt.njobs, pt.nitems, pt.args, pt.ctr,
-                                      pt.nctr, pt.state, status, spin, launched > 0 ? 1 : 0, extra, st));
+        S2DW_CHECK_HIP(launch_persist(dir, order[k], f32, pt.workers, pt.jobs, pt.ents, pt.qoff, pt.qn, pt.args,
+                                      pt.ctr, pt.nctr, pt.state, status, spin, launched > 0 ? 1 : 0, extra, pt.chunk,
+                                      st));
         ++launched;
     }
     return S2DW_OK;

@@ -266,17 +266,22 @@ hipError_t rec_job(int kind, long long gx, int maps, int nt, const A &a) {
     t_rec->jobs.push_back(std::move(j));
     return hipSuccess;
 }
-// The executor's job table (device): job j takes tickets [item0, item0 + maps nx); ticket
-// item0 + z nx + i is work item i of map z, covering (256 / nt) rounds consecutive workgroups
-// of the ordinary launch (gx per map).  A job waits, per map, until every item of job prev
-// (-1: none) has signalled counter ctr0 + z of that job.
+// The executor's tables (device).  Job j: nx work items per map, item i covering (256 / nt)
+// rounds consecutive workgroups of the ordinary launch (gx per map); for map z it waits until
+// every item of job prev (-1: none) has signalled counter ctr0 + z of that job.  The work is
+// split into kPersistQueues ticket queues, each a list of entries (job, map) in dependency
+// order, entry e of queue q taking tickets [item0, item0 + nx) of that queue.
 struct PJob {
-    int kind, gx, nt, rounds, nx, maps, item0, prev, ctr0;
-    int pad_;
+    int kind, gx, nt, rounds, nx, maps, prev, ctr0;
     unsigned long long arg;  // byte offset of the argument block
 };
+struct PEnt {
+    int job, map, item0, pad_;
+};
+constexpr int kPersistQueues = 8;
 struct PState {
-    int ticket, exited, error, pad_;
+    int ticket[kPersistQueues];
+    int exited, error, pad_[2];
 };
 // The executor's two parts: 0 the Wigner stages (with the input padding and the final
 // synthesis reduction), 1 the separation-of-variables stages; part of a body kind.
@@ -288,10 +293,13 @@ int persist_slots(int K);
 int persist_workers(int dir, int part, int f32);
 // status (device, may be null): the launch's error word (1: a dependency wait ran out of
 // polls); with status_or only a nonzero value is written.  wait_extra = 1 (tests only) makes
-// every dependency wait unsatisfiable, so that each runs out after spin_limit polls.
-hipError_t launch_persist(int dir, int part, int f32, int workers, const PJob *jobs, int njobs, int nitems,
-                          const unsigned char *args, int *ctr, int nctr, PState *state, int *status, int spin_limit,
-                          int status_or, int wait_extra, hipStream_t st);
+// every dependency wait unsatisfiable, so that each runs out after spin_limit polls.  chunk:
+// tickets a worker takes at a time (>= 1).
+// qoff[q] .. qoff[q + 1]: the entries of queue q; qn[q]: its tickets.
+hipError_t launch_persist(int dir, int part, int f32, int workers, const PJob *jobs, const PEnt *ents,
+                          const int *qoff, const int *qn, const unsigned char *args, int *ctr, int nctr,
+                          PState *state, int *status, int spin_limit, int status_or, int wait_extra, int chunk,
+                          hipStream_t st);
 
 inline int log2_exact(int P) {
     int k = 0;

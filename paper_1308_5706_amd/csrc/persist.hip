@@ -5,21 +5,26 @@
 //
 // The work list is the ordinary launch sequence of every parameter set, recorded (kernels.h):
 // each launch becomes a job whose workgroups ("work items") the executor runs as device
-// functions.  A launch of `workers` workgroups of 256 threads stays resident; each worker
-// takes tickets from one counter in increasing order, finds the ticket's job (the job table is
-// ordered by ticket), waits until the job it depends on has finished for the same map, runs
-// the item and signals the job's counter for that map.  Jobs are ordered so that every
-// dependency has smaller tickets; a ticket is only taken by a running worker, and the
-// smallest unfinished ticket never waits on an unfinished one, so the launch drains whatever
-// the number of resident workers.
+// functions.  The maps are spread over 8 ticket queues (each map's work in one queue); a
+// queue lists (job, map) entries in dependency order.  A launch of `workers` workgroups of
+// 256 threads stays resident; each worker takes tickets in increasing order from its home
+// queue and, once that is exhausted, from the others in turn; it finds the ticket's entry,
+// waits until the job it depends on has finished for the same map, runs the item and
+// signals the job's counter for that map.  Every dependency lies in the same queue with
+// smaller tickets; a ticket is only taken by a running worker, and the smallest unfinished
+// ticket of a queue never waits on an unfinished one, so the launch drains whatever the
+// number of resident workers.
 //
 // Within a parameter set a job depends on the job before it (the launch order of the
 // ordinary path, per map); the parameter sets are independent, and their jobs interleave by
 // position in their sequences so that every set's maps move through the stages together.
-// Visibility between workgroups follows the agent-scope release/acquire pairs: every thread
-// fences (release) after its item's stores and the signal is an atomic add after a barrier;
-// the waiting thread polls with atomic loads, fences (acquire), and a barrier and an acquire
-// fence in every thread follow.
+// A worker takes `chunk` consecutive tickets at a time and runs them in order; consecutive
+// tickets of one job and map form a run, which waits once for its dependency and signals once
+// (the count of its items) when it ends, before the next run waits (so the ordering argument
+// above still holds).  Visibility between workgroups: at the end of a run every wave waits
+// for its stores (vmcnt 0), a barrier follows, and one thread releases at agent scope and
+// adds the count; the waiting thread polls with atomic loads and acquires at agent scope
+// (the caches it invalidates are the ones the workgroup shares), and a barrier follows.
 //
 // Work items of the FFT stages take P / 8 threads; a worker runs 256 / (P / 8) of them side by
 // side, each with its own LDS column.  Past the end of a job the extra columns repeat its last
@@ -45,6 +50,7 @@ namespace {
 constexpr int kPersistThreads = 256;
 constexpr int kPersistAW = kPersistThreads / 64;  // waves of the synthesis Wigner items
 constexpr int kMaxNH = 4;                          // orders n >= 0 of the direct fused passes (N <= 8)
+constexpr int kVmcnt0 = 0x0F70;                    // s_waitcnt vmcnt(0) (gfx9 encoding; expcnt, lgkmcnt not waited)
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // LDS of a worker: the FFT columns (256 threads' worth: padded(2048) elements of the largest
@@ -84,16 +90,13 @@ __device__ __forceinline__ void fft_item(int vb0, int gx, int tid, unsigned char
         default: break;       \
     }
 
-// The Wigner tile shapes of the executor: K R <= 4 and R <= 2 (persist_slots), whose kernels
-// fit 128 registers.
+// The Wigner tile shapes of the executor (persist_slots: the ordinary kernels' defaults).
 #define S2DW_PERSIST_KR(CALL) \
     switch (ka * 8 + kb) {    \
-        case 9: CALL(1, 1) break; \
-        case 10: CALL(1, 2) break; \
-        case 17: CALL(2, 1) break; \
+        case 12: CALL(1, 4) break; \
         case 18: CALL(2, 2) break; \
-        case 25: CALL(3, 1) break; \
-        case 33: CALL(4, 1) break; \
+        case 26: CALL(3, 2) break; \
+        case 34: CALL(4, 2) break; \
         default: break;       \
     }
 
@@ -284,54 +287,101 @@ __device__ __forceinline__ void persist_item(int kind, const unsigned char *ap, 
     }
 }
 
+// Two workers per CU for the Wigner part (the register budget of its tile shapes, as in the
+// ordinary kernels), four for the others.
 template <class C, int DIR, int PART>
-__global__ void __launch_bounds__(kPersistThreads, 4) persist_kernel(const PJob *__restrict__ jobs, int njobs, int nitems,
+__global__ void __launch_bounds__(kPersistThreads, PART == 0 ? 2 : 4) persist_kernel(const PJob *__restrict__ jobs,
+                                                                  const PEnt *__restrict__ ents,
+                                                                  const int *__restrict__ qoff,
+                                                                  const int *__restrict__ qn,
                                                                   const unsigned char *__restrict__ args, int *ctr,
                                                                   int nctr, PState *state, int *status, int spin_limit,
-                                                                  int status_or, int wait_extra) {
+                                                                  int status_or, int wait_extra, int chunk) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[kPersistLds];
     __shared__ int s_ticket, s_err, s_last;
     const int tid = threadIdx.x;
-    int j = 0;
-    for (;;) {
-        if (tid == 0) s_ticket = __hip_atomic_fetch_add(&state->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // The end of a run of n items of one job and map: every wave waits for its stores, then
+    // one agent-scope release and the count.
+    auto signal = [&](int c, int n) {
+        __builtin_amdgcn_s_waitcnt(kVmcnt0);
         __syncthreads();
-        const int t = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform: job and item fields go to SGPRs
-        if (t >= nitems) break;
-        while (j + 1 < njobs && jobs[j + 1].item0 <= t) ++j;
-        const PJob J = jobs[j];
-        const int r = t - J.item0, by = r / J.nx, ix = r - (r / J.nx) * J.nx;
         if (tid == 0) {
-            // no wait once a wait has run out: the rest of the launch only drains
-            if (J.prev >= 0 && !__hip_atomic_load(&state->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                const PJob Q = jobs[J.prev];
-                int *c = ctr + Q.ctr0 + by;
-                const int need = Q.nx + wait_extra;  // wait_extra = 1 (tests only): never satisfied
-                int polls = 0;
-                while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    if (++polls > spin_limit) {
-                        __hip_atomic_store(&state->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(8);
-                }
-            }
-            s_err = __hip_atomic_load(&state->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(kVmcnt0);
+            __hip_atomic_fetch_add(ctr + c, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+    };
+    // the home queue first (workgroups of one queue share an XCD: q = blockIdx mod 8), then the
+    // others in turn; a worker leaves after finding every queue exhausted in a row
+    int q = blockIdx.x % kPersistQueues, empty = 0, e = -1;  // e: entry cursor in queue q (-1: not placed)
+    for (;;) {
+        if (tid == 0) s_ticket = __hip_atomic_fetch_add(&state->ticket[q], chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (!__builtin_amdgcn_readfirstlane(s_err)) {
-            const int per = (kPersistThreads / J.nt) ;  // workgroups of the ordinary launch side by side
-            for (int k = 0; k < J.rounds; ++k) {
-                const int vb0 = (ix * J.rounds + k) * per;
-                if (vb0 >= J.gx) break;
-                persist_item<C, DIR, PART>(J.kind, args + J.arg, vb0, J.gx, by, tid, lds);
+        const int t0 = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform: job and item fields go to SGPRs
+        __syncthreads();                                          // s_ticket is read before it is rewritten
+        const int nq = qn[q];
+        if (t0 >= nq) {
+            if (++empty == kPersistQueues) break;
+            q = (q + 1) % kPersistQueues;
+            e = -1;
+            continue;
+        }
+        empty = 0;
+        const int t1 = min(t0 + chunk, nq), eend = qoff[q + 1];
+        if (e < 0) {  // the last entry of the queue starting at or before t0 (binary search)
+            int lo = qoff[q], hi = eend;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (ents[mid].item0 <= t0) lo = mid;
+                else hi = mid;
+            }
+            e = lo;
+        }
+        int run_job = -1, run_by = -1, run_n = 0;
+        for (int t = t0; t < t1; ++t) {
+            while (e + 1 < eend && ents[e + 1].item0 <= t) ++e;
+            const PEnt E = ents[e];
+            const int j = E.job, by = E.map, ix = t - E.item0;
+            const PJob J = jobs[j];
+            if (j != run_job || by != run_by) {
+                // a new run: signal the last one (an item of this chunk may wait for it), then wait
+                // for this one's dependency
+                if (run_n) signal(jobs[run_job].ctr0 + run_by, run_n);
+                run_job = j;
+                run_by = by;
+                run_n = 0;
+                if (tid == 0) {
+                    // no wait once a wait has run out: the rest of the launch only drains
+                    if (J.prev >= 0 && !__hip_atomic_load(&state->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        const PJob Q = jobs[J.prev];
+                        int *c = ctr + Q.ctr0 + by;
+                        const int need = Q.nx + wait_extra;  // wait_extra = 1 (tests only): never satisfied
+                        int polls = 0;
+                        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                            if (++polls > spin_limit) {
+                                __hip_atomic_store(&state->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(8);
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                    s_err = __hip_atomic_load(&state->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
                 __syncthreads();
             }
+            if (!__builtin_amdgcn_readfirstlane(s_err)) {
+                const int per = kPersistThreads / J.nt;  // workgroups of the ordinary launch side by side
+                for (int k = 0; k < J.rounds; ++k) {
+                    const int vb0 = (ix * J.rounds + k) * per;
+                    if (vb0 >= J.gx) break;
+                    persist_item<C, DIR, PART>(J.kind, args + J.arg, vb0, J.gx, by, tid, lds);
+                    __syncthreads();
+                }
+            }
+            ++run_n;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (tid == 0) __hip_atomic_fetch_add(ctr + J.ctr0 + by, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (run_n) signal(jobs[run_job].ctr0 + run_by, run_n);
     }
     // leave; the last worker resets the state for the next launch
     if (tid == 0) {
@@ -347,7 +397,7 @@ __global__ void __launch_bounds__(kPersistThreads, 4) persist_kernel(const PJob 
             const int err = __hip_atomic_load(&state->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (status && (err || !status_or)) *status = err;
             state->error = 0;
-            state->ticket = 0;
+            for (int k = 0; k < kPersistQueues; ++k) state->ticket[k] = 0;
             state->exited = 0;
         }
     }
@@ -372,7 +422,7 @@ int persist_part(int kind) {
     return (s == PS_PAD || s == PS_WIGF || s == PS_WIGA || s == PS_SYNF) ? 0 : 1;
 }
 
-int persist_slots(int K) { return K <= 2 ? 2 : 1; }
+int persist_slots(int K) { return K <= 1 ? 4 : 2; }
 
 int persist_workers(int dir, int part, int f32) {
 #define S2DW_PW(D, PT) return f32 ? workers_of<float2, D, PT>() : workers_of<double2, D, PT>()
@@ -385,14 +435,15 @@ int persist_workers(int dir, int part, int f32) {
 #undef S2DW_PW
 }
 
-hipError_t launch_persist(int dir, int part, int f32, int workers, const PJob *jobs, int njobs, int nitems,
-                          const unsigned char *args, int *ctr, int nctr, PState *state, int *status, int spin_limit,
-                          int status_or, int wait_extra, hipStream_t st) {
-    if (workers < 1 || njobs < 1 || nitems < 1) return hipErrorInvalidValue;
+hipError_t launch_persist(int dir, int part, int f32, int workers, const PJob *jobs, const PEnt *ents,
+                          const int *qoff, const int *qn, const unsigned char *args, int *ctr, int nctr,
+                          PState *state, int *status, int spin_limit, int status_or, int wait_extra, int chunk,
+                          hipStream_t st) {
+    if (workers < 1 || chunk < 1) return hipErrorInvalidValue;
     const dim3 grid((unsigned)workers), block(kPersistThreads);
 #define S2DW_PL(C, D, PT)                                                                                    \
-    hipLaunchKernelGGL((persist_kernel<C, D, PT>), grid, block, 0, st, jobs, njobs, nitems, args, ctr, nctr, state, \
-                       status, spin_limit, status_or, wait_extra)
+    hipLaunchKernelGGL((persist_kernel<C, D, PT>), grid, block, 0, st, jobs, ents, qoff, qn, args, ctr, nctr, state, \
+                       status, spin_limit, status_or, wait_extra, chunk)
     const int sel = dir * 4 + part * 2 + (f32 ? 1 : 0);
     switch (sel) {
         case 0: S2DW_PL(double2, 0, 0); break;
