@@ -247,26 +247,29 @@ def step_stats(ms):
 
 
 def batched_leg(maps=256, replays=5, oracle_maps=4):
-    """The batched mixed-precision form (many maps of mixed (L, N) in one HIP graph): its
-    throughput against the plain FP64 path, each map's error against the FP64 GPU result,
-    and the checker: sampled maps (L <= 128) against the FP64 CPU oracle."""
+    """The batched mixed-precision form (many maps of mixed (L, N) in one HIP graph, and the
+    same maps through the persistent executor): throughput against the plain FP64 path, each
+    map's error against the FP64 GPU result, and the checker: sampled maps (L <= 128) of both
+    forms against the FP64 CPU oracle."""
     import numpy as np
     import oracle
     from paper_1308_5706_amd import batch
     out, data = batch.run(maps, replays)
-    errs = []
-    for (L, N), (idx, F, W, fr) in sorted(data.items()):
+    errs, perrs = [], []
+    for (L, N), (idx, F, W, fr, PW) in sorted(data.items()):
         if L > 128:
             continue
         for k in range(min(F.shape[0], oracle_maps - len(errs))):
             ref = oracle.analysis(F[k].cpu().numpy(), L, N, 2.0, 1)
-            got = W[k].double().cpu().numpy()
-            errs.append(max(float(np.max(np.abs(got[j] - ref[j])) / np.max(np.abs(ref[j])))
-                            for j in range(ref.shape[0])))
+            for got, lst in ((W[k], errs), (PW[k], perrs)):
+                g = got.double().cpu().numpy()
+                lst.append(max(float(np.max(np.abs(g[j] - ref[j])) / np.max(np.abs(ref[j])))
+                               for j in range(ref.shape[0])))
         if len(errs) >= oracle_maps:
             break
     out["oracle_maps"] = len(errs)
     out["max_rel_err_W_vs_oracle"] = max(errs) if errs else None
+    out["persistent"]["max_rel_err_W_vs_oracle"] = max(perrs) if perrs else None
     del data
     return out
 
@@ -590,7 +593,8 @@ def main():
     W = None
     torch.cuda.empty_cache()
     if not args.no_extras:
-        print("# batched leg: 256 maps of mixed (L, N), mixed precision, one graph", file=sys.stderr, flush=True)
+        print("# batched leg: 256 maps of mixed (L, N), mixed precision, one graph; then the persistent executor",
+              file=sys.stderr, flush=True)
         extras["batched"] = batched_leg(args.batch_maps)
         s2dw.release_caches()
         torch.cuda.empty_cache()
@@ -626,6 +630,7 @@ def main():
             out["p99_ms" + sfx] = r["p99_ms"]
     if "batched" in extras:
         out["batched_coeffs_per_s"] = extras["batched"]["value"]
+        out["persistent_coeffs_per_s"] = extras["batched"]["persistent"]["value"]
     if not args.no_cpu_baseline:
         print("# cpu baseline sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(L, N, lam, J_min)

@@ -39,8 +39,9 @@ def draw_maps(maps: int, seed: int = 3):
 
 def run(maps: int = 256, replays: int = 5, lam: float = 2.0, J_min: int = 1):
     """Runs the batched leg; returns (result dict, per-map data) where per-map data maps
-    (L, N) -> (map indices, f_lm [B][L*L], mixed W [B][...], round trip f [B][L*L]) on the
-    device, for callers that check sampled maps against a reference."""
+    (L, N) -> (map indices, f_lm [B][L*L], mixed W [B][...], round trip f [B][L*L], the
+    persistent executor's mixed W [B][...]) on the device, for callers that check sampled
+    maps against a reference."""
     Ls, Ns = draw_maps(maps)
     groups = {}
     for i, key in enumerate(zip(Ls, Ns)):
@@ -147,7 +148,8 @@ def run(maps: int = 256, replays: int = 5, lam: float = 2.0, J_min: int = 1):
            "tuned": {f"{k[0]},{k[1]}": v for k, v in tuned.items()},
            "max_rel_err_W_vs_fp64": max(errs_w), "max_rel_err_round_trip": max(errs_rt),
            "median_rel_err_W_vs_fp64": float(np.median(errs_w)), "persistent": persistent, "data": "synthetic"}
-    data = {key: (groups[key], F[key], bufs[key][0], bufs[key][2]) for key in F}
+    pW = {key: W for key, (W, _) in zip(keys, pouts)}
+    data = {key: (groups[key], F[key], bufs[key][0], bufs[key][2], pW[key]) for key in F}
     return out, data
 
 
