@@ -1606,7 +1606,9 @@ int run_persistent(int dir, const s2dw_group *groups, int32_t ngroups, int32_t *
         int rc = build_program(*np, dir, f32, gs, st);
         if (rc != S2DW_OK) return rc;
         std::lock_guard<std::mutex> lk(g_mu);
-        pr = (g_programs[key] = std::move(np)).get();
+        auto it = g_programs.find(key);
+        if (it != g_programs.end()) pr = it->second.get();  // built meanwhile by another thread: keep that one
+        else pr = (g_programs[key] = std::move(np)).get();
     }
     int spin, extra;
     {
