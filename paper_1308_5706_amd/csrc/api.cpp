@@ -456,13 +456,15 @@ std::vector<double2> pfa_tables(int T) {
     if (T == 2047) {
         roots(23);
         roots(89);
-        const int NW = 4, KG = 11, H = 44;
-        for (int w = 0; w < NW; ++w)
-            for (int r = 1; r <= H; ++r)
-                for (int kk = 0; kk < KG; ++kk) {
-                    const int k = 1 + w * KG + kk;
-                    t.push_back(cs(2.0L * kPiL * ((r * k) % 89) / 89));
-                }
+        // per wave of the length-89 stage, in its four-wave and eight-wave groupings
+        const int H = 44;
+        for (const auto &g : {std::make_pair(4, 11), std::make_pair(8, 6)})
+            for (int w = 0; w < g.first; ++w)
+                for (int r = 1; r <= H; ++r)
+                    for (int kk = 0; kk < g.second; ++kk) {
+                        const int k = 1 + w * g.second + kk;
+                        t.push_back(cs(2.0L * kPiL * ((r * k) % 89) / 89));
+                    }
     } else if (T == 4095) {
         roots(5);
         roots(7);

@@ -39,7 +39,10 @@ using fft::real_t;
 struct Tab2047 {
     static constexpr int c23 = 0, c89 = 23, g89 = 23 + 89;
     static constexpr int NW = 4, KG = 11;  // waves of the large stage, output pairs per wave
-    static constexpr int size = 23 + 89 + NW * 44 * KG;
+    // the same constants grouped for eight waves of six output pairs (the last wave's four
+    // pairs beyond k = 44 are computed and not used)
+    static constexpr int g89w = g89 + NW * 44 * KG, NWW = 8, KGW = 6;
+    static constexpr int size = g89w + NWW * 44 * KGW;
 };
 struct Tab4095 {
     static constexpr int c5 = 0, c7 = 5, c9 = 12, c13 = 21;
@@ -152,33 +155,40 @@ __device__ __forceinline__ void stage89(C *buf, int CS, int NC, const C *__restr
 struct Len2047 {
     static constexpr int T = 2047, NC = 2, NTH = 256, CS = 2047;
     static constexpr int lds = NC * CS;
+    // the length-89 stage: waves, output pairs per wave, offset of its constants
+    static constexpr int NW = Tab2047::NW, KG = Tab2047::KG, G89 = Tab2047::g89;
     // coordinates of index n: (n mod 23) * 15 mod 23 (15 = 89^-1 mod 23) and
     // (n mod 89) * 31 mod 89 (31 = 23^-1 mod 89); the array is [23][89]
     __device__ static __forceinline__ int pos_in(int n) { return ((n % 23) * 15 % 23) * 89 + (n % 89) * 31 % 89; }
     __device__ static __forceinline__ int pos_out(int k) { return (k % 23) * 89 + (k % 89); }
 };
 
+// The same length on workgroups of 512 threads (8 waves): two columns as before, the
+// length-89 stage spread over eight waves of six output pairs each, so that a wave holds
+// fewer accumulators and twice as many waves share the CU.
+struct Len2047W : Len2047 {
+    static constexpr int NTH = 512, NW = Tab2047::NWW, KG = Tab2047::KGW, G89 = Tab2047::g89w;
+};
+
 // The stages alone, on inputs already placed at buf[c * CS + pos_in(n)] (after a barrier);
 // output k of column c ends at buf[c * CS + pos_out(k)] (after a barrier).
-template <int S, class C>
+template <int S, class LN, class C>
 __device__ __forceinline__ void dft2047_stages(C *buf, const C *__restrict__ tab, int tid, int ncol) {
-    using L = Len2047;
-    stage_small<23, 89, L::T, L::NTH, S>(buf, L::CS, ncol, tab + Tab2047::c23, tid);
+    stage_small<23, 89, LN::T, LN::NTH, S>(buf, LN::CS, ncol, tab + Tab2047::c23, tid);
     __syncthreads();
-    stage89<L::T, Tab2047::NW, Tab2047::KG, S>(buf, L::CS, ncol, tab + Tab2047::g89, tid);
+    stage89<LN::T, LN::NW, LN::KG, S>(buf, LN::CS, ncol, tab + LN::G89, tid);
 }
 
 // in(c, n) gives element n < T of column c; on return output k of column c sits at
 // buf[c * CS + pos_out(k)] (after a barrier).
-template <int S, class C, class In>
+template <int S, class LN, class C, class In>
 __device__ __forceinline__ void dft2047_lds(C *buf, const C *__restrict__ tab, int tid, int ncol, In in) {
-    using L = Len2047;
-    for (int e = tid; e < ncol * L::T; e += L::NTH) {
-        const int c = e / L::T, n = e - (e / L::T) * L::T;
-        buf[c * L::CS + L::pos_in(n)] = in(c, n);
+    for (int e = tid; e < ncol * LN::T; e += LN::NTH) {
+        const int c = e / LN::T, n = e - (e / LN::T) * LN::T;
+        buf[c * LN::CS + LN::pos_in(n)] = in(c, n);
     }
     __syncthreads();
-    dft2047_stages<S>(buf, tab, tid, ncol);
+    dft2047_stages<S, LN>(buf, tab, tid, ncol);
 }
 
 // ------------------------------------------------------------------ T = 4095 = 5 x 7 x 9 x 13
@@ -227,7 +237,7 @@ __device__ __forceinline__ void dft4095_lds(C *buf, const C *__restrict__ tab, i
 // out(c, k, X) takes output k.
 template <class LN, int S, class C, class In, class Out>
 __device__ __forceinline__ void dft(C *buf, const C *__restrict__ tab, int tid, int ncol, In in, Out out) {
-    if constexpr (LN::T == 2047) dft2047_lds<S>(buf, tab, tid, ncol, in);
+    if constexpr (LN::T == 2047) dft2047_lds<S, LN>(buf, tab, tid, ncol, in);
     else dft4095_lds<S, LN::NTH>(buf, tab, tid, ncol, in);
     for (int e = tid; e < ncol * LN::T; e += LN::NTH) {
         const int c = e / LN::T, k = e - (e / LN::T) * LN::T;
@@ -239,14 +249,14 @@ __device__ __forceinline__ void dft(C *buf, const C *__restrict__ tab, int tid, 
 // output k of column c ends at buf[c * CS + pos_out(k)] (after a barrier).
 template <class LN, int S, class C>
 __device__ __forceinline__ void dft_stages(C *buf, const C *__restrict__ tab, int tid, int ncol) {
-    if constexpr (LN::T == 2047) dft2047_stages<S>(buf, tab, tid, ncol);
+    if constexpr (LN::T == 2047) dft2047_stages<S, LN>(buf, tab, tid, ncol);
     else dft4095_stages<S, LN::NTH>(buf, tab, tid, ncol);
 }
 
 // As dft, leaving output k of column c at buf[c * CS + pos_out(k)].
 template <class LN, int S, class C, class In>
 __device__ __forceinline__ void dft_lds(C *buf, const C *__restrict__ tab, int tid, int ncol, In in) {
-    if constexpr (LN::T == 2047) dft2047_lds<S>(buf, tab, tid, ncol, in);
+    if constexpr (LN::T == 2047) dft2047_lds<S, LN>(buf, tab, tid, ncol, in);
     else dft4095_lds<S, LN::NTH>(buf, tab, tid, ncol, in);
 }
 

@@ -56,7 +56,10 @@ hipError_t launch_alpha_adj_fft(const StageArgs &a, int P, int maps, hipStream_t
 
 bool pfa_length(int T) { return T == 2047 || T == 4095; }
 
-// T = 2L - 1 in {2047, 4095}
+// T = 2L - 1 in {2047, 4095}.  T = 4095 on eight-wave workgroups: the LDS of a column allows
+// two workgroups per CU, so the wider form doubles the waves (measured at L = 2048, N = 4:
+// the fused analysis alpha/gamma pass 1.76 -> 1.47 ms, the fused synthesis one 1.48 -> 1.37
+// ms per step); T = 2047 keeps four waves (its alpha kernels ran 7 % slower with eight).
 #define S2DW_PFA_LAUNCH(KER)                                                                         \
     {                                                                                                \
         if (t_rec) return hipErrorNotSupported;                                                      \
@@ -66,11 +69,11 @@ bool pfa_length(int T) { return T == 2047 || T == 4095; }
         const int nwg = (a.Nh * a.nb + NC - 1) / NC;                                                 \
         const dim3 grid((unsigned)(8 * ((nwg + 7) / 8)), (unsigned)maps);                            \
         if (T == 2047) {                                                                             \
-            if (a.f32) hipLaunchKernelGGL((KER<float2, pfa::Len2047>), grid, dim3(256), 0, st, a);   \
-            else hipLaunchKernelGGL((KER<double2, pfa::Len2047>), grid, dim3(256), 0, st, a);        \
+            if (a.f32) hipLaunchKernelGGL((KER<float2, pfa::Len2047>), grid, dim3(pfa::Len2047::NTH), 0, st, a); \
+            else hipLaunchKernelGGL((KER<double2, pfa::Len2047>), grid, dim3(pfa::Len2047::NTH), 0, st, a); \
         } else {                                                                                     \
-            if (a.f32) hipLaunchKernelGGL((KER<float2, pfa::Len4095>), grid, dim3(256), 0, st, a);   \
-            else hipLaunchKernelGGL((KER<double2, pfa::Len4095>), grid, dim3(256), 0, st, a);        \
+            if (a.f32) hipLaunchKernelGGL((KER<float2, pfa::Len4095T<512>>), grid, dim3(512), 0, st, a); \
+            else hipLaunchKernelGGL((KER<double2, pfa::Len4095T<512>>), grid, dim3(512), 0, st, a); \
         }                                                                                            \
         return hipGetLastError();                                                                    \
     }
@@ -83,12 +86,15 @@ hipError_t launch_beta_fwd_pfa(const StageArgs &a, int maps, hipStream_t st) {
     if (T != 2047 && T != 4095) return hipErrorInvalidValue;
     const int NC = T == 2047 ? pfa::Len2047::NC : pfa::Len4095::NC;
     const dim3 grid((unsigned)((a.N * ((a.Lj + 1) / 2) + NC - 1) / NC), (unsigned)maps);
+    // eight-wave workgroups at both lengths (measured: 0.58 -> 0.50 ms per step for the stage
+    // at L = 1024, N = 8; 0.76 -> 0.61 ms at L = 2048, N = 4)
     if (T == 2047) {
-        if (a.f32) hipLaunchKernelGGL((beta_fwd_pfa_kernel<float2, pfa::Len2047>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((beta_fwd_pfa_kernel<double2, pfa::Len2047>), grid, dim3(256), 0, st, a);
+        if (a.f32) hipLaunchKernelGGL((beta_fwd_pfa_kernel<float2, pfa::Len2047W>), grid, dim3(pfa::Len2047W::NTH), 0, st, a);
+        else hipLaunchKernelGGL((beta_fwd_pfa_kernel<double2, pfa::Len2047W>), grid, dim3(pfa::Len2047W::NTH), 0, st, a);
     } else {
-        if (a.f32) hipLaunchKernelGGL((beta_fwd_pfa_kernel<float2, pfa::Len4095>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((beta_fwd_pfa_kernel<double2, pfa::Len4095>), grid, dim3(256), 0, st, a);
+        using LW = pfa::Len4095T<512>;
+        if (a.f32) hipLaunchKernelGGL((beta_fwd_pfa_kernel<float2, LW>), grid, dim3(LW::NTH), 0, st, a);
+        else hipLaunchKernelGGL((beta_fwd_pfa_kernel<double2, LW>), grid, dim3(LW::NTH), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -98,14 +104,14 @@ hipError_t launch_alpha_adj_pfa(const StageArgs &a, int maps, hipStream_t st) S2
 // Orders n >= 0 whose transforms can wait in registers: at most 16 complex values per thread.
 bool pfa_fused(int T, int Nh) {
     if (T == 2047) return Nh >= 1 && Nh <= 4;  // two orders per pass, 8 samples per thread
-    if (T == 4095) return Nh >= 1 && Nh <= 2;  // one order per pass, 16 samples per thread
+    if (T == 4095) return Nh >= 1 && Nh <= 2;  // one order per pass, 8 samples per thread (512)
     return false;
 }
 
 #define S2DW_FUSED_CASE(KER, LN, NH)                                                                     \
     case NH:                                                                                             \
-        if (a.f32) hipLaunchKernelGGL((KER<float2, LN, NH>), grid, dim3(256), 0, st, a);                 \
-        else hipLaunchKernelGGL((KER<double2, LN, NH>), grid, dim3(256), 0, st, a);                      \
+        if (a.f32) hipLaunchKernelGGL((KER<float2, LN, NH>), grid, dim3(LN::NTH), 0, st, a);             \
+        else hipLaunchKernelGGL((KER<double2, LN, NH>), grid, dim3(LN::NTH), 0, st, a);                  \
         break;
 
 #define S2DW_FUSED_LAUNCH(KER)                                                                           \
@@ -124,8 +130,8 @@ bool pfa_fused(int T, int Nh) {
             }                                                                                            \
         } else {                                                                                         \
             switch (a.Nh) {                                                                              \
-                S2DW_FUSED_CASE(KER, pfa::Len4095, 1)                                                    \
-                S2DW_FUSED_CASE(KER, pfa::Len4095, 2)                                                    \
+                S2DW_FUSED_CASE(KER, pfa::Len4095T<512>, 1)                                          \
+                S2DW_FUSED_CASE(KER, pfa::Len4095T<512>, 2)                                          \
                 default: return hipErrorInvalidValue;                                                    \
             }                                                                                            \
         }                                                                                                \

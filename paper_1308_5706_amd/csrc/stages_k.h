@@ -156,12 +156,17 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) beta_fwd_pair_kernel(const
     beta_fwd_pair_body<C, P>(a, blockIdx.x, blockIdx.y, threadIdx.x, buf);
 }
 
+// Waves per SIMD the prime-factor kernels are built for: two eight-wave workgroups per CU
+// (their LDS allows two) for the eight-wave form, else as the registers fall.
+template <class LN>
+constexpr int pfa_min_waves() { return LN::NTH == 512 ? 4 : 1; }
+
 // The same two-column transform as a direct prime-factor transform of length T (pfa.h):
 //   F_z(beta_t) = sum_{m'} [z(m') e^{i pi m'/T}] e^{2 pi i m' t/T},  input index n = m' mod T,
 // for every scale of the equiangular grid when T is one of its lengths; LN::NC column pairs per
 // workgroup.  e^{i pi m'/T} = eph[m'/2 mod T] for even m', -eph[(m' + T)/2 mod T] for odd m'.
 template <class C, class LN>
-__global__ void __launch_bounds__(256) beta_fwd_pfa_kernel(const StageArgs a) {
+__global__ void __launch_bounds__(LN::NTH, pfa_min_waves<LN>()) beta_fwd_pfa_kernel(const StageArgs a) {
     __shared__ C buf[LN::lds];
     const int tid = threadIdx.x;
     const int Lj = a.Lj, L = a.L, T = LN::T, N = a.N;
@@ -313,7 +318,7 @@ __global__ void __launch_bounds__(P / kRM, kMinWaves) alpha_adj_fft_kernel(const
 //   analysis:  Y(a) = sum_{|m|<Lj} C(m) e^{2 pi i m a/T}: input index n = m mod T (sign +1)
 //   synthesis: Gs(m) = wa wg sum_a X(a) e^{-2 pi i m a/T}: output index k = m mod T (sign -1)
 template <class C, class LN>
-__global__ void __launch_bounds__(256) alpha_fwd_pfa_kernel(const StageArgs a) {
+__global__ void __launch_bounds__(LN::NTH, pfa_min_waves<LN>()) alpha_fwd_pfa_kernel(const StageArgs a) {
     __shared__ C buf[LN::lds];
     const int tid = threadIdx.x;
     const int Lj = a.Lj, T = LN::T, N = a.N, Nh = a.Nh, nb = a.nb;
@@ -342,7 +347,7 @@ __global__ void __launch_bounds__(256) alpha_fwd_pfa_kernel(const StageArgs a) {
 }
 
 template <class C, class LN>
-__global__ void __launch_bounds__(256) alpha_adj_pfa_kernel(const StageArgs a) {
+__global__ void __launch_bounds__(LN::NTH, pfa_min_waves<LN>()) alpha_adj_pfa_kernel(const StageArgs a) {
     __shared__ C buf[LN::lds];
     const int tid = threadIdx.x;
     const int Lj = a.Lj, T = LN::T, N = a.N, Nh = a.Nh, nb = a.nb;
@@ -384,7 +389,7 @@ template <class LN>
 constexpr int pfa_ks() { return (LN::T + LN::NTH - 1) / LN::NTH; }
 
 template <class C, class LN, int NH>
-__global__ void __launch_bounds__(256) alpha_gamma_fwd_pfa_kernel(const StageArgs a) {
+__global__ void __launch_bounds__(LN::NTH, pfa_min_waves<LN>()) alpha_gamma_fwd_pfa_kernel(const StageArgs a) {
     using R = real_t<C>;
     constexpr int T = LN::T, NC = LN::NC, NTH = LN::NTH, KS = pfa_ks<LN>();
     constexpr int NP = (NH + NC - 1) / NC, NHOLD = (NP - 1) * NC, NLAST = NH - NHOLD;
@@ -447,7 +452,7 @@ __global__ void __launch_bounds__(256) alpha_gamma_fwd_pfa_kernel(const StageArg
 }
 
 template <class C, class LN, int NH>
-__global__ void __launch_bounds__(256) gamma_alpha_adj_pfa_kernel(const StageArgs a) {
+__global__ void __launch_bounds__(LN::NTH, pfa_min_waves<LN>()) gamma_alpha_adj_pfa_kernel(const StageArgs a) {
     using R = real_t<C>;
     constexpr int T = LN::T, NC = LN::NC, NTH = LN::NTH, KS = pfa_ks<LN>();
     constexpr int NP = (NH + NC - 1) / NC;
