@@ -68,6 +68,10 @@ struct Plan {
     // full grid): their G arrays sit at goff[j] in the beta-stage workspace; mtab / mtabf
     // describe them to the kernel (mns scales, mnwg workgroups per map)
     int mj0 = -1, mns = 0, mnwg = 0;
+    // the analysis beta stage of the same coarse scales in one launch at the prime-factor
+    // lengths (their Ub arrays at goff[j]); atab describes them (ans scales, anwg workgroups)
+    int ans = 0, anwg = 0;
+    BetaAdjScale *atab = nullptr;
     size_t goff[kMaxScales] = {};
     BetaAdjScale *mtab = nullptr, *mtabf = nullptr;
     size_t woff[kMaxScales + 1] = {};           // element offset of scale j in the W of one map
@@ -754,6 +758,20 @@ int build_plan(int kind, int L, int N, double lam, int J_min, int grid, Plan *&o
             P.mj0 = j0;
             P.mns = (int)tab.size();
             P.mnwg = nwg;
+            if (pfa_length(2 * L - 1)) {
+                const int NC = 2 * L - 1 == 2047 ? 2 : 1;  // column pairs per workgroup
+                std::vector<BetaAdjScale> at;
+                int anwg = 0;
+                for (int j = j0; j < t.S; ++j) {
+                    const int Lj = P.sc.Lj[j];
+                    if (Lj == 0) continue;
+                    at.push_back(BetaAdjScale{anwg, Lj, (long long)P.sc.off[j], (long long)P.goff[j], nullptr});
+                    anwg += (t.N * ((Lj + 1) / 2) + NC - 1) / NC;
+                }
+                if (!upload(P, P.atab, at)) return S2DW_E_NOMEM;
+                P.ans = (int)at.size();
+                P.anwg = anwg;
+            }
         }
     }
     for (int Psz : sizes) {
@@ -1029,6 +1047,10 @@ int run_inverse(Plan &P, const Shape &sh, Work &w, int maps, const double2 *flm,
             continue;
         }
         const Plan::GridTab &gtab = P.gt[Lg];
+        // coarse scales: the beta stage of all of them in one launch at the first, each scale's
+        // Ub at goff[j]
+        const bool bmerged = P.ans > 0 && j >= P.mj0 && gtab.pcs && P.grid == S2DW_GRID_MW;
+        void *ubj = bmerged ? (f32 ? (void *)((float2 *)w.Ub + P.goff[j]) : (void *)(w.Ub + P.goff[j])) : (void *)w.Ub;
         StageArgs b{};
         b.f32 = f32;
         b.in = w.U + P.sc.off[j];
@@ -1050,7 +1072,15 @@ int run_inverse(Plan &P, const Shape &sh, Work &w, int maps, const double2 *flm,
             // two columns per transform: as a prime-factor transform of length T where T is one
             // of its lengths, else as a chirp convolution where that needs no larger transform
             // than one column's (equiangular grid)
-            if (!dh && gtab.pcs) {
+            if (bmerged) {
+                if (j == P.mj0) {
+                    StageArgs bm = b;
+                    bm.in = w.U;
+                    bm.eph = f32 ? (const void *)gtab.ephf : gtab.eph;
+                    bm.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
+                    S2DW_CHECK_HIP(launch_beta_fwd_pfa_multi(bm, P.atab, P.ans, P.anwg, maps, st));
+                }
+            } else if (!dh && gtab.pcs) {
                 b.eph = f32 ? (const void *)gtab.ephf : gtab.eph;
                 b.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
                 S2DW_CHECK_HIP(launch_beta_fwd_pfa(b, maps, st));
@@ -1061,7 +1091,7 @@ int run_inverse(Plan &P, const Shape &sh, Work &w, int maps, const double2 *flm,
         }
         if (direct_alpha_gamma(P.Nh, P.ng, Lj, cx)) {
             AlphaGammaArgs d{};
-            d.in = w.Ub;
+            d.in = ubj;
             d.wout = Wj;
             d.tg = P.tgf;
             d.eph = gtab.eph;
@@ -1081,7 +1111,7 @@ int run_inverse(Plan &P, const Shape &sh, Work &w, int maps, const double2 *flm,
         if (gtab.pcs && !cx && pfa_fused(2 * Lg - 1, P.Nh) && fuse_fwd(P, sh, j, 2 * Lg - 1)) {
             // the alpha and gamma passes in one prime-factor kernel, one beta ring per workgroup
             StageArgs d = b;
-            d.in = w.Ub;
+            d.in = ubj;
             d.s_in = P.s_Ub;
             d.pcs = f32 ? (const void *)gtab.pcsf : gtab.pcs;
             d.wout = Wj;
@@ -1093,7 +1123,7 @@ int run_inverse(Plan &P, const Shape &sh, Work &w, int maps, const double2 *flm,
             continue;
         }
         StageArgs c = b;
-        c.in = w.Ub;
+        c.in = ubj;
         c.out = w.Y;
         c.s_in = P.s_Ub;
         c.s_out = P.s_Y;

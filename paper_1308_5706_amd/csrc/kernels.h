@@ -110,8 +110,9 @@ hipError_t launch_gamma_alpha_adj_pfa(const StageArgs &a, int maps, hipStream_t 
 hipError_t launch_alpha_adj_blk(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_fft(const StageArgs &a, int P, int maps, hipStream_t st);
 hipError_t launch_beta_adj_dh(const StageArgs &a, int P, int maps, hipStream_t st);
-// One scale of a multi-scale synthesis beta launch: its first workgroup, band-limit, the
-// offsets (complex elements) of its G and V in the stage arrays, and its w(q) spectrum.
+// One scale of a multi-scale beta launch: its first workgroup, band-limit, the offsets
+// (elements) of its input and output in the stage arrays (synthesis: G and V; analysis: U and
+// Ub), and, in the synthesis, its w(q) spectrum.
 struct BetaAdjScale {
     int first, Lj;
     long long in_off, out_off;
@@ -119,6 +120,9 @@ struct BetaAdjScale {
 };
 hipError_t launch_beta_adj_multi(const StageArgs &a, const BetaAdjScale *tab, int ns, int nwg, int P, int maps,
                                  hipStream_t st);
+// The analysis beta stage of several scales at a prime-factor length T = 2L - 1 (2047, 4095).
+hipError_t launch_beta_fwd_pfa_multi(const StageArgs &a, const BetaAdjScale *tab, int ns, int nwg, int maps,
+                                     hipStream_t st);
 
 struct GammaArgs {
     const void *win;       // W read (synthesis): double, or float if f32

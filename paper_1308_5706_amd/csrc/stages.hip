@@ -99,6 +99,24 @@ hipError_t launch_beta_fwd_pfa(const StageArgs &a, int maps, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_beta_fwd_pfa_multi(const StageArgs &a, const BetaAdjScale *tab, int ns, int nwg, int maps,
+                                     hipStream_t st) {
+    if (t_rec) return hipErrorNotSupported;
+    const int T = 2 * a.L - 1;
+    if ((T != 2047 && T != 4095) || ns < 1 || nwg < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nwg, (unsigned)maps);
+    if (T == 2047) {
+        using LW = pfa::Len2047W;
+        if (a.f32) hipLaunchKernelGGL((beta_fwd_pfa_multi_kernel<float2, LW>), grid, dim3(LW::NTH), 0, st, a, tab, ns);
+        else hipLaunchKernelGGL((beta_fwd_pfa_multi_kernel<double2, LW>), grid, dim3(LW::NTH), 0, st, a, tab, ns);
+    } else {
+        using LW = pfa::Len4095T<512>;
+        if (a.f32) hipLaunchKernelGGL((beta_fwd_pfa_multi_kernel<float2, LW>), grid, dim3(LW::NTH), 0, st, a, tab, ns);
+        else hipLaunchKernelGGL((beta_fwd_pfa_multi_kernel<double2, LW>), grid, dim3(LW::NTH), 0, st, a, tab, ns);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_alpha_adj_pfa(const StageArgs &a, int maps, hipStream_t st) S2DW_PFA_LAUNCH(alpha_adj_pfa_kernel)
 
 // Orders n >= 0 whose transforms can wait in registers: at most 16 complex values per thread.

@@ -165,15 +165,13 @@ constexpr int pfa_min_waves() { return LN::NTH == 512 ? 4 : 1; }
 //   F_z(beta_t) = sum_{m'} [z(m') e^{i pi m'/T}] e^{2 pi i m' t/T},  input index n = m' mod T,
 // for every scale of the equiangular grid when T is one of its lengths; LN::NC column pairs per
 // workgroup.  e^{i pi m'/T} = eph[m'/2 mod T] for even m', -eph[(m' + T)/2 mod T] for odd m'.
+// Workgroup g of a scale of band-limit Lj; U and Ub: the scale's arrays of the map.
 template <class C, class LN>
-__global__ void __launch_bounds__(LN::NTH, pfa_min_waves<LN>()) beta_fwd_pfa_kernel(const StageArgs a) {
-    __shared__ C buf[LN::lds];
-    const int tid = threadIdx.x;
-    const int Lj = a.Lj, L = a.L, T = LN::T, N = a.N;
-    const int Mp = (Lj + 1) >> 1, ncols = N * Mp, nwg = (ncols + LN::NC - 1) / LN::NC;
-    if ((int)blockIdx.x >= nwg) return;
-    const int u0 = blockIdx.x * LN::NC, ncol = min(LN::NC, ncols - u0);
-    const double2 *__restrict__ U = (const double2 *)a.in + blockIdx.y * a.s_in;
+__device__ __forceinline__ void beta_fwd_pfa_body(const StageArgs &a, int Lj, const double2 *__restrict__ U,
+                                                  C *__restrict__ Ub, int g, int tid, C *buf) {
+    const int L = a.L, T = LN::T, N = a.N;
+    const int Mp = (Lj + 1) >> 1, ncols = N * Mp;
+    const int u0 = g * LN::NC, ncol = min(LN::NC, ncols - u0);
     const C *__restrict__ eph = (const C *)a.eph;
     auto in = [&](int c, int n) {
         const int u = u0 + c, ni = u / Mp, m0 = 2 * (u - (u / Mp) * Mp);
@@ -206,10 +204,36 @@ __global__ void __launch_bounds__(LN::NTH, pfa_min_waves<LN>()) beta_fwd_pfa_ker
         const bool odd0 = ((m0 + 2 * ni - (N - 1)) & 1) != 0;
         const C x = buf[c * LN::CS + LN::pos_out(b)], y = buf[c * LN::CS + LN::pos_out(T - 1 - b)];
         const C p = cscale(cadd(x, y), h), q = cscale(csub(x, y), h);
-        C *__restrict__ oa = (C *)a.out + blockIdx.y * a.s_out + ((size_t)ni * Lj + m0) * L;
+        C *__restrict__ oa = Ub + ((size_t)ni * Lj + m0) * L;
         oa[b] = odd0 ? q : p;
         if (two) oa[L + b] = odd0 ? p : q;
     }
+}
+
+template <class C, class LN>
+__global__ void __launch_bounds__(LN::NTH, pfa_min_waves<LN>()) beta_fwd_pfa_kernel(const StageArgs a) {
+    __shared__ C buf[LN::lds];
+    const int nwg = (a.N * ((a.Lj + 1) >> 1) + LN::NC - 1) / LN::NC;
+    if ((int)blockIdx.x >= nwg) return;
+    beta_fwd_pfa_body<C, LN>(a, a.Lj, (const double2 *)a.in + blockIdx.y * a.s_in,
+                             (C *)a.out + blockIdx.y * a.s_out, blockIdx.x, threadIdx.x, buf);
+}
+
+// The coarse scales of a map in one launch (each alone fills only a few workgroups and takes a
+// launch's latency): workgroups [tab[s].first, tab[s + 1].first) take scale s, whose U starts
+// tab[s].in_off elements after a.in and whose Ub goes tab[s].out_off elements after a.out.
+template <class C, class LN>
+__global__ void __launch_bounds__(LN::NTH, pfa_min_waves<LN>()) beta_fwd_pfa_multi_kernel(const StageArgs a,
+                                                                                          const BetaAdjScale *tab,
+                                                                                          int ns) {
+    __shared__ C buf[LN::lds];
+    const int bx = blockIdx.x;
+    int s = 0;
+    for (int i = 1; i < ns; ++i)
+        if (bx >= tab[i].first) s = i;
+    const BetaAdjScale e = tab[s];
+    beta_fwd_pfa_body<C, LN>(a, e.Lj, (const double2 *)a.in + blockIdx.y * a.s_in + e.in_off,
+                             (C *)a.out + blockIdx.y * a.s_out + e.out_off, bx - e.first, threadIdx.x, buf);
 }
 
 // ------------------------------------------------------------------ alpha and gamma stages
