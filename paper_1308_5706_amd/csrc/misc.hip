@@ -98,11 +98,13 @@ hipError_t launch_scaling(const double2 *flm, const double *phi, double2 *wphi, 
 // Fpart holds double2 (FP64 path) or float2 (mixed precision) partial sums; the final sum
 // over the m' groups and the harmonic synthesis factor are applied in FP64.
 template <class VC>
+// Rows in decreasing l: a row sums about l/group partial rows, so the heaviest rows start first
+// and the light ones fill in at the end.
 __global__ void syn_final_kernel(const VC *Fpart, size_t s_F, int nblk, int group, int Lmax, const double *fac,
                                  const double *gsc, const double2 *wphi, const double *phi, double2 *flm, int L,
                                  int Lp) {
     syn_final_elem(Fpart, s_F, nblk, group, Lmax, fac, gsc, wphi, phi, flm, L, Lp, blockIdx.x * blockDim.x + threadIdx.x,
-                   blockIdx.y, blockIdx.z);
+                   (int)gridDim.y - 1 - (int)blockIdx.y, blockIdx.z);
 }
 
 hipError_t launch_syn_final(const void *Fpart, size_t s_F, int f32, int nblk, int group, int Lmax, const double *fac,
