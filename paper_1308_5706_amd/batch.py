@@ -72,22 +72,37 @@ def run(maps: int = 256, replays: int = 5, lam: float = 2.0, J_min: int = 1):
     tuned = {}
     for key, f in F.items():
         tuned[key] = s2dw.autotune(key[0], key[1], lam, J_min, count=f.shape[0], precision="mixed")
+    # The groups are independent: they go to `branches` streams forked from the capture stream
+    # (heaviest first, each to the least loaded branch), so that the graph runs the small-L
+    # groups' latency-bound kernels side by side.  The library keeps a workspace per stream.
     s = torch.cuda.Stream()
+    branches = [torch.cuda.Stream() for _ in range(4)]
+    load = [0.0] * len(branches)
+    where = {}
+    for key in sorted(F, key=lambda k: -F[k].shape[0] * k[0] ** 3 * k[1]):
+        b = min(range(len(branches)), key=lambda i: load[i])
+        where[key] = b
+        load[b] += F[key].shape[0] * key[0] ** 3 * key[1]
     bufs = {}
-    with torch.cuda.stream(s):  # warm-up on the capture stream: allocates its workspaces
-        for key, f in F.items():
-            L, N = key
+    for key, f in F.items():  # warm-up on each group's stream: allocates its workspace
+        L, N = key
+        with torch.cuda.stream(branches[where[key]]):
             W, Wp = s2dw.analysis_batched(f, L, N, lam, J_min, precision="mixed")
             fr = s2dw.synthesis_batched(W, Wp, L, N, lam, J_min, precision="mixed")
             bufs[key] = (W, Wp, fr)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
+        for b in branches:
+            b.wait_stream(s)
         for key, f in F.items():
             L, N = key
             W, Wp, fr = bufs[key]
-            s2dw.analysis_batched(f, L, N, lam, J_min, out=W, precision="mixed")
-            s2dw.synthesis_batched(W, Wp, L, N, lam, J_min, out=fr, precision="mixed")
+            with torch.cuda.stream(branches[where[key]]):
+                s2dw.analysis_batched(f, L, N, lam, J_min, out=W, precision="mixed")
+                s2dw.synthesis_batched(W, Wp, L, N, lam, J_min, out=fr, precision="mixed")
+        for b in branches:
+            s.wait_stream(b)
     g.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
