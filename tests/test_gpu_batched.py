@@ -83,6 +83,51 @@ def test_graph_capture_replays_match_eager():
         torch.cuda.synchronize()
 
 
+def test_graph_branches_replay_match_eager():
+    # two (L, N) groups on two streams forked from the capture stream and joined back (as the
+    # batched leg captures its groups): every replay equals the eager results bitwise, with
+    # eager work between the replays
+    print("graph capture on two branches", flush=True)
+    groups = [(40, 4, 1, 3), (33, 3, 0, 2)]
+    s = torch.cuda.Stream()
+    branches = [torch.cuda.Stream(), torch.cuda.Stream()]
+    F, bufs, refs = {}, {}, {}
+    for k, (L, N, J_min, B) in enumerate(groups):
+        F[k] = torch.stack([dev(random_flm(L, 500 + 10 * k + i)) for i in range(B)])
+        S = s2dw.num_scales(L, 2.0, J_min)
+        W = torch.empty((B, S, 2 * N - 1, L, 2 * L - 1), dtype=torch.float64, device="cuda")
+        fr = torch.empty((B, L * L), dtype=torch.complex128, device="cuda")
+        with torch.cuda.stream(branches[k]):  # warm-up on the branch: its workspace
+            s2dw.analysis_batched(F[k], L, N, 2.0, J_min, out=W)
+            s2dw.synthesis_batched(W, None, L, N, 2.0, J_min, out=fr)
+        torch.cuda.synchronize()
+        bufs[k] = (W, fr)
+        refs[k] = (W.clone(), fr.clone())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for b in branches:
+            b.wait_stream(s)
+        for k, (L, N, J_min, B) in enumerate(groups):
+            W, fr = bufs[k]
+            with torch.cuda.stream(branches[k]):
+                s2dw.analysis_batched(F[k], L, N, 2.0, J_min, out=W)
+                s2dw.synthesis_batched(W, None, L, N, 2.0, J_min, out=fr)
+        for b in branches:
+            s.wait_stream(b)
+    for r in range(3):
+        for W, fr in bufs.values():
+            W.zero_()
+            fr.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in bufs:
+            assert torch.equal(bufs[k][0], refs[k][0]), (r, k)
+            assert torch.equal(bufs[k][1], refs[k][1]), (r, k)
+        L, N, J_min, _ = groups[0]
+        s2dw.analysis(F[0][0], L, N, 2.0, J_min)  # eager work between replays
+        torch.cuda.synchronize()
+
+
 def test_batched_mixed_maps_against_oracle():
     # the batched mixed-precision form of the many-maps configuration (L from {64, 128}, N from
     # {2, 4, 8}, J_min = 1), every map of each batch against the FP64 oracle at the mixed bar
