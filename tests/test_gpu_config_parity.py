@@ -6,8 +6,9 @@ afford sampled outputs:
   among them) and zero elsewhere, so the oracle's alpha/gamma rules run on those rows only;
   its beta integral and Wigner step then run on sampled m columns, including columns whose
   Delta start values lie below the double range (the extended-exponent tiles, m > 1022).
-* Mixed precision at L = 512 and L = 1024, N = 8, J_min = 1 (the FP32 transforms of size
-  2048 and 4096 and the FP32 m'-sum): sampled analysis rows and synthesis columns.
+* Mixed precision at L = 512 and L = 1024, N = 8, J_min = 1 and at L = 2048, N = 4,
+  J_min = 4 (the FP32 transforms of size 2048, 4096 and the prime-factor lengths 2047, 4095,
+  and the FP32 m'-sum): sampled analysis rows and synthesis columns.
 * The forward spherical-harmonic transform at L = 1024 on sampled m columns.
 * Results of the serving loop (one L = 1024 request among small ones, FP64; one mixed
   request) against the oracle.
@@ -92,9 +93,9 @@ def test_full_size_synthesis_of_arbitrary_samples(L, N, J_min, cols):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("L", [512, 1024])
-def test_mixed_precision_at_config_sizes(L):
-    N, J_min, lam = 8, 1, 2.0
+@pytest.mark.parametrize("L,N,J_min", [(512, 8, 1), (1024, 8, 1), (2048, 4, 4)])
+def test_mixed_precision_at_config_sizes(L, N, J_min):
+    lam = 2.0
     print(f"mixed precision L={L} N={N} J_min={J_min}: analysis rows", flush=True)
     f = random_flm(L, 31)
     rows = [0, L // 3, L - 1]
